@@ -390,9 +390,11 @@ def gmres(matvec, b, x0=None, tol=1e-10, restart=30, maxit=5000):
             H[j + 1, j] = np.linalg.norm(w)
             if H[j + 1, j] != 0:
                 Vb[j + 1] = w / H[j + 1, j]
+            # earlier rotations G_i = [[conj(c), conj(s)], [-s, c]], the same
+            # unitary map that zeroed column i's subdiagonal and updated e
             for i in range(j):
-                t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
-                H[i + 1, j] = -np.conj(sn[i]) * H[i, j] + np.conj(cs[i]) * H[i + 1, j]
+                t = np.conj(cs[i]) * H[i, j] + np.conj(sn[i]) * H[i + 1, j]
+                H[i + 1, j] = -sn[i] * H[i, j] + cs[i] * H[i + 1, j]
                 H[i, j] = t
             den = math.hypot(abs(H[j, j]), abs(H[j + 1, j]))
             cs[j] = H[j, j] / den if den else 1.0

@@ -133,6 +133,22 @@ def test_interface_solvers_agree():
         assert _rel(g, g_lu) < 1e-11
 
 
+def test_full_gmres_terminates_in_n_steps():
+    """Without restarts GMRES is exact after n steps on an n x n system
+    (Saad, Prop. 6.10), also for a complex, strongly non-normal matrix; the
+    Givens bookkeeping must keep the residual estimate equal to the true
+    residual."""
+    rng = np.random.default_rng(7)
+    n = 60
+    A = np.triu(rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)), -1)
+    A += 3 * np.eye(n)
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    x, its, hist = O.gmres(lambda v: A @ v, b, tol=1e-12, restart=n + 5, maxit=n + 5)
+    assert 0 < its <= n
+    assert np.linalg.norm(b - A @ x) / np.linalg.norm(b) < 1e-11
+    assert _rel(x, np.linalg.solve(A, b)) < 1e-9
+
+
 def test_gmres_on_dense_random_system():
     rng = np.random.default_rng(3)
     A = np.eye(40) + 0.3 * rng.standard_normal((40, 40)) / np.sqrt(40)
