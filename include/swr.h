@@ -1,0 +1,174 @@
+/*
+ * swr.h -- C ABI of the MI355X (gfx950) Schwarz waveform relaxation library
+ * for the 1-D Schroedinger equation  i u_t + u_xx + V u = 0  on (a0, b0) with
+ * homogeneous Neumann walls (Besse & Xing, arXiv 1503.02564, eq. Schequ).
+ *
+ * Method (paper Secs. 2-5):
+ *   - N non-overlapping subdomains, each solved over the whole time window by
+ *     Crank-Nicolson in the v-form of eq. CNS_L with P1 finite elements
+ *     (eq. AvML; nonlinear |u|^2: eq. CNS_NL / AvMNL);
+ *   - transmission B = dn + S written with fluxes (eq. TransmissionCondlocal)
+ *     and exchanged as in eq. TransmissionCond_disc; S is either Robin
+ *     (dn u + s u, complex s) or the potential strategy of order 2, S0^2;
+ *   - the interface vector g = (r_1 | l_2, r_2 | ... | l_N) of Sec. 3 and the
+ *     affine map g -> R g = L g + d (Props. 1-2);
+ *   - for time-independent V, L is built from impulse responses (Sec. 4.1;
+ *     every block lower-triangular Toeplitz, Props. 3-4) and (I - L) g = d is
+ *     solved on the device (Sec. 4 "New algorithm");
+ *   - for V(t,x) and |u|^2 the iteration is preconditioned by P = I - L_0,
+ *     L_0 the interface operator of the zero potential (Sec. 5).
+ *
+ * Conventions
+ *   - Every array argument is a DEVICE pointer (e.g. torch .data_ptr()) unless
+ *     marked "host".  Complex arrays are interleaved FP64 (re, im) pairs, i.e.
+ *     double[2] per entry (torch.complex128 / std::complex<double>).
+ *   - The caller owns every argument buffer.  The library copies what it
+ *     needs at setup (potential, mesh tables) into device memory it owns until
+ *     swr_destroy.  Outputs are written asynchronously on the context's stream;
+ *     the call returns after the last host read-back it needs (convergence
+ *     scalars), so outputs are complete when the stream is synchronised.
+ *   - Mesh: uniform, nc = sum(J) cells, h = (b0 - a0)/nc, nodes x_i = a0 + i h,
+ *     nx = nc + 1.  Subdomain k (0-based) owns nodes o_k .. o_k + J_k with
+ *     o_0 = 0, o_{k+1} = o_k + J_k; the node shared by two subdomains is
+ *     duplicated internally and reported as the average of the two sides.
+ *   - Time: nt = round(T/dt) steps; V(t,x) rows are t_n = n dt, n = 0..nt.
+ *   - Interface vectors g are [B][2N-2][nt]: slot 2k-1 holds l_k (k >= 1),
+ *     slot 2k holds r_k (k <= N-2); entry n-1 of a slot is time step n.
+ *   - A context is not thread-safe; separate contexts are independent.
+ *   - Errors are status codes; nothing is thrown across the ABI.  After any
+ *     status other than SWR_OK or SWR_ENOCONV the context remains valid for
+ *     swr_destroy.
+ */
+#ifndef SWR_H
+#define SWR_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct swr_ctx swr_ctx;
+
+typedef enum {
+    SWR_OK = 0,
+    SWR_EINVAL = 1,   /* invalid argument (see swr_setup / each call) */
+    SWR_ENOMEM = 2,   /* device allocation failed */
+    SWR_EDEVICE = 3,  /* a HIP call or kernel launch failed */
+    SWR_ENOCONV = 4,  /* iteration limit reached; outputs hold the last iterate */
+    SWR_ENAN = 5      /* NaN/Inf met in the interface residual */
+} swr_status;
+
+/* transmission operator S of B = dn + S (Sec. 2.1) */
+typedef enum { SWR_ROBIN = 0, SWR_S02 = 1 } swr_transmission;
+
+/* potential: static V(x) [nx] | time dependent V(t,x) [nt+1][nx] | |u|^2 (V NULL) */
+typedef enum { SWR_V_STATIC = 0, SWR_V_TIME = 1, SWR_V_CUBIC = 2 } swr_vkind;
+
+/* interface solver */
+typedef enum {
+    SWR_SOLVER_FIXED = 0,   /* fixed point g <- R g (Sec. 4 "Classical algorithm") */
+    SWR_SOLVER_GMRES = 1,   /* restarted GMRES on (I - L) g = d (Sec. 4) */
+    SWR_SOLVER_CAUSAL = 2   /* exact forward substitution in time on (I - L) g = d */
+} swr_solver;
+
+typedef struct {
+    double tol;        /* FIXED: max |g^{k+1} - g^k| < tol; GMRES: ||d - (I-L)g||_2 <= tol ||d||_2.
+                          default 1e-10 */
+    int max_iter;      /* iteration cap (default 20000) */
+    int restart;       /* GMRES restart length m (default 30) */
+    int solver;        /* swr_solver (default SWR_SOLVER_CAUSAL) */
+    int precond;       /* V_TIME / V_CUBIC: 1 = precondition with P = I - L_0 (default 1) */
+    int batch;         /* B independent problems sharing mesh and transmission (default 1) */
+    int v_per_problem; /* V_STATIC only: V is [B][nx], one potential per problem (default 0) */
+    int checkpoint_K;  /* adjoint checkpoint interval in steps (default 64) */
+    int nl_max_iter;   /* |u|^2 inner fixed point cap per step (default 100) */
+    double nl_tol;     /* |u|^2 inner fixed point tolerance (default 1e-14) */
+} swr_opts;
+
+typedef struct {
+    int iters;          /* interface iterations (FIXED/GMRES), 1 for CAUSAL */
+    double residual;    /* certified ||g - R g||_2 / ||R 0||_2 of the final sweep
+                           (max over the batch); FIXED: last max change */
+    double t_factor_ms; /* assembly + factorisation */
+    double t_build_ms;  /* impulse sweeps and d (Sec. 4.1) */
+    double t_iface_ms;  /* interface solve */
+    double t_final_ms;  /* final sweep and u(T) */
+    int nl_worst;       /* |u|^2: largest inner iteration count */
+} swr_info;
+
+/* Fill *o with the defaults listed above. */
+void swr_default_opts(swr_opts* o);
+
+/* Create a context.
+ *   a0 < b0: the domain.  N >= 1 subdomains with J[k] >= 1 cells each (J: host
+ *   array of N ints).  dt > 0, T > 0 with T/dt an integer to 1e-9 relative.
+ *   vk: potential kind; V: device array [nx] (STATIC), [B][nx] (STATIC with
+ *   opts->v_per_problem), [nt+1][nx] (TIME), or NULL (CUBIC; also allowed for
+ *   STATIC, meaning V = 0).  tr: transmission; s_re + i s_im is the Robin
+ *   coefficient s of dn u + s u (ignored for S0^2; must be nonzero for Robin).
+ *   opts: NULL for defaults.  stream: hipStream_t the work is enqueued on
+ *   (NULL = default stream).  *out receives the context.
+ * Errors: SWR_EINVAL for any violated condition above, a nonzero-size
+ * subdomain larger than the kernel's node bound (512 nodes per subdomain),
+ * batch < 1, or CUBIC combined with batch > 1 problems of different V;
+ * SWR_ENOMEM / SWR_EDEVICE on allocation / launch failure. */
+swr_status swr_setup(double a0, double b0, int N, const int* J, double dt, double T,
+                     int vk, const double* V, int tr, double s_re, double s_im,
+                     const swr_opts* opts, void* stream, swr_ctx** out);
+
+/* Solve the B problems with initial data u0 [B][nx] complex.
+ * Static V: Sec. 4 "New algorithm" -- factorise, impulse sweeps for L and the
+ * d sweep (one launch), interface solve by opts.solver, final sweep.  V(t,x) /
+ * |u|^2: Sec. 5 preconditioned iteration.  Outputs: uT [B][nx] complex
+ * (required); g [B][2N-2][nt] converged interface vector (NULL to skip);
+ * utrace [B][N][2][nt+1]: u_n at the left/right end node of every subdomain,
+ * n = 0..nt (NULL to skip).  info: host struct (NULL to skip).
+ * Returns SWR_ENOCONV if the solver hit max_iter (outputs hold the last
+ * iterate), SWR_ENAN on a non-finite residual. */
+swr_status swr_solve(swr_ctx* ctx, const double* u0, double* uT, double* g, double* utrace,
+                     swr_info* info);
+
+/* Gradient of a real objective J(u(T)) with respect to the static potential
+ * and the initial data, by the discrete adjoint of the Crank-Nicolson scheme
+ * solved through the same decomposition (STATIC potential only).
+ *   u0 [B][nx] complex; gbar [B][nx] complex upstream gradient
+ *   dJ/dRe u(T) + i dJ/dIm u(T) (for J = sum |u(T) - u*|^2 it is 2(u(T) - u*)).
+ *   dJdV [B][nx] real, dJdu0 [B][nx] complex (same convention).
+ * Forward states are checkpointed every opts.checkpoint_K steps and
+ * recomputed segment by segment in reverse. */
+swr_status swr_grad(swr_ctx* ctx, const double* u0, const double* gbar, double* dJdV,
+                    double* dJdu0, swr_info* info);
+
+/* ---- step-level entry points (each one row of the hot path) ------------ */
+
+/* One SWR iteration for all B problems (Sec. 3, eq. interfacepbR):
+ * g_out = R g_in, i.e. every subdomain swept with the fluxes of g_in and the
+ * data u0 (NULL = zero data and zero history, which gives g_out = L g_in).
+ * g_in, g_out: [B][2N-2][nt]; must not overlap.  uT [B][nx] (NULL to skip)
+ * receives u(T) of this sweep.  maxdiff (host, NULL to skip) receives
+ * max |g_out - g_in|. */
+swr_status swr_apply_R(swr_ctx* ctx, const double* u0, const double* g_in, double* g_out,
+                       double* uT, double* maxdiff);
+
+/* Build the explicit interface problem (Sec. 4.1, static V): impulse sweeps
+ * give the first columns of all blocks X^{k,p}, cols [nv][N][4][nt] (p = 0..3
+ * for X^{k,1..4}; entries of absent blocks are left untouched), and
+ * d = R 0 [B][2N-2][nt] from the data u0.  Either output may be NULL. */
+swr_status swr_build_interface(swr_ctx* ctx, const double* u0, double* cols, double* d);
+
+/* y = x - L x for [B][2N-2][nt] vectors with L from the last build (the
+ * matrix of the Krylov solver; static V). */
+swr_status swr_interface_matvec(swr_ctx* ctx, const double* x, double* y);
+
+/* Release the context and all device memory it owns. */
+void swr_destroy(swr_ctx* ctx);
+
+/* Static description of a status code. */
+const char* swr_strerror(swr_status s);
+
+/* Number of time steps and global nodes of a context (host ints). */
+swr_status swr_sizes(const swr_ctx* ctx, int* nt, int* nx, int* B, int* nv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SWR_H */

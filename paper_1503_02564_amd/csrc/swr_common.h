@@ -1,0 +1,191 @@
+// swr_common.h -- types and wave-level helpers shared by the SWR kernels.
+//
+// All arithmetic is FP64 complex, interleaved (re, im) -- the layout of
+// std::complex<double> / torch.complex128.  One wavefront is 64 lanes.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace swr {
+
+constexpr int kWave = 64;
+
+struct __align__(16) cd {
+    double x, y;
+};
+
+__host__ __device__ inline cd mk(double x, double y) { cd r; r.x = x; r.y = y; return r; }
+__host__ __device__ inline cd operator+(cd a, cd b) { return mk(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline cd operator-(cd a, cd b) { return mk(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline cd operator-(cd a) { return mk(-a.x, -a.y); }
+__host__ __device__ inline cd operator*(cd a, cd b) { return mk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__host__ __device__ inline cd operator*(double s, cd a) { return mk(s * a.x, s * a.y); }
+__host__ __device__ inline cd conjc(cd a) { return mk(a.x, -a.y); }
+__host__ __device__ inline double abs2(cd a) { return a.x * a.x + a.y * a.y; }
+// 1/z as conj(z)/|z|^2 (reciprocal-multiply; only used outside the time loop)
+__host__ __device__ inline cd inv(cd a) { double s = 1.0 / abs2(a); return mk(a.x * s, -a.y * s); }
+// i*a
+__host__ __device__ inline cd mul_i(cd a) { return mk(-a.y, a.x); }
+// a - b*c (one complex multiply-subtract)
+__host__ __device__ inline cd msub(cd a, cd b, cd c) {
+    return mk(a.x - b.x * c.x + b.y * c.y, a.y - b.x * c.y - b.y * c.x);
+}
+// a + b*c
+__host__ __device__ inline cd madd(cd a, cd b, cd c) {
+    return mk(a.x + b.x * c.x - b.y * c.y, a.y + b.x * c.y + b.y * c.x);
+}
+
+__device__ inline int lane_id() { return __lane_id(); }
+
+__device__ inline double rdlane(double v, int l) {
+    int2 t = *reinterpret_cast<int2*>(&v);
+    t.x = __builtin_amdgcn_readlane(t.x, l);
+    t.y = __builtin_amdgcn_readlane(t.y, l);
+    return *reinterpret_cast<double*>(&t);
+}
+__device__ inline cd rdlane(cd v, int l) { return mk(rdlane(v.x, l), rdlane(v.y, l)); }
+
+// value of lane (lane - d); lanes below d receive `fill`
+__device__ inline cd shfl_up_c(cd v, int d, cd fill) {
+    int src = lane_id() - d;
+    cd r = mk(__shfl(v.x, src < 0 ? 0 : src), __shfl(v.y, src < 0 ? 0 : src));
+    return src < 0 ? fill : r;
+}
+// value of lane (lane + d); lanes with lane + d >= 64 receive `fill`
+__device__ inline cd shfl_dn_c(cd v, int d, cd fill) {
+    int src = lane_id() + d;
+    cd r = mk(__shfl(v.x, src > 63 ? 63 : src), __shfl(v.y, src > 63 ? 63 : src));
+    return src > 63 ? fill : r;
+}
+
+__device__ inline double wave_max(double v) {
+    for (int d = 32; d >= 1; d >>= 1) v = fmax(v, __shfl_xor(v, d));
+    return v;
+}
+__device__ inline double wave_sum(double v) {
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Problem-wide constants handed to every kernel.
+// ---------------------------------------------------------------------------
+enum Trans { TR_ROBIN = 0, TR_S02 = 1 };
+enum VKind { VK_STATIC = 0, VK_TIME = 1, VK_CUBIC = 2 };
+
+// Task flags: one sweep of one subdomain of one problem.
+enum TaskFlags {
+    T_DATA_U0   = 1 << 0,   // initial data from u0 (else zero data, zero v_0 history)
+    T_FLUX_G    = 1 << 1,   // incoming fluxes l_k, r_k from g_in slots
+    T_IMP_L     = 1 << 2,   // l_{k,1} = 1, everything else 0
+    T_IMP_R     = 1 << 3,   // r_{k,1} = 1
+    T_OUT_G     = 1 << 4,   // outgoing fluxes -> g_out slots
+    T_OUT_COLS  = 1 << 5,   // outgoing fluxes -> first-column store
+    T_OUT_UT    = 1 << 6,   // u(T) -> uT (interior nodes) + ends
+    T_OUT_TRACE = 1 << 7,   // u_n at the two end nodes -> trace store
+    T_MAXDIFF   = 1 << 8,   // fold max |g_out - g_in| over written slots
+};
+
+struct Task {
+    int k;      // subdomain
+    int b;      // problem (batch member)
+    int f;      // factor set (potential index)
+    int flags;
+};
+
+// Layout of the per-lane factor record of one subdomain (see factor kernel).
+// For a chunk of up to P nodes per lane: P-1 interior nodes with
+// {inv, ainv, cp, alpha, gamma}, then {a_sep, c_sep}, then PCR {k1[6], k2[6]},
+// then 1/B of the decoupled reduced equation.
+constexpr int kPcrLevels = 6;
+__host__ __device__ constexpr int fac_fields(int P) { return 5 * (P - 1) + 2 + 2 * kPcrLevels + 1; }
+constexpr int kMaxP = 8;
+
+struct SweepArgs {
+    int N, nt, B, nx, ns;        // ns = 2N-2 interface slots
+    int ntasks;
+    int P;                       // nodes-per-lane bound the factors were built for
+    double kappa;                // h / (3 dt):  c M = i kappa * tridiag(1,4,1)
+    cd sigma;                    // implicit transmission coefficient
+    cd c2;                       // S0^2 history prefactor e^{-i pi/4} sqrt(2/dt)
+    const int* J;                // [N] cells per subdomain
+    const int* off;              // [N] first global node
+    const Task* tasks;
+    const cd* fac;               // [nf][fac_fields(P)][64]
+    const double* beta;          // [nt + 65]
+    const cd* u0;                // [B][nx]
+    const cd* g_in;              // [B][ns][nt]
+    cd* g_out;                   // [B][ns][nt]
+    cd* cols;                    // [nf/N ... ] first columns [nv][N][4][nt]
+    cd* hist;                    // [ntasks][2][nt+1] boundary v_n history
+    cd* uT;                      // [B][nx]
+    cd* ends;                    // [B][N][2] u(T) at the two end nodes
+    cd* trace;                   // [B][N][2][nt+1] u_n at the two end nodes
+    unsigned long long* maxdiff; // max |g_out - g_in| as ordered bits
+};
+
+struct FactorArgs {
+    int N, nx, nf, P;
+    double h, dt;
+    cd sigma;
+    const int* J;
+    const int* off;
+    const double* V;             // [nv][nx] static potential (nullptr = 0)
+    cd* fac;
+};
+
+struct LttArgs {
+    int N, nt, ns, B;
+    int per_problem;       // cols indexed by problem (1) or shared (0)
+    const cd* cols;        // [nv][N][4][nt]
+    const cd* x;           // [B][ns][nt]
+    cd* y;                 // output, see y_ld / n_lo
+    const cd* base;        // y = base + sign * L x  (base may be x itself or null)
+    double sign;
+    int n_lo, n_hi;        // output time window
+    int s_hi;              // only inputs s < s_hi contribute
+    int y_ld;              // leading dimension of y / base per (b, slot)
+};
+
+// In-block forward substitution of the causal interface solve.
+struct CausalArgs {
+    int N, nt, ns, B, per_problem;
+    int n0, nb;
+    const cd* cols;
+    const cd* Minv;    // [nv][ns][ns]  (I - C_0)^{-1}
+    const cd* d;       // [B][ns][nt]
+    const cd* far;     // [B][ns][kCausalTb]
+    cd* g;             // [B][ns][nt]
+};
+constexpr int kCausalTb = 64;
+constexpr int kRedBlocks = 240;   // partial-sum blocks per problem
+constexpr int kRedThreads = 256;
+
+// launchers (swr_sweep.hip)
+hipError_t launch_factor(const FactorArgs& a, hipStream_t st);
+hipError_t launch_sweep(const SweepArgs& a, int trans, hipStream_t st);
+hipError_t launch_finalize_ut(int N, int nx, int B, const int* off, const cd* ends, cd* uT,
+                              hipStream_t st);
+hipError_t launch_beta(int n, double* beta, hipStream_t st);
+// launchers (swr_iface.hip)
+hipError_t launch_ltt(const LttArgs& a, hipStream_t st);
+hipError_t launch_multidot(const cd* basis, int nv, const cd* w, long M, int B, double* partial,
+                           cd* out, int out_ld, int accumulate, hipStream_t st);
+hipError_t launch_multiaxpy(const cd* basis, int nv, const cd* coef, int coef_ld, double sign,
+                            cd* w, long M, int B, hipStream_t st);
+hipError_t launch_norm(const cd* w, long M, int B, double* partial, double* nrm, hipStream_t st);
+hipError_t launch_scale(const cd* src, const double* den, cd* dst, long M, int B, const int* active,
+                        hipStream_t st);
+hipError_t launch_givens(int j, int m, int B, const cd* hproj, const double* hnext, cd* H, cd* cs,
+                         cd* sn, cd* e, const double* bnorm, double* resid, int* active,
+                         hipStream_t st);
+hipError_t launch_gmres_solve(int jj, int m, int B, const cd* H, const cd* e, cd* y,
+                              const int* active, hipStream_t st);
+hipError_t launch_gmres_init(int m, int B, const double* beta, cd* e, int* active,
+                             const double* bnorm, double tol, double* resid, hipStream_t st);
+hipError_t launch_c0_inverse(int N, int ns, int nt, int nv, const cd* cols, cd* work, cd* Minv,
+                             int* piv_ok, hipStream_t st);
+hipError_t launch_causal_block(const CausalArgs& a, hipStream_t st);
+hipError_t launch_axpby(const cd* x, double a, const cd* y, double b, cd* z, long n, hipStream_t st);
+
+}  // namespace swr

@@ -1,0 +1,432 @@
+// swr_iface.hip -- the interface problem (I - L) g = d of Schwarz waveform
+// relaxation (Besse & Xing, arXiv 1503.02564, Secs. 3-4) on gfx950.
+//
+// L is stored as the first columns of its blocks X^{k,p} (Sec. 4.1); every
+// block is lower-triangular Toeplitz (Props. 3-4), so a block product is the
+// causal convolution  y_n = sum_{s<=n} c_{n-s} x_s.
+//
+// Slot algebra (Sec. 3, vector g; eq. chp1_L_N):  output slot 2k-2 (r_{k-1})
+// is written by subdomain k from columns p = 0, 1 (X^{k,1} l_k + X^{k,2} r_k);
+// output slot 2k+1 (l_{k+1}) from p = 2, 3 (X^{k,3} l_k + X^{k,4} r_k); l_k
+// lives in slot 2k-1 and r_k in slot 2k.
+#include <algorithm>
+
+#include "swr_common.h"
+
+namespace swr {
+
+
+__device__ inline void slot_sources(int o, int N, int& k, int& pl, int& pr, int& sl, int& sr) {
+    if ((o & 1) == 0) { k = o / 2 + 1; pl = 0; pr = 1; }
+    else { k = (o - 1) / 2; pl = 2; pr = 3; }
+    sl = (k >= 1) ? 2 * k - 1 : -1;
+    sr = (k <= N - 2) ? 2 * k : -1;
+}
+
+// One thread per output entry (b, slot, n).
+__global__ __launch_bounds__(256) void ltt_apply_kernel(LttArgs a) {
+    const int n = a.n_lo + blockIdx.x * blockDim.x + threadIdx.x;
+    const int o = blockIdx.y, b = blockIdx.z;
+    if (n >= a.n_hi) return;
+    int k, pl, pr, sl, sr;
+    slot_sources(o, a.N, k, pl, pr, sl, sr);
+    const int v = a.per_problem ? b : 0;
+    const cd* cl = a.cols + ((size_t)(v * a.N + k) * 4 + pl) * a.nt;
+    const cd* cr = a.cols + ((size_t)(v * a.N + k) * 4 + pr) * a.nt;
+    const cd* xl = sl >= 0 ? a.x + ((size_t)b * a.ns + sl) * a.nt : nullptr;
+    const cd* xr = sr >= 0 ? a.x + ((size_t)b * a.ns + sr) * a.nt : nullptr;
+    const int send = min(n + 1, a.s_hi);
+    double ax = 0, ay = 0, bx = 0, by = 0;
+    if (xl) {
+        for (int s = 0; s < send; ++s) {
+            const cd c = cl[n - s], xv = xl[s];
+            ax += c.x * xv.x - c.y * xv.y;
+            ay += c.x * xv.y + c.y * xv.x;
+        }
+    }
+    if (xr) {
+        for (int s = 0; s < send; ++s) {
+            const cd c = cr[n - s], xv = xr[s];
+            bx += c.x * xv.x - c.y * xv.y;
+            by += c.x * xv.y + c.y * xv.x;
+        }
+    }
+    const size_t yi = ((size_t)b * a.ns + o) * a.y_ld + (n - a.n_lo);
+    cd r = mk(a.sign * (ax + bx), a.sign * (ay + by));
+    if (a.base) r = r + a.base[yi];
+    a.y[yi] = r;
+}
+
+hipError_t launch_ltt(const LttArgs& a, hipStream_t st) {
+    if (a.ns == 0 || a.n_hi <= a.n_lo) return hipSuccess;
+    dim3 grid((a.n_hi - a.n_lo + 255) / 256, a.ns, a.B);
+    ltt_apply_kernel<<<grid, 256, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Batched vector kernels for GMRES.  Vectors are [B][M] complex; the Krylov
+// basis is V[i] = basis + i * B * M.  Reductions are two-stage and
+// deterministic: per-block partials, then one reduction kernel.
+// ---------------------------------------------------------------------------
+
+__device__ inline double block_sum(double v, double* sh) {
+    v = wave_sum(v);
+    const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+    if (l == 0) sh[w] = v;
+    __syncthreads();
+    double r = 0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x / kWave); ++i) r += sh[i];
+    __syncthreads();
+    return r;
+}
+
+// partial[b][blk][i] = sum over the block's range of conj(V_i) w,  i < nv
+__global__ __launch_bounds__(kRedThreads) void multidot_kernel(const cd* basis, int nv, const cd* w,
+                                                              long M, int B, double* partial) {
+    __shared__ double sh[8];
+    const int b = blockIdx.y;
+    const long per = (M + gridDim.x - 1) / gridDim.x;
+    const long lo = blockIdx.x * per, hi = min(M, lo + per);
+    const cd* wb = w + (size_t)b * M;
+    for (int i = 0; i < nv; ++i) {
+        const cd* vb = basis + ((size_t)i * B + b) * M;
+        double sx = 0, sy = 0;
+        for (long e = lo + threadIdx.x; e < hi; e += blockDim.x) {
+            const cd p = vb[e], q = wb[e];
+            sx += p.x * q.x + p.y * q.y;
+            sy += p.x * q.y - p.y * q.x;
+        }
+        const double tx = block_sum(sx, sh);
+        const double ty = block_sum(sy, sh);
+        if (threadIdx.x == 0) {
+            double* pp = partial + (((size_t)b * gridDim.x + blockIdx.x) * nv + i) * 2;
+            pp[0] = tx;
+            pp[1] = ty;
+        }
+    }
+}
+
+// out[b][i] (+)= sum over blocks of partial[b][blk][i]
+__global__ void reduce_partials_kernel(const double* partial, int nblk, int nv, int B, cd* out,
+                                       int out_ld, int accumulate) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= B * nv) return;
+    const int b = idx / nv, i = idx % nv;
+    double sx = 0, sy = 0;
+    for (int k = 0; k < nblk; ++k) {
+        const double* pp = partial + (((size_t)b * nblk + k) * nv + i) * 2;
+        sx += pp[0];
+        sy += pp[1];
+    }
+    cd r = mk(sx, sy);
+    cd* o = out + (size_t)b * out_ld + i;
+    if (accumulate) r = r + *o;
+    *o = r;
+}
+
+// w[b] += sign * sum_{i<nv} coef[b][i] V_i[b]
+__global__ __launch_bounds__(256) void multiaxpy_kernel(const cd* basis, int nv, const cd* coef,
+                                                        int coef_ld, double sign, cd* w, long M,
+                                                        int B) {
+    const int b = blockIdx.y;
+    const cd* cb = coef + (size_t)b * coef_ld;
+    cd* wb = w + (size_t)b * M;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < M; e += (long)gridDim.x * blockDim.x) {
+        cd acc = wb[e];
+        for (int i = 0; i < nv; ++i) {
+            const cd c = sign * cb[i];
+            acc = madd(acc, c, basis[((size_t)i * B + b) * M + e]);
+        }
+        wb[e] = acc;
+    }
+}
+
+// partial[b][blk] = sum |w|^2 over the block's range
+__global__ __launch_bounds__(kRedThreads) void norm2_kernel(const cd* w, long M, double* partial) {
+    __shared__ double sh[8];
+    const int b = blockIdx.y;
+    const long per = (M + gridDim.x - 1) / gridDim.x;
+    const long lo = blockIdx.x * per, hi = min(M, lo + per);
+    const cd* wb = w + (size_t)b * M;
+    double s = 0;
+    for (long e = lo + threadIdx.x; e < hi; e += blockDim.x) s += abs2(wb[e]);
+    const double t = block_sum(s, sh);
+    if (threadIdx.x == 0) partial[(size_t)b * gridDim.x + blockIdx.x] = t;
+}
+
+// nrm[b] = sqrt(sum partial[b][:])
+__global__ void reduce_norm_kernel(const double* partial, int nblk, int B, double* nrm) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    double s = 0;
+    for (int k = 0; k < nblk; ++k) s += partial[(size_t)b * nblk + k];
+    nrm[b] = sqrt(s);
+}
+
+// dst[b] = src[b] * (1 / den[b]) (den == 0 -> zero)
+__global__ __launch_bounds__(256) void scale_kernel(const cd* src, const double* den, cd* dst, long M,
+                                                    int B, const int* active) {
+    const int b = blockIdx.y;
+    if (active && !active[b]) return;
+    const double s = den[b] != 0.0 ? 1.0 / den[b] : 0.0;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < M; e += (long)gridDim.x * blockDim.x)
+        dst[(size_t)b * M + e] = s * src[(size_t)b * M + e];
+}
+
+// Arnoldi column j of problem b: H[b] (m+1) x m column-major in hcol, Givens
+// rotations cs/sn, residual vector e.  hcol[b][0..j] holds the projections,
+// hnext[b] = ||w||.  Writes the residual estimate |e_{j+1}| / bnorm.
+__global__ void givens_kernel(int j, int m, int B, const cd* hproj, const double* hnext, cd* H,
+                              cd* cs, cd* sn, cd* e, const double* bnorm, double* resid,
+                              int* active) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B || !active[b]) return;
+    cd* Hb = H + (size_t)b * (m + 1) * m;
+    cd* col = Hb + (size_t)j * (m + 1);
+    for (int i = 0; i <= j; ++i) col[i] = hproj[(size_t)b * (m + 1) + i];
+    col[j + 1] = mk(hnext[b], 0);
+    cd* c = cs + (size_t)b * m;
+    cd* s = sn + (size_t)b * m;
+    cd* eb = e + (size_t)b * (m + 1);
+    // earlier rotations [[conj c, conj s], [-s, c]] (unitary; the same map
+    // that annihilated their own subdiagonal entries and updated e)
+    for (int i = 0; i < j; ++i) {
+        const cd t = conjc(c[i]) * col[i] + conjc(s[i]) * col[i + 1];
+        col[i + 1] = c[i] * col[i + 1] - s[i] * col[i];
+        col[i] = t;
+    }
+    const double den = sqrt(abs2(col[j]) + abs2(col[j + 1]));
+    cd cj = mk(1, 0), sj = mk(0, 0);
+    if (den > 0) { cj = (1.0 / den) * col[j]; sj = (1.0 / den) * col[j + 1]; }
+    c[j] = cj;
+    s[j] = sj;
+    col[j] = conjc(cj) * col[j] + conjc(sj) * col[j + 1];
+    col[j + 1] = mk(0, 0);
+    eb[j + 1] = -(sj * eb[j]);
+    eb[j] = conjc(cj) * eb[j];
+    resid[b] = sqrt(abs2(eb[j + 1])) / bnorm[b];
+}
+
+// Back substitution H y = e on the leading jj x jj block; y stored in ycoef.
+__global__ void gmres_solve_kernel(int jj, int m, int B, const cd* H, const cd* e, cd* y,
+                                   const int* active) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    cd* yb = y + (size_t)b * (m + 1);
+    if (!active[b]) {
+        for (int i = 0; i <= m; ++i) yb[i] = mk(0, 0);
+        return;
+    }
+    const cd* Hb = H + (size_t)b * (m + 1) * m;
+    const cd* eb = e + (size_t)b * (m + 1);
+    for (int i = jj - 1; i >= 0; --i) {
+        cd r = eb[i];
+        for (int q = i + 1; q < jj; ++q) r = msub(r, Hb[(size_t)q * (m + 1) + i], yb[q]);
+        yb[i] = r * inv(Hb[(size_t)i * (m + 1) + i]);
+    }
+    for (int i = jj; i <= m; ++i) yb[i] = mk(0, 0);
+}
+
+// e[b] = (beta_b, 0, ...), cycle initialisation
+__global__ void gmres_init_kernel(int m, int B, const double* beta, cd* e, int* active,
+                                  const double* bnorm, double tol, double* resid) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    cd* eb = e + (size_t)b * (m + 1);
+    for (int i = 0; i <= m; ++i) eb[i] = mk(0, 0);
+    eb[0] = mk(beta[b], 0);
+    resid[b] = bnorm[b] > 0 ? beta[b] / bnorm[b] : 0.0;
+    active[b] = (bnorm[b] > 0 && beta[b] > tol * bnorm[b]) ? 1 : 0;
+}
+
+hipError_t launch_multidot(const cd* basis, int nv, const cd* w, long M, int B, double* partial,
+                           cd* out, int out_ld, int accumulate, hipStream_t st) {
+    multidot_kernel<<<dim3(kRedBlocks, B), kRedThreads, 0, st>>>(basis, nv, w, M, B, partial);
+    reduce_partials_kernel<<<(B * nv + 127) / 128, 128, 0, st>>>(partial, kRedBlocks, nv, B, out,
+                                                                  out_ld, accumulate);
+    return hipGetLastError();
+}
+hipError_t launch_multiaxpy(const cd* basis, int nv, const cd* coef, int coef_ld, double sign,
+                            cd* w, long M, int B, hipStream_t st) {
+    const int blocks = (int)std::min<long>(1024, (M + 255) / 256);
+    multiaxpy_kernel<<<dim3(blocks, B), 256, 0, st>>>(basis, nv, coef, coef_ld, sign, w, M, B);
+    return hipGetLastError();
+}
+hipError_t launch_norm(const cd* w, long M, int B, double* partial, double* nrm, hipStream_t st) {
+    norm2_kernel<<<dim3(kRedBlocks, B), kRedThreads, 0, st>>>(w, M, partial);
+    reduce_norm_kernel<<<(B + 63) / 64, 64, 0, st>>>(partial, kRedBlocks, B, nrm);
+    return hipGetLastError();
+}
+hipError_t launch_scale(const cd* src, const double* den, cd* dst, long M, int B, const int* active,
+                        hipStream_t st) {
+    const int blocks = (int)std::min<long>(1024, (M + 255) / 256);
+    scale_kernel<<<dim3(blocks, B), 256, 0, st>>>(src, den, dst, M, B, active);
+    return hipGetLastError();
+}
+hipError_t launch_givens(int j, int m, int B, const cd* hproj, const double* hnext, cd* H, cd* cs,
+                         cd* sn, cd* e, const double* bnorm, double* resid, int* active,
+                         hipStream_t st) {
+    givens_kernel<<<(B + 63) / 64, 64, 0, st>>>(j, m, B, hproj, hnext, H, cs, sn, e, bnorm, resid,
+                                                active);
+    return hipGetLastError();
+}
+hipError_t launch_gmres_solve(int jj, int m, int B, const cd* H, const cd* e, cd* y,
+                              const int* active, hipStream_t st) {
+    gmres_solve_kernel<<<(B + 63) / 64, 64, 0, st>>>(jj, m, B, H, e, y, active);
+    return hipGetLastError();
+}
+hipError_t launch_gmres_init(int m, int B, const double* beta, cd* e, int* active,
+                             const double* bnorm, double tol, double* resid, hipStream_t st) {
+    gmres_init_kernel<<<(B + 63) / 64, 64, 0, st>>>(m, B, beta, e, active, bnorm, tol, resid);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Causal forward substitution for (I - L) g = d.
+// Every block of L is lower triangular in time (Props. 3-4), so with C_m the
+// ns x ns matrix of m-th Toeplitz coefficients, step n reads
+//   (I - C_0) g_n = d_n + sum_{s<n} C_{n-s} g_s.
+// (I - C_0)^{-1} is formed once (Gauss-Jordan, partial pivoting); time is
+// processed in blocks of kCausalTb steps: the contribution of all earlier
+// blocks comes from the LTT apply kernel, the in-block part is summed here.
+// ---------------------------------------------------------------------------
+// C0 assembly: M = I - C_0 for potential v, row-major ns x ns.
+__global__ void c0_assemble_kernel(int N, int ns, int nt, const cd* cols, cd* Mat) {
+    const int v = blockIdx.y;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= ns * ns) return;
+    const int o = idx / ns, in = idx % ns;
+    int k, pl, pr, sl, sr;
+    slot_sources(o, N, k, pl, pr, sl, sr);
+    cd val = mk(o == in ? 1.0 : 0.0, 0);
+    const cd* base = cols + (size_t)(v * N + k) * 4 * nt;
+    if (in == sl) val = val - base[(size_t)pl * nt];
+    if (in == sr) val = val - base[(size_t)pr * nt];
+    Mat[(size_t)v * ns * ns + idx] = val;
+}
+
+// In-place Gauss-Jordan inverse with partial pivoting, one workgroup per
+// potential.  A: [ns][ns] row-major (destroyed), Ainv: [ns][ns].
+__global__ __launch_bounds__(256) void gauss_jordan_kernel(int ns, cd* A, cd* Ainv, int* piv_ok) {
+    const int v = blockIdx.x;
+    cd* a = A + (size_t)v * ns * ns;
+    cd* x = Ainv + (size_t)v * ns * ns;
+    __shared__ int s_piv;
+    __shared__ double s_val[256];
+    __shared__ int s_idx[256];
+    for (int i = threadIdx.x; i < ns * ns; i += blockDim.x) x[i] = mk((i / ns) == (i % ns) ? 1 : 0, 0);
+    __syncthreads();
+    for (int c = 0; c < ns; ++c) {
+        double best = -1;
+        int bi = c;
+        for (int r = c + threadIdx.x; r < ns; r += blockDim.x) {
+            const double m2 = abs2(a[(size_t)r * ns + c]);
+            if (m2 > best) { best = m2; bi = r; }
+        }
+        s_val[threadIdx.x] = best;
+        s_idx[threadIdx.x] = bi;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double bb = -1;
+            int ii = c;
+            for (int q = 0; q < (int)blockDim.x; ++q)
+                if (s_val[q] > bb) { bb = s_val[q]; ii = s_idx[q]; }
+            s_piv = ii;
+            if (bb <= 0) piv_ok[v] = 0;
+        }
+        __syncthreads();
+        const int p = s_piv;
+        if (p != c) {
+            for (int q = threadIdx.x; q < ns; q += blockDim.x) {
+                cd t = a[(size_t)c * ns + q]; a[(size_t)c * ns + q] = a[(size_t)p * ns + q]; a[(size_t)p * ns + q] = t;
+                t = x[(size_t)c * ns + q]; x[(size_t)c * ns + q] = x[(size_t)p * ns + q]; x[(size_t)p * ns + q] = t;
+            }
+        }
+        __syncthreads();
+        const cd pinv = inv(a[(size_t)c * ns + c]);
+        __syncthreads();
+        for (int q = threadIdx.x; q < ns; q += blockDim.x) {
+            a[(size_t)c * ns + q] = pinv * a[(size_t)c * ns + q];
+            x[(size_t)c * ns + q] = pinv * x[(size_t)c * ns + q];
+        }
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < ns * ns; idx += blockDim.x) {
+            const int r = idx / ns, q = idx % ns;
+            if (r == c) continue;
+            const cd f = a[(size_t)r * ns + c];
+            if (q == c) continue;
+            a[(size_t)r * ns + q] = msub(a[(size_t)r * ns + q], f, a[(size_t)c * ns + q]);
+            x[(size_t)r * ns + q] = msub(x[(size_t)r * ns + q], f, x[(size_t)c * ns + q]);
+        }
+        __syncthreads();
+        for (int r = threadIdx.x; r < ns; r += blockDim.x) {
+            if (r == c) continue;
+            const cd f = a[(size_t)r * ns + c];
+            x[(size_t)r * ns + c] = msub(x[(size_t)r * ns + c], f, x[(size_t)c * ns + c]);
+            a[(size_t)r * ns + c] = mk(0, 0);
+        }
+        __syncthreads();
+    }
+}
+
+
+__global__ __launch_bounds__(256) void causal_block_kernel(CausalArgs a) {
+    extern __shared__ cd s_rhs[];
+    const int b = blockIdx.x;
+    const int v = a.per_problem ? b : 0;
+    const cd* Mi = a.Minv + (size_t)v * a.ns * a.ns;
+    cd* gb = a.g + (size_t)b * a.ns * a.nt;
+    for (int i = 0; i < a.nb; ++i) {
+        const int n = a.n0 + i;
+        for (int o = threadIdx.x; o < a.ns; o += blockDim.x) {
+            int k, pl, pr, sl, sr;
+            slot_sources(o, a.N, k, pl, pr, sl, sr);
+            const cd* base = a.cols + (size_t)(v * a.N + k) * 4 * a.nt;
+            cd r = a.d[((size_t)b * a.ns + o) * a.nt + n] + a.far[((size_t)b * a.ns + o) * kCausalTb + i];
+            for (int s = a.n0; s < n; ++s) {
+                if (sl >= 0) r = madd(r, base[(size_t)pl * a.nt + (n - s)], gb[(size_t)sl * a.nt + s]);
+                if (sr >= 0) r = madd(r, base[(size_t)pr * a.nt + (n - s)], gb[(size_t)sr * a.nt + s]);
+            }
+            s_rhs[o] = r;
+        }
+        __syncthreads();
+        for (int o = threadIdx.x; o < a.ns; o += blockDim.x) {
+            cd r = mk(0, 0);
+            const cd* row = Mi + (size_t)o * a.ns;
+            for (int q = 0; q < a.ns; ++q) r = madd(r, row[q], s_rhs[q]);
+            gb[(size_t)o * a.nt + n] = r;
+        }
+        __threadfence_block();
+        __syncthreads();
+    }
+}
+
+// z = a x + b y (elementwise, complex vectors of n entries; z may alias x or y)
+__global__ __launch_bounds__(256) void axpby_kernel(const cd* x, double a, const cd* y, double b,
+                                                    cd* z, long n) {
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
+        z[e] = a * x[e] + b * y[e];
+}
+hipError_t launch_axpby(const cd* x, double a, const cd* y, double b, cd* z, long n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int blocks = (int)std::min<long>(2048, (n + 255) / 256);
+    axpby_kernel<<<blocks, 256, 0, st>>>(x, a, y, b, z, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_c0_inverse(int N, int ns, int nt, int nv, const cd* cols, cd* work, cd* Minv,
+                             int* piv_ok, hipStream_t st) {
+    if (ns == 0) return hipSuccess;
+    c0_assemble_kernel<<<dim3((ns * ns + 255) / 256, nv), 256, 0, st>>>(N, ns, nt, cols, work);
+    gauss_jordan_kernel<<<nv, 256, 0, st>>>(ns, work, Minv, piv_ok);
+    return hipGetLastError();
+}
+
+hipError_t launch_causal_block(const CausalArgs& a, hipStream_t st) {
+    causal_block_kernel<<<a.B, 256, a.ns * sizeof(cd), st>>>(a);
+    return hipGetLastError();
+}
+
+}  // namespace swr

@@ -1,0 +1,213 @@
+"""GPU parity: every step of the hot path, called through the C ABI, against
+the CPU oracle on the same seeded inputs.
+
+Tolerances (FP64 throughout):
+* one sweep / one interface product (no iteration): 1e-12 relative -- the two
+  sides differ only in rounding order over <= a few hundred steps;
+* converged solves: 1e-10 relative in the state, the target stated for this
+  method (parity runs iterate to 1e-13 where an iteration is involved).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1503_02564_amd import workloads as W
+from tests.gpu_util import make_problem, rel, say, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+SWEEP_CASES = [
+    # (label, J, nt, trans, sigma)
+    ("P5-ragged-s02", [40, 63, 64, 100, 127, 128, 200, 255, 256, 300], 150, W.S02, 0j),
+    ("P5-ragged-robin", [40, 63, 64, 100, 127, 128, 200, 255, 256, 300], 150, W.ROBIN, 1 - 1j),
+    ("P1-short-s02", [30, 50, 63], 40, W.S02, 0j),
+    ("P2-robin", [100, 90, 127], 64, W.ROBIN, 3 - 2j),
+    ("P8-s02", [511, 200, 17], 70, W.S02, 0j),
+]
+
+
+def _case(J, nt, trans, sigma, B=1, seed=3):
+    return W.small_case(J=J, nt=nt, trans=trans, sigma=sigma, B=B, seed=seed, a0=-12.0, b0=12.0)
+
+
+@pytest.mark.parametrize("label,J,nt,trans,sigma", SWEEP_CASES)
+@pytest.mark.parametrize("with_data", [True, False])
+def test_one_sweep_matches_oracle(dev, label, J, nt, trans, sigma, with_data):
+    import torch
+    wl = _case(J, nt, trans, sigma)
+    say("one_sweep", label, "data" if with_data else "zero-data")
+    pb = make_problem(wl)
+    rng = np.random.default_rng(11)
+    g = rng.standard_normal((pb.ns, nt)) + 1j * rng.standard_normal((pb.ns, nt))
+    u0 = wl.u0[0] if with_data else None
+    g_out = torch.zeros((1, pb.ns, nt), dtype=torch.complex128, device=dev)
+    uT = torch.zeros((1, wl.nx), dtype=torch.complex128, device=dev)
+    u0d = to_dev(wl.u0) if with_data else None
+    from paper_1503_02564_amd import swr
+    md = swr.swr_apply_R(pb.ctx, u0d, to_dev(g[None]), g_out, uT, want_maxdiff=True)
+    torch.cuda.synchronize()
+    want = O.apply_R(wl, u0, g, hist0_zero=not with_data)
+    assert rel(to_np(g_out)[0], want) < 1e-12
+    assert md == pytest.approx(float(np.max(np.abs(want - g))), rel=1e-12)
+    if with_data:
+        uwant, _ = O.local_solution(wl, u0, g)
+        assert rel(to_np(uT)[0], uwant) < 1e-12
+    pb.close()
+
+
+@pytest.mark.parametrize("label,J,nt,trans,sigma", SWEEP_CASES[:3])
+def test_impulse_columns_and_d_match_oracle(dev, label, J, nt, trans, sigma):
+    import torch
+    from paper_1503_02564_amd import swr
+    wl = _case(J, nt, trans, sigma)
+    say("build_interface", label)
+    pb = make_problem(wl)
+    cols = torch.zeros((1, wl.N, 4, nt), dtype=torch.complex128, device=dev)
+    d = torch.zeros((1, pb.ns, nt), dtype=torch.complex128, device=dev)
+    swr.swr_build_interface(pb.ctx, to_dev(wl.u0), cols, d)
+    torch.cuda.synchronize()
+    assert rel(to_np(cols)[0], O.impulse_columns(wl)) < 1e-12
+    assert rel(to_np(d)[0], O.interface_d(wl, wl.u0[0])) < 1e-12
+    # the interface matrix of the Krylov solver: y = x - L x
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal((pb.ns, nt)) + 1j * rng.standard_normal((pb.ns, nt))
+    y = torch.zeros_like(d)
+    swr.swr_interface_matvec(pb.ctx, to_dev(x[None]), y)
+    torch.cuda.synchronize()
+    want = x - O.ltt_apply(wl, O.impulse_columns(wl), x)
+    assert rel(to_np(y)[0], want) < 1e-12
+    pb.close()
+
+
+SOLVE_CASES = [
+    ("uneven-s02", [40, 63, 64, 100, 127, 200, 31], 130, W.S02, 0j),
+    ("uneven-robin", [50, 70, 90, 33], 100, W.ROBIN, 1 - 1j),
+]
+
+
+@pytest.mark.parametrize("label,J,nt,trans,sigma", SOLVE_CASES)
+@pytest.mark.parametrize("solver", ["causal", "gmres"])
+def test_solve_matches_monodomain(dev, label, J, nt, trans, sigma, solver):
+    import torch
+    from paper_1503_02564_amd import swr
+    wl = _case(J, nt, trans, sigma)
+    sv = dict(causal=swr.SWR_SOLVER_CAUSAL, gmres=swr.SWR_SOLVER_GMRES)[solver]
+    say("solve", label, solver)
+    pb = make_problem(wl, solver=sv, tol=1e-13, restart=60, max_iter=3000)
+    uT = torch.zeros((1, wl.nx), dtype=torch.complex128, device=dev)
+    g = torch.zeros((1, pb.ns, nt), dtype=torch.complex128, device=dev)
+    st, info = swr.swr_solve(pb.ctx, to_dev(wl.u0), uT, g)
+    torch.cuda.synchronize()
+    assert st == swr.SWR_OK
+    um = O.mono(wl, wl.u0[0])
+    assert rel(to_np(uT)[0], um) < 1e-10
+    assert info.residual < 1e-11
+    gw = O.causal_solve(wl, O.impulse_columns(wl), O.interface_d(wl, wl.u0[0]))
+    assert rel(to_np(g)[0], gw) < 1e-10
+    pb.close()
+
+
+def test_classical_iteration_matches_oracle_iterates(dev):
+    """Config-1 grid with S0^2: classical SWR to max change < 1e-10 (the
+    Robin value of config 1 does not converge by fixed point; see the next
+    test).  Converged u(T) = monodomain; iteration count = oracle's."""
+    import copy
+    import torch
+    from paper_1503_02564_amd import swr
+    wl = copy.copy(W.config1())
+    wl.trans = W.S02
+    say("classical", "config1-grid-s02")
+    pb = make_problem(wl, solver=swr.SWR_SOLVER_FIXED, tol=1e-10, max_iter=2000)
+    uT = torch.zeros((1, wl.nx), dtype=torch.complex128, device=dev)
+    st, info = swr.swr_solve(pb.ctx, to_dev(wl.u0), uT)
+    torch.cuda.synchronize()
+    assert st == swr.SWR_OK
+    g, it, _ = O.classical(wl, wl.u0[0], tol=1e-10, maxit=2000)
+    assert abs(info.iters - it) <= 1
+    assert rel(to_np(uT)[0], O.mono(wl, wl.u0[0])) < 1e-9
+    pb.close()
+
+
+def test_config1_robin(dev):
+    """Config 1 as stated (dn u + (1-i) u): the first classical iterates match
+    the oracle's, and the interface problem solved directly gives the
+    monodomain solution."""
+    import torch
+    from paper_1503_02564_amd import swr
+    wl = W.config1()
+    say("config1-robin")
+    pb = make_problem(wl)
+    u0 = to_dev(wl.u0)
+    g = np.zeros((pb.ns, wl.nt), complex)
+    gd = torch.zeros((1, pb.ns, wl.nt), dtype=torch.complex128, device=dev)
+    go = torch.zeros_like(gd)
+    for it in range(5):
+        swr.swr_apply_R(pb.ctx, u0, gd, go)
+        g = O.apply_R(wl, wl.u0[0], g)
+        assert rel(to_np(go)[0], g) < 1e-11, it
+        gd, go = go.clone(), gd
+    pb.close()
+    pb = make_problem(wl, solver=swr.SWR_SOLVER_CAUSAL)
+    uT = torch.zeros((1, wl.nx), dtype=torch.complex128, device=dev)
+    st, info = swr.swr_solve(pb.ctx, u0, uT)
+    torch.cuda.synchronize()
+    assert rel(to_np(uT)[0], O.mono(wl, wl.u0[0])) < 1e-10
+    pb.close()
+
+
+def test_batch_and_per_problem_potentials(dev):
+    import torch
+    from paper_1503_02564_amd import swr
+    wl = W.small_case(J=[60, 80, 70], nt=90, B=3, seed=13, a0=-10, b0=10)
+    say("batch", "shared V, B=3")
+    pb = make_problem(wl)
+    uT = torch.zeros((3, wl.nx), dtype=torch.complex128, device=dev)
+    st, info = swr.swr_solve(pb.ctx, to_dev(wl.u0), uT)
+    torch.cuda.synchronize()
+    for b in range(3):
+        assert rel(to_np(uT)[b], O.mono(wl, wl.u0[b])) < 1e-10
+    pb.close()
+    # one potential per problem
+    Vs = np.stack([wl.V, 0.5 * wl.V[::-1], np.zeros_like(wl.V)])
+    wl2 = W.Workload("pp", wl.a0, wl.b0, wl.J, wl.dt, wl.nt, W.V_STATIC, Vs, W.S02, 0j, wl.u0)
+    say("batch", "per-problem V, B=3")
+    pb = make_problem(wl2, v_per_problem=True)
+    st, info = swr.swr_solve(pb.ctx, to_dev(wl.u0), uT)
+    torch.cuda.synchronize()
+    for b in range(3):
+        assert rel(to_np(uT)[b], O.mono(wl2, wl.u0[b], V=Vs[b])) < 1e-10
+    pb.close()
+
+
+@pytest.mark.parametrize("J,nt", [([50], 33), ([300], 70), ([20, 20], 1)])
+def test_edge_cases(dev, J, nt):
+    """One subdomain (no interface), one time step."""
+    import torch
+    from paper_1503_02564_amd import swr
+    wl = W.small_case(J=J, nt=nt, seed=17)
+    say("edge", J, nt)
+    pb = make_problem(wl)
+    uT = torch.zeros((1, wl.nx), dtype=torch.complex128, device=dev)
+    st, info = swr.swr_solve(pb.ctx, to_dev(wl.u0), uT)
+    torch.cuda.synchronize()
+    assert rel(to_np(uT)[0], O.mono(wl, wl.u0[0])) < 1e-10
+    pb.close()
+
+
+def test_full_size_config2_matches_monodomain(dev):
+    """Config 2 at full size, in the configuration the benchmark times
+    (N = 64 x 256 cells, 2000 steps, S0^2, causal interface solve): u(T)
+    against the monodomain oracle, and the certified interface residual."""
+    import torch
+    from paper_1503_02564_amd import swr
+    wl = W.config2()
+    say("full-size", "config2")
+    pb = make_problem(wl)
+    uT = torch.zeros((1, wl.nx), dtype=torch.complex128, device=dev)
+    st, info = swr.swr_solve(pb.ctx, to_dev(wl.u0), uT)
+    torch.cuda.synchronize()
+    say("full-size", "config2 done", info.as_dict())
+    assert st == swr.SWR_OK
+    assert info.residual < 1e-10
+    assert rel(to_np(uT)[0], O.mono(wl, wl.u0[0])) < 1e-10
+    pb.close()
