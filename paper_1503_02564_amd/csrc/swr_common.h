@@ -186,6 +186,15 @@ hipError_t launch_gmres_init(int m, int B, const double* beta, cd* e, int* activ
 hipError_t launch_c0_inverse(int N, int ns, int nt, int nv, const cd* cols, cd* work, cd* Minv,
                              int* piv_ok, hipStream_t st);
 hipError_t launch_causal_block(const CausalArgs& a, hipStream_t st);
+// launchers (swr_causal.hip): block-PCR causal solve for N - 1 <= 64
+// interfaces and ns <= kNearSlots slots
+constexpr int kNearTb = 32;
+constexpr int kNearSlots = 128;
+constexpr int kPcrRec = kPcrLevels * 8 + 4;   // complex entries per lane of the PCR record
+hipError_t launch_causal_pcr_setup(int N, int nt, int nv, const cd* cols, cd* pcr, double* eta,
+                                   hipStream_t st);
+hipError_t launch_causal_fast(int N, int nt, int ns, int B, int per_problem, const cd* cols,
+                              const cd* pcr, const cd* d, cd* base, cd* g, hipStream_t st);
 hipError_t launch_axpby(const cd* x, double a, const cd* y, double b, cd* z, long n, hipStream_t st);
 
 }  // namespace swr

@@ -69,6 +69,10 @@ struct swr_ctx {
     cd* dMwork = nullptr;
     cd* dFar = nullptr;
     int* dPivOk = nullptr;
+    cd* dPcr = nullptr;
+    cd* dBase = nullptr;
+    double* dEta = nullptr;
+    int causal_path = 0;   // 1 = block PCR, 2 = dense inverse
     bool built = false;
     // host staging (pinned)
     double* hRes = nullptr;
@@ -396,16 +400,39 @@ static swr_status run_gmres(swr_ctx* c, int* iters_out) {
     return its >= c->o.max_iter ? SWR_ENOCONV : SWR_OK;
 }
 
-// causal forward substitution in time (exact up to rounding)
+// causal forward substitution in time (exact up to rounding).  Block PCR
+// per step when it applies (N - 1 <= 64, ns <= 128) and the block system is
+// certified diagonally dominant; otherwise a dense (I - C_0)^{-1} by
+// Gauss-Jordan with partial pivoting.
 static swr_status run_causal(swr_ctx* c) {
     const int ns = c->ns, nt = c->nt, B = c->B;
+    hipStream_t st = c->st;
+    if (ns <= kNearSlots && c->N - 1 <= kWave) {
+        if (!c->dPcr) {
+            ALLOC_LIVE(c->dPcr, (size_t)c->nv * kPcrRec * kWave);
+            ALLOC_LIVE(c->dBase, (size_t)B * ns * kNearTb);
+            ALLOC_LIVE(c->dEta, c->nv);
+        }
+        HIPCHK(launch_causal_pcr_setup(c->N, nt, c->nv, c->dCols, c->dPcr, c->dEta, st));
+        std::vector<double> eta(c->nv);
+        HIPCHK(hipMemcpyAsync(eta.data(), c->dEta, sizeof(double) * c->nv, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        bool ok = true;
+        for (double e : eta) ok = ok && std::isfinite(e) && e < 1.0;
+        if (ok) {
+            c->causal_path = 1;
+            HIPCHK(launch_causal_fast(c->N, nt, ns, B, c->nv > 1, c->dCols, c->dPcr, c->dD, c->dBase,
+                                      c->dG, st));
+            return SWR_OK;
+        }
+    }
+    c->causal_path = 2;
     if (!c->dMinv) {
         ALLOC_LIVE(c->dMinv, (size_t)c->nv * ns * ns);
         ALLOC_LIVE(c->dMwork, (size_t)c->nv * ns * ns);
         ALLOC_LIVE(c->dFar, (size_t)B * ns * kCausalTb);
         ALLOC_LIVE(c->dPivOk, c->nv);
     }
-    hipStream_t st = c->st;
     HIPCHK(launch_c0_inverse(c->N, ns, nt, c->nv, c->dCols, c->dMwork, c->dMinv, c->dPivOk, st));
     for (int n0 = 0; n0 < nt; n0 += kCausalTb) {
         const int nb = std::min(kCausalTb, nt - n0);

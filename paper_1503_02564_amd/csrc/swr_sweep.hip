@@ -180,6 +180,8 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
     using L = FacLayout<P>;
     constexpr int PI = P > 1 ? P - 1 : 1;
     __shared__ double sbeta[kWave + 1];
+    __shared__ cd sha[kWave], shb[kWave];     // staged chunk of the boundary history
+    __shared__ double sb[2 * kWave];          // beta window of that chunk
     const Task task = a.tasks[blockIdx.x];
     const int k = task.k, b = task.b, f = task.f, fl = task.flags;
     const int t = threadIdx.x;
@@ -287,16 +289,31 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
             if ((fl & T_IMP_L) && n0 + t == 0) lb = mk(1, 0);
             if ((fl & T_IMP_R) && n0 + t == 0) rb = mk(1, 0);
         }
-        // far part of the S0^2 history for the outputs of this block
+        // far part of the S0^2 history for the outputs of this block:
+        // acc_j = sum_{q <= n0} beta_{n0+1+j-q} v_q, over chunks of 64 past
+        // values staged in LDS with one coalesced load each, together with
+        // the 127-entry window of beta the chunk needs
         cd acc_a = zero, acc_b = zero;
         if (TR == TR_S02) {
             __threadfence_block();
             const int nj = n0 + 1 + t;
-            for (int q = 0; q <= n0; ++q) {
-                const double bt = a.beta[nj - q];
-                const cd ha = Ha[q], hb = Hb[q];
-                acc_a = acc_a + bt * ha;
-                acc_b = acc_b + bt * hb;
+            for (int q0 = 0; q0 <= n0; q0 += kWave) {
+                const int qn = min(kWave, n0 + 1 - q0);
+                const int bbase = n0 - q0 - (kWave - 2);   // beta index of sb[0]
+                sha[t] = (t < qn) ? Ha[q0 + t] : zero;
+                shb[t] = (t < qn) ? Hb[q0 + t] : zero;
+                const int i0 = bbase + t, i1 = bbase + kWave + t;
+                sb[t] = (i0 >= 0) ? a.beta[i0] : 0.0;
+                sb[kWave + t] = (i1 >= 0) ? a.beta[i1] : 0.0;
+                __syncthreads();
+                const double* bw = sb + (nj - q0 - bbase);  // beta_{nj - q0 - i} = bw[-i]
+                for (int i = 0; i < qn; ++i) {
+                    const double bt = bw[-i];
+                    const cd ha = sha[i], hb = shb[i];
+                    acc_a = mk(acc_a.x + bt * ha.x, acc_a.y + bt * ha.y);
+                    acc_b = mk(acc_b.x + bt * hb.x, acc_b.y + bt * hb.y);
+                }
+                __syncthreads();
             }
         }
         cd rl_b = zero, rr_b = zero, va_b = zero, vb_b = zero, ua_b = zero, ub_b = zero;

@@ -82,6 +82,8 @@ def test_impulse_columns_and_d_match_oracle(dev, label, J, nt, trans, sigma):
 SOLVE_CASES = [
     ("uneven-s02", [40, 63, 64, 100, 127, 200, 31], 130, W.S02, 0j),
     ("uneven-robin", [50, 70, 90, 33], 100, W.ROBIN, 1 - 1j),
+    # 70 subdomains: more interfaces than one wave, the dense-inverse path
+    ("many-subdomains", [9, 12, 7, 10] * 17 + [8, 11], 75, W.S02, 0j),
 ]
 
 
