@@ -129,12 +129,19 @@ swr_status swr_solve(swr_ctx* ctx, const double* u0, double* uT, double* g, doub
 
 /* Gradient of a real objective J(u(T)) with respect to the static potential
  * and the initial data, by the discrete adjoint of the Crank-Nicolson scheme
- * solved through the same decomposition (STATIC potential only).
+ * solved through the same decomposition (STATIC potential only; the adjoint
+ * uses the same interface operator L as the forward).
  *   u0 [B][nx] complex; gbar [B][nx] complex upstream gradient
  *   dJ/dRe u(T) + i dJ/dIm u(T) (for J = sum |u(T) - u*|^2 it is 2(u(T) - u*)).
- *   dJdV [B][nx] real, dJdu0 [B][nx] complex (same convention).
- * Forward states are checkpointed every opts.checkpoint_K steps and
- * recomputed segment by segment in reverse. */
+ *   dJdV [B][nx] real (per problem; with a shared V sum over the batch),
+ *   dJdu0 [B][nx] complex (same convention).
+ * The call runs the forward solve (final sweep checkpointing u every 64 steps
+ * counted back from nt), the adjoint interface problem, and one adjoint sweep
+ * that replays each 64-step forward segment from its checkpoint and consumes
+ * it in reverse.  opts.checkpoint_K must be 64 and the solver not FIXED
+ * (SWR_EINVAL otherwise).  info: iters / residual of the adjoint interface
+ * solve; t_factor_ms = whole forward, t_build_ms = adjoint d sweep,
+ * t_iface_ms = adjoint interface solve, t_final_ms = replay + adjoint sweep. */
 swr_status swr_grad(swr_ctx* ctx, const double* u0, const double* gbar, double* dJdV,
                     double* dJdu0, swr_info* info);
 
@@ -158,6 +165,12 @@ swr_status swr_build_interface(swr_ctx* ctx, const double* u0, double* cols, dou
 /* y = x - L x for [B][2N-2][nt] vectors with L from the last build (the
  * matrix of the Krylov solver; static V). */
 swr_status swr_interface_matvec(swr_ctx* ctx, const double* x, double* y);
+
+/* Replace the potential of a context (same layout as the V of swr_setup:
+ * [nx], [B][nx] with v_per_problem, or [nt+1][nx] for V_TIME); the next
+ * solve refactorises and rebuilds the interface problem.  SWR_EINVAL for a
+ * cubic context or a NULL V. */
+swr_status swr_set_potential(swr_ctx* ctx, const double* V);
 
 /* Release the context and all device memory it owns. */
 void swr_destroy(swr_ctx* ctx);

@@ -84,6 +84,7 @@ enum TaskFlags {
     T_OUT_UT    = 1 << 6,   // u(T) -> uT (interior nodes) + ends
     T_OUT_TRACE = 1 << 7,   // u_n at the two end nodes -> trace store
     T_MAXDIFF   = 1 << 8,   // fold max |g_out - g_in| over written slots
+    T_CKPT      = 1 << 9,   // store u at steps nt - 64 j (and u_0) for the adjoint
 };
 
 struct Task {
@@ -122,6 +123,14 @@ struct SweepArgs {
     cd* ends;                    // [B][N][2] u(T) at the two end nodes
     cd* trace;                   // [B][N][2][nt+1] u_n at the two end nodes
     unsigned long long* maxdiff; // max |g_out - g_in| as ordered bits
+    double h;                    // mesh size
+    const double* Vt;            // [nt+1][nx] time-dependent potential
+    int nl_maxit;                // |u|^2 inner fixed point: cap and tolerance
+    double nl_tol;
+    int* nl_stats;               // [0] largest inner count, [1] nonconvergence flag
+    int flags_and, flags_or;     // per-launch override of the task flags
+    cd* ckpt;                    // [ntasks][Jc+1][P][64] checkpoints of u
+    int Jc;                      // ceil(nt / 64)
 };
 
 struct FactorArgs {
@@ -163,7 +172,7 @@ constexpr int kRedThreads = 256;
 
 // launchers (swr_sweep.hip)
 hipError_t launch_factor(const FactorArgs& a, hipStream_t st);
-hipError_t launch_sweep(const SweepArgs& a, int trans, hipStream_t st);
+hipError_t launch_sweep(const SweepArgs& a, int trans, int vk, hipStream_t st);
 hipError_t launch_finalize_ut(int N, int nx, int B, const int* off, const cd* ends, cd* uT,
                               hipStream_t st);
 hipError_t launch_beta(int n, double* beta, hipStream_t st);
@@ -195,6 +204,33 @@ hipError_t launch_causal_pcr_setup(int N, int nt, int nv, const cd* cols, cd* pc
                                    hipStream_t st);
 hipError_t launch_causal_fast(int N, int nt, int ns, int B, int per_problem, const cd* cols,
                               const cd* pcr, const cd* d, cd* base, cd* g, hipStream_t st);
+struct AdjArgs {
+    int N, nt, B, nx, ns, ntasks, P, Jc;
+    double kappa, h;
+    cd sigma, c2;
+    const int* J;
+    const int* off;
+    const Task* tasks;
+    const cd* fac;
+    const double* beta;
+    const cd* gbar;          // [B][nx]
+    const cd* g_in;          // adjoint fluxes [B][ns][nt] (null: zero)
+    cd* g_out;               // outgoing adjoint fluxes (null: not written)
+    cd* hist;                // adjoint boundary history [ntasks][2][nt+1]
+    int grad;                // replay the forward and accumulate dJ/dV
+    const cd* ckpt;          // [ntasks][Jc+1][P][64]
+    const cd* g_fwd;         // forward converged fluxes
+    const cd* hist_fwd;      // forward boundary history [ntasks][2][nt+1]
+    cd* seg;                 // [ntasks][64][P][64] forward v of one block
+    double* dV;              // [B][nx] (nodes interior to a subdomain)
+    cd* du0;                 // [B][nx] (nodes interior to a subdomain)
+    double* gends;           // [B][N][2] dJ/dV partial sums at the end nodes
+    cd* wends;               // [B][N][2] w at the end nodes
+};
+hipError_t launch_adjoint(const AdjArgs& a, int trans, hipStream_t st);
+hipError_t launch_finalize_grad(int N, int nx, int B, const int* off, const double* gends,
+                                const cd* wends, double* dV, cd* du0, hipStream_t st);
+hipError_t launch_maxabs(const cd* x, long M, int B, double* partial, double* out, hipStream_t st);
 hipError_t launch_axpby(const cd* x, double a, const cd* y, double b, cd* z, long n, hipStream_t st);
 
 }  // namespace swr

@@ -11,9 +11,11 @@
 //   4. final sweep with the converged g -> u(T), R g           (sweep_kernel)
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <new>
 #include <vector>
 
@@ -23,6 +25,24 @@
 
 using namespace swr;
 
+// One interface operator built from impulse responses (Sec. 4.1): the first
+// columns of its blocks, the factor records its impulse sweeps use, and the
+// state of the causal solver built on it.
+struct Iface {
+    cd* cols = nullptr;     // [nv][N][4][nt]
+    cd* fac = nullptr;      // factor records [nv*N][fields][64]
+    Task* tasks = nullptr;  // impulse tasks
+    int ntasks = 0;
+    int nv = 1;
+    bool dirty = true;      // columns rebuilt since the causal setup
+    int path = 0;           // causal solver: 1 = block PCR, 2 = dense inverse
+    cd* pcr = nullptr;
+    double* eta = nullptr;
+    cd* Minv = nullptr;
+    cd* Mwork = nullptr;
+    int* piv = nullptr;
+};
+
 struct swr_ctx {
     // problem
     double a0 = 0, b0 = 0, h = 0, dt = 0;
@@ -31,23 +51,26 @@ struct swr_ctx {
     swr_opts o{};
     hipStream_t st = nullptr;
     std::vector<int> J, off;
-    std::vector<Task> build_tasks, final_tasks;
     // device memory
     int* dJ = nullptr;
     int* dOff = nullptr;
     double* dV = nullptr;
     double* dBeta = nullptr;
-    cd* dFac = nullptr;
-    cd* dCols = nullptr;
     cd* dHist = nullptr;
     cd* dEnds = nullptr;
-    Task* dBuild = nullptr;
-    Task* dFinal = nullptr;
+    Task* dBuild = nullptr;   // impulses + d sweeps of the potential (static V)
+    int nBuild = 0;
+    Task* dSub = nullptr;     // one task per (problem, subdomain)
+    int nSub = 0;
+    Iface L, L0;              // interface operator of V and of V = 0
     cd* dD = nullptr;
     cd* dG = nullptr;
     cd* dG2 = nullptr;
-    cd* dZero = nullptr;   // [B][ns][nt] zeros
+    cd* dT1 = nullptr;        // work vectors [B][ns][nt]
+    cd* dT2 = nullptr;
+    cd* dZero = nullptr;      // [B][ns][nt] zeros
     unsigned long long* dMax = nullptr;
+    int* dNl = nullptr;       // |u|^2 inner statistics
     // GMRES workspace
     int gm_m = 0;
     cd* dBasis = nullptr;
@@ -64,16 +87,19 @@ struct swr_ctx {
     double* dBn = nullptr;
     double* dRes = nullptr;
     int* dAct = nullptr;
-    // causal workspace
-    cd* dMinv = nullptr;
-    cd* dMwork = nullptr;
-    cd* dFar = nullptr;
-    int* dPivOk = nullptr;
-    cd* dPcr = nullptr;
-    cd* dBase = nullptr;
-    double* dEta = nullptr;
-    int causal_path = 0;   // 1 = block PCR, 2 = dense inverse
-    bool built = false;
+    cd* dFar = nullptr;       // causal dense path
+    cd* dBase = nullptr;      // causal PCR path
+    // adjoint
+    int Jc = 0;
+    cd* dCkpt = nullptr;
+    cd* dSeg = nullptr;
+    cd* dHist2 = nullptr;
+    cd* dGfwd = nullptr;
+    cd* dDadj = nullptr;
+    cd* dGadj = nullptr;
+    double* dGends = nullptr;
+    cd* dWends = nullptr;
+    cd* dUT = nullptr;
     // host staging (pinned)
     double* hRes = nullptr;
     int* hAct = nullptr;
@@ -87,6 +113,11 @@ struct swr_ctx {
         if (e_ != hipSuccess) {                        \
             return SWR_EDEVICE;                        \
         }                                              \
+    } while (0)
+#define CHK(x)                                         \
+    do {                                               \
+        swr_status s_ = (x);                           \
+        if (s_ != SWR_OK) return s_;                   \
     } while (0)
 
 template <class T>
@@ -140,6 +171,16 @@ extern "C" const char* swr_strerror(swr_status s) {
 
 static int vof(const swr_ctx* c, int b) { return (c->o.v_per_problem && c->vk == SWR_V_STATIC) ? b : 0; }
 
+static std::vector<Task> impulse_tasks(int N, int nv) {
+    std::vector<Task> t;
+    for (int v = 0; v < nv; ++v)
+        for (int k = 0; k < N; ++k) {
+            if (k >= 1) t.push_back(Task{k, 0, v * N + k, T_IMP_L | T_OUT_COLS});
+            if (k <= N - 2) t.push_back(Task{k, 0, v * N + k, T_IMP_R | T_OUT_COLS});
+        }
+    return t;
+}
+
 extern "C" swr_status swr_setup(double a0, double b0, int N, const int* J, double dt, double T,
                                 int vk, const double* V, int tr, double s_re, double s_im,
                                 const swr_opts* opts, void* stream, swr_ctx** out) {
@@ -157,7 +198,9 @@ extern "C" swr_status swr_setup(double a0, double b0, int N, const int* J, doubl
     if (tr == SWR_ROBIN && s_re == 0.0 && s_im == 0.0) return SWR_EINVAL;
     if (!std::isfinite(s_re) || !std::isfinite(s_im)) return SWR_EINVAL;
     if (o.batch < 1 || o.restart < 1 || o.max_iter < 1 || !(o.tol > 0)) return SWR_EINVAL;
+    if (o.nl_max_iter < 1 || !(o.nl_tol > 0) || o.checkpoint_K < 1) return SWR_EINVAL;
     if (vk == SWR_V_TIME && !V) return SWR_EINVAL;
+    if (vk == SWR_V_CUBIC && V) return SWR_EINVAL;
     if (vk != SWR_V_STATIC && o.v_per_problem) return SWR_EINVAL;
     long nc = 0;
     int nmax = 0;
@@ -167,8 +210,6 @@ extern "C" swr_status swr_setup(double a0, double b0, int N, const int* J, doubl
         nmax = J[k] + 1 > nmax ? J[k] + 1 : nmax;
     }
     if (nmax > kWave * kMaxP || nc > (1L << 30)) return SWR_EINVAL;
-    // only the static potential is served by this build
-    if (vk != SWR_V_STATIC) return SWR_EINVAL;
 
     swr_ctx* c = new (std::nothrow) swr_ctx();
     if (!c) return SWR_ENOMEM;
@@ -185,44 +226,61 @@ extern "C" swr_status swr_setup(double a0, double b0, int N, const int* J, doubl
     for (int k = 0, acc = 0; k < N; ++k) { c->off[k] = acc; acc += J[k]; }
 
     const int nt = c->nt, B = c->B, ns = c->ns, nv = c->nv;
-    // task lists: impulses (per potential) + d sweeps (per problem); final sweeps
-    for (int v = 0; v < nv; ++v)
-        for (int k = 0; k < N; ++k) {
-            if (k >= 1) c->build_tasks.push_back(Task{k, 0, v * N + k, T_IMP_L | T_OUT_COLS});
-            if (k <= N - 2) c->build_tasks.push_back(Task{k, 0, v * N + k, T_IMP_R | T_OUT_COLS});
-        }
+    // task lists
+    std::vector<Task> build = impulse_tasks(N, nv), sub, imp0 = impulse_tasks(N, 1);
     for (int b = 0; b < B; ++b)
-        for (int k = 0; k < N; ++k) c->build_tasks.push_back(Task{k, b, vof(c, b) * N + k, T_DATA_U0 | T_OUT_G});
+        for (int k = 0; k < N; ++k) build.push_back(Task{k, b, vof(c, b) * N + k, T_DATA_U0 | T_OUT_G});
     for (int b = 0; b < B; ++b)
-        for (int k = 0; k < N; ++k)
-            c->final_tasks.push_back(Task{k, b, vof(c, b) * N + k, T_DATA_U0 | T_FLUX_G | T_OUT_G});
-
+        for (int k = 0; k < N; ++k) sub.push_back(Task{k, b, vof(c, b) * N + k, 0});
+    c->nBuild = (int)build.size();
+    c->nSub = (int)sub.size();
     const size_t vec = (size_t)B * ns * nt;
-    const size_t max_tasks = c->build_tasks.size() > c->final_tasks.size() ? c->build_tasks.size()
-                                                                            : c->final_tasks.size();
+    const size_t max_tasks = std::max(build.size(), std::max(sub.size(), imp0.size()));
+    const int fields = fac_fields(c->P);
     ALLOC(c->dJ, N);
     ALLOC(c->dOff, N);
     ALLOC(c->dBeta, nt + kWave + 1);
-    ALLOC(c->dFac, (size_t)nv * N * fac_fields(c->P) * kWave);
-    ALLOC(c->dCols, (size_t)nv * N * 4 * nt);
     ALLOC(c->dHist, (tr == SWR_S02) ? max_tasks * 2 * (nt + 1) : 1);
     ALLOC(c->dEnds, (size_t)B * N * 2);
-    ALLOC(c->dBuild, c->build_tasks.size());
-    ALLOC(c->dFinal, c->final_tasks.size());
+    ALLOC(c->dBuild, build.size());
+    ALLOC(c->dSub, sub.size());
     ALLOC(c->dD, vec);
     ALLOC(c->dG, vec);
     ALLOC(c->dG2, vec);
+    ALLOC(c->dT1, vec);
+    ALLOC(c->dT2, vec);
     ALLOC(c->dZero, vec);
     ALLOC(c->dMax, 1);
+    ALLOC(c->dNl, 2);
     ALLOC(c->dPart, (size_t)B * kRedBlocks * 2 * (o.restart + 2));
     ALLOC(c->dNrm, B);
     ALLOC(c->dBn, B);
     ALLOC(c->dRes, B);
     ALLOC(c->dAct, B);
-    if (V) {
-        const size_t vn = (size_t)c->nx * (o.v_per_problem ? B : 1);
+    // interface operator of the potential (static V) ...
+    c->L.nv = nv;
+    c->L.tasks = c->dBuild;   // its impulse tasks lead the build list
+    c->L.ntasks = (int)impulse_tasks(N, nv).size();
+    if (vk == SWR_V_STATIC) {
+        ALLOC(c->L.fac, (size_t)nv * N * fields * kWave);
+        ALLOC(c->L.cols, (size_t)nv * N * 4 * nt);
+    }
+    // ... and of the zero potential (preconditioner; also the V-free factors
+    // of the |u|^2 scheme)
+    if (vk != SWR_V_STATIC) {
+        c->L0.nv = 1;
+        c->L0.ntasks = (int)imp0.size();
+        ALLOC(c->L0.fac, (size_t)N * fields * kWave);
+        ALLOC(c->L0.cols, (size_t)N * 4 * nt);
+        ALLOC(c->L0.tasks, imp0.size());
+    }
+    if (vk != SWR_V_CUBIC) {
+        // the library's own copy of the potential (zeros when V is NULL)
+        const size_t vn = (vk == SWR_V_TIME) ? (size_t)c->nx * (nt + 1)
+                                             : (size_t)c->nx * (o.v_per_problem ? B : 1);
         ALLOC(c->dV, vn);
-        HIPCHK(hipMemcpyAsync(c->dV, V, vn * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+        if (V) HIPCHK(hipMemcpyAsync(c->dV, V, vn * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+        else HIPCHK(hipMemsetAsync(c->dV, 0, vn * sizeof(double), c->st));
     }
     if (hipHostMalloc(&c->hRes, sizeof(double) * B) != hipSuccess ||
         hipHostMalloc(&c->hAct, sizeof(int) * B) != hipSuccess) { swr_destroy(c); return SWR_ENOMEM; }
@@ -230,12 +288,13 @@ extern "C" swr_status swr_setup(double a0, double b0, int N, const int* J, doubl
         if (hipEventCreate(&e) != hipSuccess) { swr_destroy(c); return SWR_EDEVICE; }
     HIPCHK(hipMemcpyAsync(c->dJ, c->J.data(), N * sizeof(int), hipMemcpyHostToDevice, c->st));
     HIPCHK(hipMemcpyAsync(c->dOff, c->off.data(), N * sizeof(int), hipMemcpyHostToDevice, c->st));
-    HIPCHK(hipMemcpyAsync(c->dBuild, c->build_tasks.data(), c->build_tasks.size() * sizeof(Task),
-                          hipMemcpyHostToDevice, c->st));
-    HIPCHK(hipMemcpyAsync(c->dFinal, c->final_tasks.data(), c->final_tasks.size() * sizeof(Task),
-                          hipMemcpyHostToDevice, c->st));
+    HIPCHK(hipMemcpyAsync(c->dBuild, build.data(), build.size() * sizeof(Task), hipMemcpyHostToDevice, c->st));
+    HIPCHK(hipMemcpyAsync(c->dSub, sub.data(), sub.size() * sizeof(Task), hipMemcpyHostToDevice, c->st));
+    if (c->L0.tasks)
+        HIPCHK(hipMemcpyAsync(c->L0.tasks, imp0.data(), imp0.size() * sizeof(Task), hipMemcpyHostToDevice, c->st));
     HIPCHK(hipMemsetAsync(c->dZero, 0, vec * sizeof(cd), c->st));
-    HIPCHK(hipMemsetAsync(c->dCols, 0, (size_t)nv * N * 4 * nt * sizeof(cd), c->st));
+    if (c->L.cols) HIPCHK(hipMemsetAsync(c->L.cols, 0, (size_t)nv * N * 4 * nt * sizeof(cd), c->st));
+    if (c->L0.cols) HIPCHK(hipMemsetAsync(c->L0.cols, 0, (size_t)N * 4 * nt * sizeof(cd), c->st));
     HIPCHK(launch_beta(nt + kWave + 1, c->dBeta, c->st));
     HIPCHK(hipStreamSynchronize(c->st));
     *out = c;
@@ -264,72 +323,108 @@ extern "C" swr_status swr_sizes(const swr_ctx* c, int* nt, int* nx, int* B, int*
 }
 
 // ---------------------------------------------------------------------------
-static SweepArgs sweep_args(swr_ctx* c, const Task* tasks, int ntasks) {
+// Sweep launches
+// ---------------------------------------------------------------------------
+struct SweepIO {
+    const cd* u0 = nullptr;     // data (null: zero data and zero v_0 history)
+    const cd* g_in = nullptr;
+    cd* g_out = nullptr;
+    cd* uT = nullptr;
+    cd* trace = nullptr;
+    bool maxdiff = false;
+    bool ckpt = false;
+};
+
+static SweepArgs sweep_args(swr_ctx* c, const Task* tasks, int ntasks, const cd* fac, cd* cols) {
     SweepArgs a{};
     a.N = c->N; a.nt = c->nt; a.B = c->B; a.nx = c->nx; a.ns = c->ns; a.ntasks = ntasks;
     a.P = c->P;
     a.kappa = c->h / (3.0 * c->dt);
+    a.h = c->h;
     a.sigma = c->sigma;
     a.c2 = c->c2;
-    a.J = c->dJ; a.off = c->dOff; a.tasks = tasks; a.fac = c->dFac; a.beta = c->dBeta;
-    a.cols = c->dCols; a.hist = c->dHist; a.ends = c->dEnds; a.maxdiff = c->dMax;
+    a.J = c->dJ; a.off = c->dOff; a.tasks = tasks; a.fac = fac; a.beta = c->dBeta;
+    a.cols = cols; a.hist = c->dHist; a.ends = c->dEnds; a.maxdiff = c->dMax;
+    a.Vt = (c->vk == SWR_V_TIME) ? c->dV : nullptr;
+    a.nl_maxit = c->o.nl_max_iter;
+    a.nl_tol = c->o.nl_tol;
+    a.nl_stats = c->dNl;
+    a.flags_and = ~0;
+    a.flags_or = 0;
     return a;
 }
 
-static swr_status run_factor(swr_ctx* c) {
+// factor records of a static potential (V = null: zero potential)
+static swr_status run_factor(swr_ctx* c, const double* V, int nv, cd* fac) {
     FactorArgs f{};
-    f.N = c->N; f.nx = c->nx; f.nf = c->nv * c->N; f.P = c->P; f.h = c->h; f.dt = c->dt;
-    f.sigma = c->sigma; f.J = c->dJ; f.off = c->dOff; f.V = c->dV; f.fac = c->dFac;
+    f.N = c->N; f.nx = c->nx; f.nf = nv * c->N; f.P = c->P; f.h = c->h; f.dt = c->dt;
+    f.sigma = c->sigma; f.J = c->dJ; f.off = c->dOff; f.V = V; f.fac = fac;
     HIPCHK(launch_factor(f, c->st));
     return SWR_OK;
 }
 
-// impulse sweeps + d sweeps in one launch (Sec. 4.1)
+// the factor records used by the per-(problem, subdomain) sweeps
+static const cd* main_fac(swr_ctx* c) { return c->vk == SWR_V_STATIC ? c->L.fac : c->L0.fac; }
+
+// every (problem, subdomain) swept once with the fluxes io.g_in (null: zero)
+static swr_status run_sweeps(swr_ctx* c, const SweepIO& io) {
+    SweepArgs a = sweep_args(c, c->dSub, c->nSub, main_fac(c), nullptr);
+    a.u0 = io.u0;
+    a.g_in = io.g_in ? io.g_in : c->dZero;
+    a.g_out = io.g_out;
+    a.uT = io.uT;
+    a.trace = io.trace;
+    a.flags_and = 0;
+    a.flags_or = (io.u0 ? T_DATA_U0 : 0) | (io.g_in ? T_FLUX_G : 0) | (io.g_out ? T_OUT_G : 0) |
+                 (io.uT ? T_OUT_UT : 0) | (io.trace ? T_OUT_TRACE : 0) | (io.maxdiff ? T_MAXDIFF : 0) |
+                 (io.ckpt ? T_CKPT : 0);
+    a.ckpt = c->dCkpt;
+    a.Jc = c->Jc;
+    if (io.maxdiff) HIPCHK(hipMemsetAsync(c->dMax, 0, sizeof(unsigned long long), c->st));
+    HIPCHK(launch_sweep(a, c->tr, c->vk, c->st));
+    if (io.uT) HIPCHK(launch_finalize_ut(c->N, c->nx, c->B, c->dOff, c->dEnds, io.uT, c->st));
+    return SWR_OK;
+}
+
+// static potential: impulse sweeps of L and the d sweeps in ONE launch
 static swr_status run_build(swr_ctx* c, const double* u0) {
-    SweepArgs a = sweep_args(c, c->dBuild, (int)c->build_tasks.size());
+    SweepArgs a = sweep_args(c, c->dBuild, c->nBuild, c->L.fac, c->L.cols);
     a.u0 = reinterpret_cast<const cd*>(u0);
     a.g_in = c->dZero;
     a.g_out = c->dD;
-    HIPCHK(launch_sweep(a, c->tr, c->st));
-    c->built = true;
+    HIPCHK(launch_sweep(a, c->tr, SWR_V_STATIC, c->st));
+    c->L.dirty = true;
     return SWR_OK;
 }
 
-// sweeps of every (problem, subdomain) with fluxes g_in
-static swr_status run_sweeps(swr_ctx* c, const cd* u0, const cd* g_in, cd* g_out, cd* uT,
-                             cd* trace, bool maxdiff) {
-    std::vector<Task>& tl = c->final_tasks;
-    // flags vary per call: rebuild the list only when they change
-    int want = (u0 ? T_DATA_U0 : 0) | T_FLUX_G | T_OUT_G | (uT ? T_OUT_UT : 0) |
-               (trace ? T_OUT_TRACE : 0) | (maxdiff ? T_MAXDIFF : 0);
-    if (tl.empty() || tl[0].flags != want) {
-        for (auto& t : tl) t.flags = want;
-        HIPCHK(hipMemcpyAsync(c->dFinal, tl.data(), tl.size() * sizeof(Task), hipMemcpyHostToDevice,
-                              c->st));
-    }
-    SweepArgs a = sweep_args(c, c->dFinal, (int)tl.size());
-    a.u0 = u0;
-    a.g_in = g_in;
-    a.g_out = g_out;
-    a.uT = uT;
-    a.trace = trace;
-    if (maxdiff) HIPCHK(hipMemsetAsync(c->dMax, 0, sizeof(unsigned long long), c->st));
-    HIPCHK(launch_sweep(a, c->tr, c->st));
-    if (uT) HIPCHK(launch_finalize_ut(c->N, c->nx, c->B, c->dOff, c->dEnds, uT, c->st));
+// impulse sweeps of the zero-potential operator L_0 (Sec. 5)
+static swr_status run_build_L0(swr_ctx* c) {
+    CHK(run_factor(c, nullptr, 1, c->L0.fac));
+    SweepArgs a = sweep_args(c, c->L0.tasks, c->L0.ntasks, c->L0.fac, c->L0.cols);
+    a.g_in = c->dZero;
+    HIPCHK(launch_sweep(a, c->tr, SWR_V_STATIC, c->st));
+    c->L0.dirty = true;
     return SWR_OK;
 }
 
-static LttArgs ltt_args(swr_ctx* c, const cd* x, cd* y) {
+static LttArgs ltt_args(swr_ctx* c, const Iface& I, const cd* x, cd* y) {
     LttArgs l{};
-    l.N = c->N; l.nt = c->nt; l.ns = c->ns; l.B = c->B; l.per_problem = c->nv > 1;
-    l.cols = c->dCols; l.x = x; l.y = y; l.base = x; l.sign = -1.0;
+    l.N = c->N; l.nt = c->nt; l.ns = c->ns; l.B = c->B; l.per_problem = I.nv > 1;
+    l.cols = I.cols; l.x = x; l.y = y; l.base = x; l.sign = -1.0;
     l.n_lo = 0; l.n_hi = c->nt; l.s_hi = c->nt; l.y_ld = c->nt;
     return l;
 }
 
-// GMRES(m) on (I - L) g = d, all problems of the batch at once (each with its
-// own Krylov space); classical Gram-Schmidt applied twice.
-static swr_status run_gmres(swr_ctx* c, int* iters_out) {
+// ---------------------------------------------------------------------------
+// Interface solvers
+// ---------------------------------------------------------------------------
+using Op = std::function<swr_status(const cd* x, cd* y)>;
+
+// GMRES(m) for A x = rhs, all problems of the batch at once (each with its
+// own Krylov space); classical Gram-Schmidt applied twice; x holds the
+// initial guess on entry.  Convergence: ||rhs - A x|| <= tol ||rhs|| per
+// problem, confirmed on the true residual at a restart.
+static swr_status run_gmres(swr_ctx* c, const Op& A, const cd* rhs, cd* x, int* iters_out) {
     const int m = c->o.restart, B = c->B;
     const long M = (long)c->ns * c->nt;
     if (c->gm_m != m) {
@@ -345,16 +440,13 @@ static swr_status run_gmres(swr_ctx* c, int* iters_out) {
         c->gm_m = m;
     }
     hipStream_t st = c->st;
-    cd* x = c->dG;
-    HIPCHK(hipMemsetAsync(x, 0, (size_t)B * M * sizeof(cd), st));
-    HIPCHK(launch_norm(c->dD, M, B, c->dPart, c->dBn, st));
+    HIPCHK(launch_norm(rhs, M, B, c->dPart, c->dBn, st));
     int its = 0;
     bool conv = false;
-    while (its < c->o.max_iter && !conv) {
-        // r = d - (I - L) x  -> basis[0]
-        LttArgs l = ltt_args(c, x, c->dW);
-        HIPCHK(launch_ltt(l, st));
-        HIPCHK(launch_axpby(c->dD, 1.0, c->dW, -1.0, c->dBasis, (long)B * M, st));
+    while (true) {
+        // r = rhs - A x -> basis[0]
+        CHK(A(x, c->dW));
+        HIPCHK(launch_axpby(rhs, 1.0, c->dW, -1.0, c->dBasis, (long)B * M, st));
         HIPCHK(launch_norm(c->dBasis, M, B, c->dPart, c->dNrm, st));
         HIPCHK(launch_gmres_init(m, B, c->dNrm, c->dE, c->dAct, c->dBn, c->o.tol, c->dRes, st));
         HIPCHK(hipMemcpyAsync(c->hAct, c->dAct, sizeof(int) * B, hipMemcpyDeviceToHost, st));
@@ -362,13 +454,13 @@ static swr_status run_gmres(swr_ctx* c, int* iters_out) {
         bool any = false;
         for (int b = 0; b < B; ++b) any |= c->hAct[b] != 0;
         if (!any) { conv = true; break; }
+        if (its >= c->o.max_iter) break;
         HIPCHK(launch_scale(c->dBasis, c->dNrm, c->dBasis, M, B, nullptr, st));
         int jj = 0;
         for (int j = 0; j < m && its < c->o.max_iter; ++j) {
             cd* vj = c->dBasis + (size_t)j * B * M;
             cd* vn = c->dBasis + (size_t)(j + 1) * B * M;
-            LttArgs lj = ltt_args(c, vj, c->dW);
-            HIPCHK(launch_ltt(lj, st));
+            CHK(A(vj, c->dW));
             HIPCHK(launch_multidot(c->dBasis, j + 1, c->dW, M, B, c->dPart, c->dHp, m + 1, 0, st));
             HIPCHK(launch_multiaxpy(c->dBasis, j + 1, c->dHp, m + 1, -1.0, c->dW, M, B, st));
             HIPCHK(launch_multidot(c->dBasis, j + 1, c->dW, M, B, c->dPart, c->dHp2, m + 1, 0, st));
@@ -387,95 +479,158 @@ static swr_status run_gmres(swr_ctx* c, int* iters_out) {
                 if (!std::isfinite(c->hRes[b])) return SWR_ENAN;
                 if (c->hAct[b] && c->hRes[b] > c->o.tol) done = false;
             }
-            if (done) { conv = true; break; }
+            if (done) break;
         }
         HIPCHK(launch_gmres_solve(jj, m, B, c->dH, c->dE, c->dY, c->dAct, st));
         HIPCHK(launch_multiaxpy(c->dBasis, jj, c->dY, m + 1, 1.0, x, M, B, st));
-        if (conv) {
-            // confirm with the true residual at the next cycle start
-            conv = false;
-        }
     }
     *iters_out = its;
-    return its >= c->o.max_iter ? SWR_ENOCONV : SWR_OK;
+    return conv ? SWR_OK : SWR_ENOCONV;
 }
 
-// causal forward substitution in time (exact up to rounding).  Block PCR
-// per step when it applies (N - 1 <= 64, ns <= 128) and the block system is
-// certified diagonally dominant; otherwise a dense (I - C_0)^{-1} by
-// Gauss-Jordan with partial pivoting.
-static swr_status run_causal(swr_ctx* c) {
+// causal forward substitution in time for (I - L) g = d with the operator I
+// (exact up to rounding).  Block PCR per step when it applies (N - 1 <= 64,
+// ns <= 128) and the block system is certified diagonally dominant;
+// otherwise a dense (I - C_0)^{-1} by Gauss-Jordan with partial pivoting.
+static swr_status run_causal(swr_ctx* c, Iface& I, const cd* d, cd* g) {
     const int ns = c->ns, nt = c->nt, B = c->B;
     hipStream_t st = c->st;
-    if (ns <= kNearSlots && c->N - 1 <= kWave) {
-        if (!c->dPcr) {
-            ALLOC_LIVE(c->dPcr, (size_t)c->nv * kPcrRec * kWave);
-            ALLOC_LIVE(c->dBase, (size_t)B * ns * kNearTb);
-            ALLOC_LIVE(c->dEta, c->nv);
+    if (I.dirty) {
+        I.path = 2;
+        if (ns <= kNearSlots && c->N - 1 <= kWave) {
+            if (!I.pcr) {
+                ALLOC_LIVE(I.pcr, (size_t)I.nv * kPcrRec * kWave);
+                ALLOC_LIVE(I.eta, I.nv);
+            }
+            HIPCHK(launch_causal_pcr_setup(c->N, nt, I.nv, I.cols, I.pcr, I.eta, st));
+            std::vector<double> eta(I.nv);
+            HIPCHK(hipMemcpyAsync(eta.data(), I.eta, sizeof(double) * I.nv, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            bool ok = true;
+            for (double e : eta) ok = ok && std::isfinite(e) && e < 1.0;
+            if (ok) I.path = 1;
         }
-        HIPCHK(launch_causal_pcr_setup(c->N, nt, c->nv, c->dCols, c->dPcr, c->dEta, st));
-        std::vector<double> eta(c->nv);
-        HIPCHK(hipMemcpyAsync(eta.data(), c->dEta, sizeof(double) * c->nv, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        bool ok = true;
-        for (double e : eta) ok = ok && std::isfinite(e) && e < 1.0;
-        if (ok) {
-            c->causal_path = 1;
-            HIPCHK(launch_causal_fast(c->N, nt, ns, B, c->nv > 1, c->dCols, c->dPcr, c->dD, c->dBase,
-                                      c->dG, st));
-            return SWR_OK;
+        if (I.path == 2) {
+            if (!I.Minv) {
+                ALLOC_LIVE(I.Minv, (size_t)I.nv * ns * ns);
+                ALLOC_LIVE(I.Mwork, (size_t)I.nv * ns * ns);
+                ALLOC_LIVE(I.piv, I.nv);
+            }
+            HIPCHK(launch_c0_inverse(c->N, ns, nt, I.nv, I.cols, I.Mwork, I.Minv, I.piv, st));
         }
+        I.dirty = false;
     }
-    c->causal_path = 2;
-    if (!c->dMinv) {
-        ALLOC_LIVE(c->dMinv, (size_t)c->nv * ns * ns);
-        ALLOC_LIVE(c->dMwork, (size_t)c->nv * ns * ns);
-        ALLOC_LIVE(c->dFar, (size_t)B * ns * kCausalTb);
-        ALLOC_LIVE(c->dPivOk, c->nv);
+    if (I.path == 1) {
+        if (!c->dBase) ALLOC_LIVE(c->dBase, (size_t)B * ns * kNearTb);
+        HIPCHK(launch_causal_fast(c->N, nt, ns, B, I.nv > 1, I.cols, I.pcr, d, c->dBase, g, st));
+        return SWR_OK;
     }
-    HIPCHK(launch_c0_inverse(c->N, ns, nt, c->nv, c->dCols, c->dMwork, c->dMinv, c->dPivOk, st));
+    if (!c->dFar) ALLOC_LIVE(c->dFar, (size_t)B * ns * kCausalTb);
     for (int n0 = 0; n0 < nt; n0 += kCausalTb) {
         const int nb = std::min(kCausalTb, nt - n0);
         LttArgs l{};
-        l.N = c->N; l.nt = nt; l.ns = ns; l.B = B; l.per_problem = c->nv > 1;
-        l.cols = c->dCols; l.x = c->dG; l.y = c->dFar; l.base = nullptr; l.sign = 1.0;
+        l.N = c->N; l.nt = nt; l.ns = ns; l.B = B; l.per_problem = I.nv > 1;
+        l.cols = I.cols; l.x = g; l.y = c->dFar; l.base = nullptr; l.sign = 1.0;
         l.n_lo = n0; l.n_hi = n0 + nb; l.s_hi = n0; l.y_ld = kCausalTb;
         HIPCHK(launch_ltt(l, st));
         CausalArgs ca{};
-        ca.N = c->N; ca.nt = nt; ca.ns = ns; ca.B = B; ca.per_problem = c->nv > 1;
-        ca.n0 = n0; ca.nb = nb; ca.cols = c->dCols; ca.Minv = c->dMinv; ca.d = c->dD;
-        ca.far = c->dFar; ca.g = c->dG;
+        ca.N = c->N; ca.nt = nt; ca.ns = ns; ca.B = B; ca.per_problem = I.nv > 1;
+        ca.n0 = n0; ca.nb = nb; ca.cols = I.cols; ca.Minv = I.Minv; ca.d = d;
+        ca.far = c->dFar; ca.g = g;
         HIPCHK(launch_causal_block(ca, st));
     }
     return SWR_OK;
 }
 
+static swr_status read_max(swr_ctx* c, double* out) {
+    unsigned long long bits = 0;
+    HIPCHK(hipMemcpyAsync(&bits, c->dMax, sizeof(bits), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    std::memcpy(out, &bits, sizeof(double));
+    return SWR_OK;
+}
+
 // classical algorithm: g <- R g until max |g^{k+1} - g^k| < tol (Sec. 4)
-static swr_status run_classical(swr_ctx* c, const double* u0, int* iters, double* last) {
+static swr_status run_classical(swr_ctx* c, const cd* u0, int* iters, double* last) {
     const size_t vec = (size_t)c->B * c->ns * c->nt;
     HIPCHK(hipMemsetAsync(c->dG, 0, vec * sizeof(cd), c->st));
     cd* gi = c->dG;
     cd* go = c->dG2;
-    const cd* u = reinterpret_cast<const cd*>(u0);
     *last = INFINITY;
+    swr_status rs = SWR_ENOCONV;
     for (int it = 1; it <= c->o.max_iter; ++it) {
-        swr_status s = run_sweeps(c, u, gi, go, nullptr, nullptr, true);
-        if (s != SWR_OK) return s;
-        unsigned long long bits = 0;
-        HIPCHK(hipMemcpyAsync(&bits, c->dMax, sizeof(bits), hipMemcpyDeviceToHost, c->st));
-        HIPCHK(hipStreamSynchronize(c->st));
+        SweepIO io;
+        io.u0 = u0; io.g_in = gi; io.g_out = go; io.maxdiff = true;
+        CHK(run_sweeps(c, io));
         double d;
-        std::memcpy(&d, &bits, sizeof(d));
+        CHK(read_max(c, &d));
         *last = d;
         *iters = it;
         std::swap(gi, go);
         if (!std::isfinite(d)) return SWR_ENAN;
-        if (d < c->o.tol) {
-            if (gi != c->dG) HIPCHK(hipMemcpyAsync(c->dG, gi, vec * sizeof(cd), hipMemcpyDeviceToDevice, c->st));
-            return SWR_OK;
-        }
+        if (d < c->o.tol) { rs = SWR_OK; break; }
     }
     if (gi != c->dG) HIPCHK(hipMemcpyAsync(c->dG, gi, vec * sizeof(cd), hipMemcpyDeviceToDevice, c->st));
+    return rs;
+}
+
+// V(t,x): GMRES on (I - L) g = d with L x = R(x) - R(0) applied by one
+// zero-data sweep (Sec. 4 "Classical algorithm, version 2"), right
+// preconditioned by P = I - L_0 (Sec. 5, eq. chp2_algopd_Lpf) whose inverse is
+// applied exactly by the causal solver.
+static swr_status run_precond_time(swr_ctx* c, int* iters) {
+    const size_t vec = (size_t)c->B * c->ns * c->nt;
+    const bool pc = c->o.precond != 0;
+    Op A = [c, pc, vec](const cd* z, cd* y) -> swr_status {
+        const cd* w = z;
+        if (pc) {
+            CHK(run_causal(c, c->L0, z, c->dT1));
+            w = c->dT1;
+        }
+        SweepIO io;
+        io.g_in = w; io.g_out = c->dT2;
+        CHK(run_sweeps(c, io));                                   // L w
+        HIPCHK(launch_axpby(w, 1.0, c->dT2, -1.0, y, (long)vec, c->st));
+        return SWR_OK;
+    };
+    HIPCHK(hipMemsetAsync(c->dG2, 0, vec * sizeof(cd), c->st));   // y (preconditioned unknown)
+    swr_status rs = run_gmres(c, A, c->dD, c->dG2, iters);
+    if (rs != SWR_OK && rs != SWR_ENOCONV) return rs;
+    if (pc) CHK(run_causal(c, c->L0, c->dG2, c->dG));
+    else HIPCHK(hipMemcpyAsync(c->dG, c->dG2, vec * sizeof(cd), hipMemcpyDeviceToDevice, c->st));
+    return rs;
+}
+
+// |u|^2: preconditioned fixed point g <- g - P^{-1}(g - R_nl g) (Sec. 5,
+// eq. chp2_algopd_NL read as in the surrounding text) until
+// max |g^{k+1} - g^k| < tol.
+static swr_status run_precond_cubic(swr_ctx* c, const cd* u0, int* iters, double* last) {
+    const size_t vec = (size_t)c->B * c->ns * c->nt;
+    const long M = (long)c->ns * c->nt;
+    HIPCHK(hipMemsetAsync(c->dG, 0, vec * sizeof(cd), c->st));
+    *last = INFINITY;
+    for (int it = 1; it <= c->o.max_iter; ++it) {
+        SweepIO io;
+        io.u0 = u0; io.g_in = c->dG; io.g_out = c->dT2;
+        CHK(run_sweeps(c, io));                                          // R_nl g
+        HIPCHK(launch_axpby(c->dG, 1.0, c->dT2, -1.0, c->dT2, (long)vec, c->st));   // g - R_nl g
+        const cd* z = c->dT2;
+        if (c->o.precond) {
+            CHK(run_causal(c, c->L0, c->dT2, c->dT1));
+            z = c->dT1;
+        }
+        HIPCHK(launch_axpby(c->dG, 1.0, z, -1.0, c->dG, (long)vec, c->st));
+        HIPCHK(launch_maxabs(z, M, c->B, c->dPart, c->dNrm, c->st));
+        std::vector<double> m(c->B);
+        HIPCHK(hipMemcpyAsync(m.data(), c->dNrm, sizeof(double) * c->B, hipMemcpyDeviceToHost, c->st));
+        HIPCHK(hipStreamSynchronize(c->st));
+        double d = 0;
+        for (double x : m) d = std::max(d, x);
+        *last = d;
+        *iters = it;
+        if (!std::isfinite(d)) return SWR_ENAN;
+        if (d < c->o.tol) return SWR_OK;
+    }
     return SWR_ENOCONV;
 }
 
@@ -485,49 +640,73 @@ static double elapsed(hipEvent_t a, hipEvent_t b) {
     return ms;
 }
 
-extern "C" swr_status swr_solve(swr_ctx* c, const double* u0, double* uT, double* g, double* utrace,
+extern "C" swr_status swr_solve(swr_ctx* c, const double* u0d, double* uT, double* g, double* utrace,
                                 swr_info* info) {
-    if (!c || !u0 || !uT) return SWR_EINVAL;
+    if (!c || !u0d || !uT) return SWR_EINVAL;
+    const cd* u0 = reinterpret_cast<const cd*>(u0d);
     const size_t vec = (size_t)c->B * c->ns * c->nt;
     hipStream_t st = c->st;
     swr_status rs = SWR_OK;
     int iters = 0;
     double fixed_last = 0;
+    HIPCHK(hipMemsetAsync(c->dNl, 0, 2 * sizeof(int), st));
     HIPCHK(hipEventRecord(c->ev[0], st));
-    swr_status s = run_factor(c);
-    if (s != SWR_OK) return s;
+    // 1. assembly + factorisation
+    if (c->vk == SWR_V_STATIC) CHK(run_factor(c, c->dV, c->nv, c->L.fac));
+    else CHK(run_build_L0(c));   // zero-potential factors + impulses of L_0
     HIPCHK(hipEventRecord(c->ev[1], st));
-    if (c->o.solver != SWR_SOLVER_FIXED) {
-        s = run_build(c, u0);
-        if (s != SWR_OK) return s;
+    // 2. explicit interface problem (static V) or d = R 0
+    const bool fixed = c->vk == SWR_V_STATIC && c->o.solver == SWR_SOLVER_FIXED;
+    if (c->vk == SWR_V_STATIC) {
+        if (!fixed) CHK(run_build(c, u0d));
+    } else {
+        SweepIO io;
+        io.u0 = u0; io.g_out = c->dD;
+        CHK(run_sweeps(c, io));
     }
     HIPCHK(hipEventRecord(c->ev[2], st));
+    // 3. interface solve
     if (c->ns == 0) {
-        HIPCHK(hipMemsetAsync(c->dG, 0, sizeof(cd), st));
-    } else if (c->o.solver == SWR_SOLVER_FIXED) {
+        rs = SWR_OK;
+    } else if (c->vk == SWR_V_TIME) {
+        rs = run_precond_time(c, &iters);
+    } else if (c->vk == SWR_V_CUBIC) {
+        rs = run_precond_cubic(c, u0, &iters, &fixed_last);
+    } else if (fixed) {
         rs = run_classical(c, u0, &iters, &fixed_last);
     } else if (c->o.solver == SWR_SOLVER_GMRES) {
-        rs = run_gmres(c, &iters);
+        HIPCHK(hipMemsetAsync(c->dG, 0, vec * sizeof(cd), st));
+        Op A = [c](const cd* x, cd* y) -> swr_status {
+            LttArgs l = ltt_args(c, c->L, x, y);
+            HIPCHK(launch_ltt(l, c->st));
+            return SWR_OK;
+        };
+        rs = run_gmres(c, A, c->dD, c->dG, &iters);
     } else if (c->o.solver == SWR_SOLVER_CAUSAL) {
-        rs = run_causal(c);
+        rs = run_causal(c, c->L, c->dD, c->dG);
         iters = 1;
     } else {
         return SWR_EINVAL;
     }
     if (rs != SWR_OK && rs != SWR_ENOCONV) return rs;
     HIPCHK(hipEventRecord(c->ev[3], st));
-    s = run_sweeps(c, reinterpret_cast<const cd*>(u0), c->dG, c->dG2, reinterpret_cast<cd*>(uT),
-                   reinterpret_cast<cd*>(utrace), false);
-    if (s != SWR_OK) return s;
+    // 4. final sweep: u(T) and R g
+    {
+        SweepIO io;
+        io.u0 = u0; io.g_in = c->ns ? c->dG : nullptr; io.g_out = c->dG2;
+        io.uT = reinterpret_cast<cd*>(uT); io.trace = reinterpret_cast<cd*>(utrace);
+        CHK(run_sweeps(c, io));
+    }
     HIPCHK(hipEventRecord(c->ev[4], st));
-    if (g) HIPCHK(hipMemcpyAsync(g, c->dG, vec * sizeof(cd), hipMemcpyDeviceToDevice, st));
-    // certified residual ||g - R g|| / ||R 0||; R 0 = d for the built path
+    if (g && vec) HIPCHK(hipMemcpyAsync(g, c->dG, vec * sizeof(cd), hipMemcpyDeviceToDevice, st));
+    // certified residual ||g - R g|| / ||R 0|| (R 0 = d; the classical
+    // algorithm reports its last change instead)
     double res = 0;
     if (c->ns > 0) {
         const long M = (long)c->ns * c->nt;
-        HIPCHK(launch_axpby(c->dG, 1.0, c->dG2, -1.0, c->dW ? c->dW : c->dG2, (long)vec, st));
-        if (c->o.solver != SWR_SOLVER_FIXED) {
-            HIPCHK(launch_norm(c->dW ? c->dW : c->dG2, M, c->B, c->dPart, c->dNrm, st));
+        if (!fixed) {
+            HIPCHK(launch_axpby(c->dG, 1.0, c->dG2, -1.0, c->dT1, (long)vec, st));
+            HIPCHK(launch_norm(c->dT1, M, c->B, c->dPart, c->dNrm, st));
             HIPCHK(launch_norm(c->dD, M, c->B, c->dPart, c->dBn, st));
             std::vector<double> a(c->B), bnv(c->B);
             HIPCHK(hipMemcpyAsync(a.data(), c->dNrm, sizeof(double) * c->B, hipMemcpyDeviceToHost, st));
@@ -542,6 +721,8 @@ extern "C" swr_status swr_solve(swr_ctx* c, const double* u0, double* uT, double
             res = fixed_last;
         }
     }
+    int nl[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(nl, c->dNl, sizeof(nl), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     if (info) {
         info->iters = iters;
@@ -550,54 +731,183 @@ extern "C" swr_status swr_solve(swr_ctx* c, const double* u0, double* uT, double
         info->t_build_ms = elapsed(c->ev[1], c->ev[2]);
         info->t_iface_ms = elapsed(c->ev[2], c->ev[3]);
         info->t_final_ms = elapsed(c->ev[3], c->ev[4]);
-        info->nl_worst = 0;
+        info->nl_worst = nl[0];
     }
+    if (nl[1]) return SWR_ENOCONV;
     return rs;
 }
 
 extern "C" swr_status swr_apply_R(swr_ctx* c, const double* u0, const double* g_in, double* g_out,
                                   double* uT, double* maxdiff) {
     if (!c || !g_in || !g_out) return SWR_EINVAL;
-    swr_status s = run_factor(c);
-    if (s != SWR_OK) return s;
-    s = run_sweeps(c, reinterpret_cast<const cd*>(u0), reinterpret_cast<const cd*>(g_in),
-                   reinterpret_cast<cd*>(g_out), reinterpret_cast<cd*>(uT), nullptr, maxdiff != nullptr);
-    if (s != SWR_OK) return s;
-    if (maxdiff) {
-        unsigned long long bits = 0;
-        HIPCHK(hipMemcpyAsync(&bits, c->dMax, sizeof(bits), hipMemcpyDeviceToHost, c->st));
-        HIPCHK(hipStreamSynchronize(c->st));
-        std::memcpy(maxdiff, &bits, sizeof(double));
-    }
+    if (c->vk == SWR_V_STATIC) CHK(run_factor(c, c->dV, c->nv, c->L.fac));
+    else CHK(run_factor(c, nullptr, 1, c->L0.fac));
+    SweepIO io;
+    io.u0 = reinterpret_cast<const cd*>(u0);
+    io.g_in = reinterpret_cast<const cd*>(g_in);
+    io.g_out = reinterpret_cast<cd*>(g_out);
+    io.uT = reinterpret_cast<cd*>(uT);
+    io.maxdiff = maxdiff != nullptr;
+    CHK(run_sweeps(c, io));
+    if (maxdiff) CHK(read_max(c, maxdiff));
     HIPCHK(hipStreamSynchronize(c->st));
     return SWR_OK;
 }
 
 extern "C" swr_status swr_build_interface(swr_ctx* c, const double* u0, double* cols, double* d) {
     if (!c || !u0) return SWR_EINVAL;
-    swr_status s = run_factor(c);
-    if (s != SWR_OK) return s;
-    s = run_build(c, u0);
-    if (s != SWR_OK) return s;
-    if (cols) HIPCHK(hipMemcpyAsync(cols, c->dCols, (size_t)c->nv * c->N * 4 * c->nt * sizeof(cd),
-                                    hipMemcpyDeviceToDevice, c->st));
+    if (c->vk == SWR_V_STATIC) {
+        CHK(run_factor(c, c->dV, c->nv, c->L.fac));
+        CHK(run_build(c, u0));
+        if (cols) HIPCHK(hipMemcpyAsync(cols, c->L.cols, (size_t)c->nv * c->N * 4 * c->nt * sizeof(cd),
+                                        hipMemcpyDeviceToDevice, c->st));
+    } else {
+        // the operator that exists for a general potential is L_0 (Sec. 5)
+        CHK(run_build_L0(c));
+        SweepIO io;
+        io.u0 = reinterpret_cast<const cd*>(u0); io.g_out = c->dD;
+        CHK(run_sweeps(c, io));
+        if (cols) HIPCHK(hipMemcpyAsync(cols, c->L0.cols, (size_t)c->N * 4 * c->nt * sizeof(cd),
+                                        hipMemcpyDeviceToDevice, c->st));
+    }
     if (d) HIPCHK(hipMemcpyAsync(d, c->dD, (size_t)c->B * c->ns * c->nt * sizeof(cd),
                                  hipMemcpyDeviceToDevice, c->st));
     HIPCHK(hipStreamSynchronize(c->st));
     return SWR_OK;
 }
 
+extern "C" swr_status swr_set_potential(swr_ctx* c, const double* V) {
+    if (!c || !V || c->vk == SWR_V_CUBIC || !c->dV) return SWR_EINVAL;
+    const size_t vn = (c->vk == SWR_V_TIME) ? (size_t)c->nx * (c->nt + 1)
+                                            : (size_t)c->nx * (c->o.v_per_problem ? c->B : 1);
+    HIPCHK(hipMemcpyAsync(c->dV, V, vn * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+    c->L.dirty = true;
+    return SWR_OK;
+}
+
 extern "C" swr_status swr_interface_matvec(swr_ctx* c, const double* x, double* y) {
-    if (!c || !x || !y || !c->built) return SWR_EINVAL;
-    LttArgs l = ltt_args(c, reinterpret_cast<const cd*>(x), reinterpret_cast<cd*>(y));
+    if (!c || !x || !y) return SWR_EINVAL;
+    Iface& I = c->vk == SWR_V_STATIC ? c->L : c->L0;
+    LttArgs l = ltt_args(c, I, reinterpret_cast<const cd*>(x), reinterpret_cast<cd*>(y));
     HIPCHK(launch_ltt(l, c->st));
     HIPCHK(hipStreamSynchronize(c->st));
     return SWR_OK;
 }
 
-extern "C" swr_status swr_grad(swr_ctx* c, const double* u0, const double* gbar, double* dJdV,
+// the interface solve of (I - L) g = d with the configured solver
+static swr_status solve_interface(swr_ctx* c, const cd* d, cd* g, int* iters) {
+    const size_t vec = (size_t)c->B * c->ns * c->nt;
+    if (c->ns == 0) return SWR_OK;
+    if (c->o.solver == SWR_SOLVER_GMRES) {
+        HIPCHK(hipMemsetAsync(g, 0, vec * sizeof(cd), c->st));
+        Op A = [c](const cd* x, cd* y) -> swr_status {
+            LttArgs l = ltt_args(c, c->L, x, y);
+            HIPCHK(launch_ltt(l, c->st));
+            return SWR_OK;
+        };
+        return run_gmres(c, A, d, g, iters);
+    }
+    *iters = 1;
+    return run_causal(c, c->L, d, g);
+}
+
+static AdjArgs adj_args(swr_ctx* c) {
+    AdjArgs a{};
+    a.N = c->N; a.nt = c->nt; a.B = c->B; a.nx = c->nx; a.ns = c->ns; a.ntasks = c->nSub;
+    a.P = c->P; a.Jc = c->Jc;
+    a.kappa = c->h / (3.0 * c->dt);
+    a.h = c->h;
+    a.sigma = c->sigma;
+    a.c2 = c->c2;
+    a.J = c->dJ; a.off = c->dOff; a.tasks = c->dSub; a.fac = c->L.fac; a.beta = c->dBeta;
+    a.hist = c->dHist2;
+    a.ckpt = c->dCkpt; a.g_fwd = c->dGfwd; a.hist_fwd = c->dHist; a.seg = c->dSeg;
+    a.gends = c->dGends; a.wends = c->dWends;
+    return a;
+}
+
+extern "C" swr_status swr_grad(swr_ctx* c, const double* u0d, const double* gbar, double* dJdV,
                                double* dJdu0, swr_info* info) {
-    (void)u0; (void)gbar; (void)dJdV; (void)dJdu0; (void)info;
-    if (!c) return SWR_EINVAL;
-    return SWR_EINVAL;
+    if (!c || !u0d || !gbar || !dJdV || !dJdu0) return SWR_EINVAL;
+    if (c->vk != SWR_V_STATIC || c->o.solver == SWR_SOLVER_FIXED || c->o.checkpoint_K != kWave)
+        return SWR_EINVAL;
+    const cd* u0 = reinterpret_cast<const cd*>(u0d);
+    const size_t vec = (size_t)c->B * c->ns * c->nt;
+    hipStream_t st = c->st;
+    if (!c->dCkpt) {
+        c->Jc = (c->nt + kWave - 1) / kWave;
+        ALLOC_LIVE(c->dCkpt, (size_t)c->nSub * (c->Jc + 1) * c->P * kWave);
+        ALLOC_LIVE(c->dSeg, (size_t)c->nSub * kWave * c->P * kWave);
+        ALLOC_LIVE(c->dHist2, (size_t)c->nSub * 2 * (c->nt + 1));
+        ALLOC_LIVE(c->dGfwd, vec);
+        ALLOC_LIVE(c->dDadj, vec);
+        ALLOC_LIVE(c->dGadj, vec);
+        ALLOC_LIVE(c->dGends, (size_t)c->B * c->N * 2);
+        ALLOC_LIVE(c->dWends, (size_t)c->B * c->N * 2);
+        ALLOC_LIVE(c->dUT, (size_t)c->B * c->nx);
+    }
+    int it_f = 0, it_b = 0;
+    // ---- forward: factor, impulses + d, interface solve, final sweep with
+    //      checkpoints (the S0^2 boundary history of this sweep stays in dHist)
+    HIPCHK(hipEventRecord(c->ev[0], st));
+    CHK(run_factor(c, c->dV, c->nv, c->L.fac));
+    CHK(run_build(c, u0d));
+    swr_status rf = solve_interface(c, c->dD, c->dGfwd, &it_f);
+    if (rf != SWR_OK && rf != SWR_ENOCONV) return rf;
+    {
+        SweepIO io;
+        io.u0 = u0; io.g_in = c->ns ? c->dGfwd : nullptr; io.g_out = c->dG2; io.uT = c->dUT;
+        io.ckpt = true;
+        CHK(run_sweeps(c, io));
+    }
+    HIPCHK(hipEventRecord(c->ev[1], st));
+    // ---- adjoint: d of the adjoint interface problem (dual data, zero fluxes)
+    AdjArgs a = adj_args(c);
+    a.gbar = reinterpret_cast<const cd*>(gbar);
+    a.g_in = nullptr;
+    a.g_out = c->ns ? c->dDadj : nullptr;
+    a.grad = 0;
+    HIPCHK(launch_adjoint(a, c->tr, st));
+    HIPCHK(hipEventRecord(c->ev[2], st));
+    swr_status rb = solve_interface(c, c->dDadj, c->dGadj, &it_b);
+    if (rb != SWR_OK && rb != SWR_ENOCONV) return rb;
+    HIPCHK(hipEventRecord(c->ev[3], st));
+    // ---- adjoint final sweep with forward replay and dJ/dV accumulation
+    a.g_in = c->ns ? c->dGadj : nullptr;
+    a.g_out = c->ns ? c->dT1 : nullptr;
+    a.grad = 1;
+    a.dV = dJdV;
+    a.du0 = reinterpret_cast<cd*>(dJdu0);
+    HIPCHK(launch_adjoint(a, c->tr, st));
+    HIPCHK(launch_finalize_grad(c->N, c->nx, c->B, c->dOff, c->dGends, c->dWends, dJdV,
+                                reinterpret_cast<cd*>(dJdu0), st));
+    HIPCHK(hipEventRecord(c->ev[4], st));
+    // certified residual of the adjoint interface problem
+    double res = 0;
+    if (c->ns > 0) {
+        const long M = (long)c->ns * c->nt;
+        HIPCHK(launch_axpby(c->dGadj, 1.0, c->dT1, -1.0, c->dT2, (long)vec, st));
+        HIPCHK(launch_norm(c->dT2, M, c->B, c->dPart, c->dNrm, st));
+        HIPCHK(launch_norm(c->dDadj, M, c->B, c->dPart, c->dBn, st));
+        std::vector<double> x(c->B), y(c->B);
+        HIPCHK(hipMemcpyAsync(x.data(), c->dNrm, sizeof(double) * c->B, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(y.data(), c->dBn, sizeof(double) * c->B, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        for (int b = 0; b < c->B; ++b) {
+            const double r = y[b] > 0 ? x[b] / y[b] : x[b];
+            if (!std::isfinite(r)) return SWR_ENAN;
+            res = std::max(res, r);
+        }
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    if (info) {
+        info->iters = it_b;
+        info->residual = res;
+        info->t_factor_ms = elapsed(c->ev[0], c->ev[1]);   // the whole forward solve
+        info->t_build_ms = elapsed(c->ev[1], c->ev[2]);    // adjoint d sweep
+        info->t_iface_ms = elapsed(c->ev[2], c->ev[3]);    // adjoint interface solve
+        info->t_final_ms = elapsed(c->ev[3], c->ev[4]);    // replay + adjoint sweep + dJ/dV
+        info->nl_worst = it_f;
+    }
+    return (rf == SWR_ENOCONV || rb == SWR_ENOCONV) ? SWR_ENOCONV : SWR_OK;
 }

@@ -156,6 +156,34 @@ __global__ __launch_bounds__(kRedThreads) void norm2_kernel(const cd* w, long M,
     if (threadIdx.x == 0) partial[(size_t)b * gridDim.x + blockIdx.x] = t;
 }
 
+// partial[b][blk] = max |w| over the block's range
+__global__ __launch_bounds__(kRedThreads) void maxabs_kernel(const cd* w, long M, double* partial) {
+    __shared__ double sh[8];
+    const int b = blockIdx.y;
+    const long per = (M + gridDim.x - 1) / gridDim.x;
+    const long lo = blockIdx.x * per, hi = min(M, lo + per);
+    const cd* wb = w + (size_t)b * M;
+    double m = 0;
+    for (long e = lo + threadIdx.x; e < hi; e += blockDim.x) m = fmax(m, abs2(wb[e]));
+    m = wave_max(m);
+    const int wv = threadIdx.x / kWave, l = threadIdx.x % kWave;
+    if (l == 0) sh[wv] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r = 0;
+        for (int i = 0; i < (int)(blockDim.x / kWave); ++i) r = fmax(r, sh[i]);
+        partial[(size_t)b * gridDim.x + blockIdx.x] = r;
+    }
+}
+
+__global__ void reduce_max_kernel(const double* partial, int nblk, int B, double* out) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    double m = 0;
+    for (int k = 0; k < nblk; ++k) m = fmax(m, partial[(size_t)b * nblk + k]);
+    out[b] = sqrt(m);
+}
+
 // nrm[b] = sqrt(sum partial[b][:])
 __global__ void reduce_norm_kernel(const double* partial, int nblk, int B, double* nrm) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
@@ -257,6 +285,11 @@ hipError_t launch_multiaxpy(const cd* basis, int nv, const cd* coef, int coef_ld
 hipError_t launch_norm(const cd* w, long M, int B, double* partial, double* nrm, hipStream_t st) {
     norm2_kernel<<<dim3(kRedBlocks, B), kRedThreads, 0, st>>>(w, M, partial);
     reduce_norm_kernel<<<(B + 63) / 64, 64, 0, st>>>(partial, kRedBlocks, B, nrm);
+    return hipGetLastError();
+}
+hipError_t launch_maxabs(const cd* x, long M, int B, double* partial, double* out, hipStream_t st) {
+    maxabs_kernel<<<dim3(kRedBlocks, B), kRedThreads, 0, st>>>(x, M, partial);
+    reduce_max_kernel<<<(B + 63) / 64, 64, 0, st>>>(partial, kRedBlocks, B, out);
     return hipGetLastError();
 }
 hipError_t launch_scale(const cd* src, const double* den, cd* dst, long M, int B, const int* active,

@@ -24,67 +24,13 @@
 // boundary history stored in global memory, and every step adds the newest
 // boundary value with one fused multiply-add per lane.  The critical path of
 // a step therefore carries no O(n) history work.
-#include "swr_common.h"
+#include "swr_lane.h"
 
 namespace swr {
 
-// Lane t owns the P consecutive nodes t*P .. t*P+P-1 of its subdomain; nodes
-// at or beyond n = J_k + 1 are padding with a decoupled identity row, so every
-// lane runs the same straight-line code with compile-time register indices.
-
-// Row i of the subdomain matrix  c M - S + M_W - sigma E  (P1 elements on a
-// uniform mesh, eq. AvML; the generalised mass integrates W interpolated in
-// P1).  a = coupling to node i-1, b = diagonal, c = coupling to node i+1.
-__device__ inline void subdomain_row(int i, int n, bool left_if, bool right_if, double h,
-                                     double kap, cd sigma, const double* W, cd& ra, cd& rb,
-                                     cd& rc) {
-    ra = mk(0, 0);
-    rb = mk(0, 0);
-    rc = mk(0, 0);
-    if (i >= n) { rb = mk(1, 0); return; }   // padding
-    const double wi = W ? W[i] : 0.0;
-    if (i > 0) {
-        const double wm = W ? W[i - 1] : 0.0;
-        rb = rb + mk(-1.0 / h + h / 12.0 * (wm + 3.0 * wi), 2.0 * kap);
-        ra = mk(1.0 / h + h / 12.0 * (wm + wi), kap);
-    }
-    if (i < n - 1) {
-        const double wp = W ? W[i + 1] : 0.0;
-        rb = rb + mk(-1.0 / h + h / 12.0 * (3.0 * wi + wp), 2.0 * kap);
-        rc = mk(1.0 / h + h / 12.0 * (wi + wp), kap);
-    }
-    if (i == 0 && left_if) rb = rb - sigma;
-    if (i == n - 1 && right_if) rb = rb - sigma;
-}
-
-// Field offsets inside one lane's factor record.
-template <int P>
-struct FacLayout {
-    static constexpr int inv(int q) { return 5 * q + 0; }
-    static constexpr int ainv(int q) { return 5 * q + 1; }
-    static constexpr int cp(int q) { return 5 * q + 2; }
-    static constexpr int al(int q) { return 5 * q + 3; }
-    static constexpr int ga(int q) { return 5 * q + 4; }
-    static constexpr int ae = 5 * (P - 1);
-    static constexpr int ce = ae + 1;
-    static constexpr int k1(int l) { return ce + 1 + l; }
-    static constexpr int k2(int l) { return ce + 1 + kPcrLevels + l; }
-    static constexpr int invB = ce + 1 + 2 * kPcrLevels;
-    static constexpr int total = invB + 1;
-};
-static_assert(FacLayout<5>::total == fac_fields(5), "factor layout");
-
 // ---------------------------------------------------------------------------
-// Assembly + factorisation: one wave per (potential, subdomain).
-//
-// Chunk of lane t: interior nodes q = 0..P-2, separator q = P-1 (X_t).  The
-// interior solves  T_t x = rhs - a_0 X_{t-1} e_0 - c_{P-2} X_t e_{P-2},
-// giving x_q = y_q + alpha_q X_{t-1} + gamma_q X_t, where y is the Thomas
-// solution for the right-hand side and alpha, gamma are the responses to the
-// two separators.  Substituting into the separator rows leaves a tridiagonal
-// system in X_0..X_63 (A X_{t-1} + B X_t + C X_{t+1} = D), reduced here by
-// parallel cyclic reduction; only the multipliers k1, k2 and the final 1/B are
-// stored.
+// Assembly + factorisation for a static potential: one wave per
+// (potential, subdomain).
 // ---------------------------------------------------------------------------
 template <int P>
 __global__ __launch_bounds__(64) void factor_kernel(FactorArgs a) {
@@ -97,93 +43,32 @@ __global__ __launch_bounds__(64) void factor_kernel(FactorArgs a) {
     const double kap = a.h / (3.0 * a.dt);
     const double* W = a.V ? a.V + (size_t)v * a.nx + o : nullptr;
     const int s = t * P;
-    cd* F = a.fac + (size_t)f * L::total * kWave + t;
-    const cd zero = mk(0, 0), one = mk(1, 0);
-
-    constexpr int PI = P > 1 ? P - 1 : 1;
-    cd iinv[PI], icp[PI], ial[PI], iga[PI];
-    cd cpp = zero, alp = zero, last_c = zero;
+    double w[P];
 #pragma unroll
-    for (int q = 0; q < P - 1; ++q) {
-        cd ra, rb, rc;
-        subdomain_row(s + q, n, lif, rif, a.h, kap, a.sigma, W, ra, rb, rc);
-        const cd piv = (q == 0) ? rb : msub(rb, ra, cpp);
-        const cd iv = inv(piv);
-        const cd ai = ra * iv;
-        const cd cp = rc * iv;
-        alp = (q == 0) ? -(ra * iv) : -(ai * alp);   // forward sweep of alpha
-        cpp = cp;
-        last_c = rc;
-        F[L::inv(q) * kWave] = iv;
-        F[L::ainv(q) * kWave] = ai;
-        F[L::cp(q) * kWave] = cp;
-        iinv[q] = iv;
-        icp[q] = cp;
-        ial[q] = alp;
-    }
-    // back substitution of alpha and gamma (gamma' = -c_{P-2} inv_{P-2} at the
-    // last interior node and zero above it)
-    if (P > 1) {
-        cd an = ial[P - 2], gn = -(last_c * iinv[P - 2]);
-        iga[P - 2] = gn;
-#pragma unroll
-        for (int q = P - 3; q >= 0; --q) {
-            gn = -(icp[q] * gn);
-            an = msub(ial[q], icp[q], an);
-            ial[q] = an;
-            iga[q] = gn;
-        }
-    }
-#pragma unroll
-    for (int q = 0; q < P - 1; ++q) {
-        F[L::al(q) * kWave] = ial[q];
-        F[L::ga(q) * kWave] = iga[q];
-    }
-
-    // separator row and the reduced system
-    cd ae, rbs, ce;
-    subdomain_row(s + P - 1, n, lif, rif, a.h, kap, a.sigma, W, ae, rbs, ce);
-    const cd aL = (P > 1) ? ial[PI - 1] : one;
-    const cd gL = (P > 1) ? iga[PI - 1] : zero;
-    // the right neighbour's first node: (alpha_0, gamma_0), or its separator
-    const cd aF = (P > 1) ? ial[0] : zero;
-    const cd gF = (P > 1) ? iga[0] : one;
-    const cd aR = shfl_dn_c(aF, 1, zero);
-    const cd gR = shfl_dn_c(gF, 1, zero);
-    cd At = ae * aL;
-    cd Bt = madd(madd(rbs, ae, gL), ce, aR);
-    cd Ct = ce * gR;
-    F[L::ae * kWave] = ae;
-    F[L::ce * kWave] = ce;
-
-#pragma unroll
-    for (int l = 0; l < kPcrLevels; ++l) {
-        const int d = 1 << l;
-        const cd Am = shfl_up_c(At, d, zero), Bm = shfl_up_c(Bt, d, one), Cm = shfl_up_c(Ct, d, zero);
-        const cd Ap = shfl_dn_c(At, d, zero), Bp = shfl_dn_c(Bt, d, one), Cp = shfl_dn_c(Ct, d, zero);
-        const cd k1 = (t - d >= 0) ? At * inv(Bm) : zero;
-        const cd k2 = (t + d < kWave) ? Ct * inv(Bp) : zero;
-        At = -(k1 * Am);
-        Ct = -(k2 * Cp);
-        Bt = msub(msub(Bt, k1, Cm), k2, Ap);
-        F[L::k1(l) * kWave] = k1;
-        F[L::k2(l) * kWave] = k2;
-    }
-    F[L::invB * kWave] = inv(Bt);
+    for (int q = 0; q < P; ++q) w[q] = (W && s + q < n) ? W[s + q] : 0.0;
+    double wL, wR;
+    neighbour_w(w, wL, wR);
+    cd ra[P], rb[P], rc[P];
+    chunk_rows<P>(s, n, lif, rif, a.h, kap, a.sigma, w, wL, wR, ra, rb, rc);
+    LaneFac<P> F;
+    lane_factor<P>(ra, rb, rc, F);
+    store_fac<P>(a.fac + (size_t)f * L::total * kWave + t, F);
 }
 
 // ---------------------------------------------------------------------------
-// The sweep.
+// The sweep.  VK selects the potential: static (factors loaded once), time
+// dependent (rows rebuilt and refactored every step from the streamed V rows)
+// or |u|^2 (V-free factors, inner fixed point of eq. AvMNL every step).
 // ---------------------------------------------------------------------------
-template <int P, int TR>
+template <int P, int TR, int VK>
 __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
     using L = FacLayout<P>;
-    constexpr int PI = P > 1 ? P - 1 : 1;
     __shared__ double sbeta[kWave + 1];
     __shared__ cd sha[kWave], shb[kWave];     // staged chunk of the boundary history
     __shared__ double sb[2 * kWave];          // beta window of that chunk
     const Task task = a.tasks[blockIdx.x];
-    const int k = task.k, b = task.b, f = task.f, fl = task.flags;
+    const int k = task.k, b = task.b, f = task.f;
+    const int fl = (task.flags & a.flags_and) | a.flags_or;
     const int t = threadIdx.x;
     const int n = a.J[k] + 1, o = a.off[k];
     const int nt = a.nt;
@@ -198,23 +83,18 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
         __syncthreads();
     }
 
-    // factors -> registers
-    const cd* F = a.fac + (size_t)f * L::total * kWave + t;
-    cd f_inv[PI], f_ainv[PI], f_cp[PI], f_al[PI], f_ga[PI];
+    LaneFac<P> F;
+    // time-dependent potential: rows n and n+1 of V at my nodes
+    double vprev[P], vnext[P];
+    const double* Vt = (VK == VK_TIME) ? a.Vt + o : nullptr;
+    if (VK == VK_TIME) {
 #pragma unroll
-    for (int q = 0; q < P - 1; ++q) {
-        f_inv[q] = F[L::inv(q) * kWave];
-        f_ainv[q] = F[L::ainv(q) * kWave];
-        f_cp[q] = F[L::cp(q) * kWave];
-        f_al[q] = F[L::al(q) * kWave];
-        f_ga[q] = F[L::ga(q) * kWave];
-    }
-    const cd f_ae = F[L::ae * kWave], f_ce = F[L::ce * kWave], f_invB = F[L::invB * kWave];
-    cd f_k1[kPcrLevels], f_k2[kPcrLevels];
-#pragma unroll
-    for (int l = 0; l < kPcrLevels; ++l) {
-        f_k1[l] = F[L::k1(l) * kWave];
-        f_k2[l] = F[L::k2(l) * kWave];
+        for (int q = 0; q < P; ++q) {
+            vprev[q] = (s + q < n) ? Vt[s + q] : 0.0;
+            vnext[q] = (s + q < n) ? Vt[(size_t)a.nx + s + q] : 0.0;
+        }
+    } else {
+        load_fac<P>(a.fac + (size_t)f * L::total * kWave + t, F);
     }
 
     // per-node constants: mass stencil weights (P1 mass: 1,4,1 inside,
@@ -228,12 +108,15 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
         wlast[q] = (i == n - 1) ? 1.0 : 0.0;
     }
 
-    // state u_0
-    cd u[P];
+    // state u_0 (and v_0 = u_0, the first guess of the |u|^2 inner iteration)
+    cd u[P], vlast[P];
     const bool data = (fl & T_DATA_U0) != 0;
     const cd* u0 = a.u0 + (size_t)b * a.nx + o;
 #pragma unroll
-    for (int q = 0; q < P; ++q) u[q] = (data && s + q < n) ? u0[s + q] : zero;
+    for (int q = 0; q < P; ++q) {
+        u[q] = (data && s + q < n) ? u0[s + q] : zero;
+        vlast[q] = u[q];
+    }
     auto at_last = [&](const cd (&arr)[P]) {
         cd r = zero;
 #pragma unroll
@@ -249,6 +132,12 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
     if (TR == TR_S02 && t == 0) {
         Ha[0] = va0;
         Hb[0] = vb0;
+    }
+    // checkpoints for the adjoint: u at forward steps max(0, nt - 64 jj), jj = 1..Jc
+    cd* ck = (fl & T_CKPT) ? a.ckpt + ((size_t)blockIdx.x * (a.Jc + 1) * P) * kWave + t : nullptr;
+    if (ck) {
+#pragma unroll
+        for (int q = 0; q < P; ++q) ck[((size_t)a.Jc * P + q) * kWave] = u[q];
     }
     cd* trace_a = (fl & T_OUT_TRACE) ? a.trace + ((size_t)(b * a.N + k) * 2) * (nt + 1) : nullptr;
     cd* trace_b = trace_a ? trace_a + (nt + 1) : nullptr;
@@ -277,6 +166,7 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
         if (rif) out_r = a.cols + ((size_t)f * 4 + pl + 2) * nt;
     }
     double maxd = 0.0;
+    int nl_worst = 0, nl_fail = 0;
 
     for (int n0 = 0; n0 < nt; n0 += kWave) {
         const int nb = min(kWave, nt - n0);
@@ -319,6 +209,26 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
         cd rl_b = zero, rr_b = zero, va_b = zero, vb_b = zero, ua_b = zero, ub_b = zero;
 
         for (int i = 0; i < nb; ++i) {
+            const int nstep = n0 + 1 + i;
+            if (VK == VK_TIME) {
+                // W_n = (V_n + V_{n-1})/2 (eq. CNS_L); refactor for this step
+                double w[P];
+#pragma unroll
+                for (int q = 0; q < P; ++q) {
+                    w[q] = 0.5 * (vnext[q] + vprev[q]);
+                    vprev[q] = vnext[q];
+                }
+                if (nstep < nt) {
+#pragma unroll
+                    for (int q = 0; q < P; ++q)
+                        vnext[q] = (s + q < n) ? Vt[(size_t)(nstep + 1) * a.nx + s + q] : 0.0;
+                }
+                double wL, wR;
+                neighbour_w(w, wL, wR);
+                cd ra[P], rbr[P], rc[P];
+                chunk_rows<P>(s, n, lif, rif, a.h, kap, a.sigma, w, wL, wR, ra, rbr, rc);
+                lane_factor<P>(ra, rbr, rc, F);
+            }
             const cd ln = rdlane(lb, i), rn = rdlane(rb, i);
             cd hA = zero, hB = zero;
             if (TR == TR_S02) {
@@ -341,35 +251,66 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
                 d[q] = mk(d[q].x + wlast[q] * tb.x, d[q].y + wlast[q] * tb.y);
             }
             if (lif && t == 0) d[0] = d[0] + (hA - ln);
-            // interior forward / backward elimination
-            cd y[PI];
-            cd yp = zero;
-#pragma unroll
-            for (int q = 0; q < P - 1; ++q) {
-                yp = msub(d[q] * f_inv[q], f_ainv[q], yp);
-                y[q] = yp;
-            }
-#pragma unroll
-            for (int q = P - 3; q >= 0; --q) y[q] = msub(y[q], f_cp[q], y[q + 1]);
-            // reduced right-hand side at my separator, then PCR
-            const cd yL = (P > 1) ? y[PI - 1] : zero;
-            const cd yR = (P > 1) ? shfl_dn_c(y[0], 1, zero) : zero;
-            cd D = msub(msub(d[P - 1], f_ae, yL), f_ce, yR);
-#pragma unroll
-            for (int l = 0; l < kPcrLevels; ++l) {
-                const int dd = 1 << l;
-                const cd Dm = shfl_up_c(D, dd, zero), Dp = shfl_dn_c(D, dd, zero);
-                D = msub(msub(D, f_k1[l], Dm), f_k2[l], Dp);
-            }
-            const cd X = D * f_invB;
-            const cd Xm = shfl_up_c(X, 1, zero);
-            // recover the chunk and advance u_n = 2 v_n - u_{n-1}
             cd x[P];
+            if (VK == VK_CUBIC) {
+                // inner fixed point of eq. AvMNL from zeta^0 = v_{n-1}:
+                // (cM - S - sigma E) zeta^{s+1} = rhs - M_{|zeta^s|^2} zeta^s
+                cd z[P];
 #pragma unroll
-            for (int q = 0; q < P - 1; ++q) x[q] = madd(madd(y[q], f_al[q], Xm), f_ga[q], X);
-            x[P - 1] = X;
+                for (int q = 0; q < P; ++q) z[q] = vlast[q];
+                const double hk = a.h / 12.0;
+                int it = 1;
+                bool conv = false;
+                for (; it <= a.nl_maxit; ++it) {
+                    double Fz[P];
+#pragma unroll
+                    for (int q = 0; q < P; ++q) Fz[q] = abs2(z[q]);
+                    const cd zL = shfl_up_c(z[P - 1], 1, zero), zR = shfl_dn_c(z[0], 1, zero);
+                    const double FL = t > 0 ? __shfl(Fz[P - 1], t - 1) : 0.0;
+                    const double FR = t < kWave - 1 ? __shfl(Fz[0], t + 1) : 0.0;
+                    cd r[P];
+#pragma unroll
+                    for (int q = 0; q < P; ++q) {
+                        // generalised mass with nodal weight |zeta|^2 (same
+                        // element matrix as M_W)
+                        const cd zm = (q == 0) ? zL : z[q - 1];
+                        const cd zp = (q == P - 1) ? zR : z[q + 1];
+                        const double fm = (q == 0) ? FL : Fz[q - 1];
+                        const double fp = (q == P - 1) ? FR : Fz[q + 1];
+                        const double fi = Fz[q];
+                        cd nl = zero;
+                        if (wl[q] != 0.0) nl = nl + hk * ((fm + fi) * zm + (fm + 3.0 * fi) * z[q]);
+                        if (wr[q] != 0.0) nl = nl + hk * ((3.0 * fi + fp) * z[q] + (fi + fp) * zp);
+                        r[q] = d[q] - nl;
+                    }
+                    lane_solve<P>(F, r, x);
+                    double dm = 0.0, zm2 = 0.0;
+#pragma unroll
+                    for (int q = 0; q < P; ++q) {
+                        if (s + q < n) {
+                            dm = fmax(dm, abs2(x[q] - z[q]));
+                            zm2 = fmax(zm2, abs2(z[q]));
+                        }
+                        z[q] = x[q];
+                    }
+                    const double dmax = sqrt(wave_max(dm)), zmax = sqrt(wave_max(zm2));
+                    if (dmax <= a.nl_tol * fmax(1.0, zmax)) { conv = true; break; }
+                }
+                if (!conv) nl_fail = 1;
+                nl_worst = max(nl_worst, conv ? it : a.nl_maxit);
+#pragma unroll
+                for (int q = 0; q < P; ++q) vlast[q] = x[q];
+            } else {
+                lane_solve<P>(F, d, x);
+            }
+            // advance u_n = 2 v_n - u_{n-1}
 #pragma unroll
             for (int q = 0; q < P; ++q) u[q] = mk(2.0 * x[q].x - u[q].x, 2.0 * x[q].y - u[q].y);
+            if (ck && nstep < nt && ((nt - nstep) & (kWave - 1)) == 0) {
+                const int jj = (nt - nstep) / kWave;
+#pragma unroll
+                for (int q = 0; q < P; ++q) ck[((size_t)jj * P + q) * kWave] = u[q];
+            }
             const cd va = rdlane(x[0], 0);
             const cd vb = at_last(x);
             const cd rhoL = (2.0 * madd(hA, a.sigma, va)) - ln;
@@ -425,6 +366,10 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
         if (t == 0 && maxd > 0.0)
             atomicMax(a.maxdiff, (unsigned long long)__double_as_longlong(maxd));
     }
+    if (VK == VK_CUBIC && t == 0 && a.nl_stats) {
+        atomicMax(&a.nl_stats[0], nl_worst);
+        if (nl_fail) atomicMax(&a.nl_stats[1], 1);
+    }
 }
 
 // u(T) at the nodes shared by two subdomains: average of the two sides;
@@ -464,18 +409,32 @@ hipError_t launch_factor(const FactorArgs& a, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_sweep(const SweepArgs& a, int trans, hipStream_t st) {
+template <int P>
+static void launch_sweep_p(const SweepArgs& a, int trans, int vk, hipStream_t st) {
+    if (trans == TR_S02) {
+        if (vk == VK_TIME) sweep_kernel<P, TR_S02, VK_TIME><<<a.ntasks, 64, 0, st>>>(a);
+        else if (vk == VK_CUBIC) sweep_kernel<P, TR_S02, VK_CUBIC><<<a.ntasks, 64, 0, st>>>(a);
+        else sweep_kernel<P, TR_S02, VK_STATIC><<<a.ntasks, 64, 0, st>>>(a);
+    } else {
+        if (vk == VK_TIME) sweep_kernel<P, TR_ROBIN, VK_TIME><<<a.ntasks, 64, 0, st>>>(a);
+        else if (vk == VK_CUBIC) sweep_kernel<P, TR_ROBIN, VK_CUBIC><<<a.ntasks, 64, 0, st>>>(a);
+        else sweep_kernel<P, TR_ROBIN, VK_STATIC><<<a.ntasks, 64, 0, st>>>(a);
+    }
+}
+
+hipError_t launch_sweep(const SweepArgs& a, int trans, int vk, hipStream_t st) {
     if (a.ntasks == 0) return hipSuccess;
-#define CASE(PP)                                                                    \
-    case PP:                                                                        \
-        if (trans == TR_S02) sweep_kernel<PP, TR_S02><<<a.ntasks, 64, 0, st>>>(a);  \
-        else sweep_kernel<PP, TR_ROBIN><<<a.ntasks, 64, 0, st>>>(a);                \
-        break;
     switch (a.P) {
-        CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+        case 1: launch_sweep_p<1>(a, trans, vk, st); break;
+        case 2: launch_sweep_p<2>(a, trans, vk, st); break;
+        case 3: launch_sweep_p<3>(a, trans, vk, st); break;
+        case 4: launch_sweep_p<4>(a, trans, vk, st); break;
+        case 5: launch_sweep_p<5>(a, trans, vk, st); break;
+        case 6: launch_sweep_p<6>(a, trans, vk, st); break;
+        case 7: launch_sweep_p<7>(a, trans, vk, st); break;
+        case 8: launch_sweep_p<8>(a, trans, vk, st); break;
         default: return hipErrorInvalidValue;
     }
-#undef CASE
     return hipGetLastError();
 }
 

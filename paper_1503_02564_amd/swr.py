@@ -46,7 +46,7 @@ class SwrInfo(ctypes.Structure):
 # exported symbols of include/swr.h
 EXPORTS = ("swr_default_opts", "swr_strerror", "swr_setup", "swr_solve", "swr_grad",
            "swr_apply_R", "swr_build_interface", "swr_interface_matvec", "swr_destroy",
-           "swr_sizes")
+           "swr_sizes", "swr_set_potential")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
@@ -74,6 +74,8 @@ _L.swr_destroy.argtypes = [_P]
 _L.swr_destroy.restype = None
 _L.swr_sizes.argtypes = [_P] + [ctypes.POINTER(ctypes.c_int)] * 4
 _L.swr_sizes.restype = ctypes.c_int
+_L.swr_set_potential.argtypes = [_P, _P]
+_L.swr_set_potential.restype = ctypes.c_int
 
 
 class SwrError(RuntimeError):
@@ -159,6 +161,10 @@ def swr_build_interface(ctx, u0, cols=None, d=None):
 
 def swr_interface_matvec(ctx, x, y):
     _check(_L.swr_interface_matvec(ctx, _ptr(x), _ptr(y)), "swr_interface_matvec")
+
+
+def swr_set_potential(ctx, V):
+    _check(_L.swr_set_potential(ctx, _ptr(V)), "swr_set_potential")
 
 
 def swr_sizes(ctx):

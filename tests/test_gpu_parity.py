@@ -213,3 +213,170 @@ def test_full_size_config2_matches_monodomain(dev):
     assert info.residual < 1e-10
     assert rel(to_np(uT)[0], O.mono(wl, wl.u0[0])) < 1e-10
     pb.close()
+
+
+# ------------------------------------------------------------------ Sec. 5 --
+
+GENERAL_CASES = [
+    ("time-s02", [40, 63, 100, 31], 90, W.V_TIME, W.S02, 0j),
+    ("time-robin", [50, 70, 90], 70, W.V_TIME, W.ROBIN, 2 - 3j),
+    ("cubic-s02", [40, 63, 100, 31], 90, W.V_CUBIC, W.S02, 0j),
+    ("cubic-robin", [50, 70, 90], 70, W.V_CUBIC, W.ROBIN, 2 - 3j),
+]
+
+
+def _general(J, nt, vk, trans, sigma, seed=23):
+    wl = W.small_case(J=J, nt=nt, vkind=vk, trans=trans, sigma=sigma, seed=seed, a0=-12.0, b0=12.0)
+    if vk == W.V_CUBIC:
+        wl.u0 = 1.5 * wl.u0
+    return wl
+
+
+@pytest.mark.parametrize("label,J,nt,vk,trans,sigma", GENERAL_CASES)
+def test_general_potential_sweep_and_L0(dev, label, J, nt, vk, trans, sigma):
+    """One sweep with V(t,x) (refactorised every step) or |u|^2 (inner fixed
+    point every step) against the oracle, and the zero-potential operator L_0
+    used as preconditioner."""
+    import copy
+    import torch
+    from paper_1503_02564_amd import swr
+    wl = _general(J, nt, vk, trans, sigma)
+    say("general-sweep", label)
+    pb = make_problem(wl)
+    rng = np.random.default_rng(3)
+    g = 0.3 * (rng.standard_normal((pb.ns, nt)) + 1j * rng.standard_normal((pb.ns, nt)))
+    g_out = torch.zeros((1, pb.ns, nt), dtype=torch.complex128, device=dev)
+    swr.swr_apply_R(pb.ctx, to_dev(wl.u0), to_dev(g[None]), g_out)
+    torch.cuda.synchronize()
+    assert rel(to_np(g_out)[0], O.apply_R(wl, wl.u0[0], g)) < 1e-11
+    cols = torch.zeros((1, wl.N, 4, nt), dtype=torch.complex128, device=dev)
+    d = torch.zeros((1, pb.ns, nt), dtype=torch.complex128, device=dev)
+    swr.swr_build_interface(pb.ctx, to_dev(wl.u0), cols, d)
+    torch.cuda.synchronize()
+    w0 = copy.copy(wl)
+    w0.vkind, w0.V = W.V_STATIC, np.zeros(wl.nx)
+    assert rel(to_np(cols)[0], O.impulse_columns(w0)) < 1e-12
+    assert rel(to_np(d)[0], O.interface_d(wl, wl.u0[0])) < 1e-11
+    pb.close()
+
+
+@pytest.mark.parametrize("label,J,nt,vk,trans,sigma", GENERAL_CASES)
+@pytest.mark.parametrize("precond", [1, 0])
+def test_general_potential_solve_matches_monodomain(dev, label, J, nt, vk, trans, sigma, precond):
+    """Sec. 5: V(t,x) by right-preconditioned GMRES on (I - L) g = d with a
+    matrix-free L; |u|^2 by the preconditioned fixed point; P = I - L_0."""
+    import torch
+    from paper_1503_02564_amd import swr
+    wl = _general(J, nt, vk, trans, sigma)
+    say("general-solve", label, "precond" if precond else "plain")
+    pb = make_problem(wl, tol=1e-13, restart=60, max_iter=3000, precond=precond)
+    uT = torch.zeros((1, wl.nx), dtype=torch.complex128, device=dev)
+    st, info = swr.swr_solve(pb.ctx, to_dev(wl.u0), uT)
+    torch.cuda.synchronize()
+    say("general-solve", label, info.as_dict())
+    assert st == swr.SWR_OK
+    assert rel(to_np(uT)[0], O.mono(wl, wl.u0[0])) < 1e-10
+    if vk == W.V_CUBIC:
+        assert info.nl_worst >= 2
+    pb.close()
+
+
+# ------------------------------------------------------------------ adjoint --
+
+ADJ_CASES = [
+    ("s02-nt100", [40, 63, 100, 31], 100, W.S02, 0j),
+    ("s02-nt128", [50, 70, 90], 128, W.S02, 0j),
+    ("robin-nt70", [50, 70, 90], 70, W.ROBIN, 2 - 3j),
+]
+
+
+def _objective_data(wl, seed=9):
+    rng = np.random.default_rng(seed)
+    target = O.mono(wl, wl.u0[0], V=wl.V + 0.3 * rng.standard_normal(wl.nx))
+    return target
+
+
+@pytest.mark.parametrize("label,J,nt,trans,sigma", ADJ_CASES)
+def test_adjoint_matches_cpu_adjoint(dev, label, J, nt, trans, sigma):
+    """swr_grad (forward solve with checkpoints, adjoint interface solve,
+    replaying adjoint sweep) against the oracle's monodomain discrete adjoint
+    for J = sum |u(T) - u*|^2."""
+    import torch
+    from paper_1503_02564_amd import swr
+    wl = _case(J, nt, trans, sigma, seed=31)
+    target = _objective_data(wl)
+    uT = O.mono(wl, wl.u0[0])
+    gbar = 2 * (uT - target)
+    dV_ref, du0_ref = O.adjoint_mono(wl, wl.u0[0], gbar)
+    say("adjoint", label)
+    pb = make_problem(wl)
+    dV = torch.zeros((1, wl.nx), dtype=torch.float64, device=dev)
+    du0 = torch.zeros((1, wl.nx), dtype=torch.complex128, device=dev)
+    st, info = swr.swr_grad(pb.ctx, to_dev(wl.u0), to_dev(gbar[None]), dV, du0)
+    torch.cuda.synchronize()
+    say("adjoint", label, info.as_dict())
+    assert st == swr.SWR_OK and info.residual < 1e-11
+    assert rel(to_np(dV)[0], dV_ref) < 1e-10
+    assert rel(to_np(du0)[0], du0_ref) < 1e-10
+    pb.close()
+
+
+def test_adjoint_against_central_differences(dev):
+    """dJ/dV and dJ/du0 from swr_grad against central differences of the GPU
+    forward solve (h = 1e-6) along seeded random directions."""
+    import torch
+    from paper_1503_02564_amd import swr
+    wl = _case([40, 63, 100, 31], 100, W.S02, 0j, seed=37)
+    target = _objective_data(wl, seed=4)
+    say("adjoint-fd")
+    pb = make_problem(wl)
+    u0 = to_dev(wl.u0)
+    tgt = to_dev(target[None])
+
+    def J(V, u):
+        swr.swr_set_potential(pb.ctx, to_dev(V))
+        uT = torch.zeros_like(u)
+        swr.swr_solve(pb.ctx, u, uT)
+        return float((uT - tgt).abs().pow(2).sum())
+
+    swr.swr_set_potential(pb.ctx, to_dev(wl.V))
+    uT = torch.zeros_like(u0)
+    swr.swr_solve(pb.ctx, u0, uT)
+    gbar = 2 * (uT - tgt)
+    dV = torch.zeros((1, wl.nx), dtype=torch.float64, device=dev)
+    du0 = torch.zeros_like(u0)
+    swr.swr_grad(pb.ctx, u0, gbar, dV, du0)
+    dV, du0 = to_np(dV)[0], to_np(du0)[0]
+    rng = np.random.default_rng(21)
+    eps = 1e-6
+    for _ in range(4):
+        p = rng.standard_normal(wl.nx)
+        fd = (J(wl.V + eps * p, u0) - J(wl.V - eps * p, u0)) / (2 * eps)
+        assert abs(fd - np.dot(dV, p)) <= 1e-6 * max(abs(fd), 1e-3)
+        q = rng.standard_normal(wl.nx) + 1j * rng.standard_normal(wl.nx)
+        fd = (J(wl.V, u0 + eps * to_dev(q[None])) - J(wl.V, u0 - eps * to_dev(q[None]))) / (2 * eps)
+        assert abs(fd - np.real(np.vdot(du0, q))) <= 1e-6 * max(abs(fd), 1e-3)
+    pb.close()
+
+
+def test_autograd_function_per_problem_potentials(dev):
+    """torch.autograd through SWRFunction with one potential per problem."""
+    import torch
+    from paper_1503_02564_amd.autograd import SWRFunction
+    wl = W.small_case(J=[60, 80, 70], nt=90, B=3, seed=13, a0=-10, b0=10)
+    Vs = np.stack([wl.V, 0.5 * wl.V[::-1], 0.2 * wl.V])
+    wl2 = W.Workload("pp", wl.a0, wl.b0, wl.J, wl.dt, wl.nt, W.V_STATIC, Vs, W.S02, 0j, wl.u0)
+    targets = np.stack([O.mono(wl2, wl.u0[b], V=Vs[(b + 1) % 3]) for b in range(3)])
+    say("autograd", "per-problem V, B=3")
+    pb = make_problem(wl2, v_per_problem=True)
+    V = to_dev(Vs).requires_grad_(True)
+    u0 = to_dev(wl.u0).requires_grad_(True)
+    uT = SWRFunction.apply(V, u0, pb)
+    loss = (uT - to_dev(targets)).abs().pow(2).sum()
+    loss.backward()
+    for b in range(3):
+        uTb = O.mono(wl2, wl.u0[b], V=Vs[b])
+        dV_ref, du0_ref = O.adjoint_mono(wl2, wl.u0[b], 2 * (uTb - targets[b]), V=Vs[b])
+        assert rel(to_np(V.grad)[b], dV_ref) < 1e-10
+        assert rel(to_np(u0.grad)[b], du0_ref) < 1e-10
+    pb.close()
