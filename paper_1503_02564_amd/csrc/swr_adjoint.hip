@@ -179,11 +179,14 @@ __global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs a) {
                     uf[q] = mk(2.0 * x[q].x - uf[q].x, 2.0 * x[q].y - uf[q].y);
                     seg[((size_t)i * P + q) * kWave] = x[q];
                 }
-                if (TR == TR_S02 && t > i) {
+                if (TR == TR_S02) {
+                    // boundary values by cross-lane reads: every lane must take part
                     const cd va = rdlane(x[0], 0), vb = at_last(x);
-                    const double bt = sbeta[t - i];
-                    fa = fa + bt * va;
-                    fb = fb + bt * vb;
+                    if (t > i) {
+                        const double bt = sbeta[t - i];
+                        fa = fa + bt * va;
+                        fb = fb + bt * vb;
+                    }
                 }
             }
         }

@@ -121,11 +121,13 @@ struct FarArgs {
 };
 
 // one workgroup per (slot, problem); thread (i, split): output step n0+i,
-// inputs s in the split's share of [0, n0)
+// inputs s in the split's share of [0, n0).  out = d + that contribution.
+template <int TB>
 __global__ __launch_bounds__(256) void causal_far_kernel(FarArgs f) {
-    __shared__ cd part[8][kTb];
+    constexpr int SPLITS = 256 / TB;
+    __shared__ cd part[SPLITS][TB];
     const int o = blockIdx.x, b = blockIdx.y;
-    const int i = threadIdx.x & (kTb - 1), sp = threadIdx.x >> 5;
+    const int i = threadIdx.x % TB, sp = threadIdx.x / TB;
     int k, pl, pr, sl, sr;
     slot_src(o, f.N, k, pl, pr, sl, sr);
     const int v = f.per_problem ? b : 0;
@@ -134,7 +136,7 @@ __global__ __launch_bounds__(256) void causal_far_kernel(FarArgs f) {
     const cd* gl = sl >= 0 ? f.g + ((size_t)b * f.ns + sl) * f.nt : nullptr;
     const cd* gr = sr >= 0 ? f.g + ((size_t)b * f.ns + sr) * f.nt : nullptr;
     const int n = f.n0 + i;
-    const int per = (f.n0 + 7) / 8;
+    const int per = (f.n0 + SPLITS - 1) / SPLITS;
     const int s_lo = sp * per, s_hi = min(f.n0, s_lo + per);
     double ax = 0, ay = 0;
     if (i < f.nb) {
@@ -155,8 +157,8 @@ __global__ __launch_bounds__(256) void causal_far_kernel(FarArgs f) {
     __syncthreads();
     if (sp == 0 && i < f.nb) {
         cd r = f.d[((size_t)b * f.ns + o) * f.nt + n];
-        for (int q = 0; q < 8; ++q) r = r + part[q][i];
-        f.out[((size_t)b * f.ns + o) * kTb + i] = r;
+        for (int q = 0; q < SPLITS; ++q) r = r + part[q][i];
+        f.out[((size_t)b * f.ns + o) * TB + i] = r;
     }
 }
 
@@ -273,10 +275,11 @@ hipError_t launch_causal_pcr_setup(int N, int nt, int nv, const cd* cols, cd* pc
     return hipGetLastError();
 }
 
-hipError_t launch_causal_far(int N, int nt, int ns, int B, int per_problem, int n0, int nb,
-                             const cd* cols, const cd* d, const cd* g, cd* out, hipStream_t st) {
+template <int TB>
+static hipError_t launch_causal_far(int N, int nt, int ns, int B, int per_problem, int n0, int nb,
+                                    const cd* cols, const cd* d, const cd* g, cd* out, hipStream_t st) {
     FarArgs f{N, nt, ns, per_problem, n0, nb, cols, d, g, out};
-    causal_far_kernel<<<dim3(ns, B), 256, 0, st>>>(f);
+    causal_far_kernel<TB><<<dim3(ns, B), 256, 0, st>>>(f);
     return hipGetLastError();
 }
 
@@ -293,9 +296,203 @@ hipError_t launch_causal_fast(int N, int nt, int ns, int B, int per_problem, con
                               const cd* pcr, const cd* d, cd* base, cd* g, hipStream_t st) {
     for (int n0 = 0; n0 < nt; n0 += kTb) {
         const int nb = min(kTb, nt - n0);
-        hipError_t e = launch_causal_far(N, nt, ns, B, per_problem, n0, nb, cols, d, g, base, st);
+        hipError_t e = launch_causal_far<kTb>(N, nt, ns, B, per_problem, n0, nb, cols, d, g, base, st);
         if (e != hipSuccess) return e;
         e = launch_causal_near(N, nt, ns, B, per_problem, n0, nb, cols, pcr, base, g, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// General path: up to kGenMaxIf interfaces.  Same algebra as above with the
+// block PCR spread over the workgroup (one thread per interface, exchange
+// through LDS) and a short near block of kGenTb steps.
+// ---------------------------------------------------------------------------
+constexpr int kGenThreads = 512;
+
+__device__ inline int pcr_levels(int ni) {
+    int l = 0;
+    while ((1 << l) < ni) ++l;
+    return l;
+}
+
+// multipliers [nv][levels][8][ni] then D^{-1} [nv][4][ni] (after the levels)
+__global__ __launch_bounds__(kGenThreads) void causal_pcr_setup_gen_kernel(int N, int nt, const cd* cols,
+                                                                          cd* pcr, int rec, double* eta) {
+    __shared__ C2x2 sD[kGenMaxIf], sL[kGenMaxIf], sU[kGenMaxIf];
+    __shared__ double se[kGenThreads / kWave];
+    const int v = blockIdx.x, j = threadIdx.x;
+    const int ni = N - 1, lv = pcr_levels(ni);
+    const cd* base = cols + (size_t)v * N * 4 * nt;
+    auto col0 = [&](int k, int p) { return base[((size_t)k * 4 + p) * nt]; };
+    const cd zero = mk(0, 0), one = mk(1, 0);
+    const C2x2 I = m2(one, zero, zero, one), Z = m2(zero, zero, zero, zero);
+    C2x2 D = I, Lm = Z, U = Z;
+    if (j < ni) {
+        const cd x1 = col0(j + 1, 0);
+        const cd x2 = (j + 1 <= N - 2) ? col0(j + 1, 1) : zero;
+        const cd x3 = (j >= 1) ? col0(j, 2) : zero;
+        const cd x4 = col0(j, 3);
+        D = m2(one, -x1, -x4, one);
+        U = m2(-x2, zero, zero, zero);
+        Lm = m2(zero, zero, zero, -x3);
+    }
+    double e = (j < ni) ? norm_inf(inv2(D)) * (norm_inf(Lm) + norm_inf(U)) : 0.0;
+    e = wave_max(e);
+    if ((j & (kWave - 1)) == 0) se[j / kWave] = e;
+    __syncthreads();
+    if (j == 0) {
+        double m = 0;
+        for (int w = 0; w < kGenThreads / kWave; ++w) m = fmax(m, se[w]);
+        eta[v] = m;
+    }
+    cd* rec_v = pcr + (size_t)v * rec;
+#pragma unroll 1
+    for (int l = 0; l < lv; ++l) {
+        const int d = 1 << l;
+        if (j < ni) { sD[j] = D; sL[j] = Lm; sU[j] = U; }
+        __syncthreads();
+        C2x2 K1 = Z, K2 = Z;
+        if (j < ni) {
+            const bool hm = j - d >= 0, hp = j + d < ni;
+            const C2x2 Dm = hm ? sD[j - d] : I, Lmm = hm ? sL[j - d] : Z, Um = hm ? sU[j - d] : Z;
+            const C2x2 Dp = hp ? sD[j + d] : I, Lp = hp ? sL[j + d] : Z, Up = hp ? sU[j + d] : Z;
+            K1 = hm ? Lm * inv2(Dm) : Z;
+            K2 = hp ? U * inv2(Dp) : Z;
+            const C2x2 Dn = D - K1 * Um - K2 * Lp;
+            const C2x2 Ln = neg(K1 * Lmm), Un = neg(K2 * Up);
+            D = Dn;
+            Lm = Ln;
+            U = Un;
+            cd* r = rec_v + (size_t)l * 8 * ni + j;
+            r[0 * ni] = K1.a; r[1 * ni] = K1.b; r[2 * ni] = K1.c; r[3 * ni] = K1.d;
+            r[4 * ni] = K2.a; r[5 * ni] = K2.b; r[6 * ni] = K2.c; r[7 * ni] = K2.d;
+        }
+        __syncthreads();
+    }
+    if (j < ni) {
+        const C2x2 Di = inv2(D);
+        cd* r = rec_v + (size_t)lv * 8 * ni + j;
+        r[0 * ni] = Di.a; r[1 * ni] = Di.b; r[2 * ni] = Di.c; r[3 * ni] = Di.d;
+    }
+}
+
+struct NearGenArgs {
+    int N, nt, ns, per_problem;
+    int n0, nb, rec;
+    const cd* cols;
+    const cd* pcr;     // [nv][rec]
+    const cd* base;    // [B][ns][kGenTb]: d + far part
+    cd* g;             // [B][ns][nt]
+};
+
+// one workgroup per problem; per step: gather the in-block history of every
+// slot (coefficients of lags 1..kGenTb-1 in registers), then block PCR
+__global__ __launch_bounds__(kGenThreads) void causal_near_gen_kernel(NearGenArgs a) {
+    extern __shared__ cd smem[];
+    const int ns = a.ns, nt = a.nt, n0 = a.n0, nb = a.nb, ni = a.N - 1;
+    cd* gh = smem;                          // [kGenTb][ns]
+    cd* rhs = gh + (size_t)kGenTb * ns;     // [ns]
+    cd* ex = rhs + ns;                      // [ni][2] PCR exchange
+    const int b = blockIdx.x, v = a.per_problem ? b : 0;
+    const int tid = threadIdx.x;
+    const int lv = pcr_levels(ni);
+    const cd zero = mk(0, 0);
+    cd* gb = a.g + (size_t)b * ns * nt;
+    const cd* bb = a.base + (size_t)b * ns * kGenTb;
+    const cd* rec = a.pcr + (size_t)v * a.rec;
+    // slots handled by this thread: o0 = tid, o1 = tid + kGenThreads
+    int sl[2], sr[2];
+    cd cl[2][kGenTb - 1], cr[2][kGenTb - 1];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int o = tid + h * kGenThreads;
+        sl[h] = sr[h] = -1;
+#pragma unroll
+        for (int m = 0; m < kGenTb - 1; ++m) { cl[h][m] = zero; cr[h][m] = zero; }
+        if (o < ns) {
+            int k, pl, pr;
+            slot_src(o, a.N, k, pl, pr, sl[h], sr[h]);
+            const cd* base = a.cols + (size_t)(v * a.N + k) * 4 * nt;
+#pragma unroll
+            for (int m = 0; m < kGenTb - 1; ++m) {
+                const int lag = m + 1;
+                if (lag < nt) {
+                    if (sl[h] >= 0) cl[h][m] = base[(size_t)pl * nt + lag];
+                    if (sr[h] >= 0) cr[h][m] = base[(size_t)pr * nt + lag];
+                }
+            }
+        }
+    }
+    for (int i = 0; i < nb; ++i) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int o = tid + h * kGenThreads;
+            if (o < ns) {
+                cd r = bb[(size_t)o * kGenTb + i];
+#pragma unroll
+                for (int m = 0; m < kGenTb - 1; ++m) {
+                    const int lag = m + 1;
+                    if (lag <= i) {
+                        if (sl[h] >= 0) r = madd(r, cl[h][m], gh[(size_t)(i - lag) * ns + sl[h]]);
+                        if (sr[h] >= 0) r = madd(r, cr[h][m], gh[(size_t)(i - lag) * ns + sr[h]]);
+                    }
+                }
+                rhs[o] = r;
+            }
+        }
+        __syncthreads();
+        // block PCR, one thread per interface
+        const int j = tid;
+        cd p0 = zero, p1 = zero;
+        if (j < ni) { p0 = rhs[2 * j]; p1 = rhs[2 * j + 1]; }
+        for (int l = 0; l < lv; ++l) {
+            const int d = 1 << l;
+            if (j < ni) { ex[2 * j] = p0; ex[2 * j + 1] = p1; }
+            __syncthreads();
+            if (j < ni) {
+                const bool hm = j - d >= 0, hp = j + d < ni;
+                const cd q0m = hm ? ex[2 * (j - d)] : zero, q1m = hm ? ex[2 * (j - d) + 1] : zero;
+                const cd q0p = hp ? ex[2 * (j + d)] : zero, q1p = hp ? ex[2 * (j + d) + 1] : zero;
+                const cd* K = rec + (size_t)l * 8 * ni + j;
+                p0 = msub(msub(msub(msub(p0, K[0 * ni], q0m), K[1 * ni], q1m), K[4 * ni], q0p), K[5 * ni], q1p);
+                p1 = msub(msub(msub(msub(p1, K[2 * ni], q0m), K[3 * ni], q1m), K[6 * ni], q0p), K[7 * ni], q1p);
+            }
+            __syncthreads();
+        }
+        if (j < ni) {
+            const cd* Di = rec + (size_t)lv * 8 * ni + j;
+            const cd x0 = madd(Di[0] * p0, Di[1 * ni], p1);
+            const cd x1 = madd(Di[2 * ni] * p0, Di[3 * ni], p1);
+            gh[(size_t)i * ns + 2 * j] = x0;
+            gh[(size_t)i * ns + 2 * j + 1] = x1;
+            gb[(size_t)(2 * j) * nt + n0 + i] = x0;
+            gb[(size_t)(2 * j + 1) * nt + n0 + i] = x1;
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_causal_pcr_setup_gen(int N, int nt, int nv, const cd* cols, cd* pcr, double* eta,
+                                       hipStream_t st) {
+    if (N - 1 > kGenMaxIf) return hipErrorInvalidValue;
+    causal_pcr_setup_gen_kernel<<<nv, kGenThreads, 0, st>>>(N, nt, cols, pcr, pcr_rec_gen(N), eta);
+    return hipGetLastError();
+}
+
+hipError_t launch_causal_gen(int N, int nt, int ns, int B, int per_problem, const cd* cols,
+                             const cd* pcr, const cd* d, cd* base, cd* g, hipStream_t st) {
+    const size_t shm = ((size_t)kGenTb * ns + ns + 2 * (size_t)(N - 1)) * sizeof(cd);
+    if (N - 1 > kGenMaxIf || N - 1 > kGenThreads || ns > 2 * kGenThreads || shm > 160 * 1024)
+        return hipErrorInvalidValue;
+    for (int n0 = 0; n0 < nt; n0 += kGenTb) {
+        const int nb = min(kGenTb, nt - n0);
+        hipError_t e = launch_causal_far<kGenTb>(N, nt, ns, B, per_problem, n0, nb, cols, d, g, base, st);
+        if (e != hipSuccess) return e;
+        NearGenArgs na{N, nt, ns, per_problem, n0, nb, pcr_rec_gen(N), cols, pcr, base, g};
+        causal_near_gen_kernel<<<B, kGenThreads, shm, st>>>(na);
+        e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

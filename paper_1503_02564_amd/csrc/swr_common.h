@@ -204,6 +204,17 @@ hipError_t launch_causal_pcr_setup(int N, int nt, int nv, const cd* cols, cd* pc
                                    hipStream_t st);
 hipError_t launch_causal_fast(int N, int nt, int ns, int B, int per_problem, const cd* cols,
                               const cd* pcr, const cd* d, cd* base, cd* g, hipStream_t st);
+// general block-PCR causal solve for up to kGenMaxIf interfaces
+constexpr int kGenTb = 8;
+constexpr int kGenMaxIf = 512;
+__host__ __device__ constexpr int pcr_rec_gen(int N) {
+    // complex entries per potential: levels * 8 * ni + 4 * ni
+    return (N - 1) * 8 * (N - 1 <= 1 ? 0 : (32 - __builtin_clz((unsigned)(N - 2)))) + 4 * (N - 1);
+}
+hipError_t launch_causal_pcr_setup_gen(int N, int nt, int nv, const cd* cols, cd* pcr, double* eta,
+                                       hipStream_t st);
+hipError_t launch_causal_gen(int N, int nt, int ns, int B, int per_problem, const cd* cols,
+                             const cd* pcr, const cd* d, cd* base, cd* g, hipStream_t st);
 struct AdjArgs {
     int N, nt, B, nx, ns, ntasks, P, Jc;
     double kappa, h;

@@ -35,8 +35,10 @@ struct Iface {
     int ntasks = 0;
     int nv = 1;
     bool dirty = true;      // columns rebuilt since the causal setup
-    int path = 0;           // causal solver: 1 = block PCR, 2 = dense inverse
+    int path = 0;           // causal solver: 1 = one-wave block PCR, 2 = workgroup block
+                            // PCR, 3 = dense inverse
     cd* pcr = nullptr;
+    size_t pcr_size = 0;
     double* eta = nullptr;
     cd* Minv = nullptr;
     cd* Mwork = nullptr;
@@ -89,6 +91,7 @@ struct swr_ctx {
     int* dAct = nullptr;
     cd* dFar = nullptr;       // causal dense path
     cd* dBase = nullptr;      // causal PCR path
+    int base_tb = 0;
     // adjoint
     int Jc = 0;
     cd* dCkpt = nullptr;
@@ -489,28 +492,35 @@ static swr_status run_gmres(swr_ctx* c, const Op& A, const cd* rhs, cd* x, int* 
 }
 
 // causal forward substitution in time for (I - L) g = d with the operator I
-// (exact up to rounding).  Block PCR per step when it applies (N - 1 <= 64,
-// ns <= 128) and the block system is certified diagonally dominant;
-// otherwise a dense (I - C_0)^{-1} by Gauss-Jordan with partial pivoting.
+// (exact up to rounding).  Block PCR per step when the block system is
+// certified diagonally dominant: on one wave for N - 1 <= 64 interfaces, on
+// a workgroup up to kGenMaxIf; otherwise a dense (I - C_0)^{-1} by
+// Gauss-Jordan with partial pivoting.
 static swr_status run_causal(swr_ctx* c, Iface& I, const cd* d, cd* g) {
-    const int ns = c->ns, nt = c->nt, B = c->B;
+    const int ns = c->ns, nt = c->nt, B = c->B, ni = c->N - 1;
     hipStream_t st = c->st;
+    const bool fast_ok = ns <= kNearSlots && ni <= kWave;
+    const size_t gen_shm = ((size_t)kGenTb * ns + ns + 2 * (size_t)ni) * sizeof(cd);
+    const bool gen_ok = ni <= kGenMaxIf && gen_shm <= 160 * 1024;
     if (I.dirty) {
-        I.path = 2;
-        if (ns <= kNearSlots && c->N - 1 <= kWave) {
-            if (!I.pcr) {
-                ALLOC_LIVE(I.pcr, (size_t)I.nv * kPcrRec * kWave);
-                ALLOC_LIVE(I.eta, I.nv);
+        I.path = 3;
+        if (fast_ok || gen_ok) {
+            const size_t rec = fast_ok ? (size_t)kPcrRec * kWave : (size_t)pcr_rec_gen(c->N);
+            if (!I.pcr || I.pcr_size < rec * I.nv) {
+                ALLOC_LIVE(I.pcr, rec * I.nv);
+                I.pcr_size = rec * I.nv;
             }
-            HIPCHK(launch_causal_pcr_setup(c->N, nt, I.nv, I.cols, I.pcr, I.eta, st));
+            if (!I.eta) ALLOC_LIVE(I.eta, I.nv);
+            if (fast_ok) HIPCHK(launch_causal_pcr_setup(c->N, nt, I.nv, I.cols, I.pcr, I.eta, st));
+            else HIPCHK(launch_causal_pcr_setup_gen(c->N, nt, I.nv, I.cols, I.pcr, I.eta, st));
             std::vector<double> eta(I.nv);
             HIPCHK(hipMemcpyAsync(eta.data(), I.eta, sizeof(double) * I.nv, hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
             bool ok = true;
             for (double e : eta) ok = ok && std::isfinite(e) && e < 1.0;
-            if (ok) I.path = 1;
+            if (ok) I.path = fast_ok ? 1 : 2;
         }
-        if (I.path == 2) {
+        if (I.path == 3) {
             if (!I.Minv) {
                 ALLOC_LIVE(I.Minv, (size_t)I.nv * ns * ns);
                 ALLOC_LIVE(I.Mwork, (size_t)I.nv * ns * ns);
@@ -520,9 +530,16 @@ static swr_status run_causal(swr_ctx* c, Iface& I, const cd* d, cd* g) {
         }
         I.dirty = false;
     }
-    if (I.path == 1) {
-        if (!c->dBase) ALLOC_LIVE(c->dBase, (size_t)B * ns * kNearTb);
-        HIPCHK(launch_causal_fast(c->N, nt, ns, B, I.nv > 1, I.cols, I.pcr, d, c->dBase, g, st));
+    if (I.path == 1 || I.path == 2) {
+        const int tb = I.path == 1 ? kNearTb : kGenTb;
+        if (!c->dBase || c->base_tb < tb) {
+            ALLOC_LIVE(c->dBase, (size_t)B * ns * tb);
+            c->base_tb = tb;
+        }
+        if (I.path == 1)
+            HIPCHK(launch_causal_fast(c->N, nt, ns, B, I.nv > 1, I.cols, I.pcr, d, c->dBase, g, st));
+        else
+            HIPCHK(launch_causal_gen(c->N, nt, ns, B, I.nv > 1, I.cols, I.pcr, d, c->dBase, g, st));
         return SWR_OK;
     }
     if (!c->dFar) ALLOC_LIVE(c->dFar, (size_t)B * ns * kCausalTb);

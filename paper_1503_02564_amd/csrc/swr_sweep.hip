@@ -266,8 +266,12 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
 #pragma unroll
                     for (int q = 0; q < P; ++q) Fz[q] = abs2(z[q]);
                     const cd zL = shfl_up_c(z[P - 1], 1, zero), zR = shfl_dn_c(z[0], 1, zero);
-                    const double FL = t > 0 ? __shfl(Fz[P - 1], t - 1) : 0.0;
-                    const double FR = t < kWave - 1 ? __shfl(Fz[0], t + 1) : 0.0;
+                    // neighbours' |zeta|^2: the shuffles run on every lane
+                    // (a lane left out of a permute hands zero to its reader)
+                    const double FLs = __shfl(Fz[P - 1], t > 0 ? t - 1 : 0);
+                    const double FRs = __shfl(Fz[0], t < kWave - 1 ? t + 1 : kWave - 1);
+                    const double FL = t > 0 ? FLs : 0.0;
+                    const double FR = t < kWave - 1 ? FRs : 0.0;
                     cd r[P];
 #pragma unroll
                     for (int q = 0; q < P; ++q) {

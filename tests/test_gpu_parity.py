@@ -260,8 +260,8 @@ def test_general_potential_sweep_and_L0(dev, label, J, nt, vk, trans, sigma):
     pb.close()
 
 
-@pytest.mark.parametrize("label,J,nt,vk,trans,sigma", GENERAL_CASES)
-@pytest.mark.parametrize("precond", [1, 0])
+@pytest.mark.parametrize("label,J,nt,vk,trans,sigma,precond",
+                         [c + (1,) for c in GENERAL_CASES] + [c + (0,) for c in GENERAL_CASES[:3]])
 def test_general_potential_solve_matches_monodomain(dev, label, J, nt, vk, trans, sigma, precond):
     """Sec. 5: V(t,x) by right-preconditioned GMRES on (I - L) g = d with a
     matrix-free L; |u|^2 by the preconditioned fixed point; P = I - L_0."""
@@ -379,4 +379,21 @@ def test_autograd_function_per_problem_potentials(dev):
         dV_ref, du0_ref = O.adjoint_mono(wl2, wl.u0[b], 2 * (uTb - targets[b]), V=Vs[b])
         assert rel(to_np(V.grad)[b], dV_ref) < 1e-10
         assert rel(to_np(u0.grad)[b], du0_ref) < 1e-10
+    pb.close()
+
+
+def test_unpreconditioned_cubic_robin_diverges_and_reports_it(dev):
+    """Without P the |u|^2 fixed point with Robin s = 2-3i blows up (the
+    oracle's inner iteration fails on the same case); the library must report
+    it (SWR_ENAN / SWR_ENOCONV), not return garbage as a result."""
+    from paper_1503_02564_amd import swr
+    import torch
+    label, J, nt, vk, trans, sigma = GENERAL_CASES[3]
+    wl = _general(J, nt, vk, trans, sigma)
+    say("general-solve", label, "plain, expected to fail")
+    pb = make_problem(wl, tol=1e-13, max_iter=300, precond=0)
+    uT = torch.zeros((1, wl.nx), dtype=torch.complex128, device=dev)
+    with pytest.raises(swr.SwrError) as ei:
+        swr.swr_solve(pb.ctx, to_dev(wl.u0), uT)
+    assert ei.value.status in (swr.SWR_ENAN, swr.SWR_ENOCONV)
     pb.close()
