@@ -8,9 +8,18 @@ full solve of the paper's new algorithm (Sec. 4): assembly + factorisation,
 all impulse sweeps and the d sweep in one launch, the interface solve and the
 final sweep -> u(T).  Inputs are resident in HBM before the timed region.
 
+Second figure of the metric: the adjoint/forward cost ratio on the
+differentiation workload ((-40,40), 256 subdomains of 64 cells, 2000 steps,
+16 seeded potentials, one per problem, J = ||u(T) - u*||^2 with u* from a
+seeded reference potential): T(swr_grad) - T(swr_solve) over T(swr_solve),
+both to interface residual 1e-10.
+
 Output: one JSON line (see the keys below).  The roofline object describes the
 dominant kernel (the subdomain sweep); the cpu_baseline object times the CPU
 oracle on the host on the same workload.
+
+``--calibrate-copy MIB`` only runs a plain device-to-device copy of MIB MiB
+five times (the reference kernel that scales the HBM byte counters).
 """
 from __future__ import annotations
 
@@ -50,18 +59,100 @@ def cpu_baseline(wl, budget_s=30.0):
         threadpool_limits = None
     import oracle as O
     ctx = threadpool_limits(limits=1) if threadpool_limits else None
-    t0 = time.perf_counter()
+    runs, t_all = 0, 0.0
     try:
-        uT, g, info = O.new_algorithm(wl, wl.u0[0], solver="causal")
+        while runs == 0 or t_all < 0.5 * budget_s:
+            t0 = time.perf_counter()
+            uT, g, info = O.new_algorithm(wl, wl.u0[0], solver="causal")
+            t_all += time.perf_counter() - t0
+            runs += 1
     finally:
         if ctx is not None:
             ctx.unregister() if hasattr(ctx, "unregister") else None
-    dt = time.perf_counter() - t0
+    dt = t_all / runs
     pts = wl.nx * wl.nt
     return dict(value=pts / dt, unit="pt-steps/s", cores=1, kind="oracle",
-                sample=f"one full solve of the same workload by the oracle "
-                       f"(impulse columns, d, causal interface solve, final sweep), "
-                       f"{dt:.2f} s single-threaded", residual=float(info["residual"])), uT
+                sample=f"{runs} full solve(s) of the same workload (batch member 0) by the "
+                       f"oracle (impulse columns, d, causal interface solve, final sweep), "
+                       f"{dt:.2f} s each, single-threaded", residual=float(info["residual"])), uT
+
+
+def adjoint_ratio(steps, warmup):
+    """Adjoint/forward cost ratio on the differentiation workload (16
+    potentials, one per problem, 256 subdomains).  Forward = swr_solve;
+    backward = swr_grad minus the forward it contains (swr_grad re-runs the
+    forward with checkpoints).  Wall clock around synchronised calls."""
+    import torch
+    from paper_1503_02564_amd import swr
+    from paper_1503_02564_amd import workloads as W
+    wl = W.config5()
+    dev = torch.device("cuda:0")
+
+    def opts(B, per_problem):
+        o = swr.swr_default_opts()
+        o.tol = wl.tol
+        o.batch = B
+        o.v_per_problem = int(per_problem)
+        o.checkpoint_K = 64
+        return o
+
+    J = tuple(int(j) for j in wl.J)
+    T = wl.dt * wl.nt
+    u0 = torch.from_numpy(np.ascontiguousarray(wl.u0)).to(dev)
+    # target state from the reference potential (outside the timed region)
+    Vr = torch.from_numpy(np.ascontiguousarray(wl.extras["V_ref"])).to(dev)
+    ref = swr.Problem(wl.a0, wl.b0, J, wl.dt, T, wl.vkind, wl.trans, wl.sigma, opts(1, False), Vr)
+    u_star = torch.zeros_like(u0[:1])
+    swr.swr_solve(ref.ctx, u0[:1].contiguous(), u_star)
+    ref.close()
+    V = torch.from_numpy(np.ascontiguousarray(wl.V)).to(dev)
+    pb = swr.Problem(wl.a0, wl.b0, J, wl.dt, T, wl.vkind, wl.trans, wl.sigma, opts(wl.B, True), V)
+    uT = torch.zeros_like(u0)
+    swr.swr_solve(pb.ctx, u0, uT)
+    gbar = (2.0 * (uT - u_star)).contiguous()
+    dV = torch.zeros_like(V)
+    du0 = torch.zeros_like(u0)
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = [fn() for _ in range(steps)]
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t0) / steps, out
+
+    t_fwd, fi = timed(lambda: swr.swr_solve(pb.ctx, u0, uT)[1].as_dict())
+    t_grad, gi = timed(lambda: swr.swr_grad(pb.ctx, u0, gbar, dV, du0)[1].as_dict())
+    ph = {k: float(np.mean([i[k] for i in gi])) for k in
+          ("t_factor_ms", "t_build_ms", "t_iface_ms", "t_final_ms")}
+    bwd_events = ph["t_build_ms"] + ph["t_iface_ms"] + ph["t_final_ms"]
+    res = dict(
+        workload="(-40,40), 256 x 64 cells, 2000 steps dt=5e-4, S0^2, 16 seeded potentials "
+                 "(one per problem), J = ||u(T)-u*||^2, checkpoints every 64 steps",
+        fwd_ms=t_fwd, grad_ms=t_grad,
+        ratio_bwd_over_fwd=(t_grad - t_fwd) / t_fwd,
+        ratio_fwd_plus_bwd_over_fwd=t_grad / t_fwd,
+        ratio_events_bwd_over_fwd=bwd_events / ph["t_factor_ms"],
+        grad_phases_ms=ph,
+        fwd_residual=max(i["residual"] for i in fi),
+        adj_residual=max(i["residual"] for i in gi),
+        fwd_pt_steps_per_s=wl.pt_steps() / (1e-3 * t_fwd))
+    pb.close()
+    return res
+
+
+def calibrate_copy(mib):
+    """A plain copy of a known size, for scaling the HBM byte counters."""
+    import torch
+    n = int(mib) * (1 << 20) // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibrate_copy_bytes_read": 8 * n, "calibrate_copy_bytes_written": 8 * n,
+                      "launches": 5}))
 
 
 def main():
@@ -72,12 +163,19 @@ def main():
     ap.add_argument("--solver", default="causal", choices=["causal", "gmres", "fixed"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
     ap.add_argument("--workload", default="config2", choices=["config2"])
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the adjoint/forward ratio on the differentiation workload")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain MIB-MiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a "
-                                   "design (see DESIGN.md), not a measured path",
-                          "n_gpus": args.gpus}))
+        print(json.dumps({"error": "only --gpus 1 is supported: the solver runs on one GPU "
+                                   "and has no multi-GPU sharding", "n_gpus": args.gpus}))
         sys.exit(2)
+
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
 
     import torch
     from paper_1503_02564_amd import swr
@@ -126,6 +224,10 @@ def main():
             "avg_launch_ms": 0.5 * (ph["t_build_ms"] + ph["t_final_ms"]),
             "flops_per_pt_step": fpp}
 
+    adj = None
+    if not args.no_adjoint:
+        adj = adjoint_ratio(max(1, min(args.steps, 5)), 1)
+
     cpu = None
     if not args.no_cpu:
         cpu, u_cpu = cpu_baseline(wl)
@@ -133,7 +235,7 @@ def main():
         cpu["max_rel_diff_gpu_vs_oracle"] = float(np.max(np.abs(got - u_cpu)) / np.max(np.abs(u_cpu)))
 
     out = {
-        "metric": "grid-point*time-steps/s to interface residual 1e-10",
+        "metric": "grid-point*time-steps/s to interface residual 1e-10; adjoint/forward cost ratio",
         "value": value, "unit": "pt-steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
@@ -142,6 +244,8 @@ def main():
                                f"{args.solver} interface solve",
                    "nx": wl.nx, "nt": wl.nt, "N": wl.N, "B": wl.B, "solver": args.solver},
         "interface_residual": resid, "phases_ms": ph,
+        "adjoint_forward_cost_ratio": None if adj is None else adj["ratio_bwd_over_fwd"],
+        "adjoint": adj,
         "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -173,6 +173,9 @@ constexpr int kRedThreads = 256;
 // launchers (swr_sweep.hip)
 hipError_t launch_factor(const FactorArgs& a, hipStream_t st);
 hipError_t launch_sweep(const SweepArgs& a, int trans, int vk, hipStream_t st);
+hipError_t launch_sweep_static(const SweepArgs& a, int trans, hipStream_t st);
+hipError_t launch_sweep_time(const SweepArgs& a, int trans, hipStream_t st);
+hipError_t launch_sweep_cubic(const SweepArgs& a, int trans, hipStream_t st);
 hipError_t launch_finalize_ut(int N, int nx, int B, const int* off, const cd* ends, cd* uT,
                               hipStream_t st);
 hipError_t launch_beta(int n, double* beta, hipStream_t st);

@@ -1,0 +1,331 @@
+// swr_sweep_kernel.h -- the subdomain sweep kernel template (see the
+// description at the top of swr_sweep.hip).  Included by the three
+// translation units that instantiate it for one potential kind each, so
+// the 48 instantiations compile in parallel.
+#pragma once
+#include "swr_lane.h"
+
+namespace swr {
+
+// ---------------------------------------------------------------------------
+// The sweep.  VK selects the potential: static (factors loaded once), time
+// dependent (rows rebuilt and refactored every step from the streamed V rows)
+// or |u|^2 (V-free factors, inner fixed point of eq. AvMNL every step).
+// ---------------------------------------------------------------------------
+template <int P, int TR, int VK>
+__global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
+    using L = FacLayout<P>;
+    __shared__ double sbeta[kWave + 1];
+    __shared__ cd sha[kWave], shb[kWave];     // staged chunk of the boundary history
+    __shared__ double sb[2 * kWave];          // beta window of that chunk
+    const Task task = a.tasks[blockIdx.x];
+    const int k = task.k, b = task.b, f = task.f;
+    const int fl = (task.flags & a.flags_and) | a.flags_or;
+    const int t = threadIdx.x;
+    const int n = a.J[k] + 1, o = a.off[k];
+    const int nt = a.nt;
+    const bool lif = k > 0, rif = k < a.N - 1;
+    const int s = t * P;
+    const int lastl = (n - 1) / P;          // lane holding node n-1
+    const cd zero = mk(0, 0);
+
+    if (TR == TR_S02) {
+        sbeta[t] = a.beta[t];
+        if (t == 0) sbeta[kWave] = a.beta[kWave];
+        __syncthreads();
+    }
+
+    LaneFac<P> F;
+    // time-dependent potential: rows n and n+1 of V at my nodes
+    double vprev[P], vnext[P];
+    const double* Vt = (VK == VK_TIME) ? a.Vt + o : nullptr;
+    if (VK == VK_TIME) {
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            vprev[q] = (s + q < n) ? Vt[s + q] : 0.0;
+            vnext[q] = (s + q < n) ? Vt[(size_t)a.nx + s + q] : 0.0;
+        }
+    } else {
+        load_fac<P>(a.fac + (size_t)f * L::total * kWave + t, F);
+    }
+
+    // per-node constants: mass stencil weights (P1 mass: 1,4,1 inside,
+    // 2,1 / 1,2 at the ends, zero on padding) and the mask of node n-1
+    double wl[P], wr[P], wlast[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        const int i = s + q;
+        wl[q] = (i >= 1 && i <= n - 1) ? 1.0 : 0.0;
+        wr[q] = (i <= n - 2) ? 1.0 : 0.0;
+        wlast[q] = (i == n - 1) ? 1.0 : 0.0;
+    }
+
+    // state u_0 (and v_0 = u_0, the first guess of the |u|^2 inner iteration)
+    cd u[P], vlast[P];
+    const bool data = (fl & T_DATA_U0) != 0;
+    const cd* u0 = a.u0 + (size_t)b * a.nx + o;
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        u[q] = (data && s + q < n) ? u0[s + q] : zero;
+        vlast[q] = u[q];
+    }
+    auto at_last = [&](const cd (&arr)[P]) {
+        cd r = zero;
+#pragma unroll
+        for (int q = 0; q < P; ++q) r = mk(r.x + wlast[q] * arr[q].x, r.y + wlast[q] * arr[q].y);
+        return rdlane(r, lastl);
+    };
+
+    const double kap = a.kappa;
+    cd* Ha = a.hist ? a.hist + (size_t)blockIdx.x * 2 * (nt + 1) : nullptr;
+    cd* Hb = Ha ? Ha + (nt + 1) : nullptr;
+    const cd va0 = rdlane(u[0], 0);
+    const cd vb0 = at_last(u);
+    if (TR == TR_S02 && t == 0) {
+        Ha[0] = va0;
+        Hb[0] = vb0;
+    }
+    // checkpoints for the adjoint: u at forward steps max(0, nt - 64 jj), jj = 1..Jc
+    cd* ck = (fl & T_CKPT) ? a.ckpt + ((size_t)blockIdx.x * (a.Jc + 1) * P) * kWave + t : nullptr;
+    if (ck) {
+#pragma unroll
+        for (int q = 0; q < P; ++q) ck[((size_t)a.Jc * P + q) * kWave] = u[q];
+    }
+    cd* trace_a = (fl & T_OUT_TRACE) ? a.trace + ((size_t)(b * a.N + k) * 2) * (nt + 1) : nullptr;
+    cd* trace_b = trace_a ? trace_a + (nt + 1) : nullptr;
+    if (trace_a && t == 0) {
+        trace_a[0] = va0;
+        trace_b[0] = vb0;
+    }
+
+    const int ns = a.ns;
+    const cd* gin_l = (lif && (fl & T_FLUX_G)) ? a.g_in + ((size_t)b * ns + 2 * k - 1) * nt : nullptr;
+    const cd* gin_r = (rif && (fl & T_FLUX_G)) ? a.g_in + ((size_t)b * ns + 2 * k) * nt : nullptr;
+    cd* out_l = nullptr;
+    cd* out_r = nullptr;
+    const cd* old_l = nullptr;
+    const cd* old_r = nullptr;
+    if (fl & T_OUT_G) {
+        if (lif) out_l = a.g_out + ((size_t)b * ns + 2 * k - 2) * nt;
+        if (rif) out_r = a.g_out + ((size_t)b * ns + 2 * k + 1) * nt;
+        if (fl & T_MAXDIFF) {
+            if (lif) old_l = a.g_in + ((size_t)b * ns + 2 * k - 2) * nt;
+            if (rif) old_r = a.g_in + ((size_t)b * ns + 2 * k + 1) * nt;
+        }
+    } else if (fl & T_OUT_COLS) {
+        const int pl = (fl & T_IMP_L) ? 0 : 1;
+        if (lif) out_l = a.cols + ((size_t)f * 4 + pl) * nt;
+        if (rif) out_r = a.cols + ((size_t)f * 4 + pl + 2) * nt;
+    }
+    double maxd = 0.0;
+    int nl_worst = 0, nl_fail = 0;
+
+    for (int n0 = 0; n0 < nt; n0 += kWave) {
+        const int nb = min(kWave, nt - n0);
+        const bool act = t < nb;
+        // incoming fluxes of this block: lane j <-> step n0+1+j
+        cd lb = zero, rb = zero;
+        if (act) {
+            if (gin_l) lb = gin_l[n0 + t];
+            if (gin_r) rb = gin_r[n0 + t];
+            if ((fl & T_IMP_L) && n0 + t == 0) lb = mk(1, 0);
+            if ((fl & T_IMP_R) && n0 + t == 0) rb = mk(1, 0);
+        }
+        // far part of the S0^2 history for the outputs of this block:
+        // acc_j = sum_{q <= n0} beta_{n0+1+j-q} v_q, over chunks of 64 past
+        // values staged in LDS with one coalesced load each, together with
+        // the 127-entry window of beta the chunk needs
+        cd acc_a = zero, acc_b = zero;
+        if (TR == TR_S02) {
+            __threadfence_block();
+            const int nj = n0 + 1 + t;
+            for (int q0 = 0; q0 <= n0; q0 += kWave) {
+                const int qn = min(kWave, n0 + 1 - q0);
+                const int bbase = n0 - q0 - (kWave - 2);   // beta index of sb[0]
+                sha[t] = (t < qn) ? Ha[q0 + t] : zero;
+                shb[t] = (t < qn) ? Hb[q0 + t] : zero;
+                const int i0 = bbase + t, i1 = bbase + kWave + t;
+                sb[t] = (i0 >= 0) ? a.beta[i0] : 0.0;
+                sb[kWave + t] = (i1 >= 0) ? a.beta[i1] : 0.0;
+                __syncthreads();
+                const double* bw = sb + (nj - q0 - bbase);  // beta_{nj - q0 - i} = bw[-i]
+                for (int i = 0; i < qn; ++i) {
+                    const double bt = bw[-i];
+                    const cd ha = sha[i], hb = shb[i];
+                    acc_a = mk(acc_a.x + bt * ha.x, acc_a.y + bt * ha.y);
+                    acc_b = mk(acc_b.x + bt * hb.x, acc_b.y + bt * hb.y);
+                }
+                __syncthreads();
+            }
+        }
+        cd rl_b = zero, rr_b = zero, va_b = zero, vb_b = zero, ua_b = zero, ub_b = zero;
+
+        for (int i = 0; i < nb; ++i) {
+            const int nstep = n0 + 1 + i;
+            if (VK == VK_TIME) {
+                // W_n = (V_n + V_{n-1})/2 (eq. CNS_L); refactor for this step
+                double w[P];
+#pragma unroll
+                for (int q = 0; q < P; ++q) {
+                    w[q] = 0.5 * (vnext[q] + vprev[q]);
+                    vprev[q] = vnext[q];
+                }
+                if (nstep < nt) {
+#pragma unroll
+                    for (int q = 0; q < P; ++q)
+                        vnext[q] = (s + q < n) ? Vt[(size_t)(nstep + 1) * a.nx + s + q] : 0.0;
+                }
+                double wL, wR;
+                neighbour_w(w, wL, wR);
+                cd ra[P], rbr[P], rc[P];
+                chunk_rows<P>(s, n, lif, rif, a.h, kap, a.sigma, w, wL, wR, ra, rbr, rc);
+                lane_factor<P>(ra, rbr, rc, F);
+            }
+            const cd ln = rdlane(lb, i), rn = rdlane(rb, i);
+            cd hA = zero, hB = zero;
+            if (TR == TR_S02) {
+                hA = a.c2 * rdlane(acc_a, i);
+                hB = a.c2 * rdlane(acc_b, i);
+            }
+            // right-hand side c M u_{n-1} + boundary terms
+            const cd uL = shfl_up_c(u[P - 1], 1, zero);
+            const cd uR = shfl_dn_c(u[0], 1, zero);
+            const cd tb = rif ? (hB - rn) : zero;
+            cd d[P];
+#pragma unroll
+            for (int q = 0; q < P; ++q) {
+                const cd up = (q == 0) ? uL : u[q - 1];
+                const cd un = (q + 1 < P) ? u[q + 1] : uR;
+                const double wc = 2.0 * (wl[q] + wr[q]);
+                const cd sum = mk(wl[q] * up.x + wc * u[q].x + wr[q] * un.x,
+                                  wl[q] * up.y + wc * u[q].y + wr[q] * un.y);
+                d[q] = kap * mul_i(sum);
+                d[q] = mk(d[q].x + wlast[q] * tb.x, d[q].y + wlast[q] * tb.y);
+            }
+            if (lif && t == 0) d[0] = d[0] + (hA - ln);
+            cd x[P];
+            if (VK == VK_CUBIC) {
+                // inner fixed point of eq. AvMNL from zeta^0 = v_{n-1}:
+                // (cM - S - sigma E) zeta^{s+1} = rhs - M_{|zeta^s|^2} zeta^s
+                cd z[P];
+#pragma unroll
+                for (int q = 0; q < P; ++q) z[q] = vlast[q];
+                const double hk = a.h / 12.0;
+                int it = 1;
+                bool conv = false;
+                for (; it <= a.nl_maxit; ++it) {
+                    double Fz[P];
+#pragma unroll
+                    for (int q = 0; q < P; ++q) Fz[q] = abs2(z[q]);
+                    const cd zL = shfl_up_c(z[P - 1], 1, zero), zR = shfl_dn_c(z[0], 1, zero);
+                    // neighbours' |zeta|^2: the shuffles run on every lane
+                    // (a lane left out of a permute hands zero to its reader)
+                    const double FLs = __shfl(Fz[P - 1], t > 0 ? t - 1 : 0);
+                    const double FRs = __shfl(Fz[0], t < kWave - 1 ? t + 1 : kWave - 1);
+                    const double FL = t > 0 ? FLs : 0.0;
+                    const double FR = t < kWave - 1 ? FRs : 0.0;
+                    cd r[P];
+#pragma unroll
+                    for (int q = 0; q < P; ++q) {
+                        // generalised mass with nodal weight |zeta|^2 (same
+                        // element matrix as M_W)
+                        const cd zm = (q == 0) ? zL : z[q - 1];
+                        const cd zp = (q == P - 1) ? zR : z[q + 1];
+                        const double fm = (q == 0) ? FL : Fz[q - 1];
+                        const double fp = (q == P - 1) ? FR : Fz[q + 1];
+                        const double fi = Fz[q];
+                        cd nl = zero;
+                        if (wl[q] != 0.0) nl = nl + hk * ((fm + fi) * zm + (fm + 3.0 * fi) * z[q]);
+                        if (wr[q] != 0.0) nl = nl + hk * ((3.0 * fi + fp) * z[q] + (fi + fp) * zp);
+                        r[q] = d[q] - nl;
+                    }
+                    lane_solve<P>(F, r, x);
+                    double dm = 0.0, zm2 = 0.0;
+#pragma unroll
+                    for (int q = 0; q < P; ++q) {
+                        if (s + q < n) {
+                            dm = fmax(dm, abs2(x[q] - z[q]));
+                            zm2 = fmax(zm2, abs2(z[q]));
+                        }
+                        z[q] = x[q];
+                    }
+                    const double dmax = sqrt(wave_max(dm)), zmax = sqrt(wave_max(zm2));
+                    if (dmax <= a.nl_tol * fmax(1.0, zmax)) { conv = true; break; }
+                }
+                if (!conv) nl_fail = 1;
+                nl_worst = max(nl_worst, conv ? it : a.nl_maxit);
+#pragma unroll
+                for (int q = 0; q < P; ++q) vlast[q] = x[q];
+            } else {
+                lane_solve<P>(F, d, x);
+            }
+            // advance u_n = 2 v_n - u_{n-1}
+#pragma unroll
+            for (int q = 0; q < P; ++q) u[q] = mk(2.0 * x[q].x - u[q].x, 2.0 * x[q].y - u[q].y);
+            if (ck && nstep < nt && ((nt - nstep) & (kWave - 1)) == 0) {
+                const int jj = (nt - nstep) / kWave;
+#pragma unroll
+                for (int q = 0; q < P; ++q) ck[((size_t)jj * P + q) * kWave] = u[q];
+            }
+            const cd va = rdlane(x[0], 0);
+            const cd vb = at_last(x);
+            const cd rhoL = (2.0 * madd(hA, a.sigma, va)) - ln;
+            const cd rhoR = (2.0 * madd(hB, a.sigma, vb)) - rn;
+            if (t == i) {
+                rl_b = rhoL;
+                rr_b = rhoR;
+                va_b = va;
+                vb_b = vb;
+            }
+            if (trace_a) {
+                const cd ua = rdlane(u[0], 0), ub = at_last(u);
+                if (t == i) { ua_b = ua; ub_b = ub; }
+            }
+            if (TR == TR_S02 && t > i) {
+                const double bt = sbeta[t - i];
+                acc_a = acc_a + bt * va;
+                acc_b = acc_b + bt * vb;
+            }
+        }
+        // block epilogue: coalesced stores
+        if (act) {
+            if (out_l) out_l[n0 + t] = rl_b;
+            if (out_r) out_r[n0 + t] = rr_b;
+            if (old_l) maxd = fmax(maxd, sqrt(abs2(rl_b - old_l[n0 + t])));
+            if (old_r) maxd = fmax(maxd, sqrt(abs2(rr_b - old_r[n0 + t])));
+            if (TR == TR_S02) {
+                Ha[n0 + 1 + t] = va_b;
+                Hb[n0 + 1 + t] = vb_b;
+            }
+            if (trace_a) {
+                trace_a[n0 + 1 + t] = ua_b;
+                trace_b[n0 + 1 + t] = ub_b;
+            }
+        }
+    }
+
+    if (fl & T_OUT_UT) {
+        cd* uT = a.uT + (size_t)b * a.nx + o;
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            const int gi = s + q;
+            if (gi > 0 && gi < n - 1) uT[gi] = u[q];
+        }
+        const cd ua = rdlane(u[0], 0), ub = at_last(u);
+        if (t == 0) {
+            a.ends[((size_t)b * a.N + k) * 2 + 0] = ua;
+            a.ends[((size_t)b * a.N + k) * 2 + 1] = ub;
+        }
+    }
+    if (fl & T_MAXDIFF) {
+        maxd = wave_max(maxd);
+        if (t == 0 && maxd > 0.0)
+            atomicMax(a.maxdiff, (unsigned long long)__double_as_longlong(maxd));
+    }
+    if (VK == VK_CUBIC && t == 0 && a.nl_stats) {
+        atomicMax(&a.nl_stats[0], nl_worst);
+        if (nl_fail) atomicMax(&a.nl_stats[1], 1);
+    }
+}
+
+}  // namespace swr

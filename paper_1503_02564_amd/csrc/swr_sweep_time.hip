@@ -1,0 +1,27 @@
+// swr_sweep_time.hip -- instantiates the subdomain sweep for a time-dependent potential V(t,x).
+#include "swr_sweep_kernel.h"
+
+namespace swr {
+
+template <int P>
+static void launch_p(const SweepArgs& a, int trans, hipStream_t st) {
+    if (trans == TR_S02) sweep_kernel<P, TR_S02, VK_TIME><<<a.ntasks, 64, 0, st>>>(a);
+    else sweep_kernel<P, TR_ROBIN, VK_TIME><<<a.ntasks, 64, 0, st>>>(a);
+}
+
+hipError_t launch_sweep_time(const SweepArgs& a, int trans, hipStream_t st) {
+    switch (a.P) {
+        case 1: launch_p<1>(a, trans, st); break;
+        case 2: launch_p<2>(a, trans, st); break;
+        case 3: launch_p<3>(a, trans, st); break;
+        case 4: launch_p<4>(a, trans, st); break;
+        case 5: launch_p<5>(a, trans, st); break;
+        case 6: launch_p<6>(a, trans, st); break;
+        case 7: launch_p<7>(a, trans, st); break;
+        case 8: launch_p<8>(a, trans, st); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace swr
