@@ -71,8 +71,9 @@ typedef enum {
 } swr_solver;
 
 typedef struct {
-    double tol;        /* FIXED: max |g^{k+1} - g^k| < tol; GMRES: ||d - (I-L)g||_2 <= tol ||d||_2.
-                          default 1e-10 */
+    double tol;        /* FIXED: max |g^{k+1} - g^k| < tol; GMRES: ||d - (I-L)g||_2 <= tol ||d||_2;
+                          |u|^2 preconditioned fixed point: max |g^{k+1} - g^k| < tol max |g^{k+1}|
+                          (per problem).  default 1e-10 */
     int max_iter;      /* iteration cap (default 20000) */
     int restart;       /* GMRES restart length m (default 30) */
     int solver;        /* swr_solver (default SWR_SOLVER_CAUSAL) */
@@ -82,6 +83,11 @@ typedef struct {
     int checkpoint_K;  /* adjoint checkpoint interval in steps (default 64) */
     int nl_max_iter;   /* |u|^2 inner fixed point cap per step (default 100) */
     double nl_tol;     /* |u|^2 inner fixed point tolerance (default 1e-14) */
+    int pipeline;      /* static V with SWR_SOLVER_CAUSAL: cut the time window into chunks of
+                          this many steps (a multiple of 64) and overlap the impulse/d sweeps,
+                          the interface solve and the final sweep chunk by chunk on two extra
+                          internal streams (joined back to the context's stream before the call
+                          returns); 0 = one stage after the other (default 256) */
 } swr_opts;
 
 typedef struct {
@@ -89,10 +95,15 @@ typedef struct {
     double residual;    /* certified ||g - R g||_2 / ||R 0||_2 of the final sweep
                            (max over the batch); FIXED: last max change */
     double t_factor_ms; /* assembly + factorisation */
-    double t_build_ms;  /* impulse sweeps and d (Sec. 4.1) */
+    double t_build_ms;  /* impulse sweeps and d (Sec. 4.1); with opts.pipeline the three
+                           phases overlap and each figure is the span of its own stream */
     double t_iface_ms;  /* interface solve */
     double t_final_ms;  /* final sweep and u(T) */
     int nl_worst;       /* |u|^2: largest inner iteration count */
+    double t_total_ms;  /* the whole call on the device, factorisation to u(T) */
+    double t_sweep_ms;  /* static V, new algorithm: summed durations of the subdomain sweep
+                           launches (impulse/d sweeps and final sweep) ... */
+    int n_sweep;        /* ... and their number (0 when not measured) */
 } swr_info;
 
 /* Fill *o with the defaults listed above. */

@@ -16,9 +16,13 @@
 // stable when the system is block diagonally dominant
 // (max_j ||D_j^{-1}|| (||L_j|| + ||U_j||) < 1), which setup checks.
 //
-// Time is processed in blocks of kTb steps.  `causal_far_kernel` adds the
-// contribution of every earlier block (a rectangle of the Toeplitz products,
-// spread over one workgroup per output slot) to d; `causal_near_kernel` then
+// Time is processed in super-blocks of 256 steps (absolute windows) and,
+// inside them, in blocks of kTb steps.  The contribution of every earlier
+// super-block to the outputs being solved is formed by one block-Toeplitz
+// product on the matrix cores (launch_ltt).  `causal_far_kernel` adds to d that product and
+// the contribution of the earlier blocks of the current super-block (a short
+// rectangle, one workgroup per output slot);
+// `causal_near_kernel` then
 // marches through the block on one workgroup per problem: wave 0 runs the
 // per-step PCR solve while waves 1..8 gather the in-block history (lags >= 2)
 // of the next step, from the block's g kept in LDS and the lag coefficients
@@ -118,6 +122,8 @@ struct FarArgs {
     const cd* d;       // [B][ns][nt]
     const cd* g;       // [B][ns][nt]
     cd* out;           // [B][ns][kTb]  = d + contribution of steps s < n0
+    const cd* facc;    // [B][ns][nt] contribution of steps s < s_from (null: none)
+    int s_from;        // this kernel sums steps s_from <= s < n0
 };
 
 // one workgroup per (slot, problem); thread (i, split): output step n0+i,
@@ -136,8 +142,8 @@ __global__ __launch_bounds__(256) void causal_far_kernel(FarArgs f) {
     const cd* gl = sl >= 0 ? f.g + ((size_t)b * f.ns + sl) * f.nt : nullptr;
     const cd* gr = sr >= 0 ? f.g + ((size_t)b * f.ns + sr) * f.nt : nullptr;
     const int n = f.n0 + i;
-    const int per = (f.n0 + SPLITS - 1) / SPLITS;
-    const int s_lo = sp * per, s_hi = min(f.n0, s_lo + per);
+    const int per = (f.n0 - f.s_from + SPLITS - 1) / SPLITS;
+    const int s_lo = f.s_from + sp * per, s_hi = min(f.n0, s_lo + per);
     double ax = 0, ay = 0;
     if (i < f.nb) {
         for (int s = s_lo; s < s_hi; ++s) {
@@ -157,6 +163,7 @@ __global__ __launch_bounds__(256) void causal_far_kernel(FarArgs f) {
     __syncthreads();
     if (sp == 0 && i < f.nb) {
         cd r = f.d[((size_t)b * f.ns + o) * f.nt + n];
+        if (f.facc) r = r + f.facc[((size_t)b * f.ns + o) * f.nt + n];
         for (int q = 0; q < SPLITS; ++q) r = r + part[q][i];
         f.out[((size_t)b * f.ns + o) * TB + i] = r;
     }
@@ -277,8 +284,9 @@ hipError_t launch_causal_pcr_setup(int N, int nt, int nv, const cd* cols, cd* pc
 
 template <int TB>
 static hipError_t launch_causal_far(int N, int nt, int ns, int B, int per_problem, int n0, int nb,
-                                    const cd* cols, const cd* d, const cd* g, cd* out, hipStream_t st) {
-    FarArgs f{N, nt, ns, per_problem, n0, nb, cols, d, g, out};
+                                    const cd* cols, const cd* d, const cd* g, cd* out,
+                                    const cd* facc, int s_from, hipStream_t st) {
+    FarArgs f{N, nt, ns, per_problem, n0, nb, cols, d, g, out, facc, s_from};
     causal_far_kernel<TB><<<dim3(ns, B), 256, 0, st>>>(f);
     return hipGetLastError();
 }
@@ -293,10 +301,14 @@ hipError_t launch_causal_near(int N, int nt, int ns, int B, int per_problem, int
 
 // the whole forward substitution: far part then near march, block by block
 hipError_t launch_causal_fast(int N, int nt, int ns, int B, int per_problem, const cd* cols,
-                              const cd* pcr, const cd* d, cd* base, cd* g, hipStream_t st) {
-    for (int n0 = 0; n0 < nt; n0 += kTb) {
-        const int nb = min(kTb, nt - n0);
-        hipError_t e = launch_causal_far<kTb>(N, nt, ns, B, per_problem, n0, nb, cols, d, g, base, st);
+                              const cd* pcr, const cd* d, cd* base, cd* g, int n_lo, int n_hi,
+                              const cd* facc, int s_from, hipStream_t st) {
+    if (n_lo % kTb != 0 || n_lo < 0 || n_hi > nt || s_from < 0 || s_from > n_lo)
+        return hipErrorInvalidValue;
+    for (int n0 = n_lo; n0 < n_hi; n0 += kTb) {
+        const int nb = min(kTb, n_hi - n0);
+        hipError_t e = launch_causal_far<kTb>(N, nt, ns, B, per_problem, n0, nb, cols, d, g, base,
+                                              facc, s_from, st);
         if (e != hipSuccess) return e;
         e = launch_causal_near(N, nt, ns, B, per_problem, n0, nb, cols, pcr, base, g, st);
         if (e != hipSuccess) return e;
@@ -482,13 +494,17 @@ hipError_t launch_causal_pcr_setup_gen(int N, int nt, int nv, const cd* cols, cd
 }
 
 hipError_t launch_causal_gen(int N, int nt, int ns, int B, int per_problem, const cd* cols,
-                             const cd* pcr, const cd* d, cd* base, cd* g, hipStream_t st) {
+                             const cd* pcr, const cd* d, cd* base, cd* g, int n_lo, int n_hi,
+                             const cd* facc, int s_from, hipStream_t st) {
     const size_t shm = ((size_t)kGenTb * ns + ns + 2 * (size_t)(N - 1)) * sizeof(cd);
     if (N - 1 > kGenMaxIf || N - 1 > kGenThreads || ns > 2 * kGenThreads || shm > 160 * 1024)
         return hipErrorInvalidValue;
-    for (int n0 = 0; n0 < nt; n0 += kGenTb) {
-        const int nb = min(kGenTb, nt - n0);
-        hipError_t e = launch_causal_far<kGenTb>(N, nt, ns, B, per_problem, n0, nb, cols, d, g, base, st);
+    if (n_lo % kGenTb != 0 || n_lo < 0 || n_hi > nt || s_from < 0 || s_from > n_lo)
+        return hipErrorInvalidValue;
+    for (int n0 = n_lo; n0 < n_hi; n0 += kGenTb) {
+        const int nb = min(kGenTb, n_hi - n0);
+        hipError_t e = launch_causal_far<kGenTb>(N, nt, ns, B, per_problem, n0, nb, cols, d, g, base,
+                                                 facc, s_from, st);
         if (e != hipSuccess) return e;
         NearGenArgs na{N, nt, ns, per_problem, n0, nb, pcr_rec_gen(N), cols, pcr, base, g};
         causal_near_gen_kernel<<<B, kGenThreads, shm, st>>>(na);

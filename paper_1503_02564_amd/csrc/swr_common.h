@@ -131,6 +131,8 @@ struct SweepArgs {
     int flags_and, flags_or;     // per-launch override of the task flags
     cd* ckpt;                    // [ntasks][Jc+1][P][64] checkpoints of u
     int Jc;                      // ceil(nt / 64)
+    int n_begin, n_end;          // steps n_begin+1 .. n_end of this launch (n_begin % 64 == 0)
+    cd* state;                   // [ntasks][2][P][64] u_n and v_n carried between launches
 };
 
 struct FactorArgs {
@@ -152,7 +154,7 @@ struct LttArgs {
     const cd* base;        // y = base + sign * L x  (base may be x itself or null)
     double sign;
     int n_lo, n_hi;        // output time window
-    int s_hi;              // only inputs s < s_hi contribute
+    int s_lo, s_hi;        // only inputs s_lo <= s < s_hi contribute (and s <= n)
     int y_ld;              // leading dimension of y / base per (b, slot)
 };
 
@@ -206,9 +208,11 @@ constexpr int kPcrRec = kPcrLevels * 8 + 4;   // complex entries per lane of the
 hipError_t launch_causal_pcr_setup(int N, int nt, int nv, const cd* cols, cd* pcr, double* eta,
                                    hipStream_t st);
 hipError_t launch_causal_fast(int N, int nt, int ns, int B, int per_problem, const cd* cols,
-                              const cd* pcr, const cd* d, cd* base, cd* g, hipStream_t st);
+                              const cd* pcr, const cd* d, cd* base, cd* g, int n_lo, int n_hi,
+                              const cd* facc, int s_from, hipStream_t st);
 // general block-PCR causal solve for up to kGenMaxIf interfaces
 constexpr int kGenTb = 8;
+constexpr int kCausalSuper = 256;    // causal solve super-block (time steps)
 constexpr int kGenMaxIf = 512;
 __host__ __device__ constexpr int pcr_rec_gen(int N) {
     // complex entries per potential: levels * 8 * ni + 4 * ni
@@ -217,7 +221,8 @@ __host__ __device__ constexpr int pcr_rec_gen(int N) {
 hipError_t launch_causal_pcr_setup_gen(int N, int nt, int nv, const cd* cols, cd* pcr, double* eta,
                                        hipStream_t st);
 hipError_t launch_causal_gen(int N, int nt, int ns, int B, int per_problem, const cd* cols,
-                             const cd* pcr, const cd* d, cd* base, cd* g, hipStream_t st);
+                             const cd* pcr, const cd* d, cd* base, cd* g, int n_lo, int n_hi,
+                             const cd* facc, int s_from, hipStream_t st);
 struct AdjArgs {
     int N, nt, B, nx, ns, ntasks, P, Jc;
     double kappa, h;

@@ -90,6 +90,7 @@ struct swr_ctx {
     double* dRes = nullptr;
     int* dAct = nullptr;
     cd* dFar = nullptr;       // causal dense path
+    cd* dFacc = nullptr;      // causal PCR paths: contribution of finished super-blocks
     cd* dBase = nullptr;      // causal PCR path
     int base_tb = 0;
     // adjoint
@@ -103,6 +104,13 @@ struct swr_ctx {
     double* dGends = nullptr;
     cd* dWends = nullptr;
     cd* dUT = nullptr;
+    // pipelined static solve: two more streams, carried sweep state, the
+    // build sweeps' own S0^2 history, and per-chunk events
+    hipStream_t s2 = nullptr, s3 = nullptr;
+    cd* dStateB = nullptr;    // [nBuild][2][P][64]
+    cd* dStateF = nullptr;    // [nSub][2][P][64]
+    cd* dHistB = nullptr;     // [nBuild][2][nt+1]
+    std::vector<hipEvent_t> evSync, evTime;
     // host staging (pinned)
     double* hRes = nullptr;
     int* hAct = nullptr;
@@ -158,6 +166,7 @@ extern "C" void swr_default_opts(swr_opts* o) {
     o->checkpoint_K = 64;
     o->nl_max_iter = 100;
     o->nl_tol = 1e-14;
+    o->pipeline = 256;
 }
 
 extern "C" const char* swr_strerror(swr_status s) {
@@ -202,6 +211,7 @@ extern "C" swr_status swr_setup(double a0, double b0, int N, const int* J, doubl
     if (!std::isfinite(s_re) || !std::isfinite(s_im)) return SWR_EINVAL;
     if (o.batch < 1 || o.restart < 1 || o.max_iter < 1 || !(o.tol > 0)) return SWR_EINVAL;
     if (o.nl_max_iter < 1 || !(o.nl_tol > 0) || o.checkpoint_K < 1) return SWR_EINVAL;
+    if (o.pipeline < 0 || o.pipeline % kWave != 0) return SWR_EINVAL;
     if (vk == SWR_V_TIME && !V) return SWR_EINVAL;
     if (vk == SWR_V_CUBIC && V) return SWR_EINVAL;
     if (vk != SWR_V_STATIC && o.v_per_problem) return SWR_EINVAL;
@@ -308,11 +318,17 @@ extern "C" void swr_destroy(swr_ctx* c) {
     if (!c) return;
     if (c->st) hipStreamSynchronize(c->st);
     else hipDeviceSynchronize();
+    if (c->s2) hipStreamSynchronize(c->s2);
+    if (c->s3) hipStreamSynchronize(c->s3);
     for (void* p : c->allocs) hipFree(p);
     if (c->hRes) hipHostFree(c->hRes);
     if (c->hAct) hipHostFree(c->hAct);
     for (auto& e : c->ev)
         if (e) hipEventDestroy(e);
+    for (auto e : c->evSync) hipEventDestroy(e);
+    for (auto e : c->evTime) hipEventDestroy(e);
+    if (c->s2) { hipStreamSynchronize(c->s2); hipStreamDestroy(c->s2); }
+    if (c->s3) { hipStreamSynchronize(c->s3); hipStreamDestroy(c->s3); }
     delete c;
 }
 
@@ -354,6 +370,9 @@ static SweepArgs sweep_args(swr_ctx* c, const Task* tasks, int ntasks, const cd*
     a.nl_stats = c->dNl;
     a.flags_and = ~0;
     a.flags_or = 0;
+    a.n_begin = 0;
+    a.n_end = c->nt;
+    a.state = nullptr;
     return a;
 }
 
@@ -370,6 +389,22 @@ static swr_status run_factor(swr_ctx* c, const double* V, int nv, cd* fac) {
 static const cd* main_fac(swr_ctx* c) { return c->vk == SWR_V_STATIC ? c->L.fac : c->L0.fac; }
 
 // every (problem, subdomain) swept once with the fluxes io.g_in (null: zero)
+static SweepArgs sub_args(swr_ctx* c, const SweepIO& io) {
+    SweepArgs a = sweep_args(c, c->dSub, c->nSub, main_fac(c), nullptr);
+    a.u0 = io.u0;
+    a.g_in = io.g_in ? io.g_in : c->dZero;
+    a.g_out = io.g_out;
+    a.uT = io.uT;
+    a.trace = io.trace;
+    a.flags_and = 0;
+    a.flags_or = (io.u0 ? T_DATA_U0 : 0) | (io.g_in ? T_FLUX_G : 0) | (io.g_out ? T_OUT_G : 0) |
+                 (io.uT ? T_OUT_UT : 0) | (io.trace ? T_OUT_TRACE : 0) | (io.maxdiff ? T_MAXDIFF : 0) |
+                 (io.ckpt ? T_CKPT : 0);
+    a.ckpt = c->dCkpt;
+    a.Jc = c->Jc;
+    return a;
+}
+
 static swr_status run_sweeps(swr_ctx* c, const SweepIO& io) {
     SweepArgs a = sweep_args(c, c->dSub, c->nSub, main_fac(c), nullptr);
     a.u0 = io.u0;
@@ -496,9 +531,9 @@ static swr_status run_gmres(swr_ctx* c, const Op& A, const cd* rhs, cd* x, int* 
 // certified diagonally dominant: on one wave for N - 1 <= 64 interfaces, on
 // a workgroup up to kGenMaxIf; otherwise a dense (I - C_0)^{-1} by
 // Gauss-Jordan with partial pivoting.
-static swr_status run_causal(swr_ctx* c, Iface& I, const cd* d, cd* g) {
+static swr_status run_causal(swr_ctx* c, Iface& I, const cd* d, cd* g, hipStream_t st,
+                             int n_lo, int n_hi) {
     const int ns = c->ns, nt = c->nt, B = c->B, ni = c->N - 1;
-    hipStream_t st = c->st;
     const bool fast_ok = ns <= kNearSlots && ni <= kWave;
     const size_t gen_shm = ((size_t)kGenTb * ns + ns + 2 * (size_t)ni) * sizeof(cd);
     const bool gen_ok = ni <= kGenMaxIf && gen_shm <= 160 * 1024;
@@ -536,15 +571,37 @@ static swr_status run_causal(swr_ctx* c, Iface& I, const cd* d, cd* g) {
             ALLOC_LIVE(c->dBase, (size_t)B * ns * tb);
             c->base_tb = tb;
         }
-        if (I.path == 1)
-            HIPCHK(launch_causal_fast(c->N, nt, ns, B, I.nv > 1, I.cols, I.pcr, d, c->dBase, g, st));
-        else
-            HIPCHK(launch_causal_gen(c->N, nt, ns, B, I.nv > 1, I.cols, I.pcr, d, c->dBase, g, st));
+        if (!c->dFacc) ALLOC_LIVE(c->dFacc, (size_t)B * ns * nt);
+        // super-blocks are the absolute windows [S, S + kCausalSuper); the
+        // steps [a0, a1) of one of them take the contribution of the finished
+        // super-blocks (steps < S) from one block-Toeplitz product, which
+        // reads lags < a1 only (written once the impulse sweeps reach a1),
+        // and the steps S <= s < n from the far kernel.  Where a call's range
+        // starts or ends therefore changes no arithmetic.
+        for (int a0 = n_lo; a0 < n_hi;) {
+            const int S = a0 / kCausalSuper * kCausalSuper;
+            const int a1 = std::min(n_hi, S + kCausalSuper);
+            if (S > 0) {
+                LttArgs l{};
+                l.N = c->N; l.nt = nt; l.ns = ns; l.B = B; l.per_problem = I.nv > 1;
+                l.cols = I.cols; l.x = g; l.y = c->dFacc + a0; l.base = nullptr;
+                l.sign = 1.0; l.n_lo = a0; l.n_hi = a1; l.s_lo = 0; l.s_hi = S; l.y_ld = nt;
+                HIPCHK(launch_ltt(l, st));
+            }
+            const cd* facc = S > 0 ? c->dFacc : nullptr;
+            if (I.path == 1)
+                HIPCHK(launch_causal_fast(c->N, nt, ns, B, I.nv > 1, I.cols, I.pcr, d, c->dBase, g,
+                                          a0, a1, facc, S, st));
+            else
+                HIPCHK(launch_causal_gen(c->N, nt, ns, B, I.nv > 1, I.cols, I.pcr, d, c->dBase, g,
+                                         a0, a1, facc, S, st));
+            a0 = a1;
+        }
         return SWR_OK;
     }
     if (!c->dFar) ALLOC_LIVE(c->dFar, (size_t)B * ns * kCausalTb);
-    for (int n0 = 0; n0 < nt; n0 += kCausalTb) {
-        const int nb = std::min(kCausalTb, nt - n0);
+    for (int n0 = n_lo; n0 < n_hi; n0 += kCausalTb) {
+        const int nb = std::min(kCausalTb, n_hi - n0);
         LttArgs l{};
         l.N = c->N; l.nt = nt; l.ns = ns; l.B = B; l.per_problem = I.nv > 1;
         l.cols = I.cols; l.x = g; l.y = c->dFar; l.base = nullptr; l.sign = 1.0;
@@ -601,7 +658,7 @@ static swr_status run_precond_time(swr_ctx* c, int* iters) {
     Op A = [c, pc, vec](const cd* z, cd* y) -> swr_status {
         const cd* w = z;
         if (pc) {
-            CHK(run_causal(c, c->L0, z, c->dT1));
+            CHK(run_causal(c, c->L0, z, c->dT1, c->st, 0, c->nt));
             w = c->dT1;
         }
         SweepIO io;
@@ -613,7 +670,7 @@ static swr_status run_precond_time(swr_ctx* c, int* iters) {
     HIPCHK(hipMemsetAsync(c->dG2, 0, vec * sizeof(cd), c->st));   // y (preconditioned unknown)
     swr_status rs = run_gmres(c, A, c->dD, c->dG2, iters);
     if (rs != SWR_OK && rs != SWR_ENOCONV) return rs;
-    if (pc) CHK(run_causal(c, c->L0, c->dG2, c->dG));
+    if (pc) CHK(run_causal(c, c->L0, c->dG2, c->dG, c->st, 0, c->nt));
     else HIPCHK(hipMemcpyAsync(c->dG, c->dG2, vec * sizeof(cd), hipMemcpyDeviceToDevice, c->st));
     return rs;
 }
@@ -633,16 +690,20 @@ static swr_status run_precond_cubic(swr_ctx* c, const cd* u0, int* iters, double
         HIPCHK(launch_axpby(c->dG, 1.0, c->dT2, -1.0, c->dT2, (long)vec, c->st));   // g - R_nl g
         const cd* z = c->dT2;
         if (c->o.precond) {
-            CHK(run_causal(c, c->L0, c->dT2, c->dT1));
+            CHK(run_causal(c, c->L0, c->dT2, c->dT1, c->st, 0, c->nt));
             z = c->dT1;
         }
         HIPCHK(launch_axpby(c->dG, 1.0, z, -1.0, c->dG, (long)vec, c->st));
         HIPCHK(launch_maxabs(z, M, c->B, c->dPart, c->dNrm, c->st));
-        std::vector<double> m(c->B);
+        HIPCHK(launch_maxabs(c->dG, M, c->B, c->dPart, c->dBn, c->st));
+        std::vector<double> m(c->B), gm(c->B);
         HIPCHK(hipMemcpyAsync(m.data(), c->dNrm, sizeof(double) * c->B, hipMemcpyDeviceToHost, c->st));
+        HIPCHK(hipMemcpyAsync(gm.data(), c->dBn, sizeof(double) * c->B, hipMemcpyDeviceToHost, c->st));
         HIPCHK(hipStreamSynchronize(c->st));
+        // change relative to the size of the traces (they scale like
+        // sqrt(2/dt) |v|, so an absolute bound can sit below FP64 resolution)
         double d = 0;
-        for (double x : m) d = std::max(d, x);
+        for (int b = 0; b < c->B; ++b) d = std::max(d, gm[b] > 0 ? m[b] / gm[b] : m[b]);
         *last = d;
         *iters = it;
         if (!std::isfinite(d)) return SWR_ENAN;
@@ -655,6 +716,116 @@ static double elapsed(hipEvent_t a, hipEvent_t b) {
     float ms = 0;
     hipEventElapsedTime(&ms, a, b);
     return ms;
+}
+
+// ---------------------------------------------------------------------------
+// Static potential with the causal interface solve, pipelined in time.
+// Every stage is causal: step n of the impulse responses and of d needs
+// steps <= n of the build sweeps, g_n needs them and g_s for s < n, and step n
+// of the final sweep needs g_s for s <= n.  The time window is cut into chunks
+// of o.pipeline steps; chunk j of the build sweeps (stream st), of the
+// interface solve (s2) and of the final sweep (s3) wait only for chunk j of
+// the stage before, so the three stages run concurrently on different CUs.
+// The sweeps carry their state between chunk launches (dStateB / dStateF)
+// and keep their S0^2 boundary history in separate buffers.
+// ---------------------------------------------------------------------------
+struct PipeTimes {
+    double build = 0, iface = 0, fin = 0, sweep_sum = 0;
+    int n_sweep = 0;
+};
+
+static bool pipelined(const swr_ctx* c) {
+    return c->vk == SWR_V_STATIC && c->o.solver == SWR_SOLVER_CAUSAL && c->o.pipeline > 0 &&
+           c->ns > 0 && c->nt > c->o.pipeline;
+}
+
+static swr_status pipe_resources(swr_ctx* c, int K) {
+    if (!c->s2) HIPCHK(hipStreamCreateWithFlags(&c->s2, hipStreamNonBlocking));
+    if (!c->s3) HIPCHK(hipStreamCreateWithFlags(&c->s3, hipStreamNonBlocking));
+    const size_t st_rec = (size_t)2 * c->P * kWave;
+    if (!c->dStateB) ALLOC_LIVE(c->dStateB, (size_t)c->nBuild * st_rec);
+    if (!c->dStateF) ALLOC_LIVE(c->dStateF, (size_t)c->nSub * st_rec);
+    if (!c->dHistB && c->tr == SWR_S02) ALLOC_LIVE(c->dHistB, (size_t)c->nBuild * 2 * (c->nt + 1));
+    // sync events: fork, build j, causal j, join; timing events: 2 per sweep
+    // launch plus the two ends of the interface solve
+    while ((int)c->evSync.size() < 2 * K + 2) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        c->evSync.push_back(e);
+    }
+    while ((int)c->evTime.size() < 4 * K + 2) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        c->evTime.push_back(e);
+    }
+    return SWR_OK;
+}
+
+static swr_status run_static_pipelined(swr_ctx* c, const cd* u0, cd* g, const SweepIO& fin,
+                                       PipeTimes* tm) {
+    const int nt = c->nt, ch = c->o.pipeline;
+    const int K = (nt + ch - 1) / ch;
+    CHK(pipe_resources(c, K));
+    hipStream_t st = c->st, s2 = c->s2, s3 = c->s3;
+    hipEvent_t* es = c->evSync.data();
+    hipEvent_t* et = c->evTime.data();
+    hipEvent_t ev_fork = es[0], ev_join = es[1];
+    // fork: the side streams start after everything queued so far on st
+    HIPCHK(hipEventRecord(ev_fork, st));
+    HIPCHK(hipStreamWaitEvent(s2, ev_fork, 0));
+    HIPCHK(hipStreamWaitEvent(s3, ev_fork, 0));
+
+    SweepArgs ab = sweep_args(c, c->dBuild, c->nBuild, c->L.fac, c->L.cols);
+    ab.u0 = u0;
+    ab.g_in = c->dZero;
+    ab.g_out = c->dD;
+    ab.state = c->dStateB;
+    if (c->dHistB) ab.hist = c->dHistB;
+    SweepArgs af = sub_args(c, fin);
+    af.state = c->dStateF;
+    c->L.dirty = true;
+
+    // stage 1: impulse + d sweeps, chunk by chunk on st
+    for (int j = 0; j < K; ++j) {
+        ab.n_begin = j * ch;
+        ab.n_end = std::min(nt, (j + 1) * ch);
+        HIPCHK(hipEventRecord(et[2 * j], st));
+        HIPCHK(launch_sweep(ab, c->tr, SWR_V_STATIC, st));
+        HIPCHK(hipEventRecord(et[2 * j + 1], st));
+        HIPCHK(hipEventRecord(es[2 + j], st));
+    }
+    // stage 2: causal interface solve on s2 (its set-up reads the first
+    // step of the impulse responses, i.e. chunk 0)
+    for (int j = 0; j < K; ++j) {
+        HIPCHK(hipStreamWaitEvent(s2, es[2 + j], 0));
+        if (j == 0) HIPCHK(hipEventRecord(et[4 * K], s2));
+        CHK(run_causal(c, c->L, c->dD, g, s2, j * ch, std::min(nt, (j + 1) * ch)));
+        HIPCHK(hipEventRecord(es[2 + K + j], s2));
+    }
+    HIPCHK(hipEventRecord(et[4 * K + 1], s2));
+    // stage 3: final sweep on s3
+    for (int j = 0; j < K; ++j) {
+        HIPCHK(hipStreamWaitEvent(s3, es[2 + K + j], 0));
+        af.n_begin = j * ch;
+        af.n_end = std::min(nt, (j + 1) * ch);
+        HIPCHK(hipEventRecord(et[2 * K + 2 * j], s3));
+        HIPCHK(launch_sweep(af, c->tr, c->vk, s3));
+        HIPCHK(hipEventRecord(et[2 * K + 2 * j + 1], s3));
+    }
+    if (fin.uT) HIPCHK(launch_finalize_ut(c->N, c->nx, c->B, c->dOff, c->dEnds, fin.uT, s3));
+    // join back onto st
+    HIPCHK(hipEventRecord(ev_join, s3));
+    HIPCHK(hipStreamWaitEvent(st, ev_join, 0));
+    if (tm) {
+        HIPCHK(hipEventSynchronize(ev_join));
+        tm->build = elapsed(et[0], et[2 * K - 1]);
+        tm->iface = elapsed(et[4 * K], et[4 * K + 1]);
+        tm->fin = elapsed(et[2 * K], et[4 * K - 1]);
+        tm->sweep_sum = 0;
+        for (int j = 0; j < 2 * K; ++j) tm->sweep_sum += elapsed(et[2 * j], et[2 * j + 1]);
+        tm->n_sweep = 2 * K;
+    }
+    return SWR_OK;
 }
 
 extern "C" swr_status swr_solve(swr_ctx* c, const double* u0d, double* uT, double* g, double* utrace,
@@ -672,8 +843,21 @@ extern "C" swr_status swr_solve(swr_ctx* c, const double* u0d, double* uT, doubl
     if (c->vk == SWR_V_STATIC) CHK(run_factor(c, c->dV, c->nv, c->L.fac));
     else CHK(run_build_L0(c));   // zero-potential factors + impulses of L_0
     HIPCHK(hipEventRecord(c->ev[1], st));
-    // 2. explicit interface problem (static V) or d = R 0
     const bool fixed = c->vk == SWR_V_STATIC && c->o.solver == SWR_SOLVER_FIXED;
+    PipeTimes tm;
+    const bool pipe = pipelined(c);
+    if (pipe) {
+        // 2-4 overlapped in time: build sweeps, causal solve, final sweep
+        SweepIO io;
+        io.u0 = u0; io.g_in = c->dG; io.g_out = c->dG2;
+        io.uT = reinterpret_cast<cd*>(uT); io.trace = reinterpret_cast<cd*>(utrace);
+        CHK(run_static_pipelined(c, u0, c->dG, io, info ? &tm : nullptr));
+        iters = 1;
+        HIPCHK(hipEventRecord(c->ev[2], st));
+        HIPCHK(hipEventRecord(c->ev[3], st));
+        HIPCHK(hipEventRecord(c->ev[4], st));
+    } else {
+    // 2. explicit interface problem (static V) or d = R 0
     if (c->vk == SWR_V_STATIC) {
         if (!fixed) CHK(run_build(c, u0d));
     } else {
@@ -700,7 +884,7 @@ extern "C" swr_status swr_solve(swr_ctx* c, const double* u0d, double* uT, doubl
         };
         rs = run_gmres(c, A, c->dD, c->dG, &iters);
     } else if (c->o.solver == SWR_SOLVER_CAUSAL) {
-        rs = run_causal(c, c->L, c->dD, c->dG);
+        rs = run_causal(c, c->L, c->dD, c->dG, c->st, 0, c->nt);
         iters = 1;
     } else {
         return SWR_EINVAL;
@@ -715,6 +899,7 @@ extern "C" swr_status swr_solve(swr_ctx* c, const double* u0d, double* uT, doubl
         CHK(run_sweeps(c, io));
     }
     HIPCHK(hipEventRecord(c->ev[4], st));
+    }
     if (g && vec) HIPCHK(hipMemcpyAsync(g, c->dG, vec * sizeof(cd), hipMemcpyDeviceToDevice, st));
     // certified residual ||g - R g|| / ||R 0|| (R 0 = d; the classical
     // algorithm reports its last change instead)
@@ -749,6 +934,19 @@ extern "C" swr_status swr_solve(swr_ctx* c, const double* u0d, double* uT, doubl
         info->t_iface_ms = elapsed(c->ev[2], c->ev[3]);
         info->t_final_ms = elapsed(c->ev[3], c->ev[4]);
         info->nl_worst = nl[0];
+        info->t_total_ms = elapsed(c->ev[0], c->ev[4]);
+        info->t_sweep_ms = 0;
+        info->n_sweep = 0;
+        if (pipe) {
+            info->t_build_ms = tm.build;
+            info->t_iface_ms = tm.iface;
+            info->t_final_ms = tm.fin;
+            info->t_sweep_ms = tm.sweep_sum;
+            info->n_sweep = tm.n_sweep;
+        } else if (c->vk == SWR_V_STATIC && !fixed) {
+            info->t_sweep_ms = info->t_build_ms + info->t_final_ms;
+            info->n_sweep = 2;
+        }
     }
     if (nl[1]) return SWR_ENOCONV;
     return rs;
@@ -825,7 +1023,7 @@ static swr_status solve_interface(swr_ctx* c, const cd* d, cd* g, int* iters) {
         return run_gmres(c, A, d, g, iters);
     }
     *iters = 1;
-    return run_causal(c, c->L, d, g);
+    return run_causal(c, c->L, d, g, c->st, 0, c->nt);
 }
 
 static AdjArgs adj_args(swr_ctx* c) {
@@ -868,10 +1066,17 @@ extern "C" swr_status swr_grad(swr_ctx* c, const double* u0d, const double* gbar
     //      checkpoints (the S0^2 boundary history of this sweep stays in dHist)
     HIPCHK(hipEventRecord(c->ev[0], st));
     CHK(run_factor(c, c->dV, c->nv, c->L.fac));
-    CHK(run_build(c, u0d));
-    swr_status rf = solve_interface(c, c->dD, c->dGfwd, &it_f);
-    if (rf != SWR_OK && rf != SWR_ENOCONV) return rf;
-    {
+    swr_status rf = SWR_OK;
+    if (pipelined(c)) {
+        SweepIO io;
+        io.u0 = u0; io.g_in = c->dGfwd; io.g_out = c->dG2; io.uT = c->dUT;
+        io.ckpt = true;
+        CHK(run_static_pipelined(c, u0, c->dGfwd, io, nullptr));
+        it_f = 1;
+    } else {
+        CHK(run_build(c, u0d));
+        rf = solve_interface(c, c->dD, c->dGfwd, &it_f);
+        if (rf != SWR_OK && rf != SWR_ENOCONV) return rf;
         SweepIO io;
         io.u0 = u0; io.g_in = c->ns ? c->dGfwd : nullptr; io.g_out = c->dG2; io.uT = c->dUT;
         io.ckpt = true;

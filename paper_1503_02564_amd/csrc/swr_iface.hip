@@ -23,44 +23,99 @@ __device__ inline void slot_sources(int o, int N, int& k, int& pl, int& pr, int&
     sr = (k <= N - 2) ? 2 * k : -1;
 }
 
-// One thread per output entry (b, slot, n).
-__global__ __launch_bounds__(256) void ltt_apply_kernel(LttArgs a) {
-    const int n = a.n_lo + blockIdx.x * blockDim.x + threadIdx.x;
+// ---------------------------------------------------------------------------
+// Block products of L on FP64 matrix cores.
+//
+// For one output slot o and one source slot (column c of X^{k,p}), the part
+// of y on targets n = n_lo + 16 I + row from sources s = s_lo + 16 J + kk is
+//     y_I += T_{I-J} x_J,   T_m[row][kk] = c[delta + 16 m + row - kk],
+// delta = n_lo - s_lo: every 16 x 16 block of a lower-triangular Toeplitz
+// matrix is itself Toeplitz, fixed by the lag block m = I - J.  One wave owns
+// 16 consecutive target blocks I0 .. I0+15 (256 outputs) as the columns of a
+// 16 x 16 accumulator and, for each lag block m, multiplies T_m (A operand,
+// 16 x 16 in four k-slices of 4) by the 16 source blocks I0+col-m (B
+// operand) with v_mfma_f64_16x16x4_f64.  Complex products use the real
+// embedding: Re y += Re T Re x - Im T Im x, Im y += Re T Im x + Im T Re x.
+// Lags < 0 (s > n) and sources outside [s_lo, s_hi) enter as zeros.
+// Operand layout of the instruction (wave64): lane l supplies A[l%16][l/16]
+// and B[l/16][l%16]; accumulator register q of lane l is D[l/16+4q][l%16]
+// (checked on the device against a host product).
+// ---------------------------------------------------------------------------
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ inline d4 mfma16(double a, double b, d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+__global__ __launch_bounds__(256) void ltt_mfma_kernel(LttArgs a) {
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int tile = blockIdx.x * 4 + w;
     const int o = blockIdx.y, b = blockIdx.z;
-    if (n >= a.n_hi) return;
+    const int nlen = a.n_hi - a.n_lo;
+    if (tile * 256 >= nlen) return;                 // whole wave leaves together
     int k, pl, pr, sl, sr;
     slot_sources(o, a.N, k, pl, pr, sl, sr);
     const int v = a.per_problem ? b : 0;
     const cd* cl = a.cols + ((size_t)(v * a.N + k) * 4 + pl) * a.nt;
     const cd* cr = a.cols + ((size_t)(v * a.N + k) * 4 + pr) * a.nt;
-    const cd* xl = sl >= 0 ? a.x + ((size_t)b * a.ns + sl) * a.nt : nullptr;
-    const cd* xr = sr >= 0 ? a.x + ((size_t)b * a.ns + sr) * a.nt : nullptr;
-    const int send = min(n + 1, a.s_hi);
-    double ax = 0, ay = 0, bx = 0, by = 0;
-    if (xl) {
-        for (int s = 0; s < send; ++s) {
-            const cd c = cl[n - s], xv = xl[s];
-            ax += c.x * xv.x - c.y * xv.y;
-            ay += c.x * xv.y + c.y * xv.x;
+    const cd* xl = sl >= 0 ? a.x + ((size_t)b * a.ns + sl) * a.nt + a.s_lo : nullptr;
+    const cd* xr = sr >= 0 ? a.x + ((size_t)b * a.ns + sr) * a.nt + a.s_lo : nullptr;
+    const int r = lane & 15, kq = lane >> 4;
+    const int I0 = tile * 16;
+    const int slen = a.s_hi - a.s_lo;
+    const int Jn = (slen + 15) / 16;
+    const int delta = a.n_lo - a.s_lo;
+    // lag blocks that can meet a source block J in [0, Jn) and a lag >= 0
+    const int q = -delta - 15;
+    const int m_lag = q >= 0 ? (q + 15) / 16 : -((-q) / 16);
+    const int m_lo = max(I0 - (Jn - 1), m_lag);
+    const int m_hi = slen > 0 ? I0 + 15 : m_lo - 1;
+    d4 yr = {0, 0, 0, 0}, yi = {0, 0, 0, 0};
+    for (int m = m_lo; m <= m_hi; ++m) {
+        const int J = I0 + r - m;                   // source block of B column r
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc) {
+            const int kk = 4 * kc + kq;
+            const int lag = delta + 16 * m + r - kk;
+            const int si = 16 * J + kk;
+            const bool lok = lag >= 0 && lag < a.nt;
+            const bool sok = J >= 0 && si < slen;
+            if (xl) {
+                const cd av = lok ? cl[lag] : mk(0, 0);
+                const cd bv = sok ? xl[si] : mk(0, 0);
+                yr = mfma16(av.x, bv.x, yr);
+                yr = mfma16(-av.y, bv.y, yr);
+                yi = mfma16(av.x, bv.y, yi);
+                yi = mfma16(av.y, bv.x, yi);
+            }
+            if (xr) {
+                const cd av = lok ? cr[lag] : mk(0, 0);
+                const cd bv = sok ? xr[si] : mk(0, 0);
+                yr = mfma16(av.x, bv.x, yr);
+                yr = mfma16(-av.y, bv.y, yr);
+                yi = mfma16(av.x, bv.y, yi);
+                yi = mfma16(av.y, bv.x, yi);
+            }
         }
     }
-    if (xr) {
-        for (int s = 0; s < send; ++s) {
-            const cd c = cr[n - s], xv = xr[s];
-            bx += c.x * xv.x - c.y * xv.y;
-            by += c.x * xv.y + c.y * xv.x;
+    const size_t yb = ((size_t)b * a.ns + o) * a.y_ld;
+#pragma unroll
+    for (int qq = 0; qq < 4; ++qq) {
+        const int nrel = 16 * (I0 + r) + kq + 4 * qq;
+        if (nrel < nlen) {
+            cd out = mk(a.sign * yr[qq], a.sign * yi[qq]);
+            if (a.base) out = out + a.base[yb + nrel];
+            a.y[yb + nrel] = out;
         }
     }
-    const size_t yi = ((size_t)b * a.ns + o) * a.y_ld + (n - a.n_lo);
-    cd r = mk(a.sign * (ax + bx), a.sign * (ay + by));
-    if (a.base) r = r + a.base[yi];
-    a.y[yi] = r;
 }
 
 hipError_t launch_ltt(const LttArgs& a, hipStream_t st) {
     if (a.ns == 0 || a.n_hi <= a.n_lo) return hipSuccess;
-    dim3 grid((a.n_hi - a.n_lo + 255) / 256, a.ns, a.B);
-    ltt_apply_kernel<<<grid, 256, 0, st>>>(a);
+    if (a.s_lo < 0 || a.s_hi > a.nt || a.n_lo < 0 || a.n_hi > a.nt) return hipErrorInvalidValue;
+    const int tiles = (a.n_hi - a.n_lo + 255) / 256;
+    dim3 grid((tiles + 3) / 4, a.ns, a.B);
+    ltt_mfma_kernel<<<grid, 256, 0, st>>>(a);
     return hipGetLastError();
 }
 

@@ -36,14 +36,20 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
     }
 
     LaneFac<P> F;
+    // this launch advances steps nbeg+1 .. nend; a launch that does not
+    // start at step 0 resumes from the state the previous one saved
+    const int nbeg = a.n_begin, nend = a.n_end;
+    const bool first = nbeg == 0, last = nend == nt;
+    cd* stp = a.state ? a.state + (size_t)blockIdx.x * 2 * P * kWave + t : nullptr;
+
     // time-dependent potential: rows n and n+1 of V at my nodes
     double vprev[P], vnext[P];
     const double* Vt = (VK == VK_TIME) ? a.Vt + o : nullptr;
     if (VK == VK_TIME) {
 #pragma unroll
         for (int q = 0; q < P; ++q) {
-            vprev[q] = (s + q < n) ? Vt[s + q] : 0.0;
-            vnext[q] = (s + q < n) ? Vt[(size_t)a.nx + s + q] : 0.0;
+            vprev[q] = (s + q < n) ? Vt[(size_t)nbeg * a.nx + s + q] : 0.0;
+            vnext[q] = (s + q < n) ? Vt[(size_t)(nbeg + 1) * a.nx + s + q] : 0.0;
         }
     } else {
         load_fac<P>(a.fac + (size_t)f * L::total * kWave + t, F);
@@ -64,10 +70,18 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
     cd u[P], vlast[P];
     const bool data = (fl & T_DATA_U0) != 0;
     const cd* u0 = a.u0 + (size_t)b * a.nx + o;
+    if (first) {
 #pragma unroll
-    for (int q = 0; q < P; ++q) {
-        u[q] = (data && s + q < n) ? u0[s + q] : zero;
-        vlast[q] = u[q];
+        for (int q = 0; q < P; ++q) {
+            u[q] = (data && s + q < n) ? u0[s + q] : zero;
+            vlast[q] = u[q];
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            u[q] = stp[q * kWave];
+            vlast[q] = (VK == VK_CUBIC) ? stp[(P + q) * kWave] : u[q];
+        }
     }
     auto at_last = [&](const cd (&arr)[P]) {
         cd r = zero;
@@ -81,19 +95,19 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
     cd* Hb = Ha ? Ha + (nt + 1) : nullptr;
     const cd va0 = rdlane(u[0], 0);
     const cd vb0 = at_last(u);
-    if (TR == TR_S02 && t == 0) {
+    if (TR == TR_S02 && t == 0 && first) {
         Ha[0] = va0;
         Hb[0] = vb0;
     }
     // checkpoints for the adjoint: u at forward steps max(0, nt - 64 jj), jj = 1..Jc
     cd* ck = (fl & T_CKPT) ? a.ckpt + ((size_t)blockIdx.x * (a.Jc + 1) * P) * kWave + t : nullptr;
-    if (ck) {
+    if (ck && first) {
 #pragma unroll
         for (int q = 0; q < P; ++q) ck[((size_t)a.Jc * P + q) * kWave] = u[q];
     }
     cd* trace_a = (fl & T_OUT_TRACE) ? a.trace + ((size_t)(b * a.N + k) * 2) * (nt + 1) : nullptr;
     cd* trace_b = trace_a ? trace_a + (nt + 1) : nullptr;
-    if (trace_a && t == 0) {
+    if (trace_a && t == 0 && first) {
         trace_a[0] = va0;
         trace_b[0] = vb0;
     }
@@ -120,8 +134,8 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
     double maxd = 0.0;
     int nl_worst = 0, nl_fail = 0;
 
-    for (int n0 = 0; n0 < nt; n0 += kWave) {
-        const int nb = min(kWave, nt - n0);
+    for (int n0 = nbeg; n0 < nend; n0 += kWave) {
+        const int nb = min(kWave, nend - n0);
         const bool act = t < nb;
         // incoming fluxes of this block: lane j <-> step n0+1+j
         cd lb = zero, rb = zero;
@@ -304,7 +318,14 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
         }
     }
 
-    if (fl & T_OUT_UT) {
+    if (!last && stp) {
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            stp[q * kWave] = u[q];
+            if (VK == VK_CUBIC) stp[(P + q) * kWave] = vlast[q];
+        }
+    }
+    if ((fl & T_OUT_UT) && last) {
         cd* uT = a.uT + (size_t)b * a.nx + o;
 #pragma unroll
         for (int q = 0; q < P; ++q) {

@@ -30,14 +30,16 @@ class SwrOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("restart", ctypes.c_int),
                 ("solver", ctypes.c_int), ("precond", ctypes.c_int), ("batch", ctypes.c_int),
                 ("v_per_problem", ctypes.c_int), ("checkpoint_K", ctypes.c_int),
-                ("nl_max_iter", ctypes.c_int), ("nl_tol", ctypes.c_double)]
+                ("nl_max_iter", ctypes.c_int), ("nl_tol", ctypes.c_double),
+                ("pipeline", ctypes.c_int)]
 
 
 class SwrInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("residual", ctypes.c_double),
                 ("t_factor_ms", ctypes.c_double), ("t_build_ms", ctypes.c_double),
                 ("t_iface_ms", ctypes.c_double), ("t_final_ms", ctypes.c_double),
-                ("nl_worst", ctypes.c_int)]
+                ("nl_worst", ctypes.c_int), ("t_total_ms", ctypes.c_double),
+                ("t_sweep_ms", ctypes.c_double), ("n_sweep", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -30,7 +30,7 @@ def rel(a, b):
 
 
 def make_problem(wl, solver=None, tol=None, restart=None, max_iter=None, v_per_problem=False,
-                 batch=None, precond=None):
+                 batch=None, precond=None, pipeline=None):
     from paper_1503_02564_amd import swr
     o = swr.swr_default_opts()
     o.batch = wl.B if batch is None else batch
@@ -45,6 +45,8 @@ def make_problem(wl, solver=None, tol=None, restart=None, max_iter=None, v_per_p
     o.v_per_problem = int(v_per_problem)
     if precond is not None:
         o.precond = int(precond)
+    if pipeline is not None:
+        o.pipeline = int(pipeline)
     V = None if wl.V is None else to_dev(np.asarray(wl.V, np.float64))
     return swr.Problem(wl.a0, wl.b0, tuple(int(j) for j in wl.J), wl.dt, wl.dt * wl.nt, wl.vkind,
                        wl.trans, wl.sigma, o, V)
