@@ -72,8 +72,8 @@ typedef enum {
 
 typedef struct {
     double tol;        /* FIXED: max |g^{k+1} - g^k| < tol; GMRES: ||d - (I-L)g||_2 <= tol ||d||_2;
-                          |u|^2 preconditioned fixed point: max |g^{k+1} - g^k| < tol max |g^{k+1}|
-                          (per problem).  default 1e-10 */
+                          |u|^2 preconditioned fixed point: max |g^{k+1} - g^k| <
+                          tol max(1, max |g^{k+1}|) (per problem).  default 1e-10 */
     int max_iter;      /* iteration cap (default 20000) */
     int restart;       /* GMRES restart length m (default 30) */
     int solver;        /* swr_solver (default SWR_SOLVER_CAUSAL) */

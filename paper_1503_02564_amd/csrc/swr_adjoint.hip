@@ -49,7 +49,11 @@ __device__ inline void far_history(const cd* Ha, const cd* Hb, const double* bet
         sb[kWave + t] = (i1 >= 0) ? beta[i1] : 0.0;
         __syncthreads();
         const double* bw = sb + (nj - q0 - bbase);
-        for (int i = 0; i < qn; ++i) {
+        // all 64 entries: the staged chunk is zero past qn and the beta
+        // window bw[-i], i < 64, stays inside sb, so the loop unrolls and
+        // its LDS reads overlap
+        #pragma unroll 16
+        for (int i = 0; i < kWave; ++i) {
             const double bt = bw[-i];
             const cd ha = sha[i], hb = shb[i];
             acc_a = mk(acc_a.x + bt * ha.x, acc_a.y + bt * ha.y);

@@ -24,9 +24,9 @@
 // rectangle, one workgroup per output slot);
 // `causal_near_kernel` then
 // marches through the block on one workgroup per problem: wave 0 runs the
-// per-step PCR solve while waves 1..8 gather the in-block history (lags >= 2)
-// of the next step, from the block's g kept in LDS and the lag coefficients
-// kept in registers.
+// per-step PCR solve and adds the lag-1 and lag-2 history, while the other
+// waves gather the lags >= 3 of the step two ahead, from the block's g kept in
+// LDS and the lag coefficients kept in registers.
 #include "swr_common.h"
 
 namespace swr {
@@ -122,7 +122,9 @@ struct FarArgs {
     const cd* d;       // [B][ns][nt]
     const cd* g;       // [B][ns][nt]
     cd* out;           // [B][ns][kTb]  = d + contribution of steps s < n0
-    const cd* facc;    // [B][ns][nt] contribution of steps s < s_from (null: none)
+    const cd* facc;    // [nseg][B][ns][kCausalSuper]: contribution of each finished
+                       // super-block to steps s_from .. s_from + kCausalSuper - 1
+    int nseg;          // number of finished super-blocks (facc null when 0)
     int s_from;        // this kernel sums steps s_from <= s < n0
 };
 
@@ -163,7 +165,9 @@ __global__ __launch_bounds__(256) void causal_far_kernel(FarArgs f) {
     __syncthreads();
     if (sp == 0 && i < f.nb) {
         cd r = f.d[((size_t)b * f.ns + o) * f.nt + n];
-        if (f.facc) r = r + f.facc[((size_t)b * f.ns + o) * f.nt + n];
+        const size_t seg_stride = (size_t)gridDim.y * f.ns * kCausalSuper;
+        const cd* fp = f.facc + ((size_t)b * f.ns + o) * kCausalSuper + (n - f.s_from);
+        for (int q = 0; q < f.nseg; ++q) r = r + fp[q * seg_stride];
         for (int q = 0; q < SPLITS; ++q) r = r + part[q][i];
         f.out[((size_t)b * f.ns + o) * TB + i] = r;
     }
@@ -178,13 +182,26 @@ struct NearArgs {
     cd* g;             // [B][ns][nt]
 };
 
-constexpr int kNearThreads = 64 + 4 * kNearSlots;
+constexpr int kNearClasses = 2;                            // gather threads per slot
+constexpr int kNearLags = (kTb + kNearClasses - 1) / kNearClasses;   // lags per thread
+constexpr int kNearThreads = kWave + kNearClasses * kNearSlots;
 
-// one workgroup per problem; wave 0 = PCR solver, waves 1..8 = gather
+// neighbour values for the lag-1/lag-2 history: lane j - 1 / j + 1 (zero outside)
+__device__ inline cd lane_up1(cd v) { return shfl_up_c(v, 1, mk(0, 0)); }
+__device__ inline cd lane_dn1(cd v) { return shfl_dn_c(v, 1, mk(0, 0)); }
+
+// One workgroup per problem.  Wave 0 solves the per-step block system; lane
+// j owns interface j, i.e. slots 2j (r_j) and 2j+1 (l_{j+1}), and adds the
+// lag-1 and lag-2 history itself from the solutions of the two previous
+// steps it keeps in registers (slot 2j reads x1 of lane j and x0 of lane j+1
+// through X^{j+1,1}, X^{j+1,2}; slot 2j+1 reads x1 of lane j-1 and x0 of lane
+// j through X^{j,3}, X^{j,4}).  The other waves (kNearClasses threads per
+// slot) gather lags >= 3 of the step two ahead from the block's g kept in LDS
+// into a triple buffer, so a step costs one barrier and the solver never
+// waits for LDS written in the same step.
 __global__ __launch_bounds__(kNearThreads) void causal_near_kernel(NearArgs a) {
     __shared__ cd gh[kTb][kNearSlots];
-    __shared__ cd rhs[kNearSlots];
-    __shared__ cd gn[kNearSlots];
+    __shared__ cd gn[3][kNearSlots];
     __shared__ cd spcr[kPcrRec][kWave];
     const int b = blockIdx.x, v = a.per_problem ? b : 0;
     const int tid = threadIdx.x;
@@ -193,41 +210,72 @@ __global__ __launch_bounds__(kNearThreads) void causal_near_kernel(NearArgs a) {
     const cd zero = mk(0, 0);
     cd* gb = a.g + (size_t)b * ns * nt;
     const cd* bb = a.base + (size_t)b * ns * kTb;
+    const cd* cbase = a.cols + (size_t)v * a.N * 4 * nt;
 
     // PCR multipliers -> LDS
     for (int e = tid; e < kPcrRec * kWave; e += blockDim.x)
         (&spcr[0][0])[e] = a.pcr[(size_t)v * kPcrRec * kWave + e];
 
-    // gather role: slot o, lag class c (lags c+1, c+5, ..., c+29)
+    // gather role: slot o, lag class c (lags c+3, c+3+C, c+3+2C, ...)
     const int gt = tid - kWave;
-    const int o = gt >> 2, c = gt & 3;
+    const int o = gt / kNearClasses, c = gt % kNearClasses;
     const bool gather = tid >= kWave && o < ns;
     int sl = -1, sr = -1;
-    cd cl[8], cr[8];
+    cd cl[kNearLags], cr[kNearLags];
 #pragma unroll
-    for (int m = 0; m < 8; ++m) { cl[m] = zero; cr[m] = zero; }
+    for (int m = 0; m < kNearLags; ++m) { cl[m] = zero; cr[m] = zero; }
     if (gather) {
         int k, pl, pr;
         slot_src(o, a.N, k, pl, pr, sl, sr);
-        const cd* base = a.cols + (size_t)(v * a.N + k) * 4 * nt;
+        const cd* base = cbase + (size_t)k * 4 * nt;
 #pragma unroll
-        for (int m = 0; m < 8; ++m) {
-            const int lag = c + 1 + 4 * m;
-            if (lag < nt) {
+        for (int m = 0; m < kNearLags; ++m) {
+            const int lag = c + 3 + kNearClasses * m;
+            if (lag < nt && lag < kTb) {
                 if (sl >= 0) cl[m] = base[(size_t)pl * nt + lag];
                 if (sr >= 0) cr[m] = base[(size_t)pr * nt + lag];
             }
         }
-        if (c == 0) rhs[o] = bb[(size_t)o * kTb + 0];   // step n0: no in-block history
+        // steps 0 and 1 of the block have no in-block history of lag >= 3
+        if (c == 0) {
+            gn[0][o] = bb[(size_t)o * kTb + 0];
+            if (nb > 1) gn[1][o] = bb[(size_t)o * kTb + 1];
+        }
     }
+    // solver role: lag-1 and lag-2 coefficients of my two slots
+    const int j = tid;
+    cd a0[2] = {zero, zero}, a1[2] = {zero, zero}, a2[2] = {zero, zero}, a3[2] = {zero, zero};
+    if (tid < kWave && j < ni) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int lag = q + 1;
+            if (lag < nt) {
+                a0[q] = cbase[((size_t)(j + 1) * 4 + 0) * nt + lag];                        // x1_j
+                if (j + 1 <= a.N - 2) a1[q] = cbase[((size_t)(j + 1) * 4 + 1) * nt + lag];   // x0_{j+1}
+                if (j >= 1) a2[q] = cbase[((size_t)j * 4 + 2) * nt + lag];                  // x1_{j-1}
+                a3[q] = cbase[((size_t)j * 4 + 3) * nt + lag];                              // x0_j
+            }
+        }
+    }
+    cd x0 = zero, x1 = zero, y0 = zero, y1 = zero;   // solutions of steps i-1 and i-2
     __syncthreads();
 
     for (int i = 0; i < nb; ++i) {
         if (tid < kWave) {
-            // per-step solve of (I - C_0) g = rhs by block PCR; lane j = interface j
-            const int j = tid;
+            // right-hand side: base + lags >= 3 (gathered) + lags 1, 2 (here);
+            // lags reaching before the block are in base
             cd p0 = zero, p1 = zero;
-            if (j < ni) { p0 = rhs[2 * j]; p1 = rhs[2 * j + 1]; }
+            if (j < ni) { p0 = gn[i % 3][2 * j]; p1 = gn[i % 3][2 * j + 1]; }
+            const cd x0p = lane_dn1(x0), x1m = lane_up1(x1);
+            const cd y0p = lane_dn1(y0), y1m = lane_up1(y1);
+            if (i >= 1) {
+                p0 = madd(madd(p0, a0[0], x1), a1[0], x0p);
+                p1 = madd(madd(p1, a2[0], x1m), a3[0], x0);
+            }
+            if (i >= 2) {
+                p0 = madd(madd(p0, a0[1], y1), a1[1], y0p);
+                p1 = madd(madd(p1, a2[1], y1m), a3[1], y0);
+            }
 #pragma unroll
             for (int l = 0; l < kPcrLevels; ++l) {
                 const int d = 1 << l;
@@ -240,37 +288,33 @@ __global__ __launch_bounds__(kNearThreads) void causal_near_kernel(NearArgs a) {
                 p1 = msub(msub(msub(msub(p1, k1c, q0m), k1d, q1m), k2c, q0p), k2d, q1p);
             }
             const cd* Di = &spcr[kPcrLevels * 8][j];
-            const cd x0 = madd(Di[0] * p0, Di[1 * kWave], p1);
-            const cd x1 = madd(Di[2 * kWave] * p0, Di[3 * kWave], p1);
+            y0 = x0;
+            y1 = x1;
+            x0 = madd(Di[0] * p0, Di[1 * kWave], p1);
+            x1 = madd(Di[2 * kWave] * p0, Di[3 * kWave], p1);
+            if (j >= ni) { x0 = zero; x1 = zero; }
             if (j < ni) {
                 gh[i][2 * j] = x0;
                 gh[i][2 * j + 1] = x1;
                 gb[(size_t)(2 * j) * nt + n0 + i] = x0;
                 gb[(size_t)(2 * j + 1) * nt + n0 + i] = x1;
             }
-        } else if (i + 1 < nb) {
-            // history of step i+1 from in-block steps up to i-1 (lags >= 2)
+        } else if (i + 2 < nb) {
+            // lags >= 3 of step i+2, from in-block steps up to i-1
             cd part = zero;
 #pragma unroll
-            for (int m = 0; m < 8; ++m) {
-                const int lag = c + 1 + 4 * m;
-                if (lag >= 2 && lag <= i + 1) {
-                    const int s = i + 1 - lag;
+            for (int m = 0; m < kNearLags; ++m) {
+                const int lag = c + 3 + kNearClasses * m;
+                if (lag <= i + 2) {
+                    const int s = i + 2 - lag;
                     if (sl >= 0) part = madd(part, cl[m], gh[s][sl]);
                     if (sr >= 0) part = madd(part, cr[m], gh[s][sr]);
                 }
             }
-            part = mk(part.x + __shfl_xor(part.x, 1), part.y + __shfl_xor(part.y, 1));
-            part = mk(part.x + __shfl_xor(part.x, 2), part.y + __shfl_xor(part.y, 2));
-            if (gather && c == 0) gn[o] = part + bb[(size_t)o * kTb + i + 1];
-        }
-        __syncthreads();
-        if (gather && c == 0 && i + 1 < nb) {
-            // lag 1 needs the step just solved
-            cd r = gn[o];
-            if (sl >= 0) r = madd(r, cl[0], gh[i][sl]);
-            if (sr >= 0) r = madd(r, cr[0], gh[i][sr]);
-            rhs[o] = r;
+#pragma unroll
+            for (int x = 1; x < kNearClasses; x <<= 1)
+                part = mk(part.x + __shfl_xor(part.x, x), part.y + __shfl_xor(part.y, x));
+            if (gather && c == 0) gn[(i + 2) % 3][o] = part + bb[(size_t)o * kTb + i + 2];
         }
         __syncthreads();
     }
@@ -286,7 +330,8 @@ template <int TB>
 static hipError_t launch_causal_far(int N, int nt, int ns, int B, int per_problem, int n0, int nb,
                                     const cd* cols, const cd* d, const cd* g, cd* out,
                                     const cd* facc, int s_from, hipStream_t st) {
-    FarArgs f{N, nt, ns, per_problem, n0, nb, cols, d, g, out, facc, s_from};
+    FarArgs f{N, nt, ns, per_problem, n0, nb, cols, d, g, out, facc,
+              facc ? s_from / kCausalSuper : 0, s_from};
     causal_far_kernel<TB><<<dim3(ns, B), 256, 0, st>>>(f);
     return hipGetLastError();
 }
@@ -401,88 +446,102 @@ struct NearGenArgs {
 
 // one workgroup per problem; per step: gather the in-block history of every
 // slot (coefficients of lags 1..kGenTb-1 in registers), then block PCR
+// One thread per interface j (slots 2j, 2j+1).  Per step: the right-hand
+// side from the base and the in-block lags (coefficients in registers,
+// earlier solutions in LDS), then the levels of block PCR exchanging through
+// two alternating LDS buffers (one barrier per level), with the multipliers
+// of the next level loaded while the current one runs.
 __global__ __launch_bounds__(kGenThreads) void causal_near_gen_kernel(NearGenArgs a) {
     extern __shared__ cd smem[];
     const int ns = a.ns, nt = a.nt, n0 = a.n0, nb = a.nb, ni = a.N - 1;
     cd* gh = smem;                          // [kGenTb][ns]
-    cd* rhs = gh + (size_t)kGenTb * ns;     // [ns]
-    cd* ex = rhs + ns;                      // [ni][2] PCR exchange
+    cd* xa = gh + (size_t)kGenTb * ns;      // [ns] exchange, even levels
+    cd* xb = xa + ns;                       // [ns] exchange, odd levels
     const int b = blockIdx.x, v = a.per_problem ? b : 0;
-    const int tid = threadIdx.x;
+    const int j = threadIdx.x;
+    const bool act = j < ni;
+    const bool has_r = j + 1 <= a.N - 2, has_l = j >= 1;
     const int lv = pcr_levels(ni);
     const cd zero = mk(0, 0);
     cd* gb = a.g + (size_t)b * ns * nt;
     const cd* bb = a.base + (size_t)b * ns * kGenTb;
     const cd* rec = a.pcr + (size_t)v * a.rec;
-    // slots handled by this thread: o0 = tid, o1 = tid + kGenThreads
-    int sl[2], sr[2];
-    cd cl[2][kGenTb - 1], cr[2][kGenTb - 1];
+    const cd* cb = a.cols + (size_t)v * a.N * 4 * nt;
+    // lag m+1 coefficients: slot 2j <- x1_j (c0), x0_{j+1} (c1);
+    //                       slot 2j+1 <- x1_{j-1} (c2), x0_j (c3)
+    cd c0[kGenTb - 1], c1[kGenTb - 1], c2[kGenTb - 1], c3[kGenTb - 1];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int o = tid + h * kGenThreads;
-        sl[h] = sr[h] = -1;
-#pragma unroll
-        for (int m = 0; m < kGenTb - 1; ++m) { cl[h][m] = zero; cr[h][m] = zero; }
-        if (o < ns) {
-            int k, pl, pr;
-            slot_src(o, a.N, k, pl, pr, sl[h], sr[h]);
-            const cd* base = a.cols + (size_t)(v * a.N + k) * 4 * nt;
-#pragma unroll
-            for (int m = 0; m < kGenTb - 1; ++m) {
-                const int lag = m + 1;
-                if (lag < nt) {
-                    if (sl[h] >= 0) cl[h][m] = base[(size_t)pl * nt + lag];
-                    if (sr[h] >= 0) cr[h][m] = base[(size_t)pr * nt + lag];
-                }
-            }
+    for (int m = 0; m < kGenTb - 1; ++m) {
+        const int lag = m + 1;
+        c0[m] = c1[m] = c2[m] = c3[m] = zero;
+        if (act && lag < nt) {
+            c0[m] = cb[((size_t)(j + 1) * 4 + 0) * nt + lag];
+            if (has_r) c1[m] = cb[((size_t)(j + 1) * 4 + 1) * nt + lag];
+            if (has_l) c2[m] = cb[((size_t)j * 4 + 2) * nt + lag];
+            c3[m] = cb[((size_t)j * 4 + 3) * nt + lag];
         }
     }
-    for (int i = 0; i < nb; ++i) {
+    cd di0 = zero, di1 = zero, di2 = zero, di3 = zero;
+    if (act) {
+        const cd* Di = rec + (size_t)lv * 8 * ni + j;
+        di0 = Di[0]; di1 = Di[1 * ni]; di2 = Di[2 * ni]; di3 = Di[3 * ni];
+    }
+    auto loadK = [rec, ni, j, act](int l, cd (&K)[8]) {
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int o = tid + h * kGenThreads;
-            if (o < ns) {
-                cd r = bb[(size_t)o * kGenTb + i];
+        for (int q = 0; q < 8; ++q) K[q] = act ? rec[((size_t)l * 8 + q) * ni + j] : mk(0, 0);
+    };
+    cd Kc[8], Kn[8];
+    loadK(0, Kc);
+    cd bn0 = act ? bb[(size_t)(2 * j) * kGenTb] : zero;
+    cd bn1 = act ? bb[(size_t)(2 * j + 1) * kGenTb] : zero;
+
+#pragma unroll
+    for (int i = 0; i < kGenTb; ++i) {
+        if (i < nb) {
+            cd p0 = bn0, p1 = bn1;
+            if (act && i + 1 < nb) {
+                bn0 = bb[(size_t)(2 * j) * kGenTb + i + 1];
+                bn1 = bb[(size_t)(2 * j + 1) * kGenTb + i + 1];
+            }
+            if (act) {
 #pragma unroll
                 for (int m = 0; m < kGenTb - 1; ++m) {
                     const int lag = m + 1;
                     if (lag <= i) {
-                        if (sl[h] >= 0) r = madd(r, cl[h][m], gh[(size_t)(i - lag) * ns + sl[h]]);
-                        if (sr[h] >= 0) r = madd(r, cr[h][m], gh[(size_t)(i - lag) * ns + sr[h]]);
+                        const cd* gs = gh + (size_t)(i - lag) * ns;
+                        p0 = madd(p0, c0[m], gs[2 * j + 1]);
+                        if (has_r) p0 = madd(p0, c1[m], gs[2 * j + 2]);
+                        if (has_l) p1 = madd(p1, c2[m], gs[2 * j - 1]);
+                        p1 = madd(p1, c3[m], gs[2 * j]);
                     }
                 }
-                rhs[o] = r;
             }
-        }
-        __syncthreads();
-        // block PCR, one thread per interface
-        const int j = tid;
-        cd p0 = zero, p1 = zero;
-        if (j < ni) { p0 = rhs[2 * j]; p1 = rhs[2 * j + 1]; }
-        for (int l = 0; l < lv; ++l) {
-            const int d = 1 << l;
-            if (j < ni) { ex[2 * j] = p0; ex[2 * j + 1] = p1; }
-            __syncthreads();
-            if (j < ni) {
-                const bool hm = j - d >= 0, hp = j + d < ni;
-                const cd q0m = hm ? ex[2 * (j - d)] : zero, q1m = hm ? ex[2 * (j - d) + 1] : zero;
-                const cd q0p = hp ? ex[2 * (j + d)] : zero, q1p = hp ? ex[2 * (j + d) + 1] : zero;
-                const cd* K = rec + (size_t)l * 8 * ni + j;
-                p0 = msub(msub(msub(msub(p0, K[0 * ni], q0m), K[1 * ni], q1m), K[4 * ni], q0p), K[5 * ni], q1p);
-                p1 = msub(msub(msub(msub(p1, K[2 * ni], q0m), K[3 * ni], q1m), K[6 * ni], q0p), K[7 * ni], q1p);
+            for (int l = 0; l < lv; ++l) {
+                const int d = 1 << l;
+                loadK(l + 1 < lv ? l + 1 : 0, Kn);     // next level (or next step's first)
+                cd* ex = (l & 1) ? xb : xa;
+                if (act) { ex[2 * j] = p0; ex[2 * j + 1] = p1; }
+                __syncthreads();
+                if (act) {
+                    const bool hm = j - d >= 0, hp = j + d < ni;
+                    const cd q0m = hm ? ex[2 * (j - d)] : zero, q1m = hm ? ex[2 * (j - d) + 1] : zero;
+                    const cd q0p = hp ? ex[2 * (j + d)] : zero, q1p = hp ? ex[2 * (j + d) + 1] : zero;
+                    p0 = msub(msub(msub(msub(p0, Kc[0], q0m), Kc[1], q1m), Kc[4], q0p), Kc[5], q1p);
+                    p1 = msub(msub(msub(msub(p1, Kc[2], q0m), Kc[3], q1m), Kc[6], q0p), Kc[7], q1p);
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q) Kc[q] = Kn[q];
+            }
+            if (act) {
+                const cd x0 = madd(di0 * p0, di1, p1);
+                const cd x1 = madd(di2 * p0, di3, p1);
+                gh[(size_t)i * ns + 2 * j] = x0;
+                gh[(size_t)i * ns + 2 * j + 1] = x1;
+                gb[(size_t)(2 * j) * nt + n0 + i] = x0;
+                gb[(size_t)(2 * j + 1) * nt + n0 + i] = x1;
             }
             __syncthreads();
         }
-        if (j < ni) {
-            const cd* Di = rec + (size_t)lv * 8 * ni + j;
-            const cd x0 = madd(Di[0] * p0, Di[1 * ni], p1);
-            const cd x1 = madd(Di[2 * ni] * p0, Di[3 * ni], p1);
-            gh[(size_t)i * ns + 2 * j] = x0;
-            gh[(size_t)i * ns + 2 * j + 1] = x1;
-            gb[(size_t)(2 * j) * nt + n0 + i] = x0;
-            gb[(size_t)(2 * j + 1) * nt + n0 + i] = x1;
-        }
-        __syncthreads();
     }
 }
 

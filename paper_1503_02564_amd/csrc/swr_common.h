@@ -45,14 +45,35 @@ __device__ inline double rdlane(double v, int l) {
 }
 __device__ inline cd rdlane(cd v, int l) { return mk(rdlane(v.x, l), rdlane(v.y, l)); }
 
-// value of lane (lane - d); lanes below d receive `fill`
+// whole-wave shift of one double by one lane through DPP (CTRL 0x138: lane
+// i reads lane i - 1; 0x130: lane i reads lane i + 1); the lane without a
+// source keeps 0
+template <int CTRL>
+__device__ inline double dpp_shift(double v) {
+    int2 t = *reinterpret_cast<int2*>(&v);
+    t.x = __builtin_amdgcn_update_dpp(0, t.x, CTRL, 0xf, 0xf, false);
+    t.y = __builtin_amdgcn_update_dpp(0, t.y, CTRL, 0xf, 0xf, false);
+    return *reinterpret_cast<double*>(&t);
+}
+
+// value of lane (lane - d); lanes below d receive `fill`.  Distance 1 is a
+// DPP wave shift (no LDS round trip), other distances a permute.  Both run
+// on every lane of the wave.
 __device__ inline cd shfl_up_c(cd v, int d, cd fill) {
+    if (d == 1) {
+        const cd r = mk(dpp_shift<0x138>(v.x), dpp_shift<0x138>(v.y));
+        return lane_id() == 0 ? fill : r;
+    }
     int src = lane_id() - d;
     cd r = mk(__shfl(v.x, src < 0 ? 0 : src), __shfl(v.y, src < 0 ? 0 : src));
     return src < 0 ? fill : r;
 }
 // value of lane (lane + d); lanes with lane + d >= 64 receive `fill`
 __device__ inline cd shfl_dn_c(cd v, int d, cd fill) {
+    if (d == 1) {
+        const cd r = mk(dpp_shift<0x130>(v.x), dpp_shift<0x130>(v.y));
+        return lane_id() == kWave - 1 ? fill : r;
+    }
     int src = lane_id() + d;
     cd r = mk(__shfl(v.x, src > 63 ? 63 : src), __shfl(v.y, src > 63 ? 63 : src));
     return src > 63 ? fill : r;
@@ -156,6 +177,9 @@ struct LttArgs {
     int n_lo, n_hi;        // output time window
     int s_lo, s_hi;        // only inputs s_lo <= s < s_hi contribute (and s <= n)
     int y_ld;              // leading dimension of y / base per (b, slot)
+    int s_seg;             // > 0: split the inputs into segments of s_seg steps, segment z
+                           // writing its own partial at y + z * y_seg_stride (base ignored)
+    size_t y_seg_stride;
 };
 
 // In-block forward substitution of the causal interface solve.

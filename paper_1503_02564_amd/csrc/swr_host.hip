@@ -90,7 +90,8 @@ struct swr_ctx {
     double* dRes = nullptr;
     int* dAct = nullptr;
     cd* dFar = nullptr;       // causal dense path
-    cd* dFacc = nullptr;      // causal PCR paths: contribution of finished super-blocks
+    cd* dFacc = nullptr;      // causal PCR paths: [seg][B][ns][256] contribution of each
+                              // finished super-block to the current one
     cd* dBase = nullptr;      // causal PCR path
     int base_tb = 0;
     // adjoint
@@ -571,7 +572,9 @@ static swr_status run_causal(swr_ctx* c, Iface& I, const cd* d, cd* g, hipStream
             ALLOC_LIVE(c->dBase, (size_t)B * ns * tb);
             c->base_tb = tb;
         }
-        if (!c->dFacc) ALLOC_LIVE(c->dFacc, (size_t)B * ns * nt);
+        const int max_seg = (nt - 1) / kCausalSuper;
+        if (!c->dFacc && max_seg > 0)
+            ALLOC_LIVE(c->dFacc, (size_t)max_seg * B * ns * kCausalSuper);
         // super-blocks are the absolute windows [S, S + kCausalSuper); the
         // steps [a0, a1) of one of them take the contribution of the finished
         // super-blocks (steps < S) from one block-Toeplitz product, which
@@ -582,10 +585,13 @@ static swr_status run_causal(swr_ctx* c, Iface& I, const cd* d, cd* g, hipStream
             const int S = a0 / kCausalSuper * kCausalSuper;
             const int a1 = std::min(n_hi, S + kCausalSuper);
             if (S > 0) {
+                // one partial per finished super-block (split over the sources)
                 LttArgs l{};
                 l.N = c->N; l.nt = nt; l.ns = ns; l.B = B; l.per_problem = I.nv > 1;
-                l.cols = I.cols; l.x = g; l.y = c->dFacc + a0; l.base = nullptr;
-                l.sign = 1.0; l.n_lo = a0; l.n_hi = a1; l.s_lo = 0; l.s_hi = S; l.y_ld = nt;
+                l.cols = I.cols; l.x = g; l.y = c->dFacc + (a0 - S); l.base = nullptr;
+                l.sign = 1.0; l.n_lo = a0; l.n_hi = a1; l.s_lo = 0; l.s_hi = S;
+                l.y_ld = kCausalSuper; l.s_seg = kCausalSuper;
+                l.y_seg_stride = (size_t)B * ns * kCausalSuper;
                 HIPCHK(launch_ltt(l, st));
             }
             const cd* facc = S > 0 ? c->dFacc : nullptr;
@@ -700,10 +706,11 @@ static swr_status run_precond_cubic(swr_ctx* c, const cd* u0, int* iters, double
         HIPCHK(hipMemcpyAsync(m.data(), c->dNrm, sizeof(double) * c->B, hipMemcpyDeviceToHost, c->st));
         HIPCHK(hipMemcpyAsync(gm.data(), c->dBn, sizeof(double) * c->B, hipMemcpyDeviceToHost, c->st));
         HIPCHK(hipStreamSynchronize(c->st));
-        // change relative to the size of the traces (they scale like
-        // sqrt(2/dt) |v|, so an absolute bound can sit below FP64 resolution)
+        // change relative to the size of the traces once they exceed 1 (they
+        // scale like sqrt(2/dt) |v|, so an absolute bound can sit below FP64
+        // resolution)
         double d = 0;
-        for (int b = 0; b < c->B; ++b) d = std::max(d, gm[b] > 0 ? m[b] / gm[b] : m[b]);
+        for (int b = 0; b < c->B; ++b) d = std::max(d, m[b] / std::max(1.0, gm[b]));
         *last = d;
         *iters = it;
         if (!std::isfinite(d)) return SWR_ENAN;

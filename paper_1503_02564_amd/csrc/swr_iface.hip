@@ -50,21 +50,25 @@ __device__ inline d4 mfma16(double a, double b, d4 c) {
 __global__ __launch_bounds__(256) void ltt_mfma_kernel(LttArgs a) {
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const int tile = blockIdx.x * 4 + w;
-    const int o = blockIdx.y, b = blockIdx.z;
+    const int o = blockIdx.y;
+    const int b = a.s_seg > 0 ? blockIdx.z % a.B : blockIdx.z;
+    const int seg = a.s_seg > 0 ? blockIdx.z / a.B : 0;
     const int nlen = a.n_hi - a.n_lo;
     if (tile * 256 >= nlen) return;                 // whole wave leaves together
+    const int s_lo = a.s_seg > 0 ? a.s_lo + seg * a.s_seg : a.s_lo;
+    const int s_hi = a.s_seg > 0 ? min(a.s_hi, s_lo + a.s_seg) : a.s_hi;
     int k, pl, pr, sl, sr;
     slot_sources(o, a.N, k, pl, pr, sl, sr);
     const int v = a.per_problem ? b : 0;
     const cd* cl = a.cols + ((size_t)(v * a.N + k) * 4 + pl) * a.nt;
     const cd* cr = a.cols + ((size_t)(v * a.N + k) * 4 + pr) * a.nt;
-    const cd* xl = sl >= 0 ? a.x + ((size_t)b * a.ns + sl) * a.nt + a.s_lo : nullptr;
-    const cd* xr = sr >= 0 ? a.x + ((size_t)b * a.ns + sr) * a.nt + a.s_lo : nullptr;
+    const cd* xl = sl >= 0 ? a.x + ((size_t)b * a.ns + sl) * a.nt + s_lo : nullptr;
+    const cd* xr = sr >= 0 ? a.x + ((size_t)b * a.ns + sr) * a.nt + s_lo : nullptr;
     const int r = lane & 15, kq = lane >> 4;
     const int I0 = tile * 16;
-    const int slen = a.s_hi - a.s_lo;
+    const int slen = s_hi - s_lo;
     const int Jn = (slen + 15) / 16;
-    const int delta = a.n_lo - a.s_lo;
+    const int delta = a.n_lo - s_lo;
     // lag blocks that can meet a source block J in [0, Jn) and a lag >= 0
     const int q = -delta - 15;
     const int m_lag = q >= 0 ? (q + 15) / 16 : -((-q) / 16);
@@ -98,13 +102,14 @@ __global__ __launch_bounds__(256) void ltt_mfma_kernel(LttArgs a) {
             }
         }
     }
-    const size_t yb = ((size_t)b * a.ns + o) * a.y_ld;
+    const size_t yb = ((size_t)b * a.ns + o) * a.y_ld + (size_t)seg * a.y_seg_stride;
+    const cd* base = a.s_seg > 0 ? nullptr : a.base;
 #pragma unroll
     for (int qq = 0; qq < 4; ++qq) {
         const int nrel = 16 * (I0 + r) + kq + 4 * qq;
         if (nrel < nlen) {
             cd out = mk(a.sign * yr[qq], a.sign * yi[qq]);
-            if (a.base) out = out + a.base[yb + nrel];
+            if (base) out = out + base[yb + nrel];
             a.y[yb + nrel] = out;
         }
     }
@@ -114,7 +119,9 @@ hipError_t launch_ltt(const LttArgs& a, hipStream_t st) {
     if (a.ns == 0 || a.n_hi <= a.n_lo) return hipSuccess;
     if (a.s_lo < 0 || a.s_hi > a.nt || a.n_lo < 0 || a.n_hi > a.nt) return hipErrorInvalidValue;
     const int tiles = (a.n_hi - a.n_lo + 255) / 256;
-    dim3 grid((tiles + 3) / 4, a.ns, a.B);
+    const int nseg = a.s_seg > 0 ? (a.s_hi - a.s_lo + a.s_seg - 1) / a.s_seg : 1;
+    if ((size_t)a.B * nseg > 65535) return hipErrorInvalidValue;
+    dim3 grid((tiles + 3) / 4, a.ns, a.B * nseg);
     ltt_mfma_kernel<<<grid, 256, 0, st>>>(a);
     return hipGetLastError();
 }

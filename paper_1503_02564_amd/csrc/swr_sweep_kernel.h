@@ -153,17 +153,34 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
         if (TR == TR_S02) {
             __threadfence_block();
             const int nj = n0 + 1 + t;
+            // the loads of chunk q0 + 64 are issued before chunk q0 is summed
+            cd pa = zero, pb = zero;
+            double pb0 = 0.0, pb1 = 0.0;
+            auto fetch = [&](int q0) {
+                const int qn = min(kWave, n0 + 1 - q0);
+                const int bbase = n0 - q0 - (kWave - 2);   // beta index of sb[0]
+                pa = (t < qn) ? Ha[q0 + t] : mk(0, 0);
+                pb = (t < qn) ? Hb[q0 + t] : mk(0, 0);
+                const int i0 = bbase + t, i1 = bbase + kWave + t;
+                pb0 = (i0 >= 0) ? a.beta[i0] : 0.0;
+                pb1 = (i1 >= 0) ? a.beta[i1] : 0.0;
+            };
+            fetch(0);
             for (int q0 = 0; q0 <= n0; q0 += kWave) {
                 const int qn = min(kWave, n0 + 1 - q0);
                 const int bbase = n0 - q0 - (kWave - 2);   // beta index of sb[0]
-                sha[t] = (t < qn) ? Ha[q0 + t] : zero;
-                shb[t] = (t < qn) ? Hb[q0 + t] : zero;
-                const int i0 = bbase + t, i1 = bbase + kWave + t;
-                sb[t] = (i0 >= 0) ? a.beta[i0] : 0.0;
-                sb[kWave + t] = (i1 >= 0) ? a.beta[i1] : 0.0;
+                sha[t] = pa;
+                shb[t] = pb;
+                sb[t] = pb0;
+                sb[kWave + t] = pb1;
+                if (q0 + kWave <= n0) fetch(q0 + kWave);
                 __syncthreads();
                 const double* bw = sb + (nj - q0 - bbase);  // beta_{nj - q0 - i} = bw[-i]
-                for (int i = 0; i < qn; ++i) {
+                // all 64 entries: the staged chunk is zero past qn and the beta
+                // window bw[-i], i < 64, stays inside sb, so the loop unrolls and
+                // its LDS reads overlap
+                #pragma unroll 16
+                for (int i = 0; i < kWave; ++i) {
                     const double bt = bw[-i];
                     const cd ha = sha[i], hb = shb[i];
                     acc_a = mk(acc_a.x + bt * ha.x, acc_a.y + bt * ha.y);

@@ -98,12 +98,14 @@ def test_full_size_config5_forward_adjoint_and_fd(dev):
         return np.real(np.sum((a - b_) * np.conj(a + b_ - 2.0 * target[None]), axis=1))
 
     def check(an, cs, d1, dR, what):
-        # h = 1e-6: J itself is reproduced only to ~1e-12 relative (GPU and
-        # oracle states agree to that at this size), so a central difference
-        # resolves dJ to ~1e-12 J / h; Richardson extrapolation of h = 1e-2
-        # and 5e-3 removes the O(h^2) term and stays far above that floor.
+        # h = 1e-6: the states are reproduced to ~1e-12 relative (GPU and
+        # oracle agree to that at this size), so J(+) - J(-) carries a
+        # rounding error up to ~2e-12 |u| |u - u*| and the central difference
+        # one of 2e-12 |u| sqrt(J) / h (the oracle's own differences stay
+        # within it).  Richardson extrapolation of h = 1e-2 and 5e-3 removes
+        # the O(h^2) term and stays far above that floor: checked to 1e-6.
         fd6 = d1 / 2e-6
-        floor6 = 1e-12 * J0 / 1e-6
+        floor6 = 2e-12 * unorm * np.sqrt(J0) / 1e-6
         tol_r = 1e-6 * np.maximum(np.abs(an), 1e-6 * cs)
         say("fd", what, "max |fd(1e-6)-an|/floor", float(np.max(np.abs(fd6 - an) / floor6)),
             "max |richardson-an|/tol", float(np.max(np.abs(dR - an) / tol_r)))
@@ -111,6 +113,7 @@ def test_full_size_config5_forward_adjoint_and_fd(dev):
         assert np.all(np.abs(dR - an) <= tol_r), (dR, an)
 
     J0 = np.sum(np.abs(got - target[None]) ** 2, axis=1)
+    unorm = np.linalg.norm(got, axis=1)
     rng = np.random.default_rng(55)
     x = W.mesh_nodes(wl.a0, wl.b0, wl.nc)
     hR = 1e-2
@@ -140,11 +143,14 @@ def test_full_size_config5_forward_adjoint_and_fd(dev):
 
 def test_full_size_config4a_time_dependent_potential(dev):
     """V(t,x) = 5 x cos t on 128 x 256 cells over 4000 steps: preconditioned
-    GMRES with the matrix-free interface operator, against the oracle."""
+    GMRES with the matrix-free interface operator, against the oracle.  Over
+    this window P = I - L_0 leaves a slowly converging problem (33 iterations
+    at 1000 steps, ~100 at 2000, several hundred at 4000; GMRES(60)
+    stagnates), so the run uses GMRES(200)."""
     from paper_1503_02564_amd import swr
     wl = W.config4a()
     say("full-size", "config4a")
-    st, info, uT = _solve(dev, wl, tol=1e-13, restart=60, max_iter=2000)
+    st, info, uT = _solve(dev, wl, tol=1e-11, restart=200, max_iter=1500)
     say("full-size", "config4a done", info.as_dict())
     assert st == swr.SWR_OK
     assert rel(uT[0], O.mono(wl, wl.u0[0])) < 1e-10
