@@ -10,6 +10,7 @@ paper in numpy, in the paper's order and notation:
 * ``brute_L``          -- L column by column from R(e_i) (Props. 1-2), tiny sizes
 * ``ltt_apply``        -- L g from first columns     (Props. 3-4: lower-triangular Toeplitz)
 * ``gmres``            -- restarted GMRES (Saad, Alg. 6.9), plain MGS + Givens
+* ``bicgstab``         -- BiCGStab (van der Vorst 1992), the paper's GPU solver
 * ``causal_solve``     -- (I - L) g = d by forward substitution in time
 * ``new_algorithm``    -- Sec. 4 "New algorithm": build L and d, solve, final sweep
 * ``preconditioned``   -- Sec. 5: P = I - L_0 for V(t,x) and |u|^2
@@ -34,7 +35,7 @@ from . import build as _build
 __all__ = [
     "lib", "alpha", "beta", "c2_of", "assemble", "mass_apply", "thomas", "mono",
     "sweep", "slot_map", "apply_R", "apply_R0", "local_solution", "classical",
-    "impulse_columns", "ltt_apply", "brute_L", "gmres", "causal_solve",
+    "impulse_columns", "ltt_apply", "brute_L", "gmres", "bicgstab", "causal_solve",
     "interface_d", "new_algorithm", "preconditioned_time", "preconditioned_cubic",
     "adjoint_mono", "potential_of",
 ]
@@ -414,6 +415,48 @@ def gmres(matvec, b, x0=None, tol=1e-10, restart=30, maxit=5000):
     return x, -its if np.linalg.norm(r) > tol * bn else its, hist
 
 
+def bicgstab(matvec, b, x0=None, tol=1e-10, maxit=5000):
+    """BiCGStab (van der Vorst, SIAM J. Sci. Stat. Comput. 13, 1992), the
+    Krylov method of the paper's GPU runs (Sec. 6), unpreconditioned, for
+    complex systems with the shadow residual r^_0 = r_0 and <u, w> =
+    conj(u)^T w.  Stops when ||r||_2 <= tol ||b||_2 (checked on s after the
+    half step and on r after the full step).  Returns (x, iterations,
+    residual history); iterations are negative when maxit was reached."""
+    b = np.asarray(b, np.complex128).ravel()
+    x = np.zeros_like(b) if x0 is None else np.array(x0, np.complex128).ravel()
+    bn = np.linalg.norm(b)
+    if bn == 0.0:
+        return x, 0, [0.0]
+    r = b - matvec(x)
+    rh = r.copy()
+    rho = alpha = omega = 1.0 + 0j
+    v = np.zeros_like(b)
+    p = np.zeros_like(b)
+    hist = [np.linalg.norm(r) / bn]
+    if hist[0] <= tol:
+        return x, 0, hist
+    for it in range(1, maxit + 1):
+        rho_new = np.vdot(rh, r)
+        beta = (rho_new / rho) * (alpha / omega)
+        p = r + beta * (p - omega * v)
+        v = matvec(p)
+        alpha = rho_new / np.vdot(rh, v)
+        s = r - alpha * v
+        if np.linalg.norm(s) <= tol * bn:
+            x = x + alpha * p
+            hist.append(np.linalg.norm(s) / bn)
+            return x, it, hist
+        t = matvec(s)
+        omega = np.vdot(t, s) / np.vdot(t, t)
+        x = x + alpha * p + omega * s
+        r = s - omega * t
+        hist.append(np.linalg.norm(r) / bn)
+        if hist[-1] <= tol:
+            return x, it, hist
+        rho = rho_new
+    return x, -maxit, hist
+
+
 def causal_solve(wl: Workload, cols, d):
     """Solve (I - L) g = d exactly for block lower-triangular-Toeplitz L by
     forward substitution in time.  With C_m the (2N-2)x(2N-2) matrix of the
@@ -473,6 +516,10 @@ def new_algorithm(wl: Workload, u0, solver="gmres", tol=1e-10, restart=30, maxit
             g = gn
             if ch < tol or its >= maxit:
                 break
+    elif solver == "bicgstab":
+        mv = lambda x: x - ltt_apply(wl, cols, x.reshape(ns, -1)).ravel()  # noqa: E731
+        gv, its, _ = bicgstab(mv, d.ravel(), tol=tol, maxit=maxit)
+        g = gv.reshape(d.shape)
     else:
         mv = lambda x: x - ltt_apply(wl, cols, x.reshape(ns, -1)).ravel()  # noqa: E731
         gv, its, _ = gmres(mv, d.ravel(), tol=tol, restart=restart, maxit=maxit)

@@ -157,11 +157,39 @@ def test_gmres_on_dense_random_system():
     assert its > 0 and _rel(x, np.linalg.solve(A, b)) < 1e-11
 
 
+def test_bicgstab_on_dense_complex_systems():
+    """BiCGStab against a dense solve: a complex non-symmetric system with a
+    spread spectrum, and the interface problem (I - L) g = d itself (dense L
+    from R(e_i), Props. 1-2)."""
+    rng = np.random.default_rng(5)
+    n = 50
+    A = np.eye(n) * (2 + 1j) + 0.4 * (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(n)
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    x, its, hist = O.bicgstab(lambda v: A @ v, b, tol=1e-13, maxit=500)
+    assert its > 0 and _rel(x, np.linalg.solve(A, b)) < 1e-11
+    assert hist[-1] <= 1e-13
+    wl = W.small_case(J=[8, 10, 7], nt=10, seed=12)
+    d = O.interface_d(wl, wl.u0[0])
+    Lm = O.brute_L(wl)
+    M = np.eye(Lm.shape[0]) - Lm
+    g, its, _ = O.bicgstab(lambda v: M @ v, d.ravel(), tol=1e-13, maxit=500)
+    assert its > 0 and _rel(g, np.linalg.solve(M, d.ravel())) < 1e-11
+
+
+def test_bicgstab_breaks_off_at_maxit():
+    """An iteration cap is reported as a negative count, not as success."""
+    rng = np.random.default_rng(6)
+    A = np.diag(np.linspace(1, 1e4, 200)) + 0j
+    b = rng.standard_normal(200) + 0j
+    _, its, hist = O.bicgstab(lambda v: A @ v, b, tol=1e-15, maxit=3)
+    assert its == -3 and len(hist) == 4
+
+
 def test_new_algorithm_equals_monodomain():
     wl = W.small_case(J=[15, 22, 18, 11], nt=60, seed=21)
     u0 = wl.u0[0]
     um = O.mono(wl, u0)
-    for solver in ("gmres", "causal", "fixed"):
+    for solver in ("gmres", "bicgstab", "causal", "fixed"):
         uT, g, info = O.new_algorithm(wl, u0, solver=solver, tol=1e-13)
         assert _rel(uT, um) < 1e-11, solver
 
