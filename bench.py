@@ -53,7 +53,7 @@ def sweep_flops_per_pt_step(wl) -> float:
 
 
 SWEEP_SOURCES = ("paper_1503_02564_amd/csrc/swr_sweep_kernel.h", "paper_1503_02564_amd/csrc/swr_lane.h",
-                 "paper_1503_02564_amd/csrc/swr_common.h", "paper_1503_02564_amd/csrc/swr_sweep_static.hip")
+                 "paper_1503_02564_amd/csrc/swr_sweep_static.hip", "paper_1503_02564_amd/csrc/swr_sweep.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_kernel_config2_hbm.txt")
 
 
@@ -180,6 +180,36 @@ def adjoint_ratio(steps, warmup):
     return res
 
 
+def batched_vs_plain(batched_ms):
+    """The same config-2 solve with every sweep task launched on its own
+    (one subdomain of one problem per launch, one stream, staged), against
+    the batched and pipelined form: same kernels, same interface solve, same
+    certified residual."""
+    import torch
+    from paper_1503_02564_amd import swr
+    from paper_1503_02564_amd import workloads as W
+    wl = W.config2()
+    dev = torch.device("cuda:0")
+    o = swr.swr_default_opts()
+    o.tol = wl.tol
+    o.plain = 1
+    V = torch.from_numpy(np.ascontiguousarray(wl.V)).to(dev)
+    u0 = torch.from_numpy(np.ascontiguousarray(wl.u0)).to(dev)
+    uT = torch.zeros_like(u0)
+    pb = swr.Problem(wl.a0, wl.b0, tuple(int(j) for j in wl.J), wl.dt, wl.dt * wl.nt, wl.vkind,
+                     wl.trans, wl.sigma, o, V)
+    swr.swr_solve(pb.ctx, u0, uT)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, info = swr.swr_solve(pb.ctx, u0, uT)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0)
+    pb.close()
+    return dict(plain_ms_per_solve=ms, batched_ms_per_solve=batched_ms,
+                speedup_batched_over_plain=ms / batched_ms, plain_residual=info.residual,
+                launches_plain=int(2 * wl.N * wl.B + 2 * wl.N - 2))
+
+
 def calibrate_copy(mib):
     """A plain copy of a known size, for scaling the HBM byte counters."""
     import torch
@@ -198,7 +228,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--solver", default="causal", choices=["causal", "gmres", "fixed"])
+    ap.add_argument("--solver", default="causal", choices=["causal", "gmres", "bicgstab", "fixed"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
     ap.add_argument("--pipeline", type=int, default=256,
                     help="steps per pipeline chunk of the causal solve (0 = staged)")
@@ -207,6 +237,8 @@ def main():
                     help="skip the adjoint/forward ratio on the differentiation workload")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain MIB-MiB device copy (counter calibration)")
+    ap.add_argument("--no-plain", dest="plain", action="store_false",
+                    help="skip the one-launch-per-subdomain comparison")
     ap.add_argument("--source-hash", action="store_true",
                     help="print the sweep kernel source hash and exit")
     args = ap.parse_args()
@@ -230,7 +262,7 @@ def main():
     dev = torch.device("cuda:0")
     o = swr.swr_default_opts()
     o.solver = dict(causal=swr.SWR_SOLVER_CAUSAL, gmres=swr.SWR_SOLVER_GMRES,
-                    fixed=swr.SWR_SOLVER_FIXED)[args.solver]
+                    bicgstab=swr.SWR_SOLVER_BICGSTAB, fixed=swr.SWR_SOLVER_FIXED)[args.solver]
     o.tol = wl.tol
     o.pipeline = args.pipeline
     V = torch.from_numpy(np.ascontiguousarray(wl.V)).to(dev)
@@ -273,6 +305,10 @@ def main():
             "avg_launch_ms": t_sweep_ms / n_launch, "launches_per_solve": n_launch,
             "flops_per_launch": flops / n_launch, "flops_per_pt_step": fpp}
 
+    plain = None
+    if args.plain:
+        plain = batched_vs_plain(ms)
+
     adj = None
     if not args.no_adjoint:
         adj = adjoint_ratio(max(1, min(args.steps, 5)), 1)
@@ -294,6 +330,7 @@ def main():
                    "nx": wl.nx, "nt": wl.nt, "N": wl.N, "B": wl.B, "solver": args.solver,
                    "pipeline": args.pipeline if args.solver == "causal" else 0},
         "interface_residual": resid, "phases_ms": ph,
+        "batched_vs_plain": plain,
         "adjoint_forward_cost_ratio": None if adj is None else adj["ratio_bwd_over_fwd"],
         "adjoint": adj,
         "roofline": roof, "cpu_baseline": cpu,

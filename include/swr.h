@@ -67,11 +67,12 @@ typedef enum { SWR_V_STATIC = 0, SWR_V_TIME = 1, SWR_V_CUBIC = 2 } swr_vkind;
 typedef enum {
     SWR_SOLVER_FIXED = 0,   /* fixed point g <- R g (Sec. 4 "Classical algorithm") */
     SWR_SOLVER_GMRES = 1,   /* restarted GMRES on (I - L) g = d (Sec. 4) */
-    SWR_SOLVER_CAUSAL = 2   /* exact forward substitution in time on (I - L) g = d */
+    SWR_SOLVER_CAUSAL = 2,  /* exact forward substitution in time on (I - L) g = d */
+    SWR_SOLVER_BICGSTAB = 3 /* BiCGStab on (I - L) g = d (the Krylov solver of Sec. 6) */
 } swr_solver;
 
 typedef struct {
-    double tol;        /* FIXED: max |g^{k+1} - g^k| < tol; GMRES: ||d - (I-L)g||_2 <= tol ||d||_2;
+    double tol;        /* FIXED: max |g^{k+1} - g^k| < tol; GMRES, BICGSTAB: ||d - (I-L)g||_2 <= tol ||d||_2;
                           |u|^2 preconditioned fixed point: max |g^{k+1} - g^k| <
                           tol max(1, max |g^{k+1}|) (per problem).  default 1e-10 */
     int max_iter;      /* iteration cap (default 20000) */
@@ -88,6 +89,9 @@ typedef struct {
                           the interface solve and the final sweep chunk by chunk on two extra
                           internal streams (joined back to the context's stream before the call
                           returns); 0 = one stage after the other (default 256) */
+    int plain;         /* 1 = launch the subdomain sweeps one task (one subdomain of one problem)
+                          per launch on the context's stream, staged: the unbatched form, for
+                          comparison with the batched launches (default 0) */
 } swr_opts;
 
 typedef struct {

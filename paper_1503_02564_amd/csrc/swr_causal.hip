@@ -81,14 +81,19 @@ __global__ __launch_bounds__(64) void causal_pcr_setup_kernel(int N, int nt, con
         U = m2(-x2, zero, zero, zero);
         Lm = m2(zero, zero, zero, -x3);
     }
-    double e = norm_inf(inv2(D)) * (norm_inf(Lm) + norm_inf(U));
-    e = wave_max(e);
-    if (j == 0) eta[v] = e;
     cd* rec = pcr + (size_t)v * kPcrRec * kWave + j;
-    // runs once per solve: keep the level loop rolled (the fully unrolled
-    // chain of 2x2 complex products is very slow to compile)
+    // per level: the coupling measure and the inverse diagonal block of the
+    // current system, then one reduction.  Runs once per solve: keep the
+    // loop rolled (the unrolled chain of 2x2 products is slow to compile).
 #pragma unroll 1
-    for (int l = 0; l < kPcrLevels; ++l) {
+    for (int l = 0; l <= kPcrLevels; ++l) {
+        double e = norm_inf(inv2(D)) * (norm_inf(Lm) + norm_inf(U));
+        e = wave_max(e);
+        if (j == 0) eta[(size_t)v * (kPcrLevels + 1) + l] = e;
+        const C2x2 Di = inv2(D);
+        cd* r = rec + (size_t)(kPcrLevels * 8 + 4 * l) * kWave;
+        r[0 * kWave] = Di.a; r[1 * kWave] = Di.b; r[2 * kWave] = Di.c; r[3 * kWave] = Di.d;
+        if (l == kPcrLevels) break;
         const int d = 1 << l;
         const C2x2 Dm = shfl_up_m(D, d, I), Lmm = shfl_up_m(Lm, d, Z), Um = shfl_up_m(U, d, Z);
         const C2x2 Dp = shfl_dn_m(D, d, I), Lp = shfl_dn_m(Lm, d, Z), Up = shfl_dn_m(U, d, Z);
@@ -99,13 +104,10 @@ __global__ __launch_bounds__(64) void causal_pcr_setup_kernel(int N, int nt, con
         D = Dn;
         Lm = Ln;
         U = Un;
-        cd* r = rec + (size_t)l * 8 * kWave;
-        r[0 * kWave] = K1.a; r[1 * kWave] = K1.b; r[2 * kWave] = K1.c; r[3 * kWave] = K1.d;
-        r[4 * kWave] = K2.a; r[5 * kWave] = K2.b; r[6 * kWave] = K2.c; r[7 * kWave] = K2.d;
+        cd* q = rec + (size_t)l * 8 * kWave;
+        q[0 * kWave] = K1.a; q[1 * kWave] = K1.b; q[2 * kWave] = K1.c; q[3 * kWave] = K1.d;
+        q[4 * kWave] = K2.a; q[5 * kWave] = K2.b; q[6 * kWave] = K2.c; q[7 * kWave] = K2.d;
     }
-    const C2x2 Di = inv2(D);
-    cd* r = rec + (size_t)kPcrLevels * 8 * kWave;
-    r[0 * kWave] = Di.a; r[1 * kWave] = Di.b; r[2 * kWave] = Di.c; r[3 * kWave] = Di.d;
 }
 
 __device__ inline void slot_src(int o, int N, int& k, int& pl, int& pr, int& sl, int& sr) {
@@ -178,6 +180,7 @@ struct NearArgs {
     int n0, nb;
     const cd* cols;
     const cd* pcr;     // [nv][kPcrRec][64]
+    int levels;        // PCR levels run per step (the rest of the coupling is negligible)
     const cd* base;    // [B][ns][kTb]: d + far part
     cd* g;             // [B][ns][nt]
 };
@@ -202,7 +205,7 @@ __device__ inline cd lane_dn1(cd v) { return shfl_dn_c(v, 1, mk(0, 0)); }
 __global__ __launch_bounds__(kNearThreads) void causal_near_kernel(NearArgs a) {
     __shared__ cd gh[kTb][kNearSlots];
     __shared__ cd gn[3][kNearSlots];
-    __shared__ cd spcr[kPcrRec][kWave];
+    __shared__ cd spcr[kPcrLevels * 8 + 4][kWave];
     const int b = blockIdx.x, v = a.per_problem ? b : 0;
     const int tid = threadIdx.x;
     const int ns = a.ns, nt = a.nt, n0 = a.n0, nb = a.nb;
@@ -212,9 +215,12 @@ __global__ __launch_bounds__(kNearThreads) void causal_near_kernel(NearArgs a) {
     const cd* bb = a.base + (size_t)b * ns * kTb;
     const cd* cbase = a.cols + (size_t)v * a.N * 4 * nt;
 
-    // PCR multipliers -> LDS
-    for (int e = tid; e < kPcrRec * kWave; e += blockDim.x)
-        (&spcr[0][0])[e] = a.pcr[(size_t)v * kPcrRec * kWave + e];
+    // multipliers of the levels run and the matching inverse diagonal -> LDS
+    const int lev = a.levels;
+    const cd* prec = a.pcr + (size_t)v * kPcrRec * kWave;
+    for (int e = tid; e < lev * 8 * kWave; e += blockDim.x) (&spcr[0][0])[e] = prec[e];
+    for (int e = tid; e < 4 * kWave; e += blockDim.x)
+        (&spcr[kPcrLevels * 8][0])[e] = prec[(size_t)(kPcrLevels * 8 + 4 * lev) * kWave + e];
 
     // gather role: slot o, lag class c (lags c+3, c+3+C, c+3+2C, ...)
     const int gt = tid - kWave;
@@ -278,6 +284,7 @@ __global__ __launch_bounds__(kNearThreads) void causal_near_kernel(NearArgs a) {
             }
 #pragma unroll
             for (int l = 0; l < kPcrLevels; ++l) {
+                if (l >= lev) break;                    // uniform over the workgroup
                 const int d = 1 << l;
                 const cd q0m = shfl_up_c(p0, d, zero), q1m = shfl_up_c(p1, d, zero);
                 const cd q0p = shfl_dn_c(p0, d, zero), q1p = shfl_dn_c(p1, d, zero);
@@ -337,17 +344,19 @@ static hipError_t launch_causal_far(int N, int nt, int ns, int B, int per_proble
 }
 
 hipError_t launch_causal_near(int N, int nt, int ns, int B, int per_problem, int n0, int nb,
-                              const cd* cols, const cd* pcr, const cd* base, cd* g, hipStream_t st) {
-    if (ns > kNearSlots || N - 1 > kWave) return hipErrorInvalidValue;
-    NearArgs a{N, nt, ns, per_problem, n0, nb, cols, pcr, base, g};
+                              const cd* cols, const cd* pcr, int levels, const cd* base, cd* g,
+                              hipStream_t st) {
+    if (ns > kNearSlots || N - 1 > kWave || levels < 0 || levels > kPcrLevels)
+        return hipErrorInvalidValue;
+    NearArgs a{N, nt, ns, per_problem, n0, nb, cols, pcr, levels, base, g};
     causal_near_kernel<<<B, kNearThreads, 0, st>>>(a);
     return hipGetLastError();
 }
 
 // the whole forward substitution: far part then near march, block by block
 hipError_t launch_causal_fast(int N, int nt, int ns, int B, int per_problem, const cd* cols,
-                              const cd* pcr, const cd* d, cd* base, cd* g, int n_lo, int n_hi,
-                              const cd* facc, int s_from, hipStream_t st) {
+                              const cd* pcr, int levels, const cd* d, cd* base, cd* g, int n_lo,
+                              int n_hi, const cd* facc, int s_from, hipStream_t st) {
     if (n_lo % kTb != 0 || n_lo < 0 || n_hi > nt || s_from < 0 || s_from > n_lo)
         return hipErrorInvalidValue;
     for (int n0 = n_lo; n0 < n_hi; n0 += kTb) {
@@ -355,7 +364,7 @@ hipError_t launch_causal_fast(int N, int nt, int ns, int B, int per_problem, con
         hipError_t e = launch_causal_far<kTb>(N, nt, ns, B, per_problem, n0, nb, cols, d, g, base,
                                               facc, s_from, st);
         if (e != hipSuccess) return e;
-        e = launch_causal_near(N, nt, ns, B, per_problem, n0, nb, cols, pcr, base, g, st);
+        e = launch_causal_near(N, nt, ns, B, per_problem, n0, nb, cols, pcr, levels, base, g, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -368,11 +377,6 @@ hipError_t launch_causal_fast(int N, int nt, int ns, int B, int per_problem, con
 // ---------------------------------------------------------------------------
 constexpr int kGenThreads = 512;
 
-__device__ inline int pcr_levels(int ni) {
-    int l = 0;
-    while ((1 << l) < ni) ++l;
-    return l;
-}
 
 // multipliers [nv][levels][8][ni] then D^{-1} [nv][4][ni] (after the levels)
 __global__ __launch_bounds__(kGenThreads) void causal_pcr_setup_gen_kernel(int N, int nt, const cd* cols,
@@ -380,7 +384,7 @@ __global__ __launch_bounds__(kGenThreads) void causal_pcr_setup_gen_kernel(int N
     __shared__ C2x2 sD[kGenMaxIf], sL[kGenMaxIf], sU[kGenMaxIf];
     __shared__ double se[kGenThreads / kWave];
     const int v = blockIdx.x, j = threadIdx.x;
-    const int ni = N - 1, lv = pcr_levels(ni);
+    const int ni = N - 1, lv = pcr_levels_for(ni);
     const cd* base = cols + (size_t)v * N * 4 * nt;
     auto col0 = [&](int k, int p) { return base[((size_t)k * 4 + p) * nt]; };
     const cd zero = mk(0, 0), one = mk(1, 0);
@@ -395,18 +399,26 @@ __global__ __launch_bounds__(kGenThreads) void causal_pcr_setup_gen_kernel(int N
         U = m2(-x2, zero, zero, zero);
         Lm = m2(zero, zero, zero, -x3);
     }
-    double e = (j < ni) ? norm_inf(inv2(D)) * (norm_inf(Lm) + norm_inf(U)) : 0.0;
-    e = wave_max(e);
-    if ((j & (kWave - 1)) == 0) se[j / kWave] = e;
-    __syncthreads();
-    if (j == 0) {
-        double m = 0;
-        for (int w = 0; w < kGenThreads / kWave; ++w) m = fmax(m, se[w]);
-        eta[v] = m;
-    }
     cd* rec_v = pcr + (size_t)v * rec;
+    // per level: coupling measure and inverse diagonal block of the current
+    // system (eta[v][l], Dinv block l), then one reduction
 #pragma unroll 1
-    for (int l = 0; l < lv; ++l) {
+    for (int l = 0; l <= lv; ++l) {
+        double e = (j < ni) ? norm_inf(inv2(D)) * (norm_inf(Lm) + norm_inf(U)) : 0.0;
+        e = wave_max(e);
+        if ((j & (kWave - 1)) == 0) se[j / kWave] = e;
+        __syncthreads();
+        if (j == 0) {
+            double m = 0;
+            for (int w = 0; w < kGenThreads / kWave; ++w) m = fmax(m, se[w]);
+            eta[(size_t)v * (kGenLevelsMax + 1) + l] = m;
+        }
+        if (j < ni) {
+            const C2x2 Di = inv2(D);
+            cd* r = rec_v + ((size_t)lv * 8 + 4 * l) * ni + j;
+            r[0 * ni] = Di.a; r[1 * ni] = Di.b; r[2 * ni] = Di.c; r[3 * ni] = Di.d;
+        }
+        if (l == lv) break;
         const int d = 1 << l;
         if (j < ni) { sD[j] = D; sL[j] = Lm; sU[j] = U; }
         __syncthreads();
@@ -428,16 +440,12 @@ __global__ __launch_bounds__(kGenThreads) void causal_pcr_setup_gen_kernel(int N
         }
         __syncthreads();
     }
-    if (j < ni) {
-        const C2x2 Di = inv2(D);
-        cd* r = rec_v + (size_t)lv * 8 * ni + j;
-        r[0 * ni] = Di.a; r[1 * ni] = Di.b; r[2 * ni] = Di.c; r[3 * ni] = Di.d;
-    }
 }
 
 struct NearGenArgs {
     int N, nt, ns, per_problem;
     int n0, nb, rec;
+    int levels;        // PCR levels run per step (the rest of the coupling is negligible)
     const cd* cols;
     const cd* pcr;     // [nv][rec]
     const cd* base;    // [B][ns][kGenTb]: d + far part
@@ -461,7 +469,7 @@ __global__ __launch_bounds__(kGenThreads) void causal_near_gen_kernel(NearGenArg
     const int j = threadIdx.x;
     const bool act = j < ni;
     const bool has_r = j + 1 <= a.N - 2, has_l = j >= 1;
-    const int lv = pcr_levels(ni);
+    const int lv = pcr_levels_for(ni);
     const cd zero = mk(0, 0);
     cd* gb = a.g + (size_t)b * ns * nt;
     const cd* bb = a.base + (size_t)b * ns * kGenTb;
@@ -481,9 +489,10 @@ __global__ __launch_bounds__(kGenThreads) void causal_near_gen_kernel(NearGenArg
             c3[m] = cb[((size_t)j * 4 + 3) * nt + lag];
         }
     }
+    const int lev = a.levels;
     cd di0 = zero, di1 = zero, di2 = zero, di3 = zero;
     if (act) {
-        const cd* Di = rec + (size_t)lv * 8 * ni + j;
+        const cd* Di = rec + ((size_t)lv * 8 + 4 * lev) * ni + j;
         di0 = Di[0]; di1 = Di[1 * ni]; di2 = Di[2 * ni]; di3 = Di[3 * ni];
     }
     auto loadK = [rec, ni, j, act](int l, cd (&K)[8]) {
@@ -491,7 +500,9 @@ __global__ __launch_bounds__(kGenThreads) void causal_near_gen_kernel(NearGenArg
         for (int q = 0; q < 8; ++q) K[q] = act ? rec[((size_t)l * 8 + q) * ni + j] : mk(0, 0);
     };
     cd Kc[8], Kn[8];
-    loadK(0, Kc);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) Kc[q] = zero;
+    if (lev > 0) loadK(0, Kc);
     cd bn0 = act ? bb[(size_t)(2 * j) * kGenTb] : zero;
     cd bn1 = act ? bb[(size_t)(2 * j + 1) * kGenTb] : zero;
 
@@ -516,9 +527,9 @@ __global__ __launch_bounds__(kGenThreads) void causal_near_gen_kernel(NearGenArg
                     }
                 }
             }
-            for (int l = 0; l < lv; ++l) {
+            for (int l = 0; l < lev; ++l) {
                 const int d = 1 << l;
-                loadK(l + 1 < lv ? l + 1 : 0, Kn);     // next level (or next step's first)
+                loadK(l + 1 < lev ? l + 1 : 0, Kn);    // next level (or next step's first)
                 cd* ex = (l & 1) ? xb : xa;
                 if (act) { ex[2 * j] = p0; ex[2 * j + 1] = p1; }
                 __syncthreads();
@@ -553,8 +564,8 @@ hipError_t launch_causal_pcr_setup_gen(int N, int nt, int nv, const cd* cols, cd
 }
 
 hipError_t launch_causal_gen(int N, int nt, int ns, int B, int per_problem, const cd* cols,
-                             const cd* pcr, const cd* d, cd* base, cd* g, int n_lo, int n_hi,
-                             const cd* facc, int s_from, hipStream_t st) {
+                             const cd* pcr, int levels, const cd* d, cd* base, cd* g, int n_lo,
+                             int n_hi, const cd* facc, int s_from, hipStream_t st) {
     const size_t shm = ((size_t)kGenTb * ns + ns + 2 * (size_t)(N - 1)) * sizeof(cd);
     if (N - 1 > kGenMaxIf || N - 1 > kGenThreads || ns > 2 * kGenThreads || shm > 160 * 1024)
         return hipErrorInvalidValue;
@@ -565,7 +576,7 @@ hipError_t launch_causal_gen(int N, int nt, int ns, int B, int per_problem, cons
         hipError_t e = launch_causal_far<kGenTb>(N, nt, ns, B, per_problem, n0, nb, cols, d, g, base,
                                                  facc, s_from, st);
         if (e != hipSuccess) return e;
-        NearGenArgs na{N, nt, ns, per_problem, n0, nb, pcr_rec_gen(N), cols, pcr, base, g};
+        NearGenArgs na{N, nt, ns, per_problem, n0, nb, pcr_rec_gen(N), levels, cols, pcr, base, g};
         causal_near_gen_kernel<<<B, kGenThreads, shm, st>>>(na);
         e = hipGetLastError();
         if (e != hipSuccess) return e;

@@ -56,13 +56,55 @@ __device__ inline double dpp_shift(double v) {
     return *reinterpret_cast<double*>(&t);
 }
 
+// Row moves of one double through the gfx950 lane swaps (rows = 16 lanes).
+// With both operands equal to x, v_permlane16_swap returns
+//   first  = (x.row0, x.row0, x.row2, x.row2)   second = (x.row1, x.row1, x.row3, x.row3)
+// and v_permlane32_swap returns
+//   first  = (x.row0, x.row1, x.row0, x.row1)   second = (x.row2, x.row3, x.row2, x.row3).
+struct RowPair { double first, second; };
+__device__ inline RowPair swap16(double v) {
+    int2 t = *reinterpret_cast<int2*>(&v);
+    const auto lo = __builtin_amdgcn_permlane16_swap(t.x, t.x, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(t.y, t.y, false, false);
+    int2 f = make_int2(lo[0], hi[0]), s = make_int2(lo[1], hi[1]);
+    return RowPair{*reinterpret_cast<double*>(&f), *reinterpret_cast<double*>(&s)};
+}
+__device__ inline RowPair swap32(double v) {
+    int2 t = *reinterpret_cast<int2*>(&v);
+    const auto lo = __builtin_amdgcn_permlane32_swap(t.x, t.x, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(t.y, t.y, false, false);
+    int2 f = make_int2(lo[0], hi[0]), s = make_int2(lo[1], hi[1]);
+    return RowPair{*reinterpret_cast<double*>(&f), *reinterpret_cast<double*>(&s)};
+}
+// value of lane - 16 (rows 1..3) and of lane + 16 (rows 0..2)
+__device__ inline double up16(double v) {
+    const RowPair a = swap16(v);
+    const double r2 = swap32(a.second).first;          // row 2 <- row 1
+    const int row = lane_id() >> 4;
+    return row == 2 ? r2 : a.first;                    // rows 1, 3 <- rows 0, 2
+}
+__device__ inline double dn16(double v) {
+    const RowPair a = swap16(v);
+    const double r1 = swap32(a.first).second;          // row 1 <- row 2
+    const int row = lane_id() >> 4;
+    return row == 1 ? r1 : a.second;                   // rows 0, 2 <- rows 1, 3
+}
+
 // value of lane (lane - d); lanes below d receive `fill`.  Distance 1 is a
-// DPP wave shift (no LDS round trip), other distances a permute.  Both run
-// on every lane of the wave.
+// DPP wave shift, distances 16 and 32 are lane swaps (no LDS round trip),
+// other distances a permute.  All run on every lane of the wave.
 __device__ inline cd shfl_up_c(cd v, int d, cd fill) {
     if (d == 1) {
         const cd r = mk(dpp_shift<0x138>(v.x), dpp_shift<0x138>(v.y));
         return lane_id() == 0 ? fill : r;
+    }
+    if (d == 32) {
+        const cd r = mk(swap32(v.x).first, swap32(v.y).first);
+        return lane_id() < 32 ? fill : r;
+    }
+    if (d == 16) {
+        const cd r = mk(up16(v.x), up16(v.y));
+        return lane_id() < 16 ? fill : r;
     }
     int src = lane_id() - d;
     cd r = mk(__shfl(v.x, src < 0 ? 0 : src), __shfl(v.y, src < 0 ? 0 : src));
@@ -73,6 +115,14 @@ __device__ inline cd shfl_dn_c(cd v, int d, cd fill) {
     if (d == 1) {
         const cd r = mk(dpp_shift<0x130>(v.x), dpp_shift<0x130>(v.y));
         return lane_id() == kWave - 1 ? fill : r;
+    }
+    if (d == 32) {
+        const cd r = mk(swap32(v.x).second, swap32(v.y).second);
+        return lane_id() >= 32 ? fill : r;
+    }
+    if (d == 16) {
+        const cd r = mk(dn16(v.x), dn16(v.y));
+        return lane_id() >= kWave - 16 ? fill : r;
     }
     int src = lane_id() + d;
     cd r = mk(__shfl(v.x, src > 63 ? 63 : src), __shfl(v.y, src > 63 ? 63 : src));
@@ -152,6 +202,7 @@ struct SweepArgs {
     int flags_and, flags_or;     // per-launch override of the task flags
     cd* ckpt;                    // [ntasks][Jc+1][P][64] checkpoints of u
     int Jc;                      // ceil(nt / 64)
+    int task0;                   // this launch runs tasks task0 .. task0 + ntasks - 1
     int n_begin, n_end;          // steps n_begin+1 .. n_end of this launch (n_begin % 64 == 0)
     cd* state;                   // [ntasks][2][P][64] u_n and v_n carried between launches
 };
@@ -198,7 +249,7 @@ constexpr int kRedThreads = 256;
 
 // launchers (swr_sweep.hip)
 hipError_t launch_factor(const FactorArgs& a, hipStream_t st);
-hipError_t launch_sweep(const SweepArgs& a, int trans, int vk, hipStream_t st);
+hipError_t launch_sweep(const SweepArgs& a, int trans, int vk, hipStream_t st, bool plain = false);
 hipError_t launch_sweep_static(const SweepArgs& a, int trans, hipStream_t st);
 hipError_t launch_sweep_time(const SweepArgs& a, int trans, hipStream_t st);
 hipError_t launch_sweep_cubic(const SweepArgs& a, int trans, hipStream_t st);
@@ -207,6 +258,8 @@ hipError_t launch_finalize_ut(int N, int nx, int B, const int* off, const cd* en
 hipError_t launch_beta(int n, double* beta, hipStream_t st);
 // launchers (swr_iface.hip)
 hipError_t launch_ltt(const LttArgs& a, hipStream_t st);
+hipError_t launch_lincomb(const cd* x0, const cd* x1, const cd* x2, const cd* coef, cd* z, long M,
+                          int B, hipStream_t st);
 hipError_t launch_multidot(const cd* basis, int nv, const cd* w, long M, int B, double* partial,
                            cd* out, int out_ld, int accumulate, hipStream_t st);
 hipError_t launch_multiaxpy(const cd* basis, int nv, const cd* coef, int coef_ld, double sign,
@@ -228,25 +281,37 @@ hipError_t launch_causal_block(const CausalArgs& a, hipStream_t st);
 // interfaces and ns <= kNearSlots slots
 constexpr int kNearTb = 32;
 constexpr int kNearSlots = 128;
-constexpr int kPcrRec = kPcrLevels * 8 + 4;   // complex entries per lane of the PCR record
+// PCR record per lane: multipliers of every level, then the inverse of the
+// reduced diagonal block after 0 .. kPcrLevels levels
+constexpr int kPcrRec = kPcrLevels * 8 + (kPcrLevels + 1) * 4;
+// remaining coupling below which further PCR levels cannot change an FP64
+// result: ||D_l^{-1}|| (||L_l|| + ||U_l||) <= 2^-60 (unit roundoff is 2^-53)
+constexpr double kPcrNegligible = 8.673617379884035e-19;
+// eta: [nv][levels + 1] coupling measure of the system before each level
 hipError_t launch_causal_pcr_setup(int N, int nt, int nv, const cd* cols, cd* pcr, double* eta,
                                    hipStream_t st);
 hipError_t launch_causal_fast(int N, int nt, int ns, int B, int per_problem, const cd* cols,
-                              const cd* pcr, const cd* d, cd* base, cd* g, int n_lo, int n_hi,
-                              const cd* facc, int s_from, hipStream_t st);
+                              const cd* pcr, int levels, const cd* d, cd* base, cd* g, int n_lo,
+                              int n_hi, const cd* facc, int s_from, hipStream_t st);
 // general block-PCR causal solve for up to kGenMaxIf interfaces
 constexpr int kGenTb = 8;
 constexpr int kCausalSuper = 256;    // causal solve super-block (time steps)
 constexpr int kGenMaxIf = 512;
+constexpr int kGenLevelsMax = 9;     // pcr_levels_for(kGenMaxIf)
+// number of block-PCR levels that decouple ni interfaces completely
+__host__ __device__ constexpr int pcr_levels_for(int ni) {
+    return ni <= 1 ? 0 : (32 - __builtin_clz((unsigned)(ni - 1)));
+}
 __host__ __device__ constexpr int pcr_rec_gen(int N) {
-    // complex entries per potential: levels * 8 * ni + 4 * ni
-    return (N - 1) * 8 * (N - 1 <= 1 ? 0 : (32 - __builtin_clz((unsigned)(N - 2)))) + 4 * (N - 1);
+    // complex entries per potential: levels * 8 * ni multipliers, then
+    // (levels + 1) * 4 * ni inverse diagonal blocks
+    return (N - 1) * 8 * pcr_levels_for(N - 1) + (pcr_levels_for(N - 1) + 1) * 4 * (N - 1);
 }
 hipError_t launch_causal_pcr_setup_gen(int N, int nt, int nv, const cd* cols, cd* pcr, double* eta,
                                        hipStream_t st);
 hipError_t launch_causal_gen(int N, int nt, int ns, int B, int per_problem, const cd* cols,
-                             const cd* pcr, const cd* d, cd* base, cd* g, int n_lo, int n_hi,
-                             const cd* facc, int s_from, hipStream_t st);
+                             const cd* pcr, int levels, const cd* d, cd* base, cd* g, int n_lo,
+                             int n_hi, const cd* facc, int s_from, hipStream_t st);
 struct AdjArgs {
     int N, nt, B, nx, ns, ntasks, P, Jc;
     double kappa, h;

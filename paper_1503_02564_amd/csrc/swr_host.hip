@@ -40,6 +40,8 @@ struct Iface {
     cd* pcr = nullptr;
     size_t pcr_size = 0;
     double* eta = nullptr;
+    int levels = 0;         // PCR levels run per step (coupling left <= 2^-60)
+    double eta0 = 0;        // block dominance measure of (I - C_0)
     cd* Minv = nullptr;
     cd* Mwork = nullptr;
     int* piv = nullptr;
@@ -89,6 +91,9 @@ struct swr_ctx {
     double* dBn = nullptr;
     double* dRes = nullptr;
     int* dAct = nullptr;
+    cd* dBi = nullptr;        // BiCGStab work vectors r, r^, p, v, s, t: [6][B][ns][nt]
+    cd* dCoef = nullptr;      // [B][3] per-problem coefficients of lincomb
+    cd* dDot = nullptr;       // [B] complex dot products
     cd* dFar = nullptr;       // causal dense path
     cd* dFacc = nullptr;      // causal PCR paths: [seg][B][ns][256] contribution of each
                               // finished super-block to the current one
@@ -168,6 +173,7 @@ extern "C" void swr_default_opts(swr_opts* o) {
     o->nl_max_iter = 100;
     o->nl_tol = 1e-14;
     o->pipeline = 256;
+    o->plain = 0;
 }
 
 extern "C" const char* swr_strerror(swr_status s) {
@@ -371,6 +377,7 @@ static SweepArgs sweep_args(swr_ctx* c, const Task* tasks, int ntasks, const cd*
     a.nl_stats = c->dNl;
     a.flags_and = ~0;
     a.flags_or = 0;
+    a.task0 = 0;
     a.n_begin = 0;
     a.n_end = c->nt;
     a.state = nullptr;
@@ -420,7 +427,7 @@ static swr_status run_sweeps(swr_ctx* c, const SweepIO& io) {
     a.ckpt = c->dCkpt;
     a.Jc = c->Jc;
     if (io.maxdiff) HIPCHK(hipMemsetAsync(c->dMax, 0, sizeof(unsigned long long), c->st));
-    HIPCHK(launch_sweep(a, c->tr, c->vk, c->st));
+    HIPCHK(launch_sweep(a, c->tr, c->vk, c->st, c->o.plain));
     if (io.uT) HIPCHK(launch_finalize_ut(c->N, c->nx, c->B, c->dOff, c->dEnds, io.uT, c->st));
     return SWR_OK;
 }
@@ -431,7 +438,7 @@ static swr_status run_build(swr_ctx* c, const double* u0) {
     a.u0 = reinterpret_cast<const cd*>(u0);
     a.g_in = c->dZero;
     a.g_out = c->dD;
-    HIPCHK(launch_sweep(a, c->tr, SWR_V_STATIC, c->st));
+    HIPCHK(launch_sweep(a, c->tr, SWR_V_STATIC, c->st, c->o.plain));
     c->L.dirty = true;
     return SWR_OK;
 }
@@ -441,7 +448,7 @@ static swr_status run_build_L0(swr_ctx* c) {
     CHK(run_factor(c, nullptr, 1, c->L0.fac));
     SweepArgs a = sweep_args(c, c->L0.tasks, c->L0.ntasks, c->L0.fac, c->L0.cols);
     a.g_in = c->dZero;
-    HIPCHK(launch_sweep(a, c->tr, SWR_V_STATIC, c->st));
+    HIPCHK(launch_sweep(a, c->tr, SWR_V_STATIC, c->st, c->o.plain));
     c->L0.dirty = true;
     return SWR_OK;
 }
@@ -527,6 +534,102 @@ static swr_status run_gmres(swr_ctx* c, const Op& A, const cd* rhs, cd* x, int* 
     return conv ? SWR_OK : SWR_ENOCONV;
 }
 
+// BiCGStab (van der Vorst 1992) on A x = rhs for all problems of the batch,
+// each with its own scalars; x starts at 0.  Stops per problem when
+// ||r||_2 <= tol ||rhs||_2, checked on s after the half step and on r after
+// the full step; finished problems keep their x (zero coefficients).
+static swr_status run_bicgstab(swr_ctx* c, const Op& A, const cd* rhs, cd* x, int* iters_out) {
+    const int B = c->B;
+    const long M = (long)c->ns * c->nt;
+    const size_t vec = (size_t)B * M;
+    hipStream_t st = c->st;
+    if (!c->dBi) {
+        ALLOC_LIVE(c->dBi, 6 * vec);
+        ALLOC_LIVE(c->dCoef, (size_t)3 * B);
+        ALLOC_LIVE(c->dDot, (size_t)B);
+    }
+    cd *r = c->dBi, *rh = r + vec, *p = rh + vec, *v = p + vec, *s = v + vec, *t = s + vec;
+    std::vector<cd> coef(3 * (size_t)B), dot(B), rho(B, mk(1, 0)), alpha(B, mk(1, 0)), omega(B, mk(1, 0)),
+        rho_new(B);
+    std::vector<double> bn(B), nr(B);
+    std::vector<char> act(B), half(B);
+    auto dots = [&](const cd* u, const cd* w) -> swr_status {   // dot[b] = <u_b, w_b>
+        HIPCHK(launch_multidot(u, 1, w, M, B, c->dPart, c->dDot, 1, 0, st));
+        HIPCHK(hipMemcpyAsync(dot.data(), c->dDot, sizeof(cd) * B, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        return SWR_OK;
+    };
+    auto norms = [&](const cd* w, std::vector<double>& out) -> swr_status {
+        HIPCHK(launch_norm(w, M, B, c->dPart, c->dNrm, st));
+        HIPCHK(hipMemcpyAsync(out.data(), c->dNrm, sizeof(double) * B, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        return SWR_OK;
+    };
+    auto comb = [&](const cd* x0, const cd* x1, const cd* x2, cd* z) -> swr_status {
+        HIPCHK(hipMemcpyAsync(c->dCoef, coef.data(), sizeof(cd) * 3 * B, hipMemcpyHostToDevice, st));
+        HIPCHK(launch_lincomb(x0, x1, x2, c->dCoef, z, M, B, st));
+        return SWR_OK;
+    };
+    auto set = [&](int b, cd a0, cd a1, cd a2) { coef[3 * b] = a0; coef[3 * b + 1] = a1; coef[3 * b + 2] = a2; };
+    const cd one = mk(1, 0), zero = mk(0, 0);
+    HIPCHK(hipMemsetAsync(x, 0, vec * sizeof(cd), st));
+    HIPCHK(hipMemsetAsync(p, 0, vec * sizeof(cd), st));
+    HIPCHK(hipMemsetAsync(v, 0, vec * sizeof(cd), st));
+    HIPCHK(hipMemcpyAsync(r, rhs, vec * sizeof(cd), hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(rh, rhs, vec * sizeof(cd), hipMemcpyDeviceToDevice, st));
+    CHK(norms(rhs, bn));
+    bool any = false;
+    for (int b = 0; b < B; ++b) { act[b] = bn[b] > 0; any |= act[b] != 0; }
+    int its = 0;
+    while (any && its < c->o.max_iter) {
+        ++its;
+        CHK(dots(rh, r));
+        for (int b = 0; b < B; ++b) {
+            rho_new[b] = dot[b];
+            if (act[b]) {
+                const cd beta = (rho_new[b] * inv(rho[b])) * (alpha[b] * inv(omega[b]));
+                set(b, one, beta, -(beta * omega[b]));
+            } else {
+                set(b, zero, one, zero);
+            }
+        }
+        CHK(comb(r, p, v, p));                                   // p = r + beta (p - omega v)
+        CHK(A(p, v));
+        CHK(dots(rh, v));
+        for (int b = 0; b < B; ++b) {
+            alpha[b] = act[b] ? rho_new[b] * inv(dot[b]) : zero;
+            set(b, one, -alpha[b], zero);
+        }
+        CHK(comb(r, v, nullptr, s));                             // s = r - alpha v
+        CHK(norms(s, nr));
+        for (int b = 0; b < B; ++b) {
+            if (!std::isfinite(nr[b])) return SWR_ENAN;
+            half[b] = act[b] && nr[b] <= c->o.tol * bn[b];
+        }
+        CHK(A(s, t));
+        CHK(dots(t, s));
+        std::vector<cd> ts = dot;
+        CHK(dots(t, t));
+        for (int b = 0; b < B; ++b) {
+            omega[b] = (act[b] && !half[b]) ? ts[b] * inv(dot[b]) : zero;
+            set(b, one, act[b] ? alpha[b] : zero, omega[b]);
+        }
+        CHK(comb(x, p, s, x));                                   // x += alpha p + omega s
+        for (int b = 0; b < B; ++b) set(b, one, -omega[b], zero);
+        CHK(comb(s, t, nullptr, r));                             // r = s - omega t
+        CHK(norms(r, nr));
+        any = false;
+        for (int b = 0; b < B; ++b) {
+            if (!std::isfinite(nr[b])) return SWR_ENAN;
+            if (half[b] || nr[b] <= c->o.tol * bn[b]) act[b] = 0;
+            any |= act[b] != 0;
+            rho[b] = rho_new[b];
+        }
+    }
+    *iters_out = its;
+    return any ? SWR_ENOCONV : SWR_OK;
+}
+
 // causal forward substitution in time for (I - L) g = d with the operator I
 // (exact up to rounding).  Block PCR per step when the block system is
 // certified diagonally dominant: on one wave for N - 1 <= 64 interfaces, on
@@ -546,14 +649,31 @@ static swr_status run_causal(swr_ctx* c, Iface& I, const cd* d, cd* g, hipStream
                 ALLOC_LIVE(I.pcr, rec * I.nv);
                 I.pcr_size = rec * I.nv;
             }
-            if (!I.eta) ALLOC_LIVE(I.eta, I.nv);
+            // eta[v][l]: ||D_l^{-1}|| (||L_l|| + ||U_l||) of the system before level l
+            const int ld = fast_ok ? kPcrLevels + 1 : kGenLevelsMax + 1;
+            const int L = fast_ok ? kPcrLevels : pcr_levels_for(ni);
+            if (!I.eta) ALLOC_LIVE(I.eta, (size_t)I.nv * (kGenLevelsMax + 1));
             if (fast_ok) HIPCHK(launch_causal_pcr_setup(c->N, nt, I.nv, I.cols, I.pcr, I.eta, st));
             else HIPCHK(launch_causal_pcr_setup_gen(c->N, nt, I.nv, I.cols, I.pcr, I.eta, st));
-            std::vector<double> eta(I.nv);
-            HIPCHK(hipMemcpyAsync(eta.data(), I.eta, sizeof(double) * I.nv, hipMemcpyDeviceToHost, st));
+            std::vector<double> eta((size_t)I.nv * ld);
+            HIPCHK(hipMemcpyAsync(eta.data(), I.eta, sizeof(double) * eta.size(), hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
+            // block diagonal dominance (eta_0 < 1) makes block PCR stable and
+            // squares the coupling every level; levels past the first l with
+            // eta_l <= 2^-60 change no FP64 result and are skipped
             bool ok = true;
-            for (double e : eta) ok = ok && std::isfinite(e) && e < 1.0;
+            int lev = 0;
+            for (int v = 0; v < I.nv; ++v) {
+                const double* ev = eta.data() + (size_t)v * ld;
+                ok = ok && std::isfinite(ev[0]) && ev[0] < 1.0;
+                int lv = L;
+                for (int l = 0; l <= L; ++l)
+                    if (std::isfinite(ev[l]) && ev[l] <= kPcrNegligible) { lv = l; break; }
+                lev = std::max(lev, lv);
+            }
+            I.levels = lev;
+            I.eta0 = 0;
+            for (int v = 0; v < I.nv; ++v) I.eta0 = std::max(I.eta0, eta[(size_t)v * ld]);
             if (ok) I.path = fast_ok ? 1 : 2;
         }
         if (I.path == 3) {
@@ -596,11 +716,11 @@ static swr_status run_causal(swr_ctx* c, Iface& I, const cd* d, cd* g, hipStream
             }
             const cd* facc = S > 0 ? c->dFacc : nullptr;
             if (I.path == 1)
-                HIPCHK(launch_causal_fast(c->N, nt, ns, B, I.nv > 1, I.cols, I.pcr, d, c->dBase, g,
-                                          a0, a1, facc, S, st));
+                HIPCHK(launch_causal_fast(c->N, nt, ns, B, I.nv > 1, I.cols, I.pcr, I.levels, d,
+                                          c->dBase, g, a0, a1, facc, S, st));
             else
-                HIPCHK(launch_causal_gen(c->N, nt, ns, B, I.nv > 1, I.cols, I.pcr, d, c->dBase, g,
-                                         a0, a1, facc, S, st));
+                HIPCHK(launch_causal_gen(c->N, nt, ns, B, I.nv > 1, I.cols, I.pcr, I.levels, d,
+                                         c->dBase, g, a0, a1, facc, S, st));
             a0 = a1;
         }
         return SWR_OK;
@@ -743,6 +863,7 @@ struct PipeTimes {
 
 static bool pipelined(const swr_ctx* c) {
     return c->vk == SWR_V_STATIC && c->o.solver == SWR_SOLVER_CAUSAL && c->o.pipeline > 0 &&
+           !c->o.plain &&
            c->ns > 0 && c->nt > c->o.pipeline;
 }
 
@@ -890,6 +1011,13 @@ extern "C" swr_status swr_solve(swr_ctx* c, const double* u0d, double* uT, doubl
             return SWR_OK;
         };
         rs = run_gmres(c, A, c->dD, c->dG, &iters);
+    } else if (c->o.solver == SWR_SOLVER_BICGSTAB) {
+        Op A = [c](const cd* x, cd* y) -> swr_status {
+            LttArgs l = ltt_args(c, c->L, x, y);
+            HIPCHK(launch_ltt(l, c->st));
+            return SWR_OK;
+        };
+        rs = run_bicgstab(c, A, c->dD, c->dG, &iters);
     } else if (c->o.solver == SWR_SOLVER_CAUSAL) {
         rs = run_causal(c, c->L, c->dD, c->dG, c->st, 0, c->nt);
         iters = 1;
@@ -1028,6 +1156,14 @@ static swr_status solve_interface(swr_ctx* c, const cd* d, cd* g, int* iters) {
             return SWR_OK;
         };
         return run_gmres(c, A, d, g, iters);
+    }
+    if (c->o.solver == SWR_SOLVER_BICGSTAB) {
+        Op A = [c](const cd* x, cd* y) -> swr_status {
+            LttArgs l = ltt_args(c, c->L, x, y);
+            HIPCHK(launch_ltt(l, c->st));
+            return SWR_OK;
+        };
+        return run_bicgstab(c, A, d, g, iters);
     }
     *iters = 1;
     return run_causal(c, c->L, d, g, c->st, 0, c->nt);

@@ -331,6 +331,29 @@ __global__ void gmres_init_kernel(int m, int B, const double* beta, cd* e, int* 
     active[b] = (bnorm[b] > 0 && beta[b] > tol * bnorm[b]) ? 1 : 0;
 }
 
+// z_b = c0_b x0_b + c1_b x1_b + c2_b x2_b with complex per-problem
+// coefficients coef[b][0..2]; a null x_k is skipped; z may alias any x_k
+__global__ __launch_bounds__(256) void lincomb_kernel(const cd* x0, const cd* x1, const cd* x2,
+                                                      const cd* coef, cd* z, long M) {
+    const int b = blockIdx.y;
+    const cd c0 = coef[3 * b], c1 = coef[3 * b + 1], c2 = coef[3 * b + 2];
+    const size_t o = (size_t)b * M;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < M; e += (long)gridDim.x * blockDim.x) {
+        cd acc = mk(0, 0);
+        if (x0) acc = madd(acc, c0, x0[o + e]);
+        if (x1) acc = madd(acc, c1, x1[o + e]);
+        if (x2) acc = madd(acc, c2, x2[o + e]);
+        z[o + e] = acc;
+    }
+}
+
+hipError_t launch_lincomb(const cd* x0, const cd* x1, const cd* x2, const cd* coef, cd* z, long M,
+                          int B, hipStream_t st) {
+    const int blocks = (int)std::min<long>(1024, (M + 255) / 256);
+    lincomb_kernel<<<dim3(blocks, B), 256, 0, st>>>(x0, x1, x2, coef, z, M);
+    return hipGetLastError();
+}
+
 hipError_t launch_multidot(const cd* basis, int nv, const cd* w, long M, int B, double* partial,
                            cd* out, int out_ld, int accumulate, hipStream_t st) {
     multidot_kernel<<<dim3(kRedBlocks, B), kRedThreads, 0, st>>>(basis, nv, w, M, B, partial);

@@ -96,12 +96,26 @@ hipError_t launch_factor(const FactorArgs& a, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_sweep(const SweepArgs& a, int trans, int vk, hipStream_t st) {
-    if (a.ntasks == 0) return hipSuccess;
-    if (a.P < 1 || a.P > kMaxP) return hipErrorInvalidValue;
+static hipError_t launch_sweep_once(const SweepArgs& a, int trans, int vk, hipStream_t st) {
     if (vk == VK_TIME) return launch_sweep_time(a, trans, st);
     if (vk == VK_CUBIC) return launch_sweep_cubic(a, trans, st);
     return launch_sweep_static(a, trans, st);
+}
+
+// All tasks in one launch, or (plain) one launch per task on the stream:
+// the unbatched form, kept as the reference the batched one is compared to.
+hipError_t launch_sweep(const SweepArgs& a, int trans, int vk, hipStream_t st, bool plain) {
+    if (a.ntasks == 0) return hipSuccess;
+    if (a.P < 1 || a.P > kMaxP) return hipErrorInvalidValue;
+    if (!plain) return launch_sweep_once(a, trans, vk, st);
+    SweepArgs one = a;
+    one.ntasks = 1;
+    for (int i = 0; i < a.ntasks; ++i) {
+        one.task0 = a.task0 + i;
+        const hipError_t e = launch_sweep_once(one, trans, vk, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_finalize_ut(int N, int nx, int B, const int* off, const cd* ends, cd* uT,

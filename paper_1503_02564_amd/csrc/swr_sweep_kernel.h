@@ -18,7 +18,8 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
     __shared__ double sbeta[kWave + 1];
     __shared__ cd sha[kWave], shb[kWave];     // staged chunk of the boundary history
     __shared__ double sb[2 * kWave];          // beta window of that chunk
-    const Task task = a.tasks[blockIdx.x];
+    const int tix = a.task0 + blockIdx.x;   // task index (per-task buffers)
+    const Task task = a.tasks[tix];
     const int k = task.k, b = task.b, f = task.f;
     const int fl = (task.flags & a.flags_and) | a.flags_or;
     const int t = threadIdx.x;
@@ -40,7 +41,7 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
     // start at step 0 resumes from the state the previous one saved
     const int nbeg = a.n_begin, nend = a.n_end;
     const bool first = nbeg == 0, last = nend == nt;
-    cd* stp = a.state ? a.state + (size_t)blockIdx.x * 2 * P * kWave + t : nullptr;
+    cd* stp = a.state ? a.state + (size_t)tix * 2 * P * kWave + t : nullptr;
 
     // time-dependent potential: rows n and n+1 of V at my nodes
     double vprev[P], vnext[P];
@@ -91,7 +92,7 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
     };
 
     const double kap = a.kappa;
-    cd* Ha = a.hist ? a.hist + (size_t)blockIdx.x * 2 * (nt + 1) : nullptr;
+    cd* Ha = a.hist ? a.hist + (size_t)tix * 2 * (nt + 1) : nullptr;
     cd* Hb = Ha ? Ha + (nt + 1) : nullptr;
     const cd va0 = rdlane(u[0], 0);
     const cd vb0 = at_last(u);
@@ -100,7 +101,7 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
         Hb[0] = vb0;
     }
     // checkpoints for the adjoint: u at forward steps max(0, nt - 64 jj), jj = 1..Jc
-    cd* ck = (fl & T_CKPT) ? a.ckpt + ((size_t)blockIdx.x * (a.Jc + 1) * P) * kWave + t : nullptr;
+    cd* ck = (fl & T_CKPT) ? a.ckpt + ((size_t)tix * (a.Jc + 1) * P) * kWave + t : nullptr;
     if (ck && first) {
 #pragma unroll
         for (int q = 0; q < P; ++q) ck[((size_t)a.Jc * P + q) * kWave] = u[q];

@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(HERE, "_swr_hip.so")
 SWR_OK, SWR_EINVAL, SWR_ENOMEM, SWR_EDEVICE, SWR_ENOCONV, SWR_ENAN = range(6)
 SWR_ROBIN, SWR_S02 = 0, 1
 SWR_V_STATIC, SWR_V_TIME, SWR_V_CUBIC = 0, 1, 2
-SWR_SOLVER_FIXED, SWR_SOLVER_GMRES, SWR_SOLVER_CAUSAL = 0, 1, 2
+SWR_SOLVER_FIXED, SWR_SOLVER_GMRES, SWR_SOLVER_CAUSAL, SWR_SOLVER_BICGSTAB = 0, 1, 2, 3
 
 
 class SwrOpts(ctypes.Structure):
@@ -31,7 +31,7 @@ class SwrOpts(ctypes.Structure):
                 ("solver", ctypes.c_int), ("precond", ctypes.c_int), ("batch", ctypes.c_int),
                 ("v_per_problem", ctypes.c_int), ("checkpoint_K", ctypes.c_int),
                 ("nl_max_iter", ctypes.c_int), ("nl_tol", ctypes.c_double),
-                ("pipeline", ctypes.c_int)]
+                ("pipeline", ctypes.c_int), ("plain", ctypes.c_int)]
 
 
 class SwrInfo(ctypes.Structure):

@@ -40,6 +40,7 @@ def test_defaults_and_strerror(swr):
     o = swr.swr_default_opts()
     assert o.tol == 1e-10 and o.restart == 30 and o.batch == 1
     assert o.solver == swr.SWR_SOLVER_CAUSAL and o.checkpoint_K == 64
+    assert o.pipeline == 256 and o.plain == 0 and o.nl_max_iter == 100
     for s in range(6):
         assert swr.swr_strerror(s)
     assert swr.swr_strerror(99) == "unknown status"
@@ -68,7 +69,8 @@ def test_setup_rejects_invalid_arguments(swr, kw):
 
 
 def test_setup_rejects_bad_opts(swr):
-    for field, val in (("batch", 0), ("restart", 0), ("max_iter", 0), ("tol", 0.0)):
+    for field, val in (("batch", 0), ("restart", 0), ("max_iter", 0), ("tol", 0.0),
+                       ("pipeline", 100), ("pipeline", -64), ("nl_max_iter", 0)):
         o = swr.swr_default_opts()
         setattr(o, field, val)
         st, _ = _setup_raw(swr, opts=o)

@@ -88,12 +88,13 @@ SOLVE_CASES = [
 
 
 @pytest.mark.parametrize("label,J,nt,trans,sigma", SOLVE_CASES)
-@pytest.mark.parametrize("solver", ["causal", "gmres"])
+@pytest.mark.parametrize("solver", ["causal", "gmres", "bicgstab"])
 def test_solve_matches_monodomain(dev, label, J, nt, trans, sigma, solver):
     import torch
     from paper_1503_02564_amd import swr
     wl = _case(J, nt, trans, sigma)
-    sv = dict(causal=swr.SWR_SOLVER_CAUSAL, gmres=swr.SWR_SOLVER_GMRES)[solver]
+    sv = dict(causal=swr.SWR_SOLVER_CAUSAL, gmres=swr.SWR_SOLVER_GMRES,
+              bicgstab=swr.SWR_SOLVER_BICGSTAB)[solver]
     say("solve", label, solver)
     pb = make_problem(wl, solver=sv, tol=1e-13, restart=60, max_iter=3000)
     uT = torch.zeros((1, wl.nx), dtype=torch.complex128, device=dev)
@@ -153,6 +154,42 @@ def test_pipelined_solve_equals_staged_solve(dev, label, J, nt, trans, sigma, B,
         wb = W.Workload(wl.name, wl.a0, wl.b0, wl.J, wl.dt, wl.nt, wl.vkind,
                         wl.V[bb] if per_problem else wl.V, wl.trans, wl.sigma, wl.u0[bb:bb + 1])
         assert rel(out[chunk][0][bb], O.mono(wb, wl.u0[bb])) < 1e-10
+
+
+def test_plain_launches_equal_batched(dev):
+    """One launch per sweep task (the unbatched reference form) performs the
+    same arithmetic as the batched launch: u(T) and g bitwise equal, for a
+    batch with per-problem potentials and for the adjoint."""
+    import torch
+    from paper_1503_02564_amd import swr
+    wl = W.small_case(J=[60, 80, 70, 45], nt=150, trans=W.S02, B=2, seed=19, a0=-12.0, b0=12.0)
+    rng = np.random.default_rng(8)
+    wl.V = np.stack([W.bumpy_harmonic(W.mesh_nodes(wl.a0, wl.b0, wl.nc), rng.uniform(-5, 5, 3),
+                                      rng.uniform(-10, 10, 3)) for _ in range(2)])
+    gbar = rng.standard_normal((2, wl.nx)) + 1j * rng.standard_normal((2, wl.nx))
+    out = []
+    for plain in (0, 1):
+        say("plain-launch", plain)
+        o = swr.swr_default_opts()
+        o.batch = 2
+        o.v_per_problem = 1
+        o.plain = plain
+        p = swr.Problem(wl.a0, wl.b0, tuple(int(j) for j in wl.J), wl.dt, wl.dt * wl.nt, wl.vkind,
+                        wl.trans, wl.sigma, o, to_dev(wl.V))
+        uT = torch.zeros((2, wl.nx), dtype=torch.complex128, device=dev)
+        g = torch.zeros((2, p.ns, wl.nt), dtype=torch.complex128, device=dev)
+        st, info = swr.swr_solve(p.ctx, to_dev(wl.u0), uT, g)
+        dV = torch.zeros((2, wl.nx), dtype=torch.float64, device=dev)
+        du0 = torch.zeros((2, wl.nx), dtype=torch.complex128, device=dev)
+        st2, _ = swr.swr_grad(p.ctx, to_dev(wl.u0), to_dev(gbar), dV, du0)
+        torch.cuda.synchronize()
+        assert st == swr.SWR_OK and st2 == swr.SWR_OK and info.residual < 1e-11
+        out.append([to_np(uT), to_np(g), to_np(dV), to_np(du0)])
+        p.close()
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)
+    for b in range(2):
+        assert rel(out[1][0][b], O.mono(wl, wl.u0[b], V=wl.V[b])) < 1e-10
 
 
 def test_classical_iteration_matches_oracle_iterates(dev):
