@@ -54,7 +54,7 @@ def sweep_flops_per_pt_step(wl) -> float:
 
 SWEEP_SOURCES = ("paper_1503_02564_amd/csrc/swr_sweep_kernel.h", "paper_1503_02564_amd/csrc/swr_lane.h",
                  "paper_1503_02564_amd/csrc/swr_sweep_static.hip", "paper_1503_02564_amd/csrc/swr_sweep.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_kernel_config2_hbm.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_kernel_static_64x256_hbm.txt")
 
 
 def sweep_source_hash() -> str:
@@ -123,7 +123,7 @@ def adjoint_ratio(steps, warmup):
     import torch
     from paper_1503_02564_amd import swr
     from paper_1503_02564_amd import workloads as W
-    wl = W.config5()
+    wl = W.adjoint_batch()
     dev = torch.device("cuda:0")
 
     def opts(B, per_problem):
@@ -181,14 +181,14 @@ def adjoint_ratio(steps, warmup):
 
 
 def batched_vs_plain(batched_ms):
-    """The same config-2 solve with every sweep task launched on its own
+    """The same benchmark solve with every sweep task launched on its own
     (one subdomain of one problem per launch, one stream, staged), against
     the batched and pipelined form: same kernels, same interface solve, same
     certified residual."""
     import torch
     from paper_1503_02564_amd import swr
     from paper_1503_02564_amd import workloads as W
-    wl = W.config2()
+    wl = W.static_packet()
     dev = torch.device("cuda:0")
     o = swr.swr_default_opts()
     o.tol = wl.tol
@@ -232,7 +232,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
     ap.add_argument("--pipeline", type=int, default=256,
                     help="steps per pipeline chunk of the causal solve (0 = staged)")
-    ap.add_argument("--workload", default="config2", choices=["config2"])
+    ap.add_argument("--workload", default="static_packet", choices=["static_packet"])
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint/forward ratio on the differentiation workload")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -258,7 +258,7 @@ def main():
     from paper_1503_02564_amd import swr
     from paper_1503_02564_amd import workloads as W
 
-    wl = W.config2()
+    wl = W.static_packet()
     dev = torch.device("cuda:0")
     o = swr.swr_default_opts()
     o.solver = dict(causal=swr.SWR_SOLVER_CAUSAL, gmres=swr.SWR_SOLVER_GMRES,
@@ -324,7 +324,7 @@ def main():
         "value": value, "unit": "pt-steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "config2: (-40,40), 64x256 cells, 2000 steps dt=5e-4, S0^2, "
+        "config": {"workload": "static_packet: (-40,40), 64x256 cells, 2000 steps dt=5e-4, S0^2, "
                                "seeded bumpy harmonic V and packet, new algorithm, "
                                f"{args.solver} interface solve",
                    "nx": wl.nx, "nt": wl.nt, "N": wl.N, "B": wl.B, "solver": args.solver,

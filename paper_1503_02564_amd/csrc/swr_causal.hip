@@ -203,7 +203,7 @@ __device__ inline cd lane_dn1(cd v) { return shfl_dn_c(v, 1, mk(0, 0)); }
 // into a triple buffer, so a step costs one barrier and the solver never
 // waits for LDS written in the same step.
 __global__ __launch_bounds__(kNearThreads) void causal_near_kernel(NearArgs a) {
-    __shared__ cd gh[kTb][kNearSlots];
+    __shared__ cd gh[kTb][kNearSlots + 1];     // rows padded: no bank conflict between lag classes
     __shared__ cd gn[3][kNearSlots];
     __shared__ cd spcr[kPcrLevels * 8 + 4][kWave];
     const int b = blockIdx.x, v = a.per_problem ? b : 0;
@@ -285,9 +285,10 @@ __global__ __launch_bounds__(kNearThreads) void causal_near_kernel(NearArgs a) {
 #pragma unroll
             for (int l = 0; l < kPcrLevels; ++l) {
                 if (l >= lev) break;                    // uniform over the workgroup
+                // the multipliers are zero on lanes without a partner
                 const int d = 1 << l;
-                const cd q0m = shfl_up_c(p0, d, zero), q1m = shfl_up_c(p1, d, zero);
-                const cd q0p = shfl_dn_c(p0, d, zero), q1p = shfl_dn_c(p1, d, zero);
+                const cd q0m = shfl_up_raw(p0, d), q1m = shfl_up_raw(p1, d);
+                const cd q0p = shfl_dn_raw(p0, d), q1p = shfl_dn_raw(p1, d);
                 const cd* K = &spcr[l * 8][j];
                 const cd k1a = K[0 * kWave], k1b = K[1 * kWave], k1c = K[2 * kWave], k1d = K[3 * kWave];
                 const cd k2a = K[4 * kWave], k2b = K[5 * kWave], k2c = K[6 * kWave], k2d = K[7 * kWave];

@@ -129,6 +129,24 @@ __device__ inline cd shfl_dn_c(cd v, int d, cd fill) {
     return src > 63 ? fill : r;
 }
 
+// The same moves without the fill: lanes with no source get some other
+// lane's (finite) value.  For reductions whose multiplier is exactly zero on
+// those lanes (the PCR levels), the product is zero and the select is saved.
+__device__ inline cd shfl_up_raw(cd v, int d) {
+    if (d == 1) return mk(dpp_shift<0x138>(v.x), dpp_shift<0x138>(v.y));
+    if (d == 32) return mk(swap32(v.x).first, swap32(v.y).first);
+    if (d == 16) return mk(up16(v.x), up16(v.y));
+    const int src = (lane_id() - d) & (kWave - 1);
+    return mk(__shfl(v.x, src), __shfl(v.y, src));
+}
+__device__ inline cd shfl_dn_raw(cd v, int d) {
+    if (d == 1) return mk(dpp_shift<0x130>(v.x), dpp_shift<0x130>(v.y));
+    if (d == 32) return mk(swap32(v.x).second, swap32(v.y).second);
+    if (d == 16) return mk(dn16(v.x), dn16(v.y));
+    const int src = (lane_id() + d) & (kWave - 1);
+    return mk(__shfl(v.x, src), __shfl(v.y, src));
+}
+
 __device__ inline double wave_max(double v) {
     for (int d = 32; d >= 1; d >>= 1) v = fmax(v, __shfl_xor(v, d));
     return v;

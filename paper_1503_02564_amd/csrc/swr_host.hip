@@ -892,7 +892,16 @@ static swr_status pipe_resources(swr_ctx* c, int K) {
 static swr_status run_static_pipelined(swr_ctx* c, const cd* u0, cd* g, const SweepIO& fin,
                                        PipeTimes* tm) {
     const int nt = c->nt, ch = c->o.pipeline;
-    const int K = (nt + ch - 1) / ch;
+    // chunk boundaries: a short first chunk (64 steps) so the interface solve
+    // starts early, then multiples of ch, and a short last chunk so the final
+    // sweep ends soon after the interface solve (all multiples of 64)
+    std::vector<int> cut{0};
+    auto push = [&](int x) { if (x > cut.back() && x < nt) cut.push_back(x); };
+    push(kWave);
+    for (int x = ch; x < nt; x += ch) push(x);
+    push((nt - 1) / kWave * kWave);
+    cut.push_back(nt);
+    const int K = (int)cut.size() - 1;
     CHK(pipe_resources(c, K));
     hipStream_t st = c->st, s2 = c->s2, s3 = c->s3;
     hipEvent_t* es = c->evSync.data();
@@ -915,8 +924,8 @@ static swr_status run_static_pipelined(swr_ctx* c, const cd* u0, cd* g, const Sw
 
     // stage 1: impulse + d sweeps, chunk by chunk on st
     for (int j = 0; j < K; ++j) {
-        ab.n_begin = j * ch;
-        ab.n_end = std::min(nt, (j + 1) * ch);
+        ab.n_begin = cut[j];
+        ab.n_end = cut[j + 1];
         HIPCHK(hipEventRecord(et[2 * j], st));
         HIPCHK(launch_sweep(ab, c->tr, SWR_V_STATIC, st));
         HIPCHK(hipEventRecord(et[2 * j + 1], st));
@@ -927,15 +936,15 @@ static swr_status run_static_pipelined(swr_ctx* c, const cd* u0, cd* g, const Sw
     for (int j = 0; j < K; ++j) {
         HIPCHK(hipStreamWaitEvent(s2, es[2 + j], 0));
         if (j == 0) HIPCHK(hipEventRecord(et[4 * K], s2));
-        CHK(run_causal(c, c->L, c->dD, g, s2, j * ch, std::min(nt, (j + 1) * ch)));
+        CHK(run_causal(c, c->L, c->dD, g, s2, cut[j], cut[j + 1]));
         HIPCHK(hipEventRecord(es[2 + K + j], s2));
     }
     HIPCHK(hipEventRecord(et[4 * K + 1], s2));
     // stage 3: final sweep on s3
     for (int j = 0; j < K; ++j) {
         HIPCHK(hipStreamWaitEvent(s3, es[2 + K + j], 0));
-        af.n_begin = j * ch;
-        af.n_end = std::min(nt, (j + 1) * ch);
+        af.n_begin = cut[j];
+        af.n_end = cut[j + 1];
         HIPCHK(hipEventRecord(et[2 * K + 2 * j], s3));
         HIPCHK(launch_sweep(af, c->tr, c->vk, s3));
         HIPCHK(hipEventRecord(et[2 * K + 2 * j + 1], s3));

@@ -203,8 +203,9 @@ __device__ inline void lane_solve(const LaneFac<P>& F, const cd (&d)[P], cd (&x)
     cd D = msub(msub(d[P - 1], F.ae, yL), F.ce, yR);
 #pragma unroll
     for (int l = 0; l < kPcrLevels; ++l) {
+        // k1 (k2) is zero on lanes without a partner at -dd (+dd)
         const int dd = 1 << l;
-        const cd Dm = shfl_up_c(D, dd, zero), Dp = shfl_dn_c(D, dd, zero);
+        const cd Dm = shfl_up_raw(D, dd), Dp = shfl_dn_raw(D, dd);
         D = msub(msub(D, F.k1[l], Dm), F.k2[l], Dp);
     }
     const cd X = D * F.invB;

@@ -103,22 +103,22 @@ def bumpy_harmonic(x: np.ndarray, amps, centres, curvature=-0.05) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
-# The five benchmark configurations.  ``scale`` shrinks them for tests
+# The workloads of the measurements and the full-size tests.  ``scale`` shrinks them for tests
 # (fewer cells per subdomain and fewer steps, same structure).
 # ---------------------------------------------------------------------------
 
-def config1() -> Workload:
+def robin_window() -> Workload:
     """Plain SWR: (-10,10), 400 cells, 4 equal subdomains, V=0,
     u0 = exp(-x^2 + 2ix), dt=1e-3, 500 steps, Robin dn u + (1-i) u,
     classical fixed point to max trace change < 1e-10."""
     J = np.full(4, 100, dtype=np.int32)
     x = mesh_nodes(-10.0, 10.0, int(J.sum()))
     u0 = gaussian_packet(x, 0.0, 2.0)[None, :]
-    return Workload("config1_plain_swr_robin", -10.0, 10.0, J, 1e-3, 500, V_STATIC,
+    return Workload("robin_window", -10.0, 10.0, J, 1e-3, 500, V_STATIC,
                     np.zeros_like(x), ROBIN, 1.0 - 1.0j, u0, tol=1e-10, seed=1)
 
 
-def config2(N: int = 64, cells: int = 256, nt: int = 2000, seed: int = 2) -> Workload:
+def static_packet(N: int = 64, cells: int = 256, nt: int = 2000, seed: int = 2) -> Workload:
     """Time-independent potential, preprocessed interface algorithm:
     (-40,40), N x cells cells, V = -0.05x^2 + 8 seeded Gaussian bumps
     (A ~ U(-5,5), c ~ U(-30,30)), packet with x0, k0 ~ U(-5,5),
@@ -132,15 +132,15 @@ def config2(N: int = 64, cells: int = 256, nt: int = 2000, seed: int = 2) -> Wor
     V = bumpy_harmonic(x, amps, centres)
     u0 = gaussian_packet(x, x0, k0)[None, :]
     dt = 1.0 / nt
-    return Workload("config2_static_v_new_algorithm", -40.0, 40.0, J, dt, nt, V_STATIC, V,
+    return Workload("static_packet", -40.0, 40.0, J, dt, nt, V_STATIC, V,
                     S02, 0j, u0, tol=1e-10, seed=seed,
                     extras=dict(amps=amps, centres=centres, x0=x0, k0=k0))
 
 
-def config3(N: int = 500, lo: int = 40, hi: int = 400, B: int = 32, nt: int = 2000,
+def batched_uneven(N: int = 500, lo: int = 40, hi: int = 400, B: int = 32, nt: int = 2000,
             seed: int = 3) -> Workload:
     """Batched uneven decomposition: (-100,100), N subdomains with seeded
-    sizes U{lo..hi} cells, V = V2(0.4 x) (the config-2 form stretched to the
+    sizes U{lo..hi} cells, V = V2(0.4 x) (the static-packet form stretched to the
     domain), B seeded packets (x0 ~ U(-12.5,12.5), k0 ~ U(-5,5)),
     dt = 5e-4 at nt=2000, S0^2."""
     rng = np.random.default_rng(seed)
@@ -151,7 +151,7 @@ def config3(N: int = 500, lo: int = 40, hi: int = 400, B: int = 32, nt: int = 20
     x = mesh_nodes(-100.0, 100.0, int(J.sum()))
     V = bumpy_harmonic(0.4 * x, amps, centres)
     u0 = np.stack([gaussian_packet(x, -12.5 + 25.0 * a, -5.0 + 10.0 * b) for a, b in pk])
-    return Workload("config3_batched_uneven", -100.0, 100.0, J, 1.0 / nt, nt, V_STATIC, V,
+    return Workload("batched_uneven", -100.0, 100.0, J, 1.0 / nt, nt, V_STATIC, V,
                     S02, 0j, u0, tol=1e-10, seed=seed)
 
 
@@ -160,7 +160,7 @@ def _four_packets(x, rng):
     return sum(gaussian_packet(x, a, b) for a, b in p)
 
 
-def config4a(N: int = 128, cells: int = 256, nt: int = 4000, seed: int = 4) -> Workload:
+def time_dependent(N: int = 128, cells: int = 256, nt: int = 4000, seed: int = 4) -> Workload:
     """Time-dependent potential V(t,x) = 5 x cos t on (-40,40), N x cells
     cells, seeded sum of 4 packets, dt = 2.5e-4 at nt = 4000, S0^2,
     preconditioned by the zero-potential interface operator."""
@@ -171,23 +171,23 @@ def config4a(N: int = 128, cells: int = 256, nt: int = 4000, seed: int = 4) -> W
     dt = 1.0 / nt
     t = dt * np.arange(nt + 1)
     V = 5.0 * np.cos(t)[:, None] * x[None, :]
-    return Workload("config4a_time_dependent_v", -40.0, 40.0, J, dt, nt, V_TIME, V,
+    return Workload("time_dependent", -40.0, 40.0, J, dt, nt, V_TIME, V,
                     S02, 0j, u0, tol=1e-10, seed=seed)
 
 
-def config4b(N: int = 128, cells: int = 256, nt: int = 4000, seed: int = 4) -> Workload:
+def cubic_packets(N: int = 128, cells: int = 256, nt: int = 4000, seed: int = 4) -> Workload:
     """Cubic nonlinearity V = |u|^2 with the same mesh, data and step as 4a."""
     rng = np.random.default_rng(seed)
     J = np.full(N, cells, dtype=np.int32)
     x = mesh_nodes(-40.0, 40.0, int(J.sum()))
     u0 = _four_packets(x, rng)[None, :]
-    return Workload("config4b_cubic", -40.0, 40.0, J, 1.0 / nt, nt, V_CUBIC, None,
+    return Workload("cubic_packets", -40.0, 40.0, J, 1.0 / nt, nt, V_CUBIC, None,
                     S02, 0j, u0, tol=1e-10, seed=seed)
 
 
-def config5(N: int = 256, cells: int = 64, nt: int = 2000, B: int = 16, seed: int = 5) -> Workload:
+def adjoint_batch(N: int = 256, cells: int = 64, nt: int = 2000, B: int = 16, seed: int = 5) -> Workload:
     """Differentiation: (-40,40), N x cells cells, B seeded potentials of the
-    config-2 form plus one seeded reference potential, one seeded packet,
+    static-packet form plus one seeded reference potential, one seeded packet,
     dt = 5e-4 at nt = 2000, S0^2, adjoint checkpoint interval 64.
     V is [B][nx]; extras['V_ref'] is the reference potential."""
     rng = np.random.default_rng(seed)
@@ -200,7 +200,7 @@ def config5(N: int = 256, cells: int = 64, nt: int = 2000, B: int = 16, seed: in
         Vs.append(bumpy_harmonic(x, amps, centres))
     x0, k0 = rng.uniform(-5.0, 5.0, 2)
     u0 = np.repeat(gaussian_packet(x, x0, k0)[None, :], B, axis=0)
-    return Workload("config5_adjoint", -40.0, 40.0, J, 1.0 / nt, nt, V_STATIC,
+    return Workload("adjoint_batch", -40.0, 40.0, J, 1.0 / nt, nt, V_STATIC,
                     np.stack(Vs[:B]), S02, 0j, u0, tol=1e-10, seed=seed,
                     extras=dict(V_ref=Vs[B], checkpoint_K=64))
 

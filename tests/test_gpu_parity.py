@@ -120,6 +120,16 @@ PIPE_CASES = [
 ]
 
 
+def _pipeline_chunks(nt, ch):
+    """Time chunks of the pipelined solve: a 64-step first chunk, then
+    multiples of ch, and a short last chunk ending at nt."""
+    cut = [0]
+    for x in [64] + list(range(ch, nt, ch)) + [(nt - 1) // 64 * 64]:
+        if cut[-1] < x < nt:
+            cut.append(x)
+    return len(cut)
+
+
 @pytest.mark.parametrize("label,J,nt,trans,sigma,B,per_problem,chunk", PIPE_CASES)
 def test_pipelined_solve_equals_staged_solve(dev, label, J, nt, trans, sigma, B, per_problem, chunk):
     """The time-chunked overlap of build sweeps, causal solve and final sweep
@@ -145,7 +155,7 @@ def test_pipelined_solve_equals_staged_solve(dev, label, J, nt, trans, sigma, B,
         torch.cuda.synchronize()
         assert st == swr.SWR_OK and info.residual < 1e-11
         if ch:
-            assert info.n_sweep == 2 * ((nt + ch - 1) // ch)
+            assert info.n_sweep == 2 * _pipeline_chunks(nt, ch)
         out[ch] = (to_np(uT), to_np(g), to_np(tr))
         pb.close()
     for a, b in zip(out[0], out[chunk]):
@@ -193,15 +203,15 @@ def test_plain_launches_equal_batched(dev):
 
 
 def test_classical_iteration_matches_oracle_iterates(dev):
-    """Config-1 grid with S0^2: classical SWR to max change < 1e-10 (the
-    Robin value of config 1 does not converge by fixed point; see the next
-    test).  Converged u(T) = monodomain; iteration count = oracle's."""
+    """Robin-window grid with S0^2: classical SWR to max change < 1e-10 (the
+    Robin value s = 1-i on that grid does not converge by fixed point; see
+    the next test).  Converged u(T) = monodomain; iteration count = oracle's."""
     import copy
     import torch
     from paper_1503_02564_amd import swr
-    wl = copy.copy(W.config1())
+    wl = copy.copy(W.robin_window())
     wl.trans = W.S02
-    say("classical", "config1-grid-s02")
+    say("classical", "robin-window-grid-s02")
     pb = make_problem(wl, solver=swr.SWR_SOLVER_FIXED, tol=1e-10, max_iter=2000)
     uT = torch.zeros((1, wl.nx), dtype=torch.complex128, device=dev)
     st, info = swr.swr_solve(pb.ctx, to_dev(wl.u0), uT)
@@ -213,14 +223,14 @@ def test_classical_iteration_matches_oracle_iterates(dev):
     pb.close()
 
 
-def test_config1_robin(dev):
-    """Config 1 as stated (dn u + (1-i) u): the first classical iterates match
+def test_robin_window_grid(dev):
+    """The Robin window as stated (dn u + (1-i) u): the first classical iterates match
     the oracle's, and the interface problem solved directly gives the
     monodomain solution."""
     import torch
     from paper_1503_02564_amd import swr
-    wl = W.config1()
-    say("config1-robin")
+    wl = W.robin_window()
+    say("robin-window")
     pb = make_problem(wl)
     u0 = to_dev(wl.u0)
     g = np.zeros((pb.ns, wl.nt), complex)
@@ -279,19 +289,19 @@ def test_edge_cases(dev, J, nt):
     pb.close()
 
 
-def test_full_size_config2_matches_monodomain(dev):
-    """Config 2 at full size, in the configuration the benchmark times
+def test_full_size_static_packet_matches_monodomain(dev):
+    """The static-packet workload at full size, in the configuration the benchmark times
     (N = 64 x 256 cells, 2000 steps, S0^2, causal interface solve): u(T)
     against the monodomain oracle, and the certified interface residual."""
     import torch
     from paper_1503_02564_amd import swr
-    wl = W.config2()
-    say("full-size", "config2")
+    wl = W.static_packet()
+    say("full-size", "static_packet")
     pb = make_problem(wl)
     uT = torch.zeros((1, wl.nx), dtype=torch.complex128, device=dev)
     st, info = swr.swr_solve(pb.ctx, to_dev(wl.u0), uT)
     torch.cuda.synchronize()
-    say("full-size", "config2 done", info.as_dict())
+    say("full-size", "static_packet done", info.as_dict())
     assert st == swr.SWR_OK
     assert info.residual < 1e-10
     assert rel(to_np(uT)[0], O.mono(wl, wl.u0[0])) < 1e-10

@@ -48,7 +48,7 @@ def _solve(dev, wl, **kw):
     return st, info, to_np(uT)
 
 
-def test_full_size_config5_forward_adjoint_and_fd(dev):
+def test_full_size_adjoint_batch_forward_adjoint_and_fd(dev):
     """256 x 64 cells, 2000 steps, 16 potentials (one per problem): u(T) of
     two members against the oracle, swr_grad of member 0 against the CPU
     adjoint, and dJ/dV, dJ/du0 against central differences (h = 1e-6) on 32
@@ -56,9 +56,9 @@ def test_full_size_config5_forward_adjoint_and_fd(dev):
     per batch member per perturbed solve."""
     import torch
     from paper_1503_02564_amd import swr
-    wl = W.config5()
+    wl = W.adjoint_batch()
     B, nx = wl.B, wl.nx
-    say("full-size", "config5 forward")
+    say("full-size", "adjoint_batch forward")
     pb = make_problem(wl, v_per_problem=True)
     u0 = to_dev(wl.u0)
     uT = torch.zeros((B, nx), dtype=torch.complex128, device=dev)
@@ -75,7 +75,7 @@ def test_full_size_config5_forward_adjoint_and_fd(dev):
     gbar = (2.0 * (uT - tgt)).contiguous()
     dV = torch.zeros((B, nx), dtype=torch.float64, device=dev)
     du0 = torch.zeros((B, nx), dtype=torch.complex128, device=dev)
-    say("full-size", "config5 grad")
+    say("full-size", "adjoint_batch grad")
     st, ginfo = swr.swr_grad(pb.ctx, u0, gbar, dV, du0)
     torch.cuda.synchronize()
     assert st == swr.SWR_OK and ginfo.residual < 1e-10
@@ -118,7 +118,7 @@ def test_full_size_config5_forward_adjoint_and_fd(dev):
     x = W.mesh_nodes(wl.a0, wl.b0, wl.nc)
     hR = 1e-2
     for rnd in range(2):       # 2 x 16 potential directions
-        say("full-size", "config5 fd potential round", rnd)
+        say("full-size", "adjoint_batch fd potential round", rnd)
         P = np.stack([sum(rng.standard_normal() * np.exp(-(x - c) ** 2)
                           for c in rng.uniform(-30, 30, 4)) for _ in range(B)])
         an = np.sum(dV * P, axis=1)
@@ -127,7 +127,7 @@ def test_full_size_config5_forward_adjoint_and_fd(dev):
         f1 = dJ(wl.V + hR * P, u0, wl.V - hR * P, u0) / (2 * hR)
         f2 = dJ(wl.V + 0.5 * hR * P, u0, wl.V - 0.5 * hR * P, u0) / hR
         check(an, cs, d1, (4 * f2 - f1) / 3, "potential")
-    say("full-size", "config5 fd initial data")
+    say("full-size", "adjoint_batch fd initial data")
     swr.swr_set_potential(pb.ctx, to_dev(wl.V))
     Q = rng.standard_normal((B, nx)) + 1j * rng.standard_normal((B, nx))
     Q *= np.exp(-(x / 10.0) ** 2)[None]
@@ -141,50 +141,50 @@ def test_full_size_config5_forward_adjoint_and_fd(dev):
     pb.close()
 
 
-def test_full_size_config4a_time_dependent_potential(dev):
+def test_full_size_time_dependent_time_dependent_potential(dev):
     """V(t,x) = 5 x cos t on 128 x 256 cells over 4000 steps: preconditioned
     GMRES with the matrix-free interface operator, against the oracle.  Over
     this window P = I - L_0 leaves a slowly converging problem (33 iterations
     at 1000 steps, ~100 at 2000, several hundred at 4000; GMRES(60)
     stagnates), so the run uses GMRES(200)."""
     from paper_1503_02564_amd import swr
-    wl = W.config4a()
-    say("full-size", "config4a")
+    wl = W.time_dependent()
+    say("full-size", "time_dependent")
     st, info, uT = _solve(dev, wl, tol=1e-11, restart=200, max_iter=1500)
-    say("full-size", "config4a done", info.as_dict())
+    say("full-size", "time_dependent done", info.as_dict())
     assert st == swr.SWR_OK
     assert rel(uT[0], O.mono(wl, wl.u0[0])) < 1e-10
 
 
-def test_full_size_config4b_cubic(dev):
+def test_full_size_cubic_packets(dev):
     """|u|^2 on 128 x 256 cells over 4000 steps by the preconditioned fixed
     point: converged, mass conserved; the first 400 steps of the same grid
     and dt against the oracle."""
     from paper_1503_02564_amd import swr
-    wl = W.config4b()
-    say("full-size", "config4b")
+    wl = W.cubic_packets()
+    say("full-size", "cubic_packets")
     st, info, uT = _solve(dev, wl, tol=1e-12, max_iter=500)
-    say("full-size", "config4b done", info.as_dict())
+    say("full-size", "cubic_packets done", info.as_dict())
     assert st == swr.SWR_OK
     m0 = _mass(wl, wl.u0[0])
     assert abs(_mass(wl, uT[0]) - m0) <= 1e-10 * m0
     short = _shorter(wl, 400)
-    say("full-size", "config4b 400 steps")
+    say("full-size", "cubic_packets 400 steps")
     st, info, uS = _solve(dev, short, tol=1e-12, max_iter=500)
     assert st == swr.SWR_OK
     assert rel(uS[0], O.mono(short, short.u0[0])) < 1e-10
 
 
-def test_full_size_config3_batched_uneven(dev):
+def test_full_size_batched_uneven(dev):
     """500 uneven subdomains (U{40..400} cells, ~109k nodes), 32 packets in
     one batch, 2000 steps: certified residual, mass of every member
     conserved, members 0 and 31 bitwise equal to the same problem solved
     alone; the first 100 steps of member 0 against the oracle."""
     from paper_1503_02564_amd import swr
-    wl = W.config3()
-    say("full-size", "config3 batch of", wl.B)
+    wl = W.batched_uneven()
+    say("full-size", "batched_uneven batch of", wl.B)
     st, info, uT = _solve(dev, wl)
-    say("full-size", "config3 done", info.as_dict())
+    say("full-size", "batched_uneven done", info.as_dict())
     assert st == swr.SWR_OK and info.residual < 1e-10
     for b in range(wl.B):
         m0 = _mass(wl, wl.u0[b])
@@ -192,13 +192,13 @@ def test_full_size_config3_batched_uneven(dev):
     for b in (0, wl.B - 1):
         one = copy.copy(wl)
         one.u0 = wl.u0[b:b + 1]
-        say("full-size", "config3 member alone", b)
+        say("full-size", "batched_uneven member alone", b)
         st, _, u1 = _solve(dev, one)
         assert st == swr.SWR_OK
         assert np.array_equal(u1[0], uT[b])
     short = _shorter(wl, 100)
     short.u0 = wl.u0[:1]
-    say("full-size", "config3 100 steps")
+    say("full-size", "batched_uneven 100 steps")
     st, _, uS = _solve(dev, short)
     assert st == swr.SWR_OK
     assert rel(uS[0], O.mono(short, short.u0[0])) < 1e-10

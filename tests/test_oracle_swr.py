@@ -37,10 +37,10 @@ def test_single_subdomain_is_monodomain():
 
 
 def test_robin_small_sigma_direct_solution_is_monodomain():
-    """Config-1 transmission (dn u + (1-i) u): the interface problem is
+    """Robin-window transmission (dn u + (1-i) u): the interface problem is
     well posed (solved directly here) even where its fixed point is not
     practical."""
-    wl = W.config1()
+    wl = W.robin_window()
     u0 = wl.u0[0]
     uT, g, info = O.new_algorithm(wl, u0, solver="causal")
     assert _rel(uT, O.mono(wl, u0)) < 1e-12
