@@ -28,7 +28,8 @@ import math
 
 import numpy as np
 
-from paper_1503_02564_amd.workloads import (S02, V_CUBIC, V_STATIC, V_TIME,  # noqa: F401
+from paper_1503_02564_amd.workloads import (S02, S03, S04, S12, S14, V_CUBIC, V_STATIC,  # noqa: F401
+                                            V_TIME,
                                             Workload, ROBIN)
 from . import build as _build
 
@@ -37,7 +38,7 @@ __all__ = [
     "sweep", "slot_map", "apply_R", "apply_R0", "local_solution", "classical",
     "impulse_columns", "ltt_apply", "brute_L", "gmres", "bicgstab", "causal_solve",
     "interface_d", "new_algorithm", "preconditioned_time", "preconditioned_cubic",
-    "adjoint_mono", "potential_of",
+    "adjoint_mono", "potential_of", "end_data", "sbar",
 ]
 
 _LIB = None
@@ -65,6 +66,8 @@ def lib():
         L.orc_sub_sweep.restype = _I
         L.orc_mono_adjoint.argtypes = [_I, _D, _D, _I, _C, _C, _C, _C, _C]
         L.orc_mono_adjoint.restype = _I
+        L.orc_end_data.argtypes = [_I, _C, _I, _I, _I, _D, _D, _I, _C, _C, _C]
+        L.orc_sbar_apply.argtypes = [_I, _I, _D, _C, _C, _C, _C, _C, _C]
         _LIB = L
     return _LIB
 
@@ -101,6 +104,34 @@ def beta(n: int) -> np.ndarray:
 def c2_of(dt: float) -> complex:
     """c2 = e^{-i pi/4} sqrt(2/dt), the S0^2 prefactor (Sec. 2.2, Prop. 3)."""
     return complex(np.exp(-1j * np.pi / 4) * math.sqrt(2.0 / dt))
+
+
+def end_data(wl: Workload, k: int, side: int, V=None):
+    """(W_n, dn W_n, calW_n), n = 0..nt, at the left (side 0) or right
+    (side 1) end of subdomain k: the potential data of the S0^3, S0^4, S1^2
+    and S1^4 operators (Sec. 2.2; readings in swr_oracle.c)."""
+    if V is None:
+        V = potential_of(wl)
+    Va = None if V is None else np.ascontiguousarray(V, np.float64)
+    g = int(wl.offsets[k]) + (int(wl.J[k]) if side else 0)
+    out = np.zeros((3, wl.nt + 1))
+    lib().orc_end_data(wl.vkind, _p(Va), wl.nx, g, 1 if side else -1, wl.h, wl.dt, wl.nt,
+                       _p(out[0]), _p(out[1]), _p(out[2]))
+    return out[0].copy(), out[1].copy(), out[2].copy()
+
+
+def sbar(kind: int, dt: float, v, W, dW, calW):
+    """Sbar v_n, n = 0..len(v)-1, of the transmission operator `kind`
+    (S02, S03, S04, S12, S14) on a given sequence v: returns (full, without
+    the order-4 normal-derivative term)."""
+    v = _cvec(v)
+    nt = len(v) - 1
+    W, dW, calW = (np.ascontiguousarray(a, np.float64) for a in (W, dW, calW))
+    assert W.shape == dW.shape == calW.shape == (nt + 1,)
+    out = np.zeros(nt + 1, np.complex128)
+    out_s = np.zeros(nt + 1, np.complex128)
+    lib().orc_sbar_apply(kind, nt, dt, _p(v), _p(W), _p(dW), _p(calW), _p(out), _p(out_s))
+    return out, out_s
 
 
 # ---------------------------------------------------------------------------

@@ -17,6 +17,11 @@
  *   v_n    = (u_n + u_{n-1})/2,   u_n = 2 v_n - u_{n-1}            (eq. CNS_L)
  *   W_n    = (V_n + V_{n-1})/2                                     (eq. CNS_L)
  *   S0^2 : Sbar v_n = c2 sum_{s=0}^{n} beta_{n-s} v_s, c2 = e^{-i pi/4} sqrt(2/dt)
+ *   S0^3 : adds - e^{i pi/4} sqrt(dt/2) (W_n/2) sum_{s=0}^{n} alpha_{n-s} v_s
+ *   S0^4 : adds - i (dn W_n / 4) (dt/2) sum_{s=0}^{n} gamma_{n-s} v_s
+ *   S1^2 : Sbar v_n = c2 e^{i calW_n} sum_{s=0}^{n} beta_{n-s} e^{-i calW_s} v_s
+ *   S1^4 : adds - i sgn(dn W_n) q_n e^{i calW_n} (dt/2) sum gamma_{n-s} q_s e^{-i calW_s} v_s,
+ *          q_n = sqrt(|dn W_n|)/2
  *   Robin: Sbar v_n = sigma v_n (the caller passes the complex sigma of dn + sigma)
  */
 #define _GNU_SOURCE
@@ -131,7 +136,7 @@ int orc_thomas(int n, const cplx *diag, const cplx *off, const cplx *rhs, cplx *
 /* Potential kinds */
 enum { ORC_V_STATIC = 0, ORC_V_TIME = 1, ORC_V_CUBIC = 2 };
 /* Transmission kinds */
-enum { ORC_ROBIN = 0, ORC_S02 = 1 };
+enum { ORC_ROBIN = 0, ORC_S02 = 1, ORC_S03 = 2, ORC_S04 = 3, ORC_S12 = 4, ORC_S14 = 5 };
 
 /* W_n on n nodes starting at global node offset `off0`.
  * Static: W = V(x).  Time dependent: W_n = (V_n + V_{n-1})/2 (eq. CNS_L),
@@ -232,23 +237,148 @@ int orc_mono_cn(int nx, double h, double dt, int nt, int vkind, const double *V,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Potential data the transmission operators need at one interface end       */
+/* (Sec. 2.2, "Potential strategy" and "Gauge change strategy"), for steps   */
+/* n = 0..nt at global node g:                                               */
+/*   W[n]    = W_n(x_g) (static: V(x_g); time dependent: (V_n + V_{n-1})/2)   */
+/*   dW[n]   = outward normal derivative of W_n at x_g, by the centred        */
+/*             difference (W_n(x_{g+1}) - W_n(x_{g-1}))/(2h) times nsign      */
+/*             (+1 at a right end b_j, -1 at a left end a_j)                  */
+/*   calW[n] = (calV_n + calV_{n-1})/2 with calV_n = int_0^{t_n} V(s, x_g) ds */
+/*             by the trapezoid rule on the time grid, calV_n = calV_{n-1} +  */
+/*             dt W_n                                                         */
+/* Step 0 has no V_{-1}: W_0 = V_0 and calW_0 = calV_0 = 0 (v_0 = u_0 is the   */
+/* state at t = 0).  Interior interfaces only (g-1 and g+1 exist).            */
+/* ------------------------------------------------------------------------ */
+void orc_end_data(int vkind, const double *V, int nx_global, int g, int nsign, double h,
+                  double dt, int nt, double *W, double *dW, double *calW)
+{
+    double calV_prev = 0.0;
+    for (int n = 0; n <= nt; ++n) {
+        double w = 0.0, wm = 0.0, wp = 0.0;
+        if (V && vkind == ORC_V_STATIC) {
+            w = V[g]; wm = V[g - 1]; wp = V[g + 1];
+        } else if (V && vkind == ORC_V_TIME) {
+            const double *Vn = V + (size_t)n * nx_global;
+            const double *Vm = V + (size_t)(n > 0 ? n - 1 : 0) * nx_global;
+            w = 0.5 * (Vn[g] + Vm[g]);
+            wm = 0.5 * (Vn[g - 1] + Vm[g - 1]);
+            wp = 0.5 * (Vn[g + 1] + Vm[g + 1]);
+        }
+        W[n] = w;
+        dW[n] = nsign * (wp - wm) / (2.0 * h);
+        if (n == 0) {
+            calW[0] = 0.0;
+        } else {
+            double calV = calV_prev + dt * w;
+            calW[n] = 0.5 * (calV + calV_prev);
+            calV_prev = calV;
+        }
+    }
+}
+
+static double sgn(double x) { return (x > 0.0) - (x < 0.0); }
+
+/* ------------------------------------------------------------------------ */
+/* The semi-discrete transmission operator Sbar at step n and one end        */
+/* (Sec. 2.2), written as                                                    */
+/*     Sbar v_n = sig v_n + hist,     hist = the terms with s < n,            */
+/* for the S0^2, S0^3, S0^4, S1^2 and S1^4 operators.  (sig_s, hist_s) is     */
+/* the same split without the order-4 normal-derivative term: that term      */
+/* changes sign with the normal, so in the exchange of eq. TransmisionCond   */
+/* it cancels and 2 (Sbar without it) v is what crosses the interface.       */
+/* v[0..n-1] are the past values at this end; W, dW, calW as orc_end_data.   */
+/* alpha, beta: weights of at least n+1 entries; gamma = (1, 2, 2, ...).     */
+/* ------------------------------------------------------------------------ */
+void orc_sbar_parts(int kind, int n, double dt, const cplx *v, const double *W,
+                    const double *dW, const double *calW, const double *alpha,
+                    const double *beta, cplx *sig, cplx *hist, cplx *sig_s, cplx *hist_s)
+{
+    const cplx c2 = cexp(-I * M_PI / 4.0) * sqrt(2.0 / dt);
+    cplx s2 = 0, h2 = 0, s4 = 0, h4 = 0;
+    if (kind == ORC_S02 || kind == ORC_S03 || kind == ORC_S04) {
+        cplx b = 0;
+        for (int s = 0; s < n; ++s) b += beta[n - s] * v[s];
+        s2 = c2 * beta[0];
+        h2 = c2 * b;
+        if (kind != ORC_S02) {
+            /* - e^{i pi/4} sqrt(dt/2) (W_n/2) sum alpha_{n-s} v_s */
+            const cplx c3 = -cexp(I * M_PI / 4.0) * sqrt(dt / 2.0) * (W[n] / 2.0);
+            cplx a = 0;
+            for (int s = 0; s < n; ++s) a += alpha[n - s] * v[s];
+            s2 += c3 * alpha[0];
+            h2 += c3 * a;
+        }
+        if (kind == ORC_S04) {
+            /* - i (dn W_n / 4) (dt/2) sum gamma_{n-s} v_s */
+            const cplx c4 = -I * (dW[n] / 4.0) * (dt / 2.0);
+            cplx gsum = 0;
+            for (int s = 0; s < n; ++s) gsum += 2.0 * v[s];
+            s4 = c4 * 1.0;
+            h4 = c4 * gsum;
+        }
+    } else if (kind == ORC_S12 || kind == ORC_S14) {
+        /* c2 e^{i calW_n} sum beta_{n-s} e^{-i calW_s} v_s; the s = n term is
+           c2 beta_0 v_n */
+        cplx b = 0;
+        for (int s = 0; s < n; ++s) b += beta[n - s] * cexp(-I * calW[s]) * v[s];
+        s2 = c2 * beta[0];
+        h2 = c2 * cexp(I * calW[n]) * b;
+        if (kind == ORC_S14) {
+            const double qn = sqrt(fabs(dW[n])) / 2.0;
+            const cplx c4 = -I * sgn(dW[n]) * qn * cexp(I * calW[n]) * (dt / 2.0);
+            cplx gsum = 0;
+            for (int s = 0; s < n; ++s) gsum += 2.0 * (sqrt(fabs(dW[s])) / 2.0) * cexp(-I * calW[s]) * v[s];
+            s4 = c4 * 1.0 * qn * cexp(-I * calW[n]);
+            h4 = c4 * gsum;
+        }
+    }
+    *sig = s2 + s4;
+    *hist = h2 + h4;
+    *sig_s = s2;
+    *hist_s = h2;
+}
+
+/* Sbar v_n for n = 0..nt of a given sequence v (test access to the operator):
+   out[n] with every term, out_s[n] without the order-4 term. */
+void orc_sbar_apply(int kind, int nt, double dt, const cplx *v, const double *W,
+                    const double *dW, const double *calW, cplx *out, cplx *out_s)
+{
+    double *alpha = malloc(sizeof(double) * (size_t)(nt + 1));
+    double *beta = malloc(sizeof(double) * (size_t)(nt + 1));
+    orc_alpha(nt + 1, alpha);
+    orc_beta(nt + 1, beta);
+    for (int n = 0; n <= nt; ++n) {
+        cplx sg, hs, sgs, hss;
+        orc_sbar_parts(kind, n, dt, v, W, dW, calW, alpha, beta, &sg, &hs, &sgs, &hss);
+        out[n] = sg * v[n] + hs;
+        out_s[n] = sgs * v[n] + hss;
+    }
+    free(alpha); free(beta);
+}
+
+/* ------------------------------------------------------------------------ */
 /* One subdomain over the whole time window (eq. AvML for linear V,          */
 /* eq. AvMNL for f(u) = |u|^2), with the transmission conditions written by  */
 /* fluxes (eq. TransmissionCondlocal) and the exchange of                    */
 /* eq. TransmissionCond_disc:                                                */
 /*                                                                           */
 /*  (A_n - B_n) v_n = c M u_{n-1} + b_n - Q^T (l_n, r_n)^T                   */
-/*  B_n = sigma E   (E picks the interface ends; walls keep Neumann)         */
-/*  b_n = Q^T (h_n(a), h_n(b)),  h_n = c2 sum_{s=0}^{n-1} beta_{n-s} v_s      */
-/*        (S0^2; zero for Robin), with v_0 = u_0 at the boundary node         */
-/*  outgoing fluxes:  rhoL_n = -l_n + 2 (sigma v_n(a) + h_n(a))              */
-/*                    rhoR_n = -r_n + 2 (sigma v_n(b) + h_n(b))              */
+/*  Sbar v_n = sig_n v_n + h_n at each end (orc_sbar_parts; Robin: sig_n =  */
+/*        sigma, h_n = 0), with v_0 = u_0 at the boundary node                */
+/*  B_n = sig_n E   (E picks the interface ends; walls keep Neumann)         */
+/*  b_n = Q^T (h_n(a), h_n(b))                                               */
+/*  outgoing fluxes:  rhoL_n = -l_n + 2 (sig'_n v_n(a) + h'_n(a))            */
+/*                    rhoR_n = -r_n + 2 (sig'_n v_n(b) + h'_n(b))            */
+/*  where ' drops the order-4 normal-derivative term (S0^4, S1^4).           */
+/*  trans: 0 Robin, 1 S0^2, 2 S0^3, 3 S0^4, 4 S1^2, 5 S1^4; the last four    */
+/*  need a linear potential (returns -4 with |u|^2).                         */
 /*                                                                           */
 /* The subdomain has n nodes starting at global node `off0` of a mesh with   */
 /* nx_global nodes (V is indexed globally).  left_iface/right_iface say      */
 /* whether each end is an interface (1) or a Neumann wall (0).               */
 /* u0: local initial data (NULL = zero).  hist0: value used for v_0 in the   */
-/* S0^2 history at each end (NULL = u0 ends, as in the paper).               */
+/* history of Sbar at each end (NULL = u0 ends, as in the paper).            */
 /* l, r: incoming fluxes for n = 1..nt (index 0..nt-1); NULL = zero.         */
 /* Outputs (each optional): rhoL/rhoR[nt], uT[n], va/vb[nt+1] (v_n at the    */
 /* two ends, n = 0..nt), v_all[nt*n].                                        */
@@ -262,47 +392,48 @@ int orc_sub_sweep(int n, double h, double dt, int nt, int vkind, const double *V
                   int nl_maxit, double nl_tol, int *nl_worst)
 {
     const cplx c = 2.0 * I / dt;
-    const cplx c2 = cexp(-I * M_PI / 4.0) * sqrt(2.0 / dt);
-    /* S0^2: the s = n term of c2 sum beta_{n-s} v_s is the implicit part,
-       coefficient c2 beta_0; Robin: the caller's sigma. */
-    const cplx sigma = (trans == ORC_S02) ? c2 * beta[0] : sigma_re + I * sigma_im;
+    const int conv = trans != ORC_ROBIN;     /* a convolution-type Sbar */
+    /* the operators beyond S0^2 carry W_n; with f(u) = |u|^2 the paper gives
+       no discretisation of them that keeps the interface continuity */
+    if (trans > ORC_S02 && vkind == ORC_V_CUBIC) return -4;
+    if (trans < ORC_ROBIN || trans > ORC_S14) return -5;
     cplx *diag = malloc(sizeof(cplx) * (size_t)n), *off = malloc(sizeof(cplx) * (size_t)(n > 1 ? n - 1 : 1));
     cplx *u = malloc(sizeof(cplx) * (size_t)n), *v = malloc(sizeof(cplx) * (size_t)n);
     cplx *rhs = malloc(sizeof(cplx) * (size_t)n), *w1 = malloc(sizeof(cplx) * (size_t)n);
     cplx *w2 = malloc(sizeof(cplx) * (size_t)n), *w3 = malloc(sizeof(cplx) * (size_t)n);
     double *W = malloc(sizeof(double) * (size_t)n);
-    cplx *ha = malloc(sizeof(cplx) * (size_t)(nt + 1)), *hb = malloc(sizeof(cplx) * (size_t)(nt + 1));
     cplx *ta = malloc(sizeof(cplx) * (size_t)(nt + 1)), *tb = malloc(sizeof(cplx) * (size_t)(nt + 1));
+    double *alpha = malloc(sizeof(double) * (size_t)(nt + 1));
+    double *ed = malloc(sizeof(double) * (size_t)(nt + 1) * 6);   /* W, dW, calW at a and b */
+    double *Wa = ed, *dWa = ed + (nt + 1), *cWa = ed + 2 * (nt + 1);
+    double *Wb = ed + 3 * (nt + 1), *dWb = ed + 4 * (nt + 1), *cWb = ed + 5 * (nt + 1);
     int rc = 0, worst = 0;
 
+    orc_alpha(nt + 1, alpha);
+    memset(ed, 0, sizeof(double) * (size_t)(nt + 1) * 6);
+    if (trans > ORC_S02) {
+        if (left_iface)  orc_end_data(vkind, V, nx_global, off0, -1, h, dt, nt, Wa, dWa, cWa);
+        if (right_iface) orc_end_data(vkind, V, nx_global, off0 + n - 1, +1, h, dt, nt, Wb, dWb, cWb);
+    }
     for (int i = 0; i < n; ++i) u[i] = u0 ? u0[i] : 0;
     memcpy(v, u, sizeof(cplx) * (size_t)n);                      /* v_0 = u_0 */
     ta[0] = hist0 ? hist0[0] : u[0];
     tb[0] = hist0 ? hist0[1] : u[n - 1];
 
-    if (vkind != ORC_V_TIME) {
-        weight_at_step(vkind, V, nx_global, off0, n, 0, W);
-        orc_assemble(n, h, creal(c), cimag(c), vkind == ORC_V_CUBIC ? NULL : W, diag, off);
-        if (left_iface)  diag[0]     -= sigma;
-        if (right_iface) diag[n - 1] -= sigma;
-    }
     for (int step = 1; step <= nt && rc == 0; ++step) {
-        if (vkind == ORC_V_TIME) {
-            weight_at_step(vkind, V, nx_global, off0, n, step, W);
-            orc_assemble(n, h, creal(c), cimag(c), W, diag, off);
-            if (left_iface)  diag[0]     -= sigma;
-            if (right_iface) diag[n - 1] -= sigma;
+        /* A_n = cM - S + M_{W_n} (rebuilt every step: W_n and the implicit
+           part of Sbar may change with n) */
+        weight_at_step(vkind, V, nx_global, off0, n, vkind == ORC_V_TIME ? step : 0, W);
+        orc_assemble(n, h, creal(c), cimag(c), vkind == ORC_V_CUBIC ? NULL : W, diag, off);
+        /* Sbar v_n = sig v_n + hist at each interface end */
+        cplx sgA = sigma_re + I * sigma_im, sgB = sgA, hA = 0, hB = 0;
+        cplx sgAs = sgA, sgBs = sgB, hAs = 0, hBs = 0;
+        if (conv) {
+            orc_sbar_parts(trans, step, dt, ta, Wa, dWa, cWa, alpha, beta, &sgA, &hA, &sgAs, &hAs);
+            orc_sbar_parts(trans, step, dt, tb, Wb, dWb, cWb, alpha, beta, &sgB, &hB, &sgBs, &hBs);
         }
-        /* history part b_n of the S0^2 operator */
-        cplx hA = 0, hB = 0;
-        if (trans == ORC_S02) {
-            for (int s = 0; s < step; ++s) {
-                hA += beta[step - s] * ta[s];
-                hB += beta[step - s] * tb[s];
-            }
-            hA *= c2; hB *= c2;
-        }
-        ha[step] = hA; hb[step] = hB;
+        if (left_iface)  diag[0]     -= sgA;
+        if (right_iface) diag[n - 1] -= sgB;
         cplx ln = l ? l[step - 1] : 0, rn = r ? r[step - 1] : 0;
         orc_mass_apply(n, h, u, rhs);
         for (int i = 0; i < n; ++i) rhs[i] *= c;
@@ -317,8 +448,8 @@ int orc_sub_sweep(int n, double h, double dt, int nt, int vkind, const double *V
         }
         for (int i = 0; i < n; ++i) u[i] = 2.0 * v[i] - u[i];
         ta[step] = v[0]; tb[step] = v[n - 1];
-        if (rhoL) rhoL[step - 1] = left_iface  ? -ln + 2.0 * (sigma * v[0] + hA) : 0;
-        if (rhoR) rhoR[step - 1] = right_iface ? -rn + 2.0 * (sigma * v[n - 1] + hB) : 0;
+        if (rhoL) rhoL[step - 1] = left_iface  ? -ln + 2.0 * (sgAs * v[0] + hAs) : 0;
+        if (rhoR) rhoR[step - 1] = right_iface ? -rn + 2.0 * (sgBs * v[n - 1] + hBs) : 0;
         if (v_all) memcpy(v_all + (size_t)(step - 1) * n, v, sizeof(cplx) * (size_t)n);
     }
     if (rc == 0) {
@@ -328,7 +459,7 @@ int orc_sub_sweep(int n, double h, double dt, int nt, int vkind, const double *V
     }
     if (nl_worst) *nl_worst = worst;
     free(diag); free(off); free(u); free(v); free(rhs); free(w1); free(w2); free(w3);
-    free(W); free(ha); free(hb); free(ta); free(tb);
+    free(W); free(ta); free(tb); free(alpha); free(ed);
     return rc;
 }
 

@@ -13,8 +13,9 @@ Conventions
   ``o_k .. o_k + J_k`` (``o_0 = 0``, ``o_{k+1} = o_k + J_k``).
 * Potential kinds: ``V_STATIC`` (``V[nx]``), ``V_TIME`` (``V[nt+1][nx]``,
   row ``n`` at ``t_n = n*dt``), ``V_CUBIC`` (``|u|^2``, no array).
-* Transmission: ``ROBIN`` (``dn u + sigma u``, complex ``sigma``) or ``S02``
-  (potential strategy of order 2).
+* Transmission: ``ROBIN`` (``dn u + sigma u``, complex ``sigma``), ``S02``,
+  ``S03``, ``S04`` (potential strategy of order 2, 3, 4) or ``S12``, ``S14``
+  (gauge change strategy of order 2, 4).
 * Complex arrays are ``complex128`` (interleaved re/im doubles).
 * Random numbers: ``numpy.random.default_rng(seed)``, fixed draw order.
 """
@@ -26,7 +27,7 @@ from typing import Optional
 import numpy as np
 
 V_STATIC, V_TIME, V_CUBIC = 0, 1, 2
-ROBIN, S02 = 0, 1
+ROBIN, S02, S03, S04, S12, S14 = 0, 1, 2, 3, 4, 5
 
 
 @dataclass
