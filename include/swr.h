@@ -57,8 +57,21 @@ typedef enum {
     SWR_ENAN = 5      /* NaN/Inf met in the interface residual */
 } swr_status;
 
-/* transmission operator S of B = dn + S (Sec. 2.1) */
-typedef enum { SWR_ROBIN = 0, SWR_S02 = 1 } swr_transmission;
+/* transmission operator S of B = dn + S (Sec. 2.1), discretised as in Sec. 2.2:
+ *   SWR_ROBIN  S = s (the complex s_re + i s_im of swr_setup)
+ *   SWR_S02    potential strategy, order 2: e^{-i pi/4} d_t^{1/2}
+ *   SWR_S03    order 3: S0^2 - e^{i pi/4} (W/2) I_t^{1/2}
+ *   SWR_S04    order 4: S0^3 - i (dn W / 4) I_t
+ *   SWR_S12    gauge change strategy, order 2: e^{-i pi/4} e^{i calW} d_t^{1/2} e^{-i calW}
+ *   SWR_S14    order 4: S1^2 - i sgn(dn W) (|dn W|^{1/2}/2) e^{i calW} I_t (|dn W|^{1/2}/2) e^{-i calW}
+ * W is the potential at the interface node, dn W its outward normal derivative
+ * (centred difference on the mesh), calW the gauge phase (time integral of V by
+ * the trapezoid rule, averaged over the two ends of the step).  S03..S14 need a
+ * static potential (SWR_V_STATIC); the order-4 terms flip sign with the normal
+ * and cancel in the exchange, which transmits S without them. */
+typedef enum {
+    SWR_ROBIN = 0, SWR_S02 = 1, SWR_S03 = 2, SWR_S04 = 3, SWR_S12 = 4, SWR_S14 = 5
+} swr_transmission;
 
 /* potential: static V(x) [nx] | time dependent V(t,x) [nt+1][nx] | |u|^2 (V NULL) */
 typedef enum { SWR_V_STATIC = 0, SWR_V_TIME = 1, SWR_V_CUBIC = 2 } swr_vkind;
@@ -118,11 +131,13 @@ void swr_default_opts(swr_opts* o);
  *   array of N ints).  dt > 0, T > 0 with T/dt an integer to 1e-9 relative.
  *   vk: potential kind; V: device array [nx] (STATIC), [B][nx] (STATIC with
  *   opts->v_per_problem), [nt+1][nx] (TIME), or NULL (CUBIC; also allowed for
- *   STATIC, meaning V = 0).  tr: transmission; s_re + i s_im is the Robin
- *   coefficient s of dn u + s u (ignored for S0^2; must be nonzero for Robin).
+ *   STATIC, meaning V = 0).  tr: transmission (swr_transmission); s_re + i s_im
+ *   is the Robin coefficient s of dn u + s u (ignored otherwise; must be
+ *   nonzero for Robin).
  *   opts: NULL for defaults.  stream: hipStream_t the work is enqueued on
  *   (NULL = default stream).  *out receives the context.
- * Errors: SWR_EINVAL for any violated condition above, a nonzero-size
+ * Errors: SWR_EINVAL for any violated condition above, tr beyond SWR_S02 with
+ * a potential that is not STATIC, a nonzero-size
  * subdomain larger than the kernel's node bound (512 nodes per subdomain),
  * batch < 1, or CUBIC combined with batch > 1 problems of different V;
  * SWR_ENOMEM / SWR_EDEVICE on allocation / launch failure. */
@@ -153,8 +168,8 @@ swr_status swr_solve(swr_ctx* ctx, const double* u0, double* uT, double* g, doub
  * The call runs the forward solve (final sweep checkpointing u every 64 steps
  * counted back from nt), the adjoint interface problem, and one adjoint sweep
  * that replays each 64-step forward segment from its checkpoint and consumes
- * it in reverse.  opts.checkpoint_K must be 64 and the solver not FIXED
- * (SWR_EINVAL otherwise).  info: iters / residual of the adjoint interface
+ * it in reverse.  opts.checkpoint_K must be 64, the solver not FIXED and the
+ * transmission Robin or S0^2 (SWR_EINVAL otherwise).  info: iters / residual of the adjoint interface
  * solve; t_factor_ms = whole forward, t_build_ms = adjoint d sweep,
  * t_iface_ms = adjoint interface solve, t_final_ms = replay + adjoint sweep. */
 swr_status swr_grad(swr_ctx* ctx, const double* u0, const double* gbar, double* dJdV,

@@ -159,7 +159,25 @@ __device__ inline double wave_sum(double v) {
 // ---------------------------------------------------------------------------
 // Problem-wide constants handed to every kernel.
 // ---------------------------------------------------------------------------
-enum Trans { TR_ROBIN = 0, TR_S02 = 1 };
+// kernel forms of the transmission operator: Robin, S0^2, and the general
+// convolution form that carries S0^3, S0^4, S1^2 and S1^4 (EndCoef)
+enum Trans { TR_ROBIN = 0, TR_S02 = 1, TR_GEN = 2 };
+
+// Coefficients of the higher-order transmission operators at one interface
+// end for a time-independent potential (Sec. 2.2).  With x_s = e^{-i calW_s}
+// v_s the stored boundary history (calW_s = (s - 1/2) omega, calW_0 = 0;
+// omega = W dt for the gauge strategy, 0 for the potential strategy):
+//   Sbar v_n = sig v_n + e^{i calW_n} [ cp E_n + cm O_n + a G_n ]
+//   E_n / O_n = sum over s < n with n-s even / odd of beta_{n-s} x_s
+//   G_n = 2 sum_{s<n} x_s
+// where cp = c2 + d, cm = c2 - d, d = -e^{i pi/4} sqrt(dt/2) W/2 (S0^3, S0^4;
+// alpha_k = +-beta_k splits the alpha sum by parity), a = -i (dn W/4)(dt/2)
+// (S0^4, S1^4), sig = c2 + d + a.  The part that crosses the interface drops
+// the a terms: sig_s = c2 + d.
+struct EndCoef {
+    cd sig, sig_s, cp, cm, a;
+    double omega, pad;
+};
 enum VKind { VK_STATIC = 0, VK_TIME = 1, VK_CUBIC = 2 };
 
 // Task flags: one sweep of one subdomain of one problem.
@@ -223,12 +241,16 @@ struct SweepArgs {
     int task0;                   // this launch runs tasks task0 .. task0 + ntasks - 1
     int n_begin, n_end;          // steps n_begin+1 .. n_end of this launch (n_begin % 64 == 0)
     cd* state;                   // [ntasks][2][P][64] u_n and v_n carried between launches
+    const EndCoef* endc;         // TR_GEN: [nf][2] end coefficients (left, right)
 };
 
 struct FactorArgs {
     int N, nx, nf, P;
     double h, dt;
-    cd sigma;
+    cd sigma;                    // Robin / S0^2: implicit coefficient at both ends
+    int tr;                      // swr_transmission code; 2..5 fill endc
+    cd c2;                       // e^{-i pi/4} sqrt(2/dt)
+    EndCoef* endc;               // [nf][2] output for the higher-order operators
     const int* J;
     const int* off;
     const double* V;             // [nv][nx] static potential (nullptr = 0)

@@ -61,6 +61,7 @@ struct swr_ctx {
     double* dV = nullptr;
     double* dBeta = nullptr;
     cd* dHist = nullptr;
+    EndCoef* dEndc = nullptr; // [nv][N][2] higher-order transmission coefficients
     cd* dEnds = nullptr;
     Task* dBuild = nullptr;   // impulses + d sweeps of the potential (static V)
     int nBuild = 0;
@@ -213,7 +214,9 @@ extern "C" swr_status swr_setup(double a0, double b0, int N, const int* J, doubl
     const double ntd = T / dt;
     const double ntr = std::round(ntd);
     if (ntr < 1 || std::fabs(ntd - ntr) > 1e-9 * ntd || ntr > 1e8) return SWR_EINVAL;
-    if (vk < SWR_V_STATIC || vk > SWR_V_CUBIC || (tr != SWR_ROBIN && tr != SWR_S02)) return SWR_EINVAL;
+    if (vk < SWR_V_STATIC || vk > SWR_V_CUBIC || tr < SWR_ROBIN || tr > SWR_S14) return SWR_EINVAL;
+    // the operators beyond S0^2 depend on W: provided for a static potential
+    if (tr > SWR_S02 && vk != SWR_V_STATIC) return SWR_EINVAL;
     if (tr == SWR_ROBIN && s_re == 0.0 && s_im == 0.0) return SWR_EINVAL;
     if (!std::isfinite(s_re) || !std::isfinite(s_im)) return SWR_EINVAL;
     if (o.batch < 1 || o.restart < 1 || o.max_iter < 1 || !(o.tol > 0)) return SWR_EINVAL;
@@ -240,7 +243,7 @@ extern "C" swr_status swr_setup(double a0, double b0, int N, const int* J, doubl
     c->P = (nmax + kWave - 1) / kWave;
     c->c2 = mk(std::cos(-M_PI / 4) * std::sqrt(2.0 / dt), std::sin(-M_PI / 4) * std::sqrt(2.0 / dt));
     // S0^2: the implicit coefficient of c2 sum beta_{n-s} v_s is c2 beta_0 = c2
-    c->sigma = (tr == SWR_S02) ? c->c2 : mk(s_re, s_im);
+    c->sigma = (tr == SWR_ROBIN) ? mk(s_re, s_im) : c->c2;
     c->J.assign(J, J + N);
     c->off.resize(N);
     for (int k = 0, acc = 0; k < N; ++k) { c->off[k] = acc; acc += J[k]; }
@@ -260,7 +263,8 @@ extern "C" swr_status swr_setup(double a0, double b0, int N, const int* J, doubl
     ALLOC(c->dJ, N);
     ALLOC(c->dOff, N);
     ALLOC(c->dBeta, nt + kWave + 1);
-    ALLOC(c->dHist, (tr == SWR_S02) ? max_tasks * 2 * (nt + 1) : 1);
+    ALLOC(c->dHist, (tr != SWR_ROBIN) ? max_tasks * 2 * (nt + 1) : 1);
+    if (tr > SWR_S02) ALLOC(c->dEndc, (size_t)nv * N * 2);
     ALLOC(c->dEnds, (size_t)B * N * 2);
     ALLOC(c->dBuild, build.size());
     ALLOC(c->dSub, sub.size());
@@ -361,6 +365,12 @@ struct SweepIO {
     bool ckpt = false;
 };
 
+// kernel form of the transmission operator: Robin, S0^2, or the general
+// convolution form of the higher-order operators
+static int ktr(const swr_ctx* c) {
+    return c->tr == SWR_ROBIN ? TR_ROBIN : (c->tr == SWR_S02 ? TR_S02 : TR_GEN);
+}
+
 static SweepArgs sweep_args(swr_ctx* c, const Task* tasks, int ntasks, const cd* fac, cd* cols) {
     SweepArgs a{};
     a.N = c->N; a.nt = c->nt; a.B = c->B; a.nx = c->nx; a.ns = c->ns; a.ntasks = ntasks;
@@ -371,6 +381,7 @@ static SweepArgs sweep_args(swr_ctx* c, const Task* tasks, int ntasks, const cd*
     a.c2 = c->c2;
     a.J = c->dJ; a.off = c->dOff; a.tasks = tasks; a.fac = fac; a.beta = c->dBeta;
     a.cols = cols; a.hist = c->dHist; a.ends = c->dEnds; a.maxdiff = c->dMax;
+    a.endc = c->dEndc;
     a.Vt = (c->vk == SWR_V_TIME) ? c->dV : nullptr;
     a.nl_maxit = c->o.nl_max_iter;
     a.nl_tol = c->o.nl_tol;
@@ -389,6 +400,7 @@ static swr_status run_factor(swr_ctx* c, const double* V, int nv, cd* fac) {
     FactorArgs f{};
     f.N = c->N; f.nx = c->nx; f.nf = nv * c->N; f.P = c->P; f.h = c->h; f.dt = c->dt;
     f.sigma = c->sigma; f.J = c->dJ; f.off = c->dOff; f.V = V; f.fac = fac;
+    f.tr = c->tr; f.c2 = c->c2; f.endc = c->dEndc;
     HIPCHK(launch_factor(f, c->st));
     return SWR_OK;
 }
@@ -427,7 +439,7 @@ static swr_status run_sweeps(swr_ctx* c, const SweepIO& io) {
     a.ckpt = c->dCkpt;
     a.Jc = c->Jc;
     if (io.maxdiff) HIPCHK(hipMemsetAsync(c->dMax, 0, sizeof(unsigned long long), c->st));
-    HIPCHK(launch_sweep(a, c->tr, c->vk, c->st, c->o.plain));
+    HIPCHK(launch_sweep(a, ktr(c), c->vk, c->st, c->o.plain));
     if (io.uT) HIPCHK(launch_finalize_ut(c->N, c->nx, c->B, c->dOff, c->dEnds, io.uT, c->st));
     return SWR_OK;
 }
@@ -438,7 +450,7 @@ static swr_status run_build(swr_ctx* c, const double* u0) {
     a.u0 = reinterpret_cast<const cd*>(u0);
     a.g_in = c->dZero;
     a.g_out = c->dD;
-    HIPCHK(launch_sweep(a, c->tr, SWR_V_STATIC, c->st, c->o.plain));
+    HIPCHK(launch_sweep(a, ktr(c), SWR_V_STATIC, c->st, c->o.plain));
     c->L.dirty = true;
     return SWR_OK;
 }
@@ -448,7 +460,7 @@ static swr_status run_build_L0(swr_ctx* c) {
     CHK(run_factor(c, nullptr, 1, c->L0.fac));
     SweepArgs a = sweep_args(c, c->L0.tasks, c->L0.ntasks, c->L0.fac, c->L0.cols);
     a.g_in = c->dZero;
-    HIPCHK(launch_sweep(a, c->tr, SWR_V_STATIC, c->st, c->o.plain));
+    HIPCHK(launch_sweep(a, ktr(c), SWR_V_STATIC, c->st, c->o.plain));
     c->L0.dirty = true;
     return SWR_OK;
 }
@@ -873,7 +885,7 @@ static swr_status pipe_resources(swr_ctx* c, int K) {
     const size_t st_rec = (size_t)2 * c->P * kWave;
     if (!c->dStateB) ALLOC_LIVE(c->dStateB, (size_t)c->nBuild * st_rec);
     if (!c->dStateF) ALLOC_LIVE(c->dStateF, (size_t)c->nSub * st_rec);
-    if (!c->dHistB && c->tr == SWR_S02) ALLOC_LIVE(c->dHistB, (size_t)c->nBuild * 2 * (c->nt + 1));
+    if (!c->dHistB && c->tr != SWR_ROBIN) ALLOC_LIVE(c->dHistB, (size_t)c->nBuild * 2 * (c->nt + 1));
     // sync events: fork, build j, causal j, join; timing events: 2 per sweep
     // launch plus the two ends of the interface solve
     while ((int)c->evSync.size() < 2 * K + 2) {
@@ -927,7 +939,7 @@ static swr_status run_static_pipelined(swr_ctx* c, const cd* u0, cd* g, const Sw
         ab.n_begin = cut[j];
         ab.n_end = cut[j + 1];
         HIPCHK(hipEventRecord(et[2 * j], st));
-        HIPCHK(launch_sweep(ab, c->tr, SWR_V_STATIC, st));
+        HIPCHK(launch_sweep(ab, ktr(c), SWR_V_STATIC, st));
         HIPCHK(hipEventRecord(et[2 * j + 1], st));
         HIPCHK(hipEventRecord(es[2 + j], st));
     }
@@ -946,7 +958,7 @@ static swr_status run_static_pipelined(swr_ctx* c, const cd* u0, cd* g, const Sw
         af.n_begin = cut[j];
         af.n_end = cut[j + 1];
         HIPCHK(hipEventRecord(et[2 * K + 2 * j], s3));
-        HIPCHK(launch_sweep(af, c->tr, c->vk, s3));
+        HIPCHK(launch_sweep(af, ktr(c), c->vk, s3));
         HIPCHK(hipEventRecord(et[2 * K + 2 * j + 1], s3));
     }
     if (fin.uT) HIPCHK(launch_finalize_ut(c->N, c->nx, c->B, c->dOff, c->dEnds, fin.uT, s3));
@@ -1198,6 +1210,7 @@ extern "C" swr_status swr_grad(swr_ctx* c, const double* u0d, const double* gbar
     if (!c || !u0d || !gbar || !dJdV || !dJdu0) return SWR_EINVAL;
     if (c->vk != SWR_V_STATIC || c->o.solver == SWR_SOLVER_FIXED || c->o.checkpoint_K != kWave)
         return SWR_EINVAL;
+    if (c->tr > SWR_S02) return SWR_EINVAL;   // adjoint provided for Robin and S0^2
     const cd* u0 = reinterpret_cast<const cd*>(u0d);
     const size_t vec = (size_t)c->B * c->ns * c->nt;
     hipStream_t st = c->st;
@@ -1241,7 +1254,7 @@ extern "C" swr_status swr_grad(swr_ctx* c, const double* u0d, const double* gbar
     a.g_in = nullptr;
     a.g_out = c->ns ? c->dDadj : nullptr;
     a.grad = 0;
-    HIPCHK(launch_adjoint(a, c->tr, st));
+    HIPCHK(launch_adjoint(a, ktr(c), st));
     HIPCHK(hipEventRecord(c->ev[2], st));
     swr_status rb = solve_interface(c, c->dDadj, c->dGadj, &it_b);
     if (rb != SWR_OK && rb != SWR_ENOCONV) return rb;
@@ -1252,7 +1265,7 @@ extern "C" swr_status swr_grad(swr_ctx* c, const double* u0d, const double* gbar
     a.grad = 1;
     a.dV = dJdV;
     a.du0 = reinterpret_cast<cd*>(dJdu0);
-    HIPCHK(launch_adjoint(a, c->tr, st));
+    HIPCHK(launch_adjoint(a, ktr(c), st));
     HIPCHK(launch_finalize_grad(c->N, c->nx, c->B, c->dOff, c->dGends, c->dWends, dJdV,
                                 reinterpret_cast<cd*>(dJdu0), st));
     HIPCHK(hipEventRecord(c->ev[4], st));

@@ -11,12 +11,13 @@ namespace swr {
 // at or beyond n = J_k + 1 are padding with a decoupled identity row, so every
 // lane runs the same straight-line code with compile-time register indices.
 
-// Rows of the subdomain matrix  c M - S + M_W - sigma E  at my P nodes (P1
+// Rows of the subdomain matrix  c M - S + M_W - sig E  at my P nodes (P1
 // elements on a uniform mesh, eq. AvML; the generalised mass integrates W
-// interpolated in P1).  w[q] = W at node s+q, wL / wR = W at nodes s-1 and
+// interpolated in P1; sig = sigL at an interface left end, sigR at an
+// interface right end).  w[q] = W at node s+q, wL / wR = W at nodes s-1 and
 // s+P.  ra = coupling to node i-1, rb = diagonal, rc = coupling to node i+1.
 template <int P>
-__device__ inline void chunk_rows(int s, int n, bool lif, bool rif, double h, double kap, cd sigma,
+__device__ inline void chunk_rows(int s, int n, bool lif, bool rif, double h, double kap, cd sigL, cd sigR,
                                   const double (&w)[P], double wL, double wR, cd (&ra)[P],
                                   cd (&rb)[P], cd (&rc)[P]) {
 #pragma unroll
@@ -37,8 +38,8 @@ __device__ inline void chunk_rows(int s, int n, bool lif, bool rif, double h, do
                 b = b + mk(-1.0 / h + h / 12.0 * (3.0 * wi + wp), 2.0 * kap);
                 c = mk(1.0 / h + h / 12.0 * (wi + wp), kap);
             }
-            if (i == 0 && lif) b = b - sigma;
-            if (i == n - 1 && rif) b = b - sigma;
+            if (i == 0 && lif) b = b - sigL;
+            if (i == n - 1 && rif) b = b - sigR;
         }
         ra[q] = a;
         rb[q] = b;

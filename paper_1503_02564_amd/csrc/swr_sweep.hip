@@ -51,8 +51,43 @@ __global__ __launch_bounds__(64) void factor_kernel(FactorArgs a) {
     for (int q = 0; q < P; ++q) w[q] = (W && s + q < n) ? W[s + q] : 0.0;
     double wL, wR;
     neighbour_w(w, wL, wR);
+    cd sigL = a.sigma, sigR = a.sigma;
+    if (a.tr >= 2) {
+        // higher-order operators (Sec. 2.2) at the two interface ends: W and
+        // its outward normal derivative (centred difference on the global
+        // mesh) at the end node
+        const double* Vg = a.V ? a.V + (size_t)v * a.nx : nullptr;
+        const cd eP = mk(M_SQRT1_2, M_SQRT1_2);                 // e^{i pi/4}
+        EndCoef e[2];
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const int g = o + (side ? n - 1 : 0);
+            const bool iface = side ? rif : lif;
+            double We = 0.0, dWe = 0.0;
+            if (Vg && iface) {
+                We = Vg[g];
+                dWe = (side ? 1.0 : -1.0) * (Vg[g + 1] - Vg[g - 1]) / (2.0 * a.h);
+            }
+            const bool pot = a.tr == 2 || a.tr == 3, ord4 = a.tr == 3 || a.tr == 5;
+            const cd d = pot ? (-(sqrt(0.5 * a.dt) * 0.5 * We)) * eP : mk(0, 0);
+            const cd aa = ord4 ? mk(0.0, -(dWe / 4.0) * (0.5 * a.dt)) : mk(0, 0);
+            e[side].cp = a.c2 + d;
+            e[side].cm = a.c2 - d;
+            e[side].a = aa;
+            e[side].sig_s = a.c2 + d;
+            e[side].sig = (a.c2 + d) + aa;
+            e[side].omega = (a.tr >= 4) ? We * a.dt : 0.0;
+            e[side].pad = 0.0;
+        }
+        sigL = e[0].sig;
+        sigR = e[1].sig;
+        if (t == 0) {
+            a.endc[(size_t)f * 2 + 0] = e[0];
+            a.endc[(size_t)f * 2 + 1] = e[1];
+        }
+    }
     cd ra[P], rb[P], rc[P];
-    chunk_rows<P>(s, n, lif, rif, a.h, kap, a.sigma, w, wL, wR, ra, rb, rc);
+    chunk_rows<P>(s, n, lif, rif, a.h, kap, sigL, sigR, w, wL, wR, ra, rb, rc);
     LaneFac<P> F;
     lane_factor<P>(ra, rb, rc, F);
     store_fac<P>(a.fac + (size_t)f * L::total * kWave + t, F);

@@ -10,6 +10,8 @@ static void launch_p(const SweepArgs& a, int trans, hipStream_t st) {
 }
 
 hipError_t launch_sweep_cubic(const SweepArgs& a, int trans, hipStream_t st) {
+    // the higher-order operators are provided for a static potential only
+    if (trans != TR_S02 && trans != TR_ROBIN) return hipErrorInvalidValue;
     switch (a.P) {
         case 1: launch_p<1>(a, trans, st); break;
         case 2: launch_p<2>(a, trans, st); break;

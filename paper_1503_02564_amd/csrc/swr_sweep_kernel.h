@@ -1,7 +1,7 @@
 // swr_sweep_kernel.h -- the subdomain sweep kernel template (see the
 // description at the top of swr_sweep.hip).  Included by the three
 // translation units that instantiate it for one potential kind each, so
-// the 48 instantiations compile in parallel.
+// the 56 instantiations compile in parallel.
 #pragma once
 #include "swr_lane.h"
 
@@ -30,10 +30,16 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
     const int lastl = (n - 1) / P;          // lane holding node n-1
     const cd zero = mk(0, 0);
 
-    if (TR == TR_S02) {
+    if (TR == TR_S02 || TR == TR_GEN) {
         sbeta[t] = a.beta[t];
         if (t == 0) sbeta[kWave] = a.beta[kWave];
         __syncthreads();
+    }
+    // higher-order operators: coefficients of the two ends (left, right)
+    EndCoef ea{}, eb{};
+    if (TR == TR_GEN) {
+        ea = a.endc[(size_t)f * 2 + 0];
+        eb = a.endc[(size_t)f * 2 + 1];
     }
 
     LaneFac<P> F;
@@ -96,7 +102,8 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
     cd* Hb = Ha ? Ha + (nt + 1) : nullptr;
     const cd va0 = rdlane(u[0], 0);
     const cd vb0 = at_last(u);
-    if (TR == TR_S02 && t == 0 && first) {
+    // history value at step 0: v_0 (calW_0 = 0, so also x_0 = v_0)
+    if ((TR == TR_S02 || TR == TR_GEN) && t == 0 && first) {
         Ha[0] = va0;
         Hb[0] = vb0;
     }
@@ -150,8 +157,11 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
         // acc_j = sum_{q <= n0} beta_{n0+1+j-q} v_q, over chunks of 64 past
         // values staged in LDS with one coalesced load each, together with
         // the 127-entry window of beta the chunk needs
-        cd acc_a = zero, acc_b = zero;
-        if (TR == TR_S02) {
+        // (higher-order operators: the same sums of the stored x_s, split by
+        // the parity of i -- acc for even i, acc1 for odd i -- and each
+        // lane's running sum of the staged values for G)
+        cd acc_a = zero, acc_b = zero, acc_a1 = zero, acc_b1 = zero, gs_a = zero, gs_b = zero;
+        if (TR == TR_S02 || TR == TR_GEN) {
             __threadfence_block();
             const int nj = n0 + 1 + t;
             // the loads of chunk q0 + 64 are issued before chunk q0 is summed
@@ -172,6 +182,10 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
                 const int bbase = n0 - q0 - (kWave - 2);   // beta index of sb[0]
                 sha[t] = pa;
                 shb[t] = pb;
+                if (TR == TR_GEN) {
+                    gs_a = gs_a + pa;
+                    gs_b = gs_b + pb;
+                }
                 sb[t] = pb0;
                 sb[kWave + t] = pb1;
                 if (q0 + kWave <= n0) fetch(q0 + kWave);
@@ -180,15 +194,45 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
                 // all 64 entries: the staged chunk is zero past qn and the beta
                 // window bw[-i], i < 64, stays inside sb, so the loop unrolls and
                 // its LDS reads overlap
-                #pragma unroll 16
-                for (int i = 0; i < kWave; ++i) {
-                    const double bt = bw[-i];
-                    const cd ha = sha[i], hb = shb[i];
-                    acc_a = mk(acc_a.x + bt * ha.x, acc_a.y + bt * ha.y);
-                    acc_b = mk(acc_b.x + bt * hb.x, acc_b.y + bt * hb.y);
+                if (TR == TR_S02) {
+                    #pragma unroll 16
+                    for (int i = 0; i < kWave; ++i) {
+                        const double bt = bw[-i];
+                        const cd ha = sha[i], hb = shb[i];
+                        acc_a = mk(acc_a.x + bt * ha.x, acc_a.y + bt * ha.y);
+                        acc_b = mk(acc_b.x + bt * hb.x, acc_b.y + bt * hb.y);
+                    }
+                } else {
+                    #pragma unroll 8
+                    for (int i = 0; i < kWave; i += 2) {
+                        const double b0 = bw[-i], b1 = bw[-i - 1];
+                        const cd h0 = sha[i], h1 = sha[i + 1], k0 = shb[i], k1 = shb[i + 1];
+                        acc_a = mk(acc_a.x + b0 * h0.x, acc_a.y + b0 * h0.y);
+                        acc_a1 = mk(acc_a1.x + b1 * h1.x, acc_a1.y + b1 * h1.y);
+                        acc_b = mk(acc_b.x + b0 * k0.x, acc_b.y + b0 * k0.y);
+                        acc_b1 = mk(acc_b1.x + b1 * k1.x, acc_b1.y + b1 * k1.y);
+                    }
                 }
                 __syncthreads();
             }
+        }
+        // higher-order operators: lane j's history Hl = cp E + cm O of step
+        // nj = n0+1+j (lag nj - q0 - i has the parity of nj - i, q0 being a
+        // multiple of 64), its phase e^{i calW_nj}, and the wave-uniform
+        // G = 2 sum_{s <= n0} x_s
+        cd Hl_a = zero, Hl_b = zero, Ga = zero, Gb = zero, pha = mk(1, 0), phb = mk(1, 0);
+        if (TR == TR_GEN) {
+            const int nj = n0 + 1 + t;
+            const bool odd = (nj & 1) != 0;
+            Hl_a = ea.cp * (odd ? acc_a1 : acc_a) + ea.cm * (odd ? acc_a : acc_a1);
+            Hl_b = eb.cp * (odd ? acc_b1 : acc_b) + eb.cm * (odd ? acc_b : acc_b1);
+            Ga = 2.0 * mk(wave_sum(gs_a.x), wave_sum(gs_a.y));
+            Gb = 2.0 * mk(wave_sum(gs_b.x), wave_sum(gs_b.y));
+            double sn, cs;
+            sincos(((double)nj - 0.5) * ea.omega, &sn, &cs);
+            pha = mk(cs, sn);
+            sincos(((double)nj - 0.5) * eb.omega, &sn, &cs);
+            phb = mk(cs, sn);
         }
         cd rl_b = zero, rr_b = zero, va_b = zero, vb_b = zero, ua_b = zero, ub_b = zero;
 
@@ -210,14 +254,26 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
                 double wL, wR;
                 neighbour_w(w, wL, wR);
                 cd ra[P], rbr[P], rc[P];
-                chunk_rows<P>(s, n, lif, rif, a.h, kap, a.sigma, w, wL, wR, ra, rbr, rc);
+                chunk_rows<P>(s, n, lif, rif, a.h, kap, a.sigma, a.sigma, w, wL, wR, ra, rbr, rc);
                 lane_factor<P>(ra, rbr, rc, F);
             }
             const cd ln = rdlane(lb, i), rn = rdlane(rb, i);
-            cd hA = zero, hB = zero;
+            // history part of Sbar v_n at each end: hA (all terms, boundary
+            // condition) and hAs (without the order-4 term, the exchange)
+            cd hA = zero, hB = zero, hAs = zero, hBs = zero, phA = mk(1, 0), phB = mk(1, 0);
             if (TR == TR_S02) {
                 hA = a.c2 * rdlane(acc_a, i);
                 hB = a.c2 * rdlane(acc_b, i);
+                hAs = hA;
+                hBs = hB;
+            }
+            if (TR == TR_GEN) {
+                phA = rdlane(pha, i);
+                phB = rdlane(phb, i);
+                hAs = phA * rdlane(Hl_a, i);
+                hBs = phB * rdlane(Hl_b, i);
+                hA = hAs + ea.a * (phA * Ga);
+                hB = hBs + eb.a * (phB * Gb);
             }
             // right-hand side c M u_{n-1} + boundary terms
             const cd uL = shfl_up_c(u[P - 1], 1, zero);
@@ -301,13 +357,18 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
             }
             const cd va = rdlane(x[0], 0);
             const cd vb = at_last(x);
-            const cd rhoL = (2.0 * madd(hA, a.sigma, va)) - ln;
-            const cd rhoR = (2.0 * madd(hB, a.sigma, vb)) - rn;
+            const cd sgA = (TR == TR_GEN) ? ea.sig_s : a.sigma;
+            const cd sgB = (TR == TR_GEN) ? eb.sig_s : a.sigma;
+            const cd rhoL = (2.0 * madd(hAs, sgA, va)) - ln;
+            const cd rhoR = (2.0 * madd(hBs, sgB, vb)) - rn;
+            // stored history value: x_n = e^{-i calW_n} v_n (= v_n for S0^2)
+            const cd xa = (TR == TR_GEN) ? conjc(phA) * va : va;
+            const cd xb = (TR == TR_GEN) ? conjc(phB) * vb : vb;
             if (t == i) {
                 rl_b = rhoL;
                 rr_b = rhoR;
-                va_b = va;
-                vb_b = vb;
+                va_b = xa;
+                vb_b = xb;
             }
             if (trace_a) {
                 const cd ua = rdlane(u[0], 0), ub = at_last(u);
@@ -318,6 +379,16 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
                 acc_a = acc_a + bt * va;
                 acc_b = acc_b + bt * vb;
             }
+            if (TR == TR_GEN) {
+                if (t > i) {
+                    const int lag = t - i;
+                    const double bt = sbeta[lag];
+                    Hl_a = Hl_a + (bt * ((lag & 1) ? ea.cm : ea.cp)) * xa;
+                    Hl_b = Hl_b + (bt * ((lag & 1) ? eb.cm : eb.cp)) * xb;
+                }
+                Ga = Ga + 2.0 * xa;
+                Gb = Gb + 2.0 * xb;
+            }
         }
         // block epilogue: coalesced stores
         if (act) {
@@ -325,7 +396,7 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
             if (out_r) out_r[n0 + t] = rr_b;
             if (old_l) maxd = fmax(maxd, sqrt(abs2(rl_b - old_l[n0 + t])));
             if (old_r) maxd = fmax(maxd, sqrt(abs2(rr_b - old_r[n0 + t])));
-            if (TR == TR_S02) {
+            if (TR == TR_S02 || TR == TR_GEN) {
                 Ha[n0 + 1 + t] = va_b;
                 Hb[n0 + 1 + t] = vb_b;
             }

@@ -6,10 +6,12 @@ namespace swr {
 template <int P>
 static void launch_p(const SweepArgs& a, int trans, hipStream_t st) {
     if (trans == TR_S02) sweep_kernel<P, TR_S02, VK_STATIC><<<a.ntasks, 64, 0, st>>>(a);
+    else if (trans == TR_GEN) sweep_kernel<P, TR_GEN, VK_STATIC><<<a.ntasks, 64, 0, st>>>(a);
     else sweep_kernel<P, TR_ROBIN, VK_STATIC><<<a.ntasks, 64, 0, st>>>(a);
 }
 
 hipError_t launch_sweep_static(const SweepArgs& a, int trans, hipStream_t st) {
+    if (trans == TR_GEN && !a.endc) return hipErrorInvalidValue;
     switch (a.P) {
         case 1: launch_p<1>(a, trans, st); break;
         case 2: launch_p<2>(a, trans, st); break;

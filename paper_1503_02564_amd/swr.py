@@ -21,7 +21,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "_swr_hip.so")
 
 SWR_OK, SWR_EINVAL, SWR_ENOMEM, SWR_EDEVICE, SWR_ENOCONV, SWR_ENAN = range(6)
-SWR_ROBIN, SWR_S02 = 0, 1
+SWR_ROBIN, SWR_S02, SWR_S03, SWR_S04, SWR_S12, SWR_S14 = 0, 1, 2, 3, 4, 5
 SWR_V_STATIC, SWR_V_TIME, SWR_V_CUBIC = 0, 1, 2
 SWR_SOLVER_FIXED, SWR_SOLVER_GMRES, SWR_SOLVER_CAUSAL, SWR_SOLVER_BICGSTAB = 0, 1, 2, 3
 

@@ -141,7 +141,7 @@ def test_full_size_adjoint_batch_forward_adjoint_and_fd(dev):
     pb.close()
 
 
-def test_full_size_time_dependent_time_dependent_potential(dev):
+def test_full_size_time_dependent_potential(dev):
     """V(t,x) = 5 x cos t on 128 x 256 cells over 4000 steps: preconditioned
     GMRES with the matrix-free interface operator, against the oracle.  Over
     this window P = I - L_0 leaves a slowly converging problem (33 iterations

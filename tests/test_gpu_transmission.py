@@ -1,0 +1,153 @@
+"""GPU parity of the higher-order transmission operators (Sec. 2.2: potential
+strategy of orders 3 and 4, gauge change strategy of orders 2 and 4) against
+the CPU oracle, through the C ABI.
+
+Tolerances as in test_gpu_parity: 1e-12 relative for one sweep or one
+interface build (rounding order only; the gauge phase is formed as
+(n - 1/2) omega on the GPU and by the trapezoid recursion in the oracle, which
+agree to ~n eps |calW|), 1e-10 for converged solves.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1503_02564_amd import workloads as W
+from tests.gpu_util import make_problem, rel, say, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+KINDS = [("s03", W.S03), ("s04", W.S04), ("s12", W.S12), ("s14", W.S14)]
+RAGGED = [40, 63, 64, 100, 127, 128, 200, 255, 256, 300]
+
+
+def _case(J, nt, trans, B=1, seed=3):
+    return W.small_case(J=J, nt=nt, trans=trans, sigma=0j, B=B, seed=seed, a0=-12.0, b0=12.0)
+
+
+@pytest.mark.parametrize("name,trans", KINDS)
+@pytest.mark.parametrize("J,nt", [(RAGGED, 150), ([511, 200, 17], 70)])
+@pytest.mark.parametrize("with_data", [True, False])
+def test_one_sweep_matches_oracle(dev, name, trans, J, nt, with_data):
+    """One SWR iteration g -> R g (and u(T) of the local solutions)."""
+    import torch
+    from paper_1503_02564_amd import swr
+    wl = _case(J, nt, trans)
+    say("one_sweep", name, len(J), nt, "data" if with_data else "zero-data")
+    pb = make_problem(wl)
+    rng = np.random.default_rng(11)
+    g = rng.standard_normal((pb.ns, nt)) + 1j * rng.standard_normal((pb.ns, nt))
+    u0 = wl.u0[0] if with_data else None
+    g_out = torch.zeros((1, pb.ns, nt), dtype=torch.complex128, device=dev)
+    uT = torch.zeros((1, wl.nx), dtype=torch.complex128, device=dev)
+    swr.swr_apply_R(pb.ctx, to_dev(wl.u0) if with_data else None, to_dev(g[None]), g_out, uT)
+    torch.cuda.synchronize()
+    want = O.apply_R(wl, u0, g, hist0_zero=not with_data)
+    assert rel(to_np(g_out)[0], want) < 1e-12
+    if with_data:
+        assert rel(to_np(uT)[0], O.local_solution(wl, u0, g)[0]) < 1e-12
+    pb.close()
+
+
+@pytest.mark.parametrize("name,trans", KINDS)
+def test_impulse_columns_and_d_match_oracle(dev, name, trans):
+    import torch
+    from paper_1503_02564_amd import swr
+    wl = _case(RAGGED, 150, trans)
+    say("build_interface", name)
+    pb = make_problem(wl)
+    cols = torch.zeros((1, wl.N, 4, wl.nt), dtype=torch.complex128, device=dev)
+    d = torch.zeros((1, pb.ns, wl.nt), dtype=torch.complex128, device=dev)
+    swr.swr_build_interface(pb.ctx, to_dev(wl.u0), cols, d)
+    torch.cuda.synchronize()
+    assert rel(to_np(cols)[0], O.impulse_columns(wl)) < 1e-12
+    assert rel(to_np(d)[0], O.interface_d(wl, wl.u0[0])) < 1e-12
+    pb.close()
+
+
+@pytest.mark.parametrize("name,trans", KINDS)
+@pytest.mark.parametrize("solver", ["causal", "gmres", "bicgstab", "fixed"])
+def test_solve_matches_monodomain(dev, name, trans, solver):
+    """Every solver reaches the monodomain solution with every operator; the
+    fixed point takes the oracle's iteration count."""
+    import torch
+    from paper_1503_02564_amd import swr
+    wl = _case([40, 63, 64, 100, 127, 200, 31], 130, trans)
+    sv = dict(causal=swr.SWR_SOLVER_CAUSAL, gmres=swr.SWR_SOLVER_GMRES,
+              bicgstab=swr.SWR_SOLVER_BICGSTAB, fixed=swr.SWR_SOLVER_FIXED)[solver]
+    say("solve", name, solver)
+    tol = 1e-12 if solver == "fixed" else 1e-13
+    pb = make_problem(wl, solver=sv, tol=tol, restart=60, max_iter=3000)
+    uT = torch.zeros((1, wl.nx), dtype=torch.complex128, device=dev)
+    g = torch.zeros((1, pb.ns, wl.nt), dtype=torch.complex128, device=dev)
+    st, info = swr.swr_solve(pb.ctx, to_dev(wl.u0), uT, g)
+    torch.cuda.synchronize()
+    assert st == swr.SWR_OK
+    um = O.mono(wl, wl.u0[0])
+    assert rel(to_np(uT)[0], um) < 1e-10
+    if solver == "fixed":
+        _, it, _ = O.classical(wl, wl.u0[0], tol=tol, maxit=3000)
+        assert abs(info.iters - it) <= 1
+    else:
+        assert info.residual < 1e-11
+        gw = O.causal_solve(wl, O.impulse_columns(wl), O.interface_d(wl, wl.u0[0]))
+        assert rel(to_np(g)[0], gw) < 1e-10
+    pb.close()
+
+
+@pytest.mark.parametrize("name,trans", [("s04", W.S04), ("s14", W.S14)])
+def test_pipelined_solve_equals_staged_solve(dev, name, trans):
+    """The time-chunked pipeline carries the order-4 running sum and the
+    gauge phase across launches: bitwise equal to the staged solve."""
+    import torch
+    from paper_1503_02564_amd import swr
+    wl = _case([40, 63, 64, 100, 127, 200, 31], 450, trans)
+    out = []
+    for ch in (0, 64):
+        say("pipeline", name, "chunk", ch)
+        pb = make_problem(wl, pipeline=ch)
+        uT = torch.zeros((1, wl.nx), dtype=torch.complex128, device=dev)
+        g = torch.zeros((1, pb.ns, wl.nt), dtype=torch.complex128, device=dev)
+        st, info = swr.swr_solve(pb.ctx, to_dev(wl.u0), uT, g)
+        torch.cuda.synchronize()
+        assert st == swr.SWR_OK and info.residual < 1e-11
+        out.append((to_np(uT), to_np(g)))
+        pb.close()
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    assert rel(out[1][0][0], O.mono(wl, wl.u0[0])) < 1e-10
+
+
+def test_one_potential_per_problem(dev):
+    """A batch with one static potential per problem: every member gets the
+    end coefficients of its own potential."""
+    import torch
+    from paper_1503_02564_amd import swr
+    wl = _case([60, 80, 70], 200, W.S14, B=3)
+    rng = np.random.default_rng(8)
+    x = W.mesh_nodes(wl.a0, wl.b0, wl.nc)
+    wl.V = np.stack([W.bumpy_harmonic(x, rng.uniform(-5, 5, 3), rng.uniform(-10, 10, 3))
+                     for _ in range(3)])
+    say("per-problem", "s14")
+    pb = make_problem(wl, v_per_problem=True)
+    uT = torch.zeros((3, wl.nx), dtype=torch.complex128, device=dev)
+    st, info = swr.swr_solve(pb.ctx, to_dev(wl.u0), uT)
+    torch.cuda.synchronize()
+    assert st == swr.SWR_OK
+    for b in range(3):
+        assert rel(to_np(uT)[b], O.mono(wl, wl.u0[b], V=wl.V[b])) < 1e-10
+    pb.close()
+
+
+def test_gradient_refuses_higher_order_operators(dev):
+    import torch
+    from paper_1503_02564_amd import swr
+    wl = _case([40, 50], 64, W.S03)
+    say("grad refuses", "s03")
+    pb = make_problem(wl)
+    u0 = to_dev(wl.u0)
+    gbar = torch.zeros_like(u0)
+    dV = torch.zeros((1, wl.nx), dtype=torch.float64, device=dev)
+    du0 = torch.zeros_like(u0)
+    with pytest.raises(swr.SwrError) as e:
+        swr.swr_grad(pb.ctx, u0, gbar, dV, du0)
+    assert e.value.status == swr.SWR_EINVAL
+    pb.close()
