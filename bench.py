@@ -180,6 +180,55 @@ def adjoint_ratio(steps, warmup):
     return res
 
 
+# the paper's own figures for these workloads (Sec. 6 tables; 1000 MPI
+# processes on its CPU cluster): context, not a target
+PAPER_CONTEXT = {
+    "harmonic": "new algorithm, N = 1000, dx = 1e-5: 7.12 s (BiCGStab), 8.17 s (GMRES)",
+    "linear_t": "preconditioned, N = 1000, dx = 1e-4: 25 iterations, 54.5 s",
+    "cubic": "preconditioned, N = 1000, dx = 1e-5: 26 iterations, 83.8 s",
+}
+
+
+def paper_workloads(reps=3):
+    """The paper's Sec. 6 workloads on its dx = 1e-4 grid at N = 1000
+    (420001 nodes, 500 steps): wall time per solve (median of reps after one
+    warm-up), iterations at interface tolerance 1e-10."""
+    import torch
+    from paper_1503_02564_amd import swr
+    from paper_1503_02564_amd import workloads as W
+    out = {}
+    for kind in ("harmonic", "linear_t", "cubic"):
+        wl = W.paper_case(kind)
+        o = swr.swr_default_opts()
+        o.tol = 1e-10
+        o.restart = 100
+        o.max_iter = 400
+        dev = torch.device("cuda:0")
+        V = None if wl.V is None else torch.from_numpy(np.ascontiguousarray(wl.V)).to(dev)
+        pb = swr.Problem(wl.a0, wl.b0, tuple(int(j) for j in wl.J), wl.dt, wl.dt * wl.nt, wl.vkind,
+                         wl.trans, wl.sigma, o, V)
+        u0 = torch.from_numpy(np.ascontiguousarray(wl.u0)).to(dev)
+        uT = torch.zeros_like(u0)
+        swr.swr_solve(pb.ctx, u0, uT)
+        torch.cuda.synchronize()
+        ts, info = [], None
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            st, info = swr.swr_solve(pb.ctx, u0, uT)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        ms = 1e3 * float(np.median(ts))
+        out[kind] = {"ms_per_solve": ms, "iterations": info.iters, "status": st,
+                     "pt_steps_per_s": wl.pt_steps() / (ms * 1e-3),
+                     "interface_residual": info.residual, "paper": PAPER_CONTEXT[kind]}
+        pb.close()
+        del V
+    out["workload"] = ("(-21,21), dx = 1e-4 (420001 nodes), dt = 1e-3, 500 steps, N = 1000 x 420 "
+                       "cells, S0^2; V = -x^2 (causal interface solve), V = 5tx (GMRES preconditioned "
+                       "by I - L_0), |u|^2 sech soliton (preconditioned fixed point)")
+    return out
+
+
 def batched_vs_plain(batched_ms):
     """The same benchmark solve with every sweep task launched on its own
     (one subdomain of one problem per launch, one stream, staged), against
@@ -233,6 +282,8 @@ def main():
     ap.add_argument("--pipeline", type=int, default=256,
                     help="steps per pipeline chunk of the causal solve (0 = staged)")
     ap.add_argument("--workload", default="static_packet", choices=["static_packet"])
+    ap.add_argument("--no-paper", dest="paper", action="store_false",
+                    help="skip the paper's Sec. 6 workloads at N = 1000")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint/forward ratio on the differentiation workload")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -309,6 +360,8 @@ def main():
     if args.plain:
         plain = batched_vs_plain(ms)
 
+    paper = paper_workloads() if args.paper else None
+
     adj = None
     if not args.no_adjoint:
         adj = adjoint_ratio(max(1, min(args.steps, 5)), 1)
@@ -333,6 +386,7 @@ def main():
         "batched_vs_plain": plain,
         "adjoint_forward_cost_ratio": None if adj is None else adj["ratio_bwd_over_fwd"],
         "adjoint": adj,
+        "paper_workloads": paper,
         "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -80,7 +80,12 @@ typedef enum { SWR_V_STATIC = 0, SWR_V_TIME = 1, SWR_V_CUBIC = 2 } swr_vkind;
 typedef enum {
     SWR_SOLVER_FIXED = 0,   /* fixed point g <- R g (Sec. 4 "Classical algorithm") */
     SWR_SOLVER_GMRES = 1,   /* restarted GMRES on (I - L) g = d (Sec. 4) */
-    SWR_SOLVER_CAUSAL = 2,  /* exact forward substitution in time on (I - L) g = d */
+    SWR_SOLVER_CAUSAL = 2,  /* exact forward substitution in time on (I - L) g = d; offered up to
+                               512 interface slots, or 513 subdomains when the per-step block
+                               system is block diagonally dominant (block PCR).  Beyond that the
+                               same system is solved by BiCGStab, and P^{-1} of the V_TIME /
+                               V_CUBIC iterations by an inner BiCGStab to relative residual
+                               1e-13 (the paper's way of applying P^{-1}, Sec. 5) */
     SWR_SOLVER_BICGSTAB = 3 /* BiCGStab on (I - L) g = d (the Krylov solver of Sec. 6) */
 } swr_solver;
 
@@ -121,6 +126,8 @@ typedef struct {
     double t_sweep_ms;  /* static V, new algorithm: summed durations of the subdomain sweep
                            launches (impulse/d sweeps and final sweep) ... */
     int n_sweep;        /* ... and their number (0 when not measured) */
+    int inner_iters;    /* V_TIME / V_CUBIC with more interfaces than the causal solve takes:
+                           total inner BiCGStab iterations spent applying P^{-1} (else 0) */
 } swr_info;
 
 /* Fill *o with the defaults listed above. */

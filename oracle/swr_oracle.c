@@ -464,6 +464,134 @@ int orc_sub_sweep(int n, double h, double dt, int nt, int vkind, const double *V
 }
 
 /* ------------------------------------------------------------------------ */
+/* The monodomain Crank-Nicolson solve of orc_mono_cn in extended precision  */
+/* (x87 80-bit long double: 64-bit significand, unit roundoff 5.4e-20), for  */
+/* grids where one FP64 Thomas sweep over the whole domain is itself the     */
+/* largest error: with dt/h^2 = 1e5 the elimination over 1e4-1e5 nodes of    */
+/* c M - S (nearly a discrete Laplacian with a small imaginary shift) loses  */
+/* about 1e-9 relative in FP64.  Same definitions, element matrices and      */
+/* inner fixed point as above; inputs and outputs are FP64.                  */
+/* ------------------------------------------------------------------------ */
+typedef long double complex lcplx;
+typedef long double lreal;
+
+static void ld_assemble(int n, lreal h, lcplx coef_m, const lreal *W, lcplx *diag, lcplx *off)
+{
+    for (int i = 0; i < n; ++i) diag[i] = 0;
+    for (int i = 0; i + 1 < n; ++i) off[i] = 0;
+    for (int e = 0; e + 1 < n; ++e) {
+        lreal w0 = W ? W[e] : 0.0L, w1 = W ? W[e + 1] : 0.0L;
+        lreal m00 = 2.0L * h / 6.0L, m01 = h / 6.0L, m11 = 2.0L * h / 6.0L;
+        lreal s00 = 1.0L / h, s01 = -1.0L / h, s11 = 1.0L / h;
+        lreal g00 = h / 12.0L * (3.0L * w0 + w1);
+        lreal g01 = h / 12.0L * (w0 + w1);
+        lreal g11 = h / 12.0L * (w0 + 3.0L * w1);
+        diag[e]     += coef_m * m00 - s00 + g00;
+        diag[e + 1] += coef_m * m11 - s11 + g11;
+        off[e]      += coef_m * m01 - s01 + g01;
+    }
+}
+
+static void ld_mass_apply(int n, lreal h, const lcplx *x, lcplx *y)
+{
+    for (int i = 0; i < n; ++i) y[i] = 0;
+    for (int e = 0; e + 1 < n; ++e) {
+        y[e]     += (2.0L * h / 6.0L) * x[e] + (h / 6.0L) * x[e + 1];
+        y[e + 1] += (h / 6.0L) * x[e] + (2.0L * h / 6.0L) * x[e + 1];
+    }
+}
+
+static void ld_genmass_apply(int n, lreal h, const lreal *F, const lcplx *x, lcplx *y)
+{
+    for (int i = 0; i < n; ++i) y[i] = 0;
+    for (int e = 0; e + 1 < n; ++e) {
+        lreal f0 = F[e], f1 = F[e + 1];
+        lreal g00 = h / 12.0L * (3.0L * f0 + f1);
+        lreal g01 = h / 12.0L * (f0 + f1);
+        lreal g11 = h / 12.0L * (f0 + 3.0L * f1);
+        y[e]     += g00 * x[e] + g01 * x[e + 1];
+        y[e + 1] += g01 * x[e] + g11 * x[e + 1];
+    }
+}
+
+static int ld_thomas(int n, const lcplx *diag, const lcplx *off, const lcplx *rhs, lcplx *x,
+                     lcplx *cp, lcplx *dp)
+{
+    lcplx piv = diag[0];
+    if (piv == 0) return -2;
+    cp[0] = (n > 1) ? off[0] / piv : 0;
+    dp[0] = rhs[0] / piv;
+    for (int i = 1; i < n; ++i) {
+        piv = diag[i] - off[i - 1] * cp[i - 1];
+        if (piv == 0) return -2;
+        cp[i] = (i + 1 < n) ? off[i] / piv : 0;
+        dp[i] = (rhs[i] - off[i - 1] * dp[i - 1]) / piv;
+    }
+    x[n - 1] = dp[n - 1];
+    for (int i = n - 2; i >= 0; --i) x[i] = dp[i] - cp[i] * x[i + 1];
+    return 0;
+}
+
+/* Same interface as orc_mono_cn (no u_all / v_all).  The |u|^2 inner fixed */
+/* point stops on max |zeta^{s+1} - zeta^s| <= tol max(1, max |zeta^s|).     */
+int orc_mono_cn_ld(int nx, double h_, double dt_, int nt, int vkind, const double *V,
+                   const cplx *u0, cplx *uT, int nl_maxit, double nl_tol, int *nl_worst)
+{
+    const lreal h = h_, dt = dt_;
+    const lcplx c = 2.0L * I / dt;
+    lcplx *diag = malloc(sizeof(lcplx) * (size_t)nx), *off = malloc(sizeof(lcplx) * (size_t)(nx > 1 ? nx - 1 : 1));
+    lcplx *u = malloc(sizeof(lcplx) * (size_t)nx), *v = malloc(sizeof(lcplx) * (size_t)nx);
+    lcplx *rhs = malloc(sizeof(lcplx) * (size_t)nx), *base = malloc(sizeof(lcplx) * (size_t)nx);
+    lcplx *nl = malloc(sizeof(lcplx) * (size_t)nx), *z = malloc(sizeof(lcplx) * (size_t)nx);
+    lcplx *cp = malloc(sizeof(lcplx) * (size_t)nx), *dp = malloc(sizeof(lcplx) * (size_t)nx);
+    lreal *W = malloc(sizeof(lreal) * (size_t)nx);
+    int rc = 0, worst = 0;
+    for (int i = 0; i < nx; ++i) { u[i] = u0[i]; v[i] = u0[i]; }     /* v_0 = u_0 */
+    if (vkind != ORC_V_TIME) {
+        for (int i = 0; i < nx; ++i) W[i] = (vkind == ORC_V_STATIC && V) ? V[i] : 0.0L;
+        ld_assemble(nx, h, c, vkind == ORC_V_CUBIC ? NULL : W, diag, off);
+    }
+    for (int n = 1; n <= nt && rc == 0; ++n) {
+        if (vkind == ORC_V_TIME) {
+            const double *Vn = V + (size_t)n * nx, *Vm = V + (size_t)(n - 1) * nx;
+            for (int i = 0; i < nx; ++i) W[i] = 0.5L * ((lreal)Vn[i] + (lreal)Vm[i]);
+            ld_assemble(nx, h, c, W, diag, off);
+        }
+        ld_mass_apply(nx, h, u, base);
+        for (int i = 0; i < nx; ++i) base[i] *= c;
+        if (vkind == ORC_V_CUBIC) {
+            /* inner fixed point from zeta^0 = v_{n-1} (eq. AvMNL) */
+            int it = 1, conv = 0;
+            for (; it <= nl_maxit; ++it) {
+                for (int i = 0; i < nx; ++i) W[i] = creall(v[i]) * creall(v[i]) + cimagl(v[i]) * cimagl(v[i]);
+                ld_genmass_apply(nx, h, W, v, nl);
+                for (int i = 0; i < nx; ++i) rhs[i] = base[i] - nl[i];
+                if (ld_thomas(nx, diag, off, rhs, z, cp, dp)) { rc = -2; break; }
+                lreal dmax = 0, zmax = 0;
+                for (int i = 0; i < nx; ++i) {
+                    lreal d = cabsl(z[i] - v[i]), a = cabsl(v[i]);
+                    if (d > dmax) dmax = d;
+                    if (a > zmax) zmax = a;
+                }
+                memcpy(v, z, sizeof(lcplx) * (size_t)nx);
+                if (dmax <= nl_tol * (zmax > 1.0L ? zmax : 1.0L)) { conv = 1; break; }
+            }
+            if (rc) break;
+            if (!conv) { rc = -3; break; }
+            if (it > worst) worst = it;
+        } else {
+            if (ld_thomas(nx, diag, off, base, v, cp, dp)) { rc = -2; break; }
+        }
+        for (int i = 0; i < nx; ++i) u[i] = 2.0L * v[i] - u[i];
+    }
+    if (rc == 0) for (int i = 0; i < nx; ++i) uT[i] = (cplx)u[i];
+    if (nl_worst) *nl_worst = worst;
+    free(diag); free(off); free(u); free(v); free(rhs); free(base); free(nl); free(z);
+    free(cp); free(dp); free(W);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Discrete adjoint of the monodomain CN map for a static real V(x).         */
 /* Forward:  A v_n = c M u_{n-1},  u_n = 2 v_n - u_{n-1},  A = cM - S + M_V.  */
 /* A is complex symmetric (A^T = A).  For a real objective J(u_nt) with       */

@@ -374,16 +374,17 @@ hipError_t launch_causal_fast(int N, int nt, int ns, int B, int per_problem, con
 // ---------------------------------------------------------------------------
 // General path: up to kGenMaxIf interfaces.  Same algebra as above with the
 // block PCR spread over the workgroup (one thread per interface, exchange
-// through LDS) and a short near block of kGenTb steps.
+// through LDS) and a short near block of TB steps (gen_threads / gen_tb).
 // ---------------------------------------------------------------------------
-constexpr int kGenThreads = 512;
 
-
-// multipliers [nv][levels][8][ni] then D^{-1} [nv][4][ni] (after the levels)
-__global__ __launch_bounds__(kGenThreads) void causal_pcr_setup_gen_kernel(int N, int nt, const cd* cols,
-                                                                          cd* pcr, int rec, double* eta) {
-    __shared__ C2x2 sD[kGenMaxIf], sL[kGenMaxIf], sU[kGenMaxIf];
-    __shared__ double se[kGenThreads / kWave];
+// multipliers [nv][levels][8][ni] then D^{-1} [nv][4][ni] (after the levels).
+// The neighbours' blocks are exchanged through LDS in two rounds (D and L,
+// then U), so 1024 interfaces fit.
+template <int THREADS>
+__global__ __launch_bounds__(THREADS) void causal_pcr_setup_gen_kernel(int N, int nt, const cd* cols,
+                                                                      cd* pcr, int rec, double* eta) {
+    __shared__ C2x2 sA[THREADS], sB[THREADS];
+    __shared__ double se[THREADS / kWave];
     const int v = blockIdx.x, j = threadIdx.x;
     const int ni = N - 1, lv = pcr_levels_for(ni);
     const cd* base = cols + (size_t)v * N * 4 * nt;
@@ -411,7 +412,7 @@ __global__ __launch_bounds__(kGenThreads) void causal_pcr_setup_gen_kernel(int N
         __syncthreads();
         if (j == 0) {
             double m = 0;
-            for (int w = 0; w < kGenThreads / kWave; ++w) m = fmax(m, se[w]);
+            for (int w = 0; w < THREADS / kWave; ++w) m = fmax(m, se[w]);
             eta[(size_t)v * (kGenLevelsMax + 1) + l] = m;
         }
         if (j < ni) {
@@ -421,13 +422,23 @@ __global__ __launch_bounds__(kGenThreads) void causal_pcr_setup_gen_kernel(int N
         }
         if (l == lv) break;
         const int d = 1 << l;
-        if (j < ni) { sD[j] = D; sL[j] = Lm; sU[j] = U; }
+        const bool hm = j - d >= 0, hp = j + d < ni;
+        if (j < ni) { sA[j] = D; sB[j] = Lm; }
         __syncthreads();
+        C2x2 Dm = I, Lmm = Z, Dp = I, Lp = Z, Um = Z, Up = Z;
+        if (j < ni) {
+            if (hm) { Dm = sA[j - d]; Lmm = sB[j - d]; }
+            if (hp) { Dp = sA[j + d]; Lp = sB[j + d]; }
+        }
+        __syncthreads();
+        if (j < ni) sA[j] = U;
+        __syncthreads();
+        if (j < ni) {
+            if (hm) Um = sA[j - d];
+            if (hp) Up = sA[j + d];
+        }
         C2x2 K1 = Z, K2 = Z;
         if (j < ni) {
-            const bool hm = j - d >= 0, hp = j + d < ni;
-            const C2x2 Dm = hm ? sD[j - d] : I, Lmm = hm ? sL[j - d] : Z, Um = hm ? sU[j - d] : Z;
-            const C2x2 Dp = hp ? sD[j + d] : I, Lp = hp ? sL[j + d] : Z, Up = hp ? sU[j + d] : Z;
             K1 = hm ? Lm * inv2(Dm) : Z;
             K2 = hp ? U * inv2(Dp) : Z;
             const C2x2 Dn = D - K1 * Um - K2 * Lp;
@@ -449,22 +460,23 @@ struct NearGenArgs {
     int levels;        // PCR levels run per step (the rest of the coupling is negligible)
     const cd* cols;
     const cd* pcr;     // [nv][rec]
-    const cd* base;    // [B][ns][kGenTb]: d + far part
+    const cd* base;    // [B][ns][TB]: d + far part
     cd* g;             // [B][ns][nt]
 };
 
 // one workgroup per problem; per step: gather the in-block history of every
-// slot (coefficients of lags 1..kGenTb-1 in registers), then block PCR
+// slot (coefficients of lags 1..TB-1 in registers), then block PCR
 // One thread per interface j (slots 2j, 2j+1).  Per step: the right-hand
 // side from the base and the in-block lags (coefficients in registers,
 // earlier solutions in LDS), then the levels of block PCR exchanging through
 // two alternating LDS buffers (one barrier per level), with the multipliers
 // of the next level loaded while the current one runs.
-__global__ __launch_bounds__(kGenThreads) void causal_near_gen_kernel(NearGenArgs a) {
+template <int THREADS, int TB>
+__global__ __launch_bounds__(THREADS) void causal_near_gen_kernel(NearGenArgs a) {
     extern __shared__ cd smem[];
     const int ns = a.ns, nt = a.nt, n0 = a.n0, nb = a.nb, ni = a.N - 1;
-    cd* gh = smem;                          // [kGenTb][ns]
-    cd* xa = gh + (size_t)kGenTb * ns;      // [ns] exchange, even levels
+    cd* gh = smem;                          // [TB][ns]
+    cd* xa = gh + (size_t)TB * ns;          // [ns] exchange, even levels
     cd* xb = xa + ns;                       // [ns] exchange, odd levels
     const int b = blockIdx.x, v = a.per_problem ? b : 0;
     const int j = threadIdx.x;
@@ -473,14 +485,14 @@ __global__ __launch_bounds__(kGenThreads) void causal_near_gen_kernel(NearGenArg
     const int lv = pcr_levels_for(ni);
     const cd zero = mk(0, 0);
     cd* gb = a.g + (size_t)b * ns * nt;
-    const cd* bb = a.base + (size_t)b * ns * kGenTb;
+    const cd* bb = a.base + (size_t)b * ns * TB;
     const cd* rec = a.pcr + (size_t)v * a.rec;
     const cd* cb = a.cols + (size_t)v * a.N * 4 * nt;
     // lag m+1 coefficients: slot 2j <- x1_j (c0), x0_{j+1} (c1);
     //                       slot 2j+1 <- x1_{j-1} (c2), x0_j (c3)
-    cd c0[kGenTb - 1], c1[kGenTb - 1], c2[kGenTb - 1], c3[kGenTb - 1];
+    cd c0[TB - 1], c1[TB - 1], c2[TB - 1], c3[TB - 1];
 #pragma unroll
-    for (int m = 0; m < kGenTb - 1; ++m) {
+    for (int m = 0; m < TB - 1; ++m) {
         const int lag = m + 1;
         c0[m] = c1[m] = c2[m] = c3[m] = zero;
         if (act && lag < nt) {
@@ -500,24 +512,28 @@ __global__ __launch_bounds__(kGenThreads) void causal_near_gen_kernel(NearGenArg
 #pragma unroll
         for (int q = 0; q < 8; ++q) K[q] = act ? rec[((size_t)l * 8 + q) * ni + j] : mk(0, 0);
     };
+    // the 512-thread form loads the next level's multipliers while the
+    // current level runs; the 1024-thread form (128 registers) loads each
+    // level's when it starts
+    constexpr bool kPrefetch = THREADS <= 512;
     cd Kc[8], Kn[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) Kc[q] = zero;
     if (lev > 0) loadK(0, Kc);
-    cd bn0 = act ? bb[(size_t)(2 * j) * kGenTb] : zero;
-    cd bn1 = act ? bb[(size_t)(2 * j + 1) * kGenTb] : zero;
+    cd bn0 = act ? bb[(size_t)(2 * j) * TB] : zero;
+    cd bn1 = act ? bb[(size_t)(2 * j + 1) * TB] : zero;
 
 #pragma unroll
-    for (int i = 0; i < kGenTb; ++i) {
+    for (int i = 0; i < TB; ++i) {
         if (i < nb) {
             cd p0 = bn0, p1 = bn1;
             if (act && i + 1 < nb) {
-                bn0 = bb[(size_t)(2 * j) * kGenTb + i + 1];
-                bn1 = bb[(size_t)(2 * j + 1) * kGenTb + i + 1];
+                bn0 = bb[(size_t)(2 * j) * TB + i + 1];
+                bn1 = bb[(size_t)(2 * j + 1) * TB + i + 1];
             }
             if (act) {
 #pragma unroll
-                for (int m = 0; m < kGenTb - 1; ++m) {
+                for (int m = 0; m < TB - 1; ++m) {
                     const int lag = m + 1;
                     if (lag <= i) {
                         const cd* gs = gh + (size_t)(i - lag) * ns;
@@ -530,7 +546,8 @@ __global__ __launch_bounds__(kGenThreads) void causal_near_gen_kernel(NearGenArg
             }
             for (int l = 0; l < lev; ++l) {
                 const int d = 1 << l;
-                loadK(l + 1 < lev ? l + 1 : 0, Kn);    // next level (or next step's first)
+                if (kPrefetch) loadK(l + 1 < lev ? l + 1 : 0, Kn);   // next level (or next step's first)
+                else loadK(l, Kc);
                 cd* ex = (l & 1) ? xb : xa;
                 if (act) { ex[2 * j] = p0; ex[2 * j + 1] = p1; }
                 __syncthreads();
@@ -542,7 +559,8 @@ __global__ __launch_bounds__(kGenThreads) void causal_near_gen_kernel(NearGenArg
                     p1 = msub(msub(msub(msub(p1, Kc[2], q0m), Kc[3], q1m), Kc[6], q0p), Kc[7], q1p);
                 }
 #pragma unroll
-                for (int q = 0; q < 8; ++q) Kc[q] = Kn[q];
+                for (int q = 0; q < 8; ++q)
+                    if (kPrefetch) Kc[q] = Kn[q];
             }
             if (act) {
                 const cd x0 = madd(di0 * p0, di1, p1);
@@ -560,25 +578,32 @@ __global__ __launch_bounds__(kGenThreads) void causal_near_gen_kernel(NearGenArg
 hipError_t launch_causal_pcr_setup_gen(int N, int nt, int nv, const cd* cols, cd* pcr, double* eta,
                                        hipStream_t st) {
     if (N - 1 > kGenMaxIf) return hipErrorInvalidValue;
-    causal_pcr_setup_gen_kernel<<<nv, kGenThreads, 0, st>>>(N, nt, cols, pcr, pcr_rec_gen(N), eta);
+    if (gen_threads(N) == 512)
+        causal_pcr_setup_gen_kernel<512><<<nv, 512, 0, st>>>(N, nt, cols, pcr, pcr_rec_gen(N), eta);
+    else
+        causal_pcr_setup_gen_kernel<1024><<<nv, 1024, 0, st>>>(N, nt, cols, pcr, pcr_rec_gen(N), eta);
     return hipGetLastError();
 }
 
 hipError_t launch_causal_gen(int N, int nt, int ns, int B, int per_problem, const cd* cols,
                              const cd* pcr, int levels, const cd* d, cd* base, cd* g, int n_lo,
                              int n_hi, const cd* facc, int s_from, hipStream_t st) {
-    const size_t shm = ((size_t)kGenTb * ns + ns + 2 * (size_t)(N - 1)) * sizeof(cd);
-    if (N - 1 > kGenMaxIf || N - 1 > kGenThreads || ns > 2 * kGenThreads || shm > 160 * 1024)
+    const size_t shm = gen_shm(N);
+    const int tb = gen_tb(N), threads = gen_threads(N);
+    if (N - 1 > kGenMaxIf || N - 1 > threads || ns != 2 * (N - 1) || shm > 160 * 1024)
         return hipErrorInvalidValue;
-    if (n_lo % kGenTb != 0 || n_lo < 0 || n_hi > nt || s_from < 0 || s_from > n_lo)
+    if (levels < 0 || levels > pcr_levels_for(N - 1)) return hipErrorInvalidValue;
+    if (n_lo % tb != 0 || n_lo < 0 || n_hi > nt || s_from < 0 || s_from > n_lo)
         return hipErrorInvalidValue;
-    for (int n0 = n_lo; n0 < n_hi; n0 += kGenTb) {
-        const int nb = min(kGenTb, n_hi - n0);
-        hipError_t e = launch_causal_far<kGenTb>(N, nt, ns, B, per_problem, n0, nb, cols, d, g, base,
-                                                 facc, s_from, st);
+    for (int n0 = n_lo; n0 < n_hi; n0 += tb) {
+        const int nb = min(tb, n_hi - n0);
+        hipError_t e = (tb == 8)
+            ? launch_causal_far<8>(N, nt, ns, B, per_problem, n0, nb, cols, d, g, base, facc, s_from, st)
+            : launch_causal_far<2>(N, nt, ns, B, per_problem, n0, nb, cols, d, g, base, facc, s_from, st);
         if (e != hipSuccess) return e;
         NearGenArgs na{N, nt, ns, per_problem, n0, nb, pcr_rec_gen(N), levels, cols, pcr, base, g};
-        causal_near_gen_kernel<<<B, kGenThreads, shm, st>>>(na);
+        if (tb == 8) causal_near_gen_kernel<512, 8><<<B, 512, shm, st>>>(na);
+        else causal_near_gen_kernel<1024, 2><<<B, 1024, shm, st>>>(na);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

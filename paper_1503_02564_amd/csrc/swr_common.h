@@ -333,11 +333,19 @@ hipError_t launch_causal_pcr_setup(int N, int nt, int nv, const cd* cols, cd* pc
 hipError_t launch_causal_fast(int N, int nt, int ns, int B, int per_problem, const cd* cols,
                               const cd* pcr, int levels, const cd* d, cd* base, cd* g, int n_lo,
                               int n_hi, const cd* facc, int s_from, hipStream_t st);
-// general block-PCR causal solve for up to kGenMaxIf interfaces
-constexpr int kGenTb = 8;
+// general block-PCR causal solve for up to kGenMaxIf interfaces: one
+// thread per interface, 512 threads and near blocks of 8 steps up to 512
+// interfaces, 1024 threads and near blocks of 2 steps (so the LDS of the
+// near march fits) up to 1024
 constexpr int kCausalSuper = 256;    // causal solve super-block (time steps)
-constexpr int kGenMaxIf = 512;
-constexpr int kGenLevelsMax = 9;     // pcr_levels_for(kGenMaxIf)
+constexpr int kGenMaxIf = 1024;
+constexpr int kGenLevelsMax = 10;    // pcr_levels_for(kGenMaxIf)
+__host__ __device__ constexpr int gen_threads(int N) { return N - 1 <= 512 ? 512 : 1024; }
+__host__ __device__ constexpr int gen_tb(int N) { return N - 1 <= 512 ? 8 : 2; }
+// dynamic LDS of the general near march: [tb][ns] solutions + two exchange rows
+__host__ __device__ constexpr size_t gen_shm(int N) {
+    return ((size_t)gen_tb(N) * (2 * N - 2) + 2 * (size_t)(2 * N - 2)) * sizeof(cd);
+}
 // number of block-PCR levels that decouple ni interfaces completely
 __host__ __device__ constexpr int pcr_levels_for(int ni) {
     return ni <= 1 ? 0 : (32 - __builtin_clz((unsigned)(ni - 1)));

@@ -36,7 +36,7 @@ struct Iface {
     int nv = 1;
     bool dirty = true;      // columns rebuilt since the causal setup
     int path = 0;           // causal solver: 1 = one-wave block PCR, 2 = workgroup block
-                            // PCR, 3 = dense inverse
+                            // PCR, 3 = dense inverse, 0 = not offered (valid once !dirty)
     cd* pcr = nullptr;
     size_t pcr_size = 0;
     double* eta = nullptr;
@@ -76,6 +76,7 @@ struct swr_ctx {
     cd* dZero = nullptr;      // [B][ns][nt] zeros
     unsigned long long* dMax = nullptr;
     int* dNl = nullptr;       // |u|^2 inner statistics
+    int inner_iters = 0;      // inner BiCGStab iterations of P^{-1} (this call)
     // GMRES workspace
     int gm_m = 0;
     cd* dBasis = nullptr;
@@ -550,7 +551,8 @@ static swr_status run_gmres(swr_ctx* c, const Op& A, const cd* rhs, cd* x, int* 
 // each with its own scalars; x starts at 0.  Stops per problem when
 // ||r||_2 <= tol ||rhs||_2, checked on s after the half step and on r after
 // the full step; finished problems keep their x (zero coefficients).
-static swr_status run_bicgstab(swr_ctx* c, const Op& A, const cd* rhs, cd* x, int* iters_out) {
+static swr_status run_bicgstab(swr_ctx* c, const Op& A, const cd* rhs, cd* x, int* iters_out,
+                               double tol, int max_iter) {
     const int B = c->B;
     const long M = (long)c->ns * c->nt;
     const size_t vec = (size_t)B * M;
@@ -593,7 +595,7 @@ static swr_status run_bicgstab(swr_ctx* c, const Op& A, const cd* rhs, cd* x, in
     bool any = false;
     for (int b = 0; b < B; ++b) { act[b] = bn[b] > 0; any |= act[b] != 0; }
     int its = 0;
-    while (any && its < c->o.max_iter) {
+    while (any && its < max_iter) {
         ++its;
         CHK(dots(rh, r));
         for (int b = 0; b < B; ++b) {
@@ -616,7 +618,7 @@ static swr_status run_bicgstab(swr_ctx* c, const Op& A, const cd* rhs, cd* x, in
         CHK(norms(s, nr));
         for (int b = 0; b < B; ++b) {
             if (!std::isfinite(nr[b])) return SWR_ENAN;
-            half[b] = act[b] && nr[b] <= c->o.tol * bn[b];
+            half[b] = act[b] && nr[b] <= tol * bn[b];
         }
         CHK(A(s, t));
         CHK(dots(t, s));
@@ -633,7 +635,7 @@ static swr_status run_bicgstab(swr_ctx* c, const Op& A, const cd* rhs, cd* x, in
         any = false;
         for (int b = 0; b < B; ++b) {
             if (!std::isfinite(nr[b])) return SWR_ENAN;
-            if (half[b] || nr[b] <= c->o.tol * bn[b]) act[b] = 0;
+            if (half[b] || nr[b] <= tol * bn[b]) act[b] = 0;
             any |= act[b] != 0;
             rho[b] = rho_new[b];
         }
@@ -642,17 +644,74 @@ static swr_status run_bicgstab(swr_ctx* c, const Op& A, const cd* rhs, cd* x, in
     return any ? SWR_ENOCONV : SWR_OK;
 }
 
+// The causal solve needs the per-step block system (I - C_0) in a form it
+// can solve quickly: block PCR on one wave or one workgroup, or a dense
+// inverse for at most kDenseMaxSlots slots.  Beyond that it is not offered:
+// (I - L) g = d is solved by BiCGStab on the same operator instead, and P^{-1}
+// of the preconditioned iterations by an inner BiCGStab (the paper's own way
+// of applying P^{-1}, Sec. 5) to a relative residual of kInnerTol.
+constexpr int kDenseMaxSlots = 512;
+constexpr double kInnerTol = 1e-13;
+// internal status (never crosses the ABI): the causal solve is not offered
+// for this system; the caller switches to BiCGStab
+constexpr swr_status kCausalOff = static_cast<swr_status>(7);
+
+// block PCR on one wave (fast) or on one workgroup (general)
+static bool causal_fast_ok(const swr_ctx* c) { return c->ns <= kNearSlots && c->N - 1 <= kWave; }
+static bool causal_gen_ok(const swr_ctx* c) {
+    return c->N - 1 <= kGenMaxIf && gen_shm(c->N) <= 160 * 1024;
+}
+
+static bool causal_sized(const swr_ctx* c) {
+    if (!c->L.dirty && c->L.path == 0 && c->vk == SWR_V_STATIC) return false;
+    return causal_fast_ok(c) || causal_gen_ok(c) || c->ns <= kDenseMaxSlots;
+}
+
+static swr_status run_causal(swr_ctx* c, Iface& I, const cd* d, cd* g, hipStream_t st,
+                             int n_lo, int n_hi);
+
+// (I - L) g = d of the static potential by BiCGStab on the MFMA operator
+static swr_status static_bicgstab(swr_ctx* c, const cd* d, cd* g, int* iters) {
+    Op A = [c](const cd* x, cd* y) -> swr_status {
+        LttArgs l = ltt_args(c, c->L, x, y);
+        HIPCHK(launch_ltt(l, c->st));
+        return SWR_OK;
+    };
+    return run_bicgstab(c, A, d, g, iters, c->o.tol, c->o.max_iter);
+}
+
+// x = (I - L_I)^{-1} rhs over the whole window: the causal solve, or an inner
+// BiCGStab when the causal solve is not offered at this size
+static swr_status apply_inverse(swr_ctx* c, Iface& I, const cd* rhs, cd* x) {
+    if (causal_sized(c) && !(!I.dirty && I.path == 0)) {
+        const swr_status rs = run_causal(c, I, rhs, x, c->st, 0, c->nt);
+        if (rs != kCausalOff) return rs;
+    }
+    Op A = [c, &I](const cd* z, cd* y) -> swr_status {
+        LttArgs l = ltt_args(c, I, z, y);
+        HIPCHK(launch_ltt(l, c->st));
+        return SWR_OK;
+    };
+    // the inner solve has its own cap (opts.max_iter bounds the outer
+    // iteration): information crosses one interface per Krylov step, so it
+    // needs a multiple of the interface count
+    int its = 0;
+    const int cap = std::max(c->o.max_iter, 20 * c->ns);
+    const swr_status rs = run_bicgstab(c, A, rhs, x, &its, kInnerTol, cap);
+    c->inner_iters += its;
+    return rs == SWR_ENOCONV ? SWR_ENOCONV : rs;
+}
+
 // causal forward substitution in time for (I - L) g = d with the operator I
 // (exact up to rounding).  Block PCR per step when the block system is
 // certified diagonally dominant: on one wave for N - 1 <= 64 interfaces, on
-// a workgroup up to kGenMaxIf; otherwise a dense (I - C_0)^{-1} by
-// Gauss-Jordan with partial pivoting.
+// a workgroup up to kGenMaxIf; otherwise (at most kDenseMaxSlots slots) a
+// dense (I - C_0)^{-1} by Gauss-Jordan with partial pivoting.
 static swr_status run_causal(swr_ctx* c, Iface& I, const cd* d, cd* g, hipStream_t st,
                              int n_lo, int n_hi) {
     const int ns = c->ns, nt = c->nt, B = c->B, ni = c->N - 1;
-    const bool fast_ok = ns <= kNearSlots && ni <= kWave;
-    const size_t gen_shm = ((size_t)kGenTb * ns + ns + 2 * (size_t)ni) * sizeof(cd);
-    const bool gen_ok = ni <= kGenMaxIf && gen_shm <= 160 * 1024;
+    const bool fast_ok = causal_fast_ok(c);
+    const bool gen_ok = causal_gen_ok(c);
     if (I.dirty) {
         I.path = 3;
         if (fast_ok || gen_ok) {
@@ -688,6 +747,8 @@ static swr_status run_causal(swr_ctx* c, Iface& I, const cd* d, cd* g, hipStream
             for (int v = 0; v < I.nv; ++v) I.eta0 = std::max(I.eta0, eta[(size_t)v * ld]);
             if (ok) I.path = fast_ok ? 1 : 2;
         }
+        // no dominance certificate and too many slots for a dense inverse
+        if (I.path == 3 && ns > kDenseMaxSlots) I.path = 0;
         if (I.path == 3) {
             if (!I.Minv) {
                 ALLOC_LIVE(I.Minv, (size_t)I.nv * ns * ns);
@@ -698,8 +759,9 @@ static swr_status run_causal(swr_ctx* c, Iface& I, const cd* d, cd* g, hipStream
         }
         I.dirty = false;
     }
+    if (I.path == 0) return kCausalOff;
     if (I.path == 1 || I.path == 2) {
-        const int tb = I.path == 1 ? kNearTb : kGenTb;
+        const int tb = I.path == 1 ? kNearTb : gen_tb(c->N);
         if (!c->dBase || c->base_tb < tb) {
             ALLOC_LIVE(c->dBase, (size_t)B * ns * tb);
             c->base_tb = tb;
@@ -796,7 +858,7 @@ static swr_status run_precond_time(swr_ctx* c, int* iters) {
     Op A = [c, pc, vec](const cd* z, cd* y) -> swr_status {
         const cd* w = z;
         if (pc) {
-            CHK(run_causal(c, c->L0, z, c->dT1, c->st, 0, c->nt));
+            CHK(apply_inverse(c, c->L0, z, c->dT1));
             w = c->dT1;
         }
         SweepIO io;
@@ -808,7 +870,7 @@ static swr_status run_precond_time(swr_ctx* c, int* iters) {
     HIPCHK(hipMemsetAsync(c->dG2, 0, vec * sizeof(cd), c->st));   // y (preconditioned unknown)
     swr_status rs = run_gmres(c, A, c->dD, c->dG2, iters);
     if (rs != SWR_OK && rs != SWR_ENOCONV) return rs;
-    if (pc) CHK(run_causal(c, c->L0, c->dG2, c->dG, c->st, 0, c->nt));
+    if (pc) CHK(apply_inverse(c, c->L0, c->dG2, c->dG));
     else HIPCHK(hipMemcpyAsync(c->dG, c->dG2, vec * sizeof(cd), hipMemcpyDeviceToDevice, c->st));
     return rs;
 }
@@ -828,7 +890,7 @@ static swr_status run_precond_cubic(swr_ctx* c, const cd* u0, int* iters, double
         HIPCHK(launch_axpby(c->dG, 1.0, c->dT2, -1.0, c->dT2, (long)vec, c->st));   // g - R_nl g
         const cd* z = c->dT2;
         if (c->o.precond) {
-            CHK(run_causal(c, c->L0, c->dT2, c->dT1, c->st, 0, c->nt));
+            CHK(apply_inverse(c, c->L0, c->dT2, c->dT1));
             z = c->dT1;
         }
         HIPCHK(launch_axpby(c->dG, 1.0, z, -1.0, c->dG, (long)vec, c->st));
@@ -875,7 +937,7 @@ struct PipeTimes {
 
 static bool pipelined(const swr_ctx* c) {
     return c->vk == SWR_V_STATIC && c->o.solver == SWR_SOLVER_CAUSAL && c->o.pipeline > 0 &&
-           !c->o.plain &&
+           !c->o.plain && causal_sized(c) &&
            c->ns > 0 && c->nt > c->o.pipeline;
 }
 
@@ -986,6 +1048,7 @@ extern "C" swr_status swr_solve(swr_ctx* c, const double* u0d, double* uT, doubl
     swr_status rs = SWR_OK;
     int iters = 0;
     double fixed_last = 0;
+    c->inner_iters = 0;
     HIPCHK(hipMemsetAsync(c->dNl, 0, 2 * sizeof(int), st));
     HIPCHK(hipEventRecord(c->ev[0], st));
     // 1. assembly + factorisation
@@ -1000,7 +1063,17 @@ extern "C" swr_status swr_solve(swr_ctx* c, const double* u0d, double* uT, doubl
         SweepIO io;
         io.u0 = u0; io.g_in = c->dG; io.g_out = c->dG2;
         io.uT = reinterpret_cast<cd*>(uT); io.trace = reinterpret_cast<cd*>(utrace);
-        CHK(run_static_pipelined(c, u0, c->dG, io, info ? &tm : nullptr));
+        const swr_status ps = run_static_pipelined(c, u0, c->dG, io, info ? &tm : nullptr);
+        if (ps == kCausalOff) {
+            // the causal solve turned out not to be offered for this system
+            // (found once the first impulse responses existed): let the
+            // streams drain, then solve again in the staged form
+            if (c->s2) HIPCHK(hipStreamSynchronize(c->s2));
+            if (c->s3) HIPCHK(hipStreamSynchronize(c->s3));
+            HIPCHK(hipStreamSynchronize(st));
+            return swr_solve(c, u0d, uT, g, utrace, info);
+        }
+        CHK(ps);
         iters = 1;
         HIPCHK(hipEventRecord(c->ev[2], st));
         HIPCHK(hipEventRecord(c->ev[3], st));
@@ -1032,16 +1105,20 @@ extern "C" swr_status swr_solve(swr_ctx* c, const double* u0d, double* uT, doubl
             return SWR_OK;
         };
         rs = run_gmres(c, A, c->dD, c->dG, &iters);
-    } else if (c->o.solver == SWR_SOLVER_BICGSTAB) {
+    } else if (c->o.solver == SWR_SOLVER_BICGSTAB ||
+               (c->o.solver == SWR_SOLVER_CAUSAL && !causal_sized(c))) {
+        // (the causal solve is not offered at this many interfaces: the same
+        // system by BiCGStab)
         Op A = [c](const cd* x, cd* y) -> swr_status {
             LttArgs l = ltt_args(c, c->L, x, y);
             HIPCHK(launch_ltt(l, c->st));
             return SWR_OK;
         };
-        rs = run_bicgstab(c, A, c->dD, c->dG, &iters);
+        rs = run_bicgstab(c, A, c->dD, c->dG, &iters, c->o.tol, c->o.max_iter);
     } else if (c->o.solver == SWR_SOLVER_CAUSAL) {
         rs = run_causal(c, c->L, c->dD, c->dG, c->st, 0, c->nt);
         iters = 1;
+        if (rs == kCausalOff) rs = static_bicgstab(c, c->dD, c->dG, &iters);
     } else {
         return SWR_EINVAL;
     }
@@ -1093,6 +1170,7 @@ extern "C" swr_status swr_solve(swr_ctx* c, const double* u0d, double* uT, doubl
         info->t_total_ms = elapsed(c->ev[0], c->ev[4]);
         info->t_sweep_ms = 0;
         info->n_sweep = 0;
+        info->inner_iters = c->inner_iters;
         if (pipe) {
             info->t_build_ms = tm.build;
             info->t_iface_ms = tm.iface;
@@ -1178,16 +1256,17 @@ static swr_status solve_interface(swr_ctx* c, const cd* d, cd* g, int* iters) {
         };
         return run_gmres(c, A, d, g, iters);
     }
-    if (c->o.solver == SWR_SOLVER_BICGSTAB) {
+    if (c->o.solver == SWR_SOLVER_BICGSTAB || !causal_sized(c)) {
         Op A = [c](const cd* x, cd* y) -> swr_status {
             LttArgs l = ltt_args(c, c->L, x, y);
             HIPCHK(launch_ltt(l, c->st));
             return SWR_OK;
         };
-        return run_bicgstab(c, A, d, g, iters);
+        return run_bicgstab(c, A, d, g, iters, c->o.tol, c->o.max_iter);
     }
     *iters = 1;
-    return run_causal(c, c->L, d, g, c->st, 0, c->nt);
+    const swr_status rs = run_causal(c, c->L, d, g, c->st, 0, c->nt);
+    return rs == kCausalOff ? static_bicgstab(c, d, g, iters) : rs;
 }
 
 static AdjArgs adj_args(swr_ctx* c) {
@@ -1236,7 +1315,14 @@ extern "C" swr_status swr_grad(swr_ctx* c, const double* u0d, const double* gbar
         SweepIO io;
         io.u0 = u0; io.g_in = c->dGfwd; io.g_out = c->dG2; io.uT = c->dUT;
         io.ckpt = true;
-        CHK(run_static_pipelined(c, u0, c->dGfwd, io, nullptr));
+        const swr_status ps = run_static_pipelined(c, u0, c->dGfwd, io, nullptr);
+        if (ps == kCausalOff) {
+            if (c->s2) HIPCHK(hipStreamSynchronize(c->s2));
+            if (c->s3) HIPCHK(hipStreamSynchronize(c->s3));
+            HIPCHK(hipStreamSynchronize(st));
+            return swr_grad(c, u0d, gbar, dJdV, dJdu0, info);
+        }
+        CHK(ps);
         it_f = 1;
     } else {
         CHK(run_build(c, u0d));

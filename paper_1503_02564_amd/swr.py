@@ -39,7 +39,8 @@ class SwrInfo(ctypes.Structure):
                 ("t_factor_ms", ctypes.c_double), ("t_build_ms", ctypes.c_double),
                 ("t_iface_ms", ctypes.c_double), ("t_final_ms", ctypes.c_double),
                 ("nl_worst", ctypes.c_int), ("t_total_ms", ctypes.c_double),
-                ("t_sweep_ms", ctypes.c_double), ("n_sweep", ctypes.c_int)]
+                ("t_sweep_ms", ctypes.c_double), ("n_sweep", ctypes.c_int),
+                ("inner_iters", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

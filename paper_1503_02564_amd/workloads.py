@@ -206,6 +206,37 @@ def adjoint_batch(N: int = 256, cells: int = 64, nt: int = 2000, B: int = 16, se
                     extras=dict(V_ref=Vs[B], checkpoint_K=64))
 
 
+def paper_case(kind: str, N: int = 1000, dx: float = 1e-4, nt: int = 500) -> Workload:
+    """The workloads of the paper's numerical section (Sec. 6): (-21, 21)
+    in N equal subdomains of mesh size dx, T = 0.5, dt = T/nt (1e-3), S0^2.
+    kind 'harmonic': V = -x^2; 'linear_t': V(t, x) = 5 t x (both with
+    u0 = exp(-(x+10)^2 + 20 i (x+10))); 'cubic': |u|^2 with
+    u0 = 2 sech(sqrt(2)(x+10)) exp(20 i (x+10)).  The paper's grids are
+    dx = 1e-5 and 1e-4 with N up to 1000; no random numbers are drawn."""
+    a0, b0, T = -21.0, 21.0, 0.5
+    nc = int(round((b0 - a0) / dx))
+    if nc % N:
+        raise ValueError("N must divide the number of cells")
+    J = np.full(N, nc // N, dtype=np.int32)
+    x = mesh_nodes(a0, b0, nc)
+    dt = T / nt
+    y = x + 10.0
+    if kind == "cubic":
+        u0 = (2.0 / np.cosh(np.sqrt(2.0) * y)) * np.exp(20j * y)
+    else:
+        u0 = np.exp(-y * y + 20j * y)
+    if kind == "harmonic":
+        vk, V = V_STATIC, -x * x
+    elif kind == "linear_t":
+        t = dt * np.arange(nt + 1)
+        vk, V = V_TIME, 5.0 * t[:, None] * x[None, :]
+    elif kind == "cubic":
+        vk, V = V_CUBIC, None
+    else:
+        raise ValueError(kind)
+    return Workload(f"paper_{kind}", a0, b0, J, dt, nt, vk, V, S02, 0j, u0[None, :], tol=1e-10)
+
+
 def small_case(N=3, J=None, nt=12, a0=-6.0, b0=6.0, vkind=V_STATIC, trans=S02,
                sigma=1.0 - 1.0j, B=1, seed=7, cells=8) -> Workload:
     """Tiny seeded case for brute-force checks (a few dozen nodes)."""

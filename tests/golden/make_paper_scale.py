@@ -1,0 +1,65 @@
+"""Write reference solutions of the paper's numerical-section workloads
+(Sec. 6: (-21, 21), T = 0.5, dt = 1e-3, mesh size 1e-4, S0^2 for the
+decomposed solvers) as sampled text fixtures for the paper-scale GPU tests.
+Calls the oracle only.
+
+    python tests/golden/make_paper_scale.py [harmonic] [linear_t] [cubic]
+
+The reference is the monodomain Crank-Nicolson solution (the plain definition
+the decomposed solvers converge to, Sec. 3), computed in extended precision
+(oracle.mono_ld): on this grid (dt/h^2 = 1e5, 420001 nodes) one FP64 sweep
+over the whole domain is itself off by ~1e-9, far more than the decomposed
+solution.  Each file holds u(T) at every STRIDE-th node plus the maximum of
+|u(T)| over all nodes (the scale of the relative comparison).
+"""
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+from oracle import oracle as O  # noqa: E402
+from paper_1503_02564_amd import workloads as W  # noqa: E402
+
+STRIDE = 200
+
+
+def fixture_path(kind):
+    return os.path.join(HERE, f"paper_scale_{kind}.txt")
+
+
+def read_fixture(kind):
+    """(node indices, u(T) there, max |u(T)| over all nodes)."""
+    scale = None
+    with open(fixture_path(kind)) as f:
+        for line in f:
+            if line.startswith("# max_abs_u"):
+                scale = float(line.split()[2])
+    dat = np.loadtxt(fixture_path(kind))
+    return dat[:, 0].astype(np.int64), dat[:, 1] + 1j * dat[:, 2], scale
+
+
+def main(kinds):
+    for kind in kinds:
+        wl = W.paper_case(kind)
+        t0 = time.time()
+        uT = O.mono_ld(wl, wl.u0[0], nl_tol=1e-16, nl_maxit=200)
+        idx = np.arange(0, wl.nx, STRIDE)
+        with open(fixture_path(kind), "w") as f:
+            f.write(f"# u(T) of the paper's Sec. 6 workload '{kind}' (nx = {wl.nx}, nt = {wl.nt}, "
+                    f"dt = {wl.dt}, h = {wl.h}): monodomain Crank-Nicolson in extended precision "
+                    f"(oracle.mono_ld).\n")
+            f.write("# written by tests/golden/make_paper_scale.py (oracle only)\n")
+            f.write(f"# max_abs_u {np.max(np.abs(uT)):.17e}\n")
+            f.write(f"# stride {STRIDE}\n")
+            f.write("# columns: node re im\n")
+            for i in idx:
+                f.write(f"{i} {uT[i].real:.17e} {uT[i].imag:.17e}\n")
+        print(kind, "written in", round(time.time() - t0, 1), "s", flush=True)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:] or ["harmonic", "linear_t", "cubic"])

@@ -516,3 +516,47 @@ def test_unpreconditioned_cubic_robin_diverges_and_reports_it(dev):
         swr.swr_solve(pb.ctx, to_dev(wl.u0), uT)
     assert ei.value.status in (swr.SWR_ENAN, swr.SWR_ENOCONV)
     pb.close()
+
+
+def test_causal_solve_with_a_thousand_interfaces(dev):
+    """599 interfaces: the 1024-thread form of the workgroup block-PCR causal
+    solve (near blocks of 2 steps); g against the oracle's causal solve,
+    u(T) against the monodomain solution."""
+    import torch
+    from paper_1503_02564_amd import swr
+    rng = np.random.default_rng(21)
+    J = rng.integers(6, 11, 600).astype(np.int32)
+    wl = W.small_case(J=J, nt=40, trans=W.S02, sigma=0j, seed=21, a0=-300.0, b0=300.0)
+    x = W.mesh_nodes(wl.a0, wl.b0, wl.nc)
+    wl.V = W.bumpy_harmonic(x, rng.uniform(-5, 5, 8), rng.uniform(-250, 250, 8), curvature=-1e-4)
+    say("causal", "600 subdomains")
+    pb = make_problem(wl, tol=1e-13)
+    uT = torch.zeros((1, wl.nx), dtype=torch.complex128, device=dev)
+    g = torch.zeros((1, pb.ns, wl.nt), dtype=torch.complex128, device=dev)
+    st, info = swr.swr_solve(pb.ctx, to_dev(wl.u0), uT, g)
+    torch.cuda.synchronize()
+    assert st == swr.SWR_OK and info.iters == 1 and info.residual < 1e-11
+    gw = O.causal_solve(wl, O.impulse_columns(wl), O.interface_d(wl, wl.u0[0]))
+    assert rel(to_np(g)[0], gw) < 1e-10
+    assert rel(to_np(uT)[0], O.mono(wl, wl.u0[0])) < 1e-10
+    pb.close()
+
+
+@pytest.mark.parametrize("pipeline", [0, 64])
+def test_causal_solve_not_offered_falls_back_to_bicgstab(dev, pipeline):
+    """599 interfaces whose per-step block system is not block diagonally
+    dominant (narrow subdomains): block PCR is not certified and the dense
+    inverse is not offered at this size, so the solve switches to BiCGStab
+    (in the pipelined form after the first impulse responses exist)."""
+    import torch
+    from paper_1503_02564_amd import swr
+    wl = W.small_case(J=np.full(600, 8, np.int32), nt=130, trans=W.S02, sigma=0j, seed=22,
+                      a0=-12.0, b0=12.0)
+    say("causal fallback", "pipeline", pipeline)
+    pb = make_problem(wl, tol=1e-13, max_iter=20000, pipeline=pipeline)
+    uT = torch.zeros((1, wl.nx), dtype=torch.complex128, device=dev)
+    st, info = swr.swr_solve(pb.ctx, to_dev(wl.u0), uT)
+    torch.cuda.synchronize()
+    assert st == swr.SWR_OK and info.iters > 1 and info.residual < 1e-11
+    assert rel(to_np(uT)[0], O.mono(wl, wl.u0[0])) < 1e-10
+    pb.close()
