@@ -53,7 +53,8 @@ def sweep_flops_per_pt_step(wl) -> float:
 
 
 SWEEP_SOURCES = ("paper_1503_02564_amd/csrc/swr_sweep_kernel.h", "paper_1503_02564_amd/csrc/swr_lane.h",
-                 "paper_1503_02564_amd/csrc/swr_sweep_static.hip", "paper_1503_02564_amd/csrc/swr_sweep.hip")
+                 "paper_1503_02564_amd/csrc/swr_sweep_static.hip", "paper_1503_02564_amd/csrc/swr_sweep_static_s02.hip",
+                 "paper_1503_02564_amd/csrc/swr_sweep.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_kernel_static_64x256_hbm.txt")
 
 

@@ -291,6 +291,7 @@ constexpr int kRedThreads = 256;
 hipError_t launch_factor(const FactorArgs& a, hipStream_t st);
 hipError_t launch_sweep(const SweepArgs& a, int trans, int vk, hipStream_t st, bool plain = false);
 hipError_t launch_sweep_static(const SweepArgs& a, int trans, hipStream_t st);
+hipError_t launch_sweep_static_s02(const SweepArgs& a, hipStream_t st);
 hipError_t launch_sweep_time(const SweepArgs& a, int trans, hipStream_t st);
 hipError_t launch_sweep_cubic(const SweepArgs& a, int trans, hipStream_t st);
 hipError_t launch_finalize_ut(int N, int nx, int B, const int* off, const cd* ends, cd* uT,

@@ -263,7 +263,10 @@ extern "C" swr_status swr_setup(double a0, double b0, int N, const int* J, doubl
     const int fields = fac_fields(c->P);
     ALLOC(c->dJ, N);
     ALLOC(c->dOff, N);
-    ALLOC(c->dBeta, nt + kWave + 1);
+    // beta_0 .. beta_{nt+64}, and at least beta_0 .. beta_{2*64-1} (the
+    // sweep's LDS copy of the first 128 weights)
+    const int nbeta = std::max(nt, kWave) + kWave + 1;
+    ALLOC(c->dBeta, nbeta);
     ALLOC(c->dHist, (tr != SWR_ROBIN) ? max_tasks * 2 * (nt + 1) : 1);
     if (tr > SWR_S02) ALLOC(c->dEndc, (size_t)nv * N * 2);
     ALLOC(c->dEnds, (size_t)B * N * 2);
@@ -320,7 +323,7 @@ extern "C" swr_status swr_setup(double a0, double b0, int N, const int* J, doubl
     HIPCHK(hipMemsetAsync(c->dZero, 0, vec * sizeof(cd), c->st));
     if (c->L.cols) HIPCHK(hipMemsetAsync(c->L.cols, 0, (size_t)nv * N * 4 * nt * sizeof(cd), c->st));
     if (c->L0.cols) HIPCHK(hipMemsetAsync(c->L0.cols, 0, (size_t)N * 4 * nt * sizeof(cd), c->st));
-    HIPCHK(launch_beta(nt + kWave + 1, c->dBeta, c->st));
+    HIPCHK(launch_beta(nbeta, c->dBeta, c->st));
     HIPCHK(hipStreamSynchronize(c->st));
     *out = c;
     return SWR_OK;

@@ -20,13 +20,17 @@
 //   rho_n = -flux_n + 2 (sigma v_n + h_n)  at each interface end
 // with h_n = c2 sum_{s<n} beta_{n-s} v_s for S0^2 (Sec. 2.2) and h = 0 for
 // Robin.  The S0^2 history is blocked by 64 steps: lane j carries the output
-// step n0+1+j; at each block start it sums the "far" past s <= n0 from the
-// boundary history stored in global memory, and every step adds the newest
-// boundary value with one fused multiply-add per lane.  The critical path of
-// a step therefore carries no O(n) history work.
+// step n0+1+j.  Its "far" part, s <= n0 - 64, is summed from the boundary
+// history stored in global memory -- by a second wave of the workgroup while
+// the sweep runs the block before (launches of up to 512 tasks, where every
+// wave gets a SIMD of its own), or at the block start by the sweeping wave
+// itself (larger launches), with the same arithmetic; the 64 terms of the
+// block before, and every step's newest value for the current block, are
+// added by the sweeping wave with one fused multiply-add per lane each.
 //
 // The kernel template itself is in swr_sweep_kernel.h; swr_sweep_static.hip,
-// swr_sweep_time.hip and swr_sweep_cubic.hip instantiate it.
+// swr_sweep_static_s02.hip, swr_sweep_time.hip and swr_sweep_cubic.hip
+// instantiate it.
 #include "swr_lane.h"
 
 namespace swr {

@@ -5,8 +5,11 @@ namespace swr {
 
 template <int P>
 static void launch_p(const SweepArgs& a, int trans, hipStream_t st) {
-    if (trans == TR_S02) sweep_kernel<P, TR_S02, VK_CUBIC><<<a.ntasks, 64, 0, st>>>(a);
-    else sweep_kernel<P, TR_ROBIN, VK_CUBIC><<<a.ntasks, 64, 0, st>>>(a);
+    if (trans == TR_S02 && a.ntasks <= kHelpMaxTasks)
+        sweep_kernel<P, TR_S02, VK_CUBIC, true><<<a.ntasks, sweep_threads(true), 0, st>>>(a);
+    else if (trans == TR_S02)
+        sweep_kernel<P, TR_S02, VK_CUBIC, false><<<a.ntasks, sweep_threads(false), 0, st>>>(a);
+    else sweep_kernel<P, TR_ROBIN, VK_CUBIC><<<a.ntasks, sweep_threads(false), 0, st>>>(a);
 }
 
 hipError_t launch_sweep_cubic(const SweepArgs& a, int trans, hipStream_t st) {

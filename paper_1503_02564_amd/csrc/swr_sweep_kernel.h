@@ -1,28 +1,73 @@
 // swr_sweep_kernel.h -- the subdomain sweep kernel template (see the
 // description at the top of swr_sweep.hip).  Included by the three
 // translation units that instantiate it for one potential kind each, so
-// the 56 instantiations compile in parallel.
+// the instantiations compile in parallel.
 #pragma once
 #include "swr_lane.h"
 
 namespace swr {
+
+// Threads per workgroup of the sweep: with HELP (S0^2, launches of at most
+// kHelpMaxTasks tasks, so every wave has a SIMD of its own) a second wave
+// sums the far history beside the sweep (far_helper below); otherwise one
+// wave does everything, with the same arithmetic in the same order.
+__host__ __device__ constexpr int sweep_threads(bool help) { return help ? 2 * kWave : kWave; }
+constexpr int kHelpMaxTasks = 512;
+
+// The far part of the S0^2 history on the workgroup's second wave.  The main
+// wave marches blocks of 64 steps, n0 = nbeg, nbeg + 64, ...; for block n0 it
+// needs, in lane j (output step n0+1+j), sum_{s <= n0} beta_{n0+1+j-s} x_s.
+// The terms s <= n0 - 64 use values stored at least one block earlier: this
+// wave sums them for the next block while the main wave runs the current one
+// and hands them over through LDS (double buffer, one barrier per block, the
+// same count as the main wave's).  The main wave adds the 64 terms of the
+// block just finished, which it accumulates step by step.
+__device__ inline void far_helper(const SweepArgs& a, const cd* Ha, const cd* Hb, int t,
+                                  cd (*ffa)[kWave], cd (*ffb)[kWave]) {
+    const int nbeg = a.n_begin, nend = a.n_end;
+    auto far = [&](int n0, int buf) {
+        const int nj = n0 + 1 + t;
+        double ax = 0.0, ay = 0.0, bx = 0.0, by = 0.0;
+#pragma unroll 8
+        for (int q = 0; q <= n0 - kWave; ++q) {
+            const double bt = a.beta[nj - q];
+            const cd xa = Ha[q], xb = Hb[q];
+            ax = fma(bt, xa.x, ax);
+            ay = fma(bt, xa.y, ay);
+            bx = fma(bt, xb.x, bx);
+            by = fma(bt, xb.y, by);
+        }
+        ffa[buf][t] = mk(ax, ay);
+        ffb[buf][t] = mk(bx, by);
+    };
+    far(nbeg, 0);
+    __syncthreads();
+    int kb = 0;
+    for (int n0 = nbeg; n0 < nend; n0 += kWave, ++kb) {
+        if (n0 + kWave < nend) far(n0 + kWave, (kb + 1) & 1);
+        __syncthreads();
+    }
+}
 
 // ---------------------------------------------------------------------------
 // The sweep.  VK selects the potential: static (factors loaded once), time
 // dependent (rows rebuilt and refactored every step from the streamed V rows)
 // or |u|^2 (V-free factors, inner fixed point of eq. AvMNL every step).
 // ---------------------------------------------------------------------------
-template <int P, int TR, int VK>
-__global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
+template <int P, int TR, int VK, bool HELP = false>
+__global__ __launch_bounds__(sweep_threads(HELP)) void sweep_kernel(SweepArgs a) {
     using L = FacLayout<P>;
-    __shared__ double sbeta[kWave + 1];
+    static_assert(!HELP || TR == TR_S02, "the helper wave serves S0^2");
+    __shared__ double sbeta[2 * kWave];       // beta_0 .. beta_127
+    __shared__ cd ffa[2][kWave], ffb[2][kWave];   // S0^2: far sums from the helper wave
     __shared__ cd sha[kWave], shb[kWave];     // staged chunk of the boundary history
     __shared__ double sb[2 * kWave];          // beta window of that chunk
     const int tix = a.task0 + blockIdx.x;   // task index (per-task buffers)
     const Task task = a.tasks[tix];
     const int k = task.k, b = task.b, f = task.f;
     const int fl = (task.flags & a.flags_and) | a.flags_or;
-    const int t = threadIdx.x;
+    const int t = threadIdx.x & (kWave - 1);
+    const int wv = threadIdx.x / kWave;     // 1: the S0^2 helper wave
     const int n = a.J[k] + 1, o = a.off[k];
     const int nt = a.nt;
     const bool lif = k > 0, rif = k < a.N - 1;
@@ -31,9 +76,17 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
     const cd zero = mk(0, 0);
 
     if (TR == TR_S02 || TR == TR_GEN) {
-        sbeta[t] = a.beta[t];
-        if (t == 0) sbeta[kWave] = a.beta[kWave];
+        if (wv == 0) {
+            sbeta[t] = a.beta[t];
+            sbeta[kWave + t] = a.beta[kWave + t];
+        }
         __syncthreads();
+    }
+    cd* Ha = a.hist ? a.hist + (size_t)tix * 2 * (nt + 1) : nullptr;
+    cd* Hb = Ha ? Ha + (nt + 1) : nullptr;
+    if (HELP && wv == 1) {
+        far_helper(a, Ha, Hb, t, ffa, ffb);
+        return;
     }
     // higher-order operators: coefficients of the two ends (left, right)
     EndCoef ea{}, eb{};
@@ -98,8 +151,6 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
     };
 
     const double kap = a.kappa;
-    cd* Ha = a.hist ? a.hist + (size_t)tix * 2 * (nt + 1) : nullptr;
-    cd* Hb = Ha ? Ha + (nt + 1) : nullptr;
     const cd va0 = rdlane(u[0], 0);
     const cd vb0 = at_last(u);
     // history value at step 0: v_0 (calW_0 = 0, so also x_0 = v_0)
@@ -142,7 +193,28 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
     double maxd = 0.0;
     int nl_worst = 0, nl_fail = 0;
 
-    for (int n0 = nbeg; n0 < nend; n0 += kWave) {
+    // S0^2: the 64 history terms of the block before the first one of this
+    // launch (s in (nbeg-64, nbeg]), in the order in which a running block
+    // accumulates them for its successor, then the barrier that pairs with
+    // the helper's first one
+    cd nxt_a = zero, nxt_b = zero;
+    if (TR == TR_S02) {
+        __threadfence_block();
+#pragma unroll 8
+        for (int i = 0; i < kWave; ++i) {
+            const int q = nbeg - kWave + 1 + i;
+            if (q >= 0) {
+                const double bt = sbeta[kWave + t - i];
+                const cd xa = Ha[q], xb = Hb[q];
+                nxt_a = mk(fma(bt, xa.x, nxt_a.x), fma(bt, xa.y, nxt_a.y));
+                nxt_b = mk(fma(bt, xb.x, nxt_b.x), fma(bt, xb.y, nxt_b.y));
+            }
+        }
+        if (HELP) __syncthreads();
+    }
+
+    int kb = 0;
+    for (int n0 = nbeg; n0 < nend; n0 += kWave, ++kb) {
         const int nb = min(kWave, nend - n0);
         const bool act = t < nb;
         // incoming fluxes of this block: lane j <-> step n0+1+j
@@ -153,15 +225,51 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
             if ((fl & T_IMP_L) && n0 + t == 0) lb = mk(1, 0);
             if ((fl & T_IMP_R) && n0 + t == 0) rb = mk(1, 0);
         }
-        // far part of the S0^2 history for the outputs of this block:
-        // acc_j = sum_{q <= n0} beta_{n0+1+j-q} v_q, over chunks of 64 past
-        // values staged in LDS with one coalesced load each, together with
-        // the 127-entry window of beta the chunk needs
-        // (higher-order operators: the same sums of the stored x_s, split by
-        // the parity of i -- acc for even i, acc1 for odd i -- and each
-        // lane's running sum of the staged values for G)
+        // far part of the history for the outputs of this block,
+        // acc_j = sum_{q <= n0} beta_{n0+1+j-q} x_q.  S0^2: the helper
+        // wave's terms q <= n0 - 64 plus the running sum of the block before.
+        // Higher-order operators: summed here over chunks of 64 past values
+        // staged in LDS with one coalesced load each, together with the
+        // 127-entry window of beta the chunk needs, split by the parity of i
+        // (acc for even i, acc1 for odd i), with each lane's running sum of
+        // the staged values for G
         cd acc_a = zero, acc_b = zero, acc_a1 = zero, acc_b1 = zero, gs_a = zero, gs_b = zero;
-        if (TR == TR_S02 || TR == TR_GEN) {
+        if (TR == TR_S02) {
+            // terms s <= n0 - 64 (from the helper wave, or summed here in the
+            // same order over staged chunks) plus the block before
+            cd fa = zero, fb = zero;
+            if (HELP) {
+                fa = ffa[kb & 1][t];
+                fb = ffb[kb & 1][t];
+            } else {
+                __threadfence_block();
+                const int qmax = n0 - kWave;
+                const int nj = n0 + 1 + t;
+                for (int q0 = 0; q0 <= qmax; q0 += kWave) {
+                    const int qn = min(kWave, qmax + 1 - q0);
+                    const int bbase = n0 - q0 - (kWave - 2);   // beta index of sb[0]
+                    sha[t] = (t < qn) ? Ha[q0 + t] : zero;
+                    shb[t] = (t < qn) ? Hb[q0 + t] : zero;
+                    sb[t] = (bbase + t >= 0) ? a.beta[bbase + t] : 0.0;
+                    sb[kWave + t] = (bbase + kWave + t >= 0) ? a.beta[bbase + kWave + t] : 0.0;
+                    __syncthreads();
+                    const double* bw = sb + (nj - q0 - bbase);  // beta_{nj - q0 - i} = bw[-i]
+                    #pragma unroll 16
+                    for (int i = 0; i < kWave; ++i) {
+                        const double bt = bw[-i];
+                        const cd ha = sha[i], hb = shb[i];
+                        fa = mk(fma(bt, ha.x, fa.x), fma(bt, ha.y, fa.y));
+                        fb = mk(fma(bt, hb.x, fb.x), fma(bt, hb.y, fb.y));
+                    }
+                    __syncthreads();
+                }
+            }
+            acc_a = fa + nxt_a;
+            acc_b = fb + nxt_b;
+            nxt_a = zero;
+            nxt_b = zero;
+        }
+        if (TR == TR_GEN) {
             __threadfence_block();
             const int nj = n0 + 1 + t;
             // the loads of chunk q0 + 64 are issued before chunk q0 is summed
@@ -182,10 +290,8 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
                 const int bbase = n0 - q0 - (kWave - 2);   // beta index of sb[0]
                 sha[t] = pa;
                 shb[t] = pb;
-                if (TR == TR_GEN) {
-                    gs_a = gs_a + pa;
-                    gs_b = gs_b + pb;
-                }
+                gs_a = gs_a + pa;
+                gs_b = gs_b + pb;
                 sb[t] = pb0;
                 sb[kWave + t] = pb1;
                 if (q0 + kWave <= n0) fetch(q0 + kWave);
@@ -194,24 +300,14 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
                 // all 64 entries: the staged chunk is zero past qn and the beta
                 // window bw[-i], i < 64, stays inside sb, so the loop unrolls and
                 // its LDS reads overlap
-                if (TR == TR_S02) {
-                    #pragma unroll 16
-                    for (int i = 0; i < kWave; ++i) {
-                        const double bt = bw[-i];
-                        const cd ha = sha[i], hb = shb[i];
-                        acc_a = mk(acc_a.x + bt * ha.x, acc_a.y + bt * ha.y);
-                        acc_b = mk(acc_b.x + bt * hb.x, acc_b.y + bt * hb.y);
-                    }
-                } else {
-                    #pragma unroll 8
-                    for (int i = 0; i < kWave; i += 2) {
-                        const double b0 = bw[-i], b1 = bw[-i - 1];
-                        const cd h0 = sha[i], h1 = sha[i + 1], k0 = shb[i], k1 = shb[i + 1];
-                        acc_a = mk(acc_a.x + b0 * h0.x, acc_a.y + b0 * h0.y);
-                        acc_a1 = mk(acc_a1.x + b1 * h1.x, acc_a1.y + b1 * h1.y);
-                        acc_b = mk(acc_b.x + b0 * k0.x, acc_b.y + b0 * k0.y);
-                        acc_b1 = mk(acc_b1.x + b1 * k1.x, acc_b1.y + b1 * k1.y);
-                    }
+                #pragma unroll 8
+                for (int i = 0; i < kWave; i += 2) {
+                    const double b0 = bw[-i], b1 = bw[-i - 1];
+                    const cd h0 = sha[i], h1 = sha[i + 1], k0 = shb[i], k1 = shb[i + 1];
+                    acc_a = mk(acc_a.x + b0 * h0.x, acc_a.y + b0 * h0.y);
+                    acc_a1 = mk(acc_a1.x + b1 * h1.x, acc_a1.y + b1 * h1.y);
+                    acc_b = mk(acc_b.x + b0 * k0.x, acc_b.y + b0 * k0.y);
+                    acc_b1 = mk(acc_b1.x + b1 * k1.x, acc_b1.y + b1 * k1.y);
                 }
                 __syncthreads();
             }
@@ -374,10 +470,16 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
                 const cd ua = rdlane(u[0], 0), ub = at_last(u);
                 if (t == i) { ua_b = ua; ub_b = ub; }
             }
-            if (TR == TR_S02 && t > i) {
-                const double bt = sbeta[t - i];
-                acc_a = acc_a + bt * va;
-                acc_b = acc_b + bt * vb;
+            if (TR == TR_S02) {
+                if (t > i) {
+                    const double bt = sbeta[t - i];
+                    acc_a = acc_a + bt * va;
+                    acc_b = acc_b + bt * vb;
+                }
+                // this value's term for the next block (lag 64 + t - i)
+                const double bn = sbeta[kWave + t - i];
+                nxt_a = mk(fma(bn, va.x, nxt_a.x), fma(bn, va.y, nxt_a.y));
+                nxt_b = mk(fma(bn, vb.x, nxt_b.x), fma(bn, vb.y, nxt_b.y));
             }
             if (TR == TR_GEN) {
                 if (t > i) {
@@ -405,6 +507,9 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
                 trace_b[n0 + 1 + t] = ub_b;
             }
         }
+        // S0^2: the block's history values are stored; the helper's sums
+        // for the next block are in LDS
+        if (HELP) __syncthreads();
     }
 
     if (!last && stp) {

@@ -1,16 +1,18 @@
-// swr_sweep_static.hip -- instantiates the subdomain sweep for a time-independent potential.
+// swr_sweep_static.hip -- instantiates the subdomain sweep for a time-independent
+// potential with the Robin and higher-order transmissions (S0^2 is in
+// swr_sweep_static_s02.hip).
 #include "swr_sweep_kernel.h"
 
 namespace swr {
 
 template <int P>
 static void launch_p(const SweepArgs& a, int trans, hipStream_t st) {
-    if (trans == TR_S02) sweep_kernel<P, TR_S02, VK_STATIC><<<a.ntasks, 64, 0, st>>>(a);
-    else if (trans == TR_GEN) sweep_kernel<P, TR_GEN, VK_STATIC><<<a.ntasks, 64, 0, st>>>(a);
-    else sweep_kernel<P, TR_ROBIN, VK_STATIC><<<a.ntasks, 64, 0, st>>>(a);
+    if (trans == TR_GEN) sweep_kernel<P, TR_GEN, VK_STATIC><<<a.ntasks, sweep_threads(false), 0, st>>>(a);
+    else sweep_kernel<P, TR_ROBIN, VK_STATIC><<<a.ntasks, sweep_threads(false), 0, st>>>(a);
 }
 
 hipError_t launch_sweep_static(const SweepArgs& a, int trans, hipStream_t st) {
+    if (trans == TR_S02) return launch_sweep_static_s02(a, st);
     if (trans == TR_GEN && !a.endc) return hipErrorInvalidValue;
     switch (a.P) {
         case 1: launch_p<1>(a, trans, st); break;

@@ -5,8 +5,11 @@ namespace swr {
 
 template <int P>
 static void launch_p(const SweepArgs& a, int trans, hipStream_t st) {
-    if (trans == TR_S02) sweep_kernel<P, TR_S02, VK_TIME><<<a.ntasks, 64, 0, st>>>(a);
-    else sweep_kernel<P, TR_ROBIN, VK_TIME><<<a.ntasks, 64, 0, st>>>(a);
+    if (trans == TR_S02 && a.ntasks <= kHelpMaxTasks)
+        sweep_kernel<P, TR_S02, VK_TIME, true><<<a.ntasks, sweep_threads(true), 0, st>>>(a);
+    else if (trans == TR_S02)
+        sweep_kernel<P, TR_S02, VK_TIME, false><<<a.ntasks, sweep_threads(false), 0, st>>>(a);
+    else sweep_kernel<P, TR_ROBIN, VK_TIME><<<a.ntasks, sweep_threads(false), 0, st>>>(a);
 }
 
 hipError_t launch_sweep_time(const SweepArgs& a, int trans, hipStream_t st) {

@@ -9,8 +9,10 @@ The reference is the monodomain Crank-Nicolson solution (the plain definition
 the decomposed solvers converge to, Sec. 3), computed in extended precision
 (oracle.mono_ld): on this grid (dt/h^2 = 1e5, 420001 nodes) one FP64 sweep
 over the whole domain is itself off by ~1e-9, far more than the decomposed
-solution.  Each file holds u(T) at every STRIDE-th node plus the maximum of
-|u(T)| over all nodes (the scale of the relative comparison).
+solution.  Each file holds u(T) at every STRIDE-th node, the maximum of
+|u(T)| over all nodes (the scale of the relative comparison), and the error
+of the FP64 monodomain oracle (oracle.mono) against it over all nodes: the
+accuracy FP64 arithmetic of the plain definition reaches on this grid.
 """
 import os
 import sys
@@ -32,14 +34,17 @@ def fixture_path(kind):
 
 
 def read_fixture(kind):
-    """(node indices, u(T) there, max |u(T)| over all nodes)."""
-    scale = None
+    """(node indices, u(T) there, max |u(T)| over all nodes, relative error
+    of the FP64 monodomain oracle)."""
+    scale = err64 = None
     with open(fixture_path(kind)) as f:
         for line in f:
             if line.startswith("# max_abs_u"):
                 scale = float(line.split()[2])
+            if line.startswith("# fp64_monodomain_rel_err"):
+                err64 = float(line.split()[2])
     dat = np.loadtxt(fixture_path(kind))
-    return dat[:, 0].astype(np.int64), dat[:, 1] + 1j * dat[:, 2], scale
+    return dat[:, 0].astype(np.int64), dat[:, 1] + 1j * dat[:, 2], scale, err64
 
 
 def main(kinds):
@@ -47,6 +52,7 @@ def main(kinds):
         wl = W.paper_case(kind)
         t0 = time.time()
         uT = O.mono_ld(wl, wl.u0[0], nl_tol=1e-16, nl_maxit=200)
+        err64 = np.max(np.abs(O.mono(wl, wl.u0[0]) - uT)) / np.max(np.abs(uT))
         idx = np.arange(0, wl.nx, STRIDE)
         with open(fixture_path(kind), "w") as f:
             f.write(f"# u(T) of the paper's Sec. 6 workload '{kind}' (nx = {wl.nx}, nt = {wl.nt}, "
@@ -54,6 +60,7 @@ def main(kinds):
                     f"(oracle.mono_ld).\n")
             f.write("# written by tests/golden/make_paper_scale.py (oracle only)\n")
             f.write(f"# max_abs_u {np.max(np.abs(uT)):.17e}\n")
+            f.write(f"# fp64_monodomain_rel_err {err64:.6e}\n")
             f.write(f"# stride {STRIDE}\n")
             f.write("# columns: node re im\n")
             for i in idx:
