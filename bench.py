@@ -230,6 +230,53 @@ def paper_workloads(reps=3):
     return out
 
 
+def filled_roofline(reps=3):
+    """The sweep kernel where its launches fill the GPU: the batched-uneven
+    workload ((-100,100), 500 subdomains of U{40..400} cells, 32 problems,
+    2000 steps, S0^2; 16998 build tasks and 16000 final-sweep tasks per
+    solve).  Algorithmic flops per task: 34 per point-step plus the S0^2
+    history, 4 nt (nt + 1) per task; time: the library's HIP-event sum over
+    the sweep launches (median solve of reps after one warm-up)."""
+    import torch
+    from paper_1503_02564_amd import swr
+    from paper_1503_02564_amd import workloads as W
+    wl = W.batched_uneven()
+    dev = torch.device("cuda:0")
+    o = swr.swr_default_opts()
+    o.batch = wl.B
+    o.tol = wl.tol
+    V = torch.from_numpy(np.ascontiguousarray(wl.V)).to(dev)
+    pb = swr.Problem(wl.a0, wl.b0, tuple(int(j) for j in wl.J), wl.dt, wl.dt * wl.nt, wl.vkind,
+                     wl.trans, wl.sigma, o, V)
+    u0 = torch.from_numpy(np.ascontiguousarray(wl.u0)).to(dev)
+    uT = torch.zeros_like(u0)
+    swr.swr_solve(pb.ctx, u0, uT)
+    torch.cuda.synchronize()
+    infos, walls = [], []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        st, info = swr.swr_solve(pb.ctx, u0, uT)
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t0)
+        infos.append(info.as_dict())
+    pb.close()
+    i = int(np.argsort([x["t_sweep_ms"] for x in infos])[len(infos) // 2])
+    info = infos[i]
+    N, nt, B = wl.N, wl.nt, wl.B
+    flops = 0.0
+    for k in range(N):
+        ntask = int(k > 0) + int(k < N - 1) + 2 * B
+        flops += ntask * (34.0 * (int(wl.J[k]) + 1) * nt + 4.0 * nt * (nt + 1))
+    achieved = flops / (1e-3 * info["t_sweep_ms"]) / 1e12
+    return {"workload": "batched_uneven: (-100,100), 500 subdomains U{40..400} cells, 32 problems, "
+                        "2000 steps, S0^2, causal interface solve",
+            "bound": "alu", "kernel": "sweep_kernel", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+            "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+            "sweep_ms_per_solve": info["t_sweep_ms"], "launches_per_solve": info["n_sweep"],
+            "ms_per_solve": 1e3 * float(np.median(walls)),
+            "pt_steps_per_s": wl.pt_steps() / float(np.median(walls)), "status": st}
+
+
 def batched_vs_plain(batched_ms):
     """The same benchmark solve with every sweep task launched on its own
     (one subdomain of one problem per launch, one stream, staged), against
@@ -284,7 +331,7 @@ def main():
                     help="steps per pipeline chunk of the causal solve (0 = staged)")
     ap.add_argument("--workload", default="static_packet", choices=["static_packet"])
     ap.add_argument("--no-paper", dest="paper", action="store_false",
-                    help="skip the paper's Sec. 6 workloads at N = 1000")
+                    help="skip the paper's Sec. 6 workloads at N = 1000 and the filled-GPU roofline point")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint/forward ratio on the differentiation workload")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -362,6 +409,7 @@ def main():
         plain = batched_vs_plain(ms)
 
     paper = paper_workloads() if args.paper else None
+    filled = filled_roofline() if args.paper else None
 
     adj = None
     if not args.no_adjoint:
@@ -388,6 +436,7 @@ def main():
         "adjoint_forward_cost_ratio": None if adj is None else adj["ratio_bwd_over_fwd"],
         "adjoint": adj,
         "paper_workloads": paper,
+        "roofline_filled": filled,
         "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(out))
