@@ -47,16 +47,28 @@ __device__ inline d4 mfma16(double a, double b, d4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// With one 256-step target tile and a source range of at most 256 steps (the
+// causal solve's history products), the workgroup first stages the sources
+// and the coefficient window they meet (at most 511 lags) in LDS with
+// coalesced loads by all four waves, so the lag-block loop reads its operands
+// from LDS instead of waiting on memory every block; the MFMA sequence, and so
+// every result bit, is the same either way.
+constexpr int kLttStage = 256;
+
 __global__ __launch_bounds__(256) void ltt_mfma_kernel(LttArgs a) {
+    __shared__ cd st_x[2][kLttStage], st_c[2][2 * kLttStage];
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const int tile = blockIdx.x * 4 + w;
     const int o = blockIdx.y;
     const int b = a.s_seg > 0 ? blockIdx.z % a.B : blockIdx.z;
     const int seg = a.s_seg > 0 ? blockIdx.z / a.B : 0;
     const int nlen = a.n_hi - a.n_lo;
-    if (tile * 256 >= nlen) return;                 // whole wave leaves together
-    const int s_lo = a.s_seg > 0 ? a.s_lo + seg * a.s_seg : a.s_lo;
-    const int s_hi = a.s_seg > 0 ? min(a.s_hi, s_lo + a.s_seg) : a.s_hi;
+    const int s_lo0 = a.s_seg > 0 ? a.s_lo + seg * a.s_seg : a.s_lo;
+    const int s_hi0 = a.s_seg > 0 ? min(a.s_hi, s_lo0 + a.s_seg) : a.s_hi;
+    const bool staged = nlen <= kLttStage && s_hi0 - s_lo0 <= kLttStage;   // uniform per workgroup
+    if (!staged && tile * 256 >= nlen) return;       // whole wave leaves together
+    const int s_lo = s_lo0;
+    const int s_hi = s_hi0;
     int k, pl, pr, sl, sr;
     slot_sources(o, a.N, k, pl, pr, sl, sr);
     const int v = a.per_problem ? b : 0;
@@ -64,6 +76,29 @@ __global__ __launch_bounds__(256) void ltt_mfma_kernel(LttArgs a) {
     const cd* cr = a.cols + ((size_t)(v * a.N + k) * 4 + pr) * a.nt;
     const cd* xl = sl >= 0 ? a.x + ((size_t)b * a.ns + sl) * a.nt + s_lo : nullptr;
     const cd* xr = sr >= 0 ? a.x + ((size_t)b * a.ns + sr) * a.nt + s_lo : nullptr;
+    // staged form: sources s_lo + [0, slen) and lags lag0 + [0, nlen + slen - 1)
+    const int lag0 = a.n_lo - s_hi + 1;
+    if (staged) {
+        const int slen0 = s_hi - s_lo, nlag = nlen + slen0 - 1;
+        for (int e = threadIdx.x; e < kLttStage; e += blockDim.x) {
+            cd x0 = mk(0, 0), x1 = mk(0, 0);
+            if (xl && e < slen0) x0 = xl[e];
+            if (xr && e < slen0) x1 = xr[e];
+            st_x[0][e] = x0;
+            st_x[1][e] = x1;
+        }
+        for (int e = threadIdx.x; e < 2 * kLttStage; e += blockDim.x) {
+            const int lag = lag0 + e;
+            const bool ok = e < nlag && lag >= 0 && lag < a.nt;
+            cd c0 = mk(0, 0), c1 = mk(0, 0);
+            if (xl && ok) c0 = cl[lag];
+            if (xr && ok) c1 = cr[lag];
+            st_c[0][e] = c0;
+            st_c[1][e] = c1;
+        }
+        __syncthreads();
+        if (tile * 256 >= nlen) return;
+    }
     const int r = lane & 15, kq = lane >> 4;
     const int I0 = tile * 16;
     const int slen = s_hi - s_lo;
@@ -75,32 +110,48 @@ __global__ __launch_bounds__(256) void ltt_mfma_kernel(LttArgs a) {
     const int m_lo = max(I0 - (Jn - 1), m_lag);
     const int m_hi = slen > 0 ? I0 + 15 : m_lo - 1;
     d4 yr = {0, 0, 0, 0}, yi = {0, 0, 0, 0};
-    for (int m = m_lo; m <= m_hi; ++m) {
-        const int J = I0 + r - m;                   // source block of B column r
+    // one lag-block loop, with the operands taken from LDS (staged) or from
+    // memory; the MFMA sequence is the same
+    auto blocks = [&](auto opA, auto opB) {
+        for (int m = m_lo; m <= m_hi; ++m) {
+            const int J = I0 + r - m;               // source block of B column r
 #pragma unroll
-        for (int kc = 0; kc < 4; ++kc) {
-            const int kk = 4 * kc + kq;
-            const int lag = delta + 16 * m + r - kk;
-            const int si = 16 * J + kk;
-            const bool lok = lag >= 0 && lag < a.nt;
-            const bool sok = J >= 0 && si < slen;
-            if (xl) {
-                const cd av = lok ? cl[lag] : mk(0, 0);
-                const cd bv = sok ? xl[si] : mk(0, 0);
-                yr = mfma16(av.x, bv.x, yr);
-                yr = mfma16(-av.y, bv.y, yr);
-                yi = mfma16(av.x, bv.y, yi);
-                yi = mfma16(av.y, bv.x, yi);
-            }
-            if (xr) {
-                const cd av = lok ? cr[lag] : mk(0, 0);
-                const cd bv = sok ? xr[si] : mk(0, 0);
-                yr = mfma16(av.x, bv.x, yr);
-                yr = mfma16(-av.y, bv.y, yr);
-                yi = mfma16(av.x, bv.y, yi);
-                yi = mfma16(av.y, bv.x, yi);
+            for (int kc = 0; kc < 4; ++kc) {
+                const int kk = 4 * kc + kq;
+                const int lag = delta + 16 * m + r - kk;
+                const int si = 16 * J + kk;
+                const bool sok = J >= 0 && si < slen;
+#pragma unroll
+                for (int side = 0; side < 2; ++side) {
+                    if (side == 0 ? !xl : !xr) continue;
+                    const cd av = opA(side, lag);
+                    cd bv = mk(0, 0);
+                    if (sok) bv = opB(side, si);
+                    yr = mfma16(av.x, bv.x, yr);
+                    yr = mfma16(-av.y, bv.y, yr);
+                    yi = mfma16(av.x, bv.y, yi);
+                    yi = mfma16(av.y, bv.x, yi);
+                }
             }
         }
+    };
+    if (staged) {
+        // a lag outside the window pairs only with sources outside [0, slen)
+        // or outputs past nlen, i.e. with a zero operand or a dropped result
+        blocks([&](int side, int lag) {
+                   const int le = lag - lag0;
+                   cd c = mk(0, 0);
+                   if (le >= 0 && le < 2 * kLttStage) c = st_c[side][le];
+                   return c;
+               },
+               [&](int side, int si) { return st_x[side][si]; });
+    } else {
+        blocks([&](int side, int lag) {
+                   cd c = mk(0, 0);
+                   if (lag >= 0 && lag < a.nt) c = (side ? cr : cl)[lag];
+                   return c;
+               },
+               [&](int side, int si) { return (side ? xr : xl)[si]; });
     }
     const size_t yb = ((size_t)b * a.ns + o) * a.y_ld + (size_t)seg * a.y_seg_stride;
     const cd* base = a.s_seg > 0 ? nullptr : a.base;
