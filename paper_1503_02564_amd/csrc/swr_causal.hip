@@ -131,11 +131,18 @@ struct FarArgs {
 };
 
 // one workgroup per (slot, problem); thread (i, split): output step n0+i,
-// inputs s in the split's share of [0, n0).  out = d + that contribution.
+// inputs s in the split's share of [s_from, n0).  out = d + that
+// contribution.  The two source rows over [s_from, n0) and the coefficient
+// window they meet (lags 1 .. n0 + TB - s_from) are first staged in LDS with
+// coalesced loads by the whole workgroup (the range is less than one 256-step
+// super-block), so the sums read no memory; each thread's order of terms is
+// the same as reading them from memory.
 template <int TB>
 __global__ __launch_bounds__(256) void causal_far_kernel(FarArgs f) {
     constexpr int SPLITS = 256 / TB;
+    constexpr int kWin = kCausalSuper + TB;
     __shared__ cd part[SPLITS][TB];
+    __shared__ cd sg[2][kCausalSuper], sc[2][kWin];
     const int o = blockIdx.x, b = blockIdx.y;
     const int i = threadIdx.x % TB, sp = threadIdx.x / TB;
     int k, pl, pr, sl, sr;
@@ -145,19 +152,39 @@ __global__ __launch_bounds__(256) void causal_far_kernel(FarArgs f) {
     const cd* cr = f.cols + ((size_t)(v * f.N + k) * 4 + pr) * f.nt;
     const cd* gl = sl >= 0 ? f.g + ((size_t)b * f.ns + sl) * f.nt : nullptr;
     const cd* gr = sr >= 0 ? f.g + ((size_t)b * f.ns + sr) * f.nt : nullptr;
+    const int len = f.n0 - f.s_from;                 // < kCausalSuper
+    // lags n - s for n in [n0, n0 + TB), s in [s_from, n0): 1 .. len + TB - 1
+    for (int e = threadIdx.x; e < len; e += blockDim.x) {
+        cd x0 = mk(0, 0), x1 = mk(0, 0);
+        if (gl) x0 = gl[f.s_from + e];
+        if (gr) x1 = gr[f.s_from + e];
+        sg[0][e] = x0;
+        sg[1][e] = x1;
+    }
+    for (int e = threadIdx.x; e < len + TB; e += blockDim.x) {
+        cd c0 = mk(0, 0), c1 = mk(0, 0);
+        if (e < f.nt) {
+            if (gl) c0 = cl[e];
+            if (gr) c1 = cr[e];
+        }
+        sc[0][e] = c0;
+        sc[1][e] = c1;
+    }
+    __syncthreads();
     const int n = f.n0 + i;
-    const int per = (f.n0 - f.s_from + SPLITS - 1) / SPLITS;
+    const int per = (len + SPLITS - 1) / SPLITS;
     const int s_lo = f.s_from + sp * per, s_hi = min(f.n0, s_lo + per);
     double ax = 0, ay = 0;
     if (i < f.nb) {
         for (int s = s_lo; s < s_hi; ++s) {
+            const int e = s - f.s_from, lag = n - s;
             if (gl) {
-                const cd c = cl[n - s], x = gl[s];
+                const cd c = sc[0][lag], x = sg[0][e];
                 ax += c.x * x.x - c.y * x.y;
                 ay += c.x * x.y + c.y * x.x;
             }
             if (gr) {
-                const cd c = cr[n - s], x = gr[s];
+                const cd c = sc[1][lag], x = sg[1][e];
                 ax += c.x * x.x - c.y * x.y;
                 ay += c.x * x.y + c.y * x.x;
             }
@@ -338,6 +365,8 @@ template <int TB>
 static hipError_t launch_causal_far(int N, int nt, int ns, int B, int per_problem, int n0, int nb,
                                     const cd* cols, const cd* d, const cd* g, cd* out,
                                     const cd* facc, int s_from, hipStream_t st) {
+    // the staged rows hold less than one super-block of sources
+    if (n0 - s_from < 0 || n0 - s_from >= kCausalSuper) return hipErrorInvalidValue;
     FarArgs f{N, nt, ns, per_problem, n0, nb, cols, d, g, out, facc,
               facc ? s_from / kCausalSuper : 0, s_from};
     causal_far_kernel<TB><<<dim3(ns, B), 256, 0, st>>>(f);
