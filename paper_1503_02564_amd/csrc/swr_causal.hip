@@ -292,23 +292,16 @@ __global__ __launch_bounds__(kNearThreads) void causal_near_kernel(NearArgs a) {
     }
     cd x0 = zero, x1 = zero, y0 = zero, y1 = zero;   // solutions of steps i-1 and i-2
     __syncthreads();
+    // lag-1 and lag-2 part of the next step's right-hand side, formed from
+    // the solver's own registers before the step's barrier
+    cd h0 = zero, h1 = zero;
 
     for (int i = 0; i < nb; ++i) {
         if (tid < kWave) {
-            // right-hand side: base + lags >= 3 (gathered) + lags 1, 2 (here);
+            // right-hand side: base + lags >= 3 (gathered) + lags 1, 2 (h);
             // lags reaching before the block are in base
             cd p0 = zero, p1 = zero;
-            if (j < ni) { p0 = gn[i % 3][2 * j]; p1 = gn[i % 3][2 * j + 1]; }
-            const cd x0p = lane_dn1(x0), x1m = lane_up1(x1);
-            const cd y0p = lane_dn1(y0), y1m = lane_up1(y1);
-            if (i >= 1) {
-                p0 = madd(madd(p0, a0[0], x1), a1[0], x0p);
-                p1 = madd(madd(p1, a2[0], x1m), a3[0], x0);
-            }
-            if (i >= 2) {
-                p0 = madd(madd(p0, a0[1], y1), a1[1], y0p);
-                p1 = madd(madd(p1, a2[1], y1m), a3[1], y0);
-            }
+            if (j < ni) { p0 = gn[i % 3][2 * j] + h0; p1 = gn[i % 3][2 * j + 1] + h1; }
 #pragma unroll
             for (int l = 0; l < kPcrLevels; ++l) {
                 if (l >= lev) break;                    // uniform over the workgroup
@@ -333,6 +326,15 @@ __global__ __launch_bounds__(kNearThreads) void causal_near_kernel(NearArgs a) {
                 gh[i][2 * j + 1] = x1;
                 gb[(size_t)(2 * j) * nt + n0 + i] = x0;
                 gb[(size_t)(2 * j + 1) * nt + n0 + i] = x1;
+            }
+            // lags 1 (this step) and 2 (the step before) for step i+1
+            const cd x0p = lane_dn1(x0), x1m = lane_up1(x1);
+            const cd y0p = lane_dn1(y0), y1m = lane_up1(y1);
+            h0 = madd(a1[0] * x0p, a0[0], x1);
+            h1 = madd(a3[0] * x0, a2[0], x1m);
+            if (i >= 1) {
+                h0 = madd(madd(h0, a0[1], y1), a1[1], y0p);
+                h1 = madd(madd(h1, a2[1], y1m), a3[1], y0);
             }
         } else if (i + 2 < nb) {
             // lags >= 3 of step i+2, from in-block steps up to i-1
