@@ -42,8 +42,12 @@ __device__ inline void far_history(const cd* Ha, const cd* Hb, const double* bet
     for (int q0 = 0; q0 <= n0; q0 += kWave) {
         const int qn = min(kWave, n0 + 1 - q0);
         const int bbase = n0 - q0 - (kWave - 2);
-        sha[t] = (t < qn) ? Ha[q0 + t] : zero;
-        shb[t] = (t < qn) ? Hb[q0 + t] : zero;
+        // (assignments, not a conditional of two lvalues: that would put
+        // the zero constant in scratch memory)
+        cd hta = zero, htb = zero;
+        if (t < qn) { hta = Ha[q0 + t]; htb = Hb[q0 + t]; }
+        sha[t] = hta;
+        shb[t] = htb;
         const int i0 = bbase + t, i1 = bbase + kWave + t;
         sb[t] = (i0 >= 0) ? beta[i0] : 0.0;
         sb[kWave + t] = (i1 >= 0) ? beta[i1] : 0.0;

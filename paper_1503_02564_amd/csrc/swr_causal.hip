@@ -212,26 +212,52 @@ struct NearArgs {
     cd* g;             // [B][ns][nt]
 };
 
-constexpr int kNearClasses = 2;                            // gather threads per slot
-constexpr int kNearLags = (kTb + kNearClasses - 1) / kNearClasses;   // lags per thread
-constexpr int kNearThreads = kWave + kNearClasses * kNearSlots;
+constexpr int kNearClasses = 4;                            // gather threads per subdomain
+constexpr int kNearLags = kTb / kNearClasses;              // lags per thread: c+3, c+3+C, ...
+constexpr int kNearGroup = 4;                              // lags whose loads are issued together
+// gather threads: kNearClasses per subdomain, N <= kWave + 1 subdomains
+constexpr int kNearGather = (kNearClasses * (kWave + 1) + kWave - 1) / kWave * kWave;
+constexpr int kNearThreads = kWave + kNearGather;
+constexpr int kNearCols = kNearSlots + 2;                  // slot q in column q + 1; 0 and ns + 1 stay zero
+static_assert(kTb % (kNearClasses * kNearGroup) == 0, "near block: whole lag groups");
 
 // neighbour values for the lag-1/lag-2 history: lane j - 1 / j + 1 (zero outside)
 __device__ inline cd lane_up1(cd v) { return shfl_up_c(v, 1, mk(0, 0)); }
 __device__ inline cd lane_dn1(cd v) { return shfl_dn_c(v, 1, mk(0, 0)); }
+
+// sum over the four lanes of a quad (DPP quad permutations); every lane of
+// the quad gets the same bits
+template <int CTRL>
+__device__ inline double quad_move(double v) {
+    int2 t = *reinterpret_cast<int2*>(&v);
+    t.x = __builtin_amdgcn_update_dpp(0, t.x, CTRL, 0xf, 0xf, false);
+    t.y = __builtin_amdgcn_update_dpp(0, t.y, CTRL, 0xf, 0xf, false);
+    return *reinterpret_cast<double*>(&t);
+}
+__device__ inline cd quad_sum(cd v) {
+    v = mk(v.x + quad_move<0xB1>(v.x), v.y + quad_move<0xB1>(v.y));   // lanes (1,0,3,2)
+    return mk(v.x + quad_move<0x4E>(v.x), v.y + quad_move<0x4E>(v.y)); // lanes (2,3,0,1)
+}
 
 // One workgroup per problem.  Wave 0 solves the per-step block system; lane
 // j owns interface j, i.e. slots 2j (r_j) and 2j+1 (l_{j+1}), and adds the
 // lag-1 and lag-2 history itself from the solutions of the two previous
 // steps it keeps in registers (slot 2j reads x1 of lane j and x0 of lane j+1
 // through X^{j+1,1}, X^{j+1,2}; slot 2j+1 reads x1 of lane j-1 and x0 of lane
-// j through X^{j,3}, X^{j,4}).  The other waves (kNearClasses threads per
-// slot) gather lags >= 3 of the step two ahead from the block's g kept in LDS
-// into a triple buffer, so a step costs one barrier and the solver never
-// waits for LDS written in the same step.
+// j through X^{j,3}, X^{j,4}).  The other waves gather lags >= 3 of the step
+// two ahead from the block's g kept in LDS, so a step costs one barrier and
+// the solver never waits for LDS written in the same step.  They work per
+// subdomain k: its two outgoing traces (slots 2k-1, 2k) enter exactly the
+// slots 2k-2 (through X^{k,1}, X^{k,2}) and 2k+1 (through X^{k,3}, X^{k,4}),
+// so each pair of LDS values read serves two slots; kNearClasses threads
+// split the lags of one subdomain and sum through DPP.  Lags are taken in
+// groups whose LDS loads are issued together: a source before the block or
+// outside the interface range reads the zero row / zero columns of `gh`,
+// which adds exact zeros.  Row s + 1 of `gh` holds, in turn, the base of step
+// s (staged at the start), its full right-hand side (written by the gather
+// two steps before) and its solution (written by the solver at step s).
 __global__ __launch_bounds__(kNearThreads) void causal_near_kernel(NearArgs a) {
-    __shared__ cd gh[kTb][kNearSlots + 1];     // rows padded: no bank conflict between lag classes
-    __shared__ cd gn[3][kNearSlots];
+    __shared__ cd gh[kTb + 1][kNearCols];
     __shared__ cd spcr[kPcrLevels * 8 + 4][kWave];
     const int b = blockIdx.x, v = a.per_problem ? b : 0;
     const int tid = threadIdx.x;
@@ -242,37 +268,80 @@ __global__ __launch_bounds__(kNearThreads) void causal_near_kernel(NearArgs a) {
     const cd* bb = a.base + (size_t)b * ns * kTb;
     const cd* cbase = a.cols + (size_t)v * a.N * 4 * nt;
 
-    // multipliers of the levels run and the matching inverse diagonal -> LDS
+    // multipliers of the levels run and the matching inverse diagonal -> LDS;
+    // base (d + far part) of every step of the block -> its row of gh.  All
+    // loads of a loop are issued before its stores.
     const int lev = a.levels;
     const cd* prec = a.pcr + (size_t)v * kPcrRec * kWave;
-    for (int e = tid; e < lev * 8 * kWave; e += blockDim.x) (&spcr[0][0])[e] = prec[e];
-    for (int e = tid; e < 4 * kWave; e += blockDim.x)
-        (&spcr[kPcrLevels * 8][0])[e] = prec[(size_t)(kPcrLevels * 8 + 4 * lev) * kWave + e];
-
-    // gather role: slot o, lag class c (lags c+3, c+3+C, c+3+2C, ...)
-    const int gt = tid - kWave;
-    const int o = gt / kNearClasses, c = gt % kNearClasses;
-    const bool gather = tid >= kWave && o < ns;
-    int sl = -1, sr = -1;
-    cd cl[kNearLags], cr[kNearLags];
+    {
+        constexpr int kIt = (kPcrLevels * 8 * kWave + kNearThreads - 1) / kNearThreads;
+        const int lim = lev * 8 * kWave;
+        cd t[kIt];
 #pragma unroll
-    for (int m = 0; m < kNearLags; ++m) { cl[m] = zero; cr[m] = zero; }
-    if (gather) {
-        int k, pl, pr;
-        slot_src(o, a.N, k, pl, pr, sl, sr);
-        const cd* base = cbase + (size_t)k * 4 * nt;
+        for (int u = 0; u < kIt; ++u) {
+            const int e = tid + u * kNearThreads;
+            t[u] = zero;
+            if (e < lim) t[u] = prec[e];
+        }
+        cd di = zero;
+        if (tid < 4 * kWave) di = prec[(size_t)(kPcrLevels * 8 + 4 * lev) * kWave + tid];
+#pragma unroll
+        for (int u = 0; u < kIt; ++u) {
+            const int e = tid + u * kNearThreads;
+            if (e < lim) (&spcr[0][0])[e] = t[u];
+        }
+        if (tid < 4 * kWave) (&spcr[kPcrLevels * 8][0])[tid] = di;
+    }
+    {
+        constexpr int kIt = (kNearSlots * kTb + kNearThreads - 1) / kNearThreads;
+        const int lim = ns * nb;
+        cd t[kIt];
+#pragma unroll
+        for (int u = 0; u < kIt; ++u) {
+            const int e = tid + u * kNearThreads;
+            const int q = e / nb, s = e - q * nb;
+            t[u] = zero;
+            if (e < lim) t[u] = bb[(size_t)q * kTb + s];
+        }
+#pragma unroll
+        for (int u = 0; u < kIt; ++u) {
+            const int e = tid + u * kNearThreads;
+            const int q = e / nb, s = e - q * nb;
+            if (e < lim) gh[s + 1][q + 1] = t[u];
+        }
+    }
+    // zero row (steps before the block) and zero columns (no such slot)
+    for (int e = tid; e < kNearCols; e += kNearThreads) gh[0][e] = zero;
+    for (int e = tid; e < kTb; e += kNearThreads) {
+        gh[e + 1][0] = zero;
+        gh[e + 1][ns + 1] = zero;
+    }
+
+    // gather role: subdomain k, lag class c (lags c+3, c+3+C, c+3+2C, ...).
+    // wa*: slot 2k-2 from slots 2k-1, 2k; wb*: slot 2k+1 from the same pair.
+    const int gt = tid - kWave;
+    const int k = gt / kNearClasses, c = gt % kNearClasses;
+    const bool gather = tid >= kWave && k < a.N;
+    const bool has_a = gather && k >= 1, has_b = gather && k <= a.N - 2;
+    const int kk = gather ? k : 0;
+    cd wa0[kNearLags], wa1[kNearLags], wb0[kNearLags], wb1[kNearLags];
+#pragma unroll
+    for (int m = 0; m < kNearLags; ++m) { wa0[m] = zero; wa1[m] = zero; wb0[m] = zero; wb1[m] = zero; }
+    {
+        const cd* cb = cbase + (size_t)kk * 4 * nt;
 #pragma unroll
         for (int m = 0; m < kNearLags; ++m) {
             const int lag = c + 3 + kNearClasses * m;
             if (lag < nt && lag < kTb) {
-                if (sl >= 0) cl[m] = base[(size_t)pl * nt + lag];
-                if (sr >= 0) cr[m] = base[(size_t)pr * nt + lag];
+                if (has_a) {
+                    wa0[m] = cb[lag];
+                    if (k <= a.N - 2) wa1[m] = cb[(size_t)nt + lag];
+                }
+                if (has_b) {
+                    if (k >= 1) wb0[m] = cb[(size_t)2 * nt + lag];
+                    wb1[m] = cb[(size_t)3 * nt + lag];
+                }
             }
-        }
-        // steps 0 and 1 of the block have no in-block history of lag >= 3
-        if (c == 0) {
-            gn[0][o] = bb[(size_t)o * kTb + 0];
-            if (nb > 1) gn[1][o] = bb[(size_t)o * kTb + 1];
         }
     }
     // solver role: lag-1 and lag-2 coefficients of my two slots
@@ -292,16 +361,20 @@ __global__ __launch_bounds__(kNearThreads) void causal_near_kernel(NearArgs a) {
     }
     cd x0 = zero, x1 = zero, y0 = zero, y1 = zero;   // solutions of steps i-1 and i-2
     __syncthreads();
+    // every load of the set-up has landed: the step loop then waits on no
+    // memory counter, so its stores never hold a step
+    __builtin_amdgcn_s_waitcnt(0);
     // lag-1 and lag-2 part of the next step's right-hand side, formed from
     // the solver's own registers before the step's barrier
     cd h0 = zero, h1 = zero;
 
     for (int i = 0; i < nb; ++i) {
         if (tid < kWave) {
-            // right-hand side: base + lags >= 3 (gathered) + lags 1, 2 (h);
-            // lags reaching before the block are in base
+            // right-hand side: base + lags >= 3 (gathered; steps 0 and 1 have
+            // none in the block) + lags 1, 2 (h); lags reaching before the
+            // block are in base
             cd p0 = zero, p1 = zero;
-            if (j < ni) { p0 = gn[i % 3][2 * j] + h0; p1 = gn[i % 3][2 * j + 1] + h1; }
+            if (j < ni) { p0 = gh[i + 1][2 * j + 1] + h0; p1 = gh[i + 1][2 * j + 2] + h1; }
 #pragma unroll
             for (int l = 0; l < kPcrLevels; ++l) {
                 if (l >= lev) break;                    // uniform over the workgroup
@@ -322,8 +395,8 @@ __global__ __launch_bounds__(kNearThreads) void causal_near_kernel(NearArgs a) {
             x1 = madd(Di[2 * kWave] * p0, Di[3 * kWave], p1);
             if (j >= ni) { x0 = zero; x1 = zero; }
             if (j < ni) {
-                gh[i][2 * j] = x0;
-                gh[i][2 * j + 1] = x1;
+                gh[i + 1][2 * j + 1] = x0;
+                gh[i + 1][2 * j + 2] = x1;
                 gb[(size_t)(2 * j) * nt + n0 + i] = x0;
                 gb[(size_t)(2 * j + 1) * nt + n0 + i] = x1;
             }
@@ -337,21 +410,31 @@ __global__ __launch_bounds__(kNearThreads) void causal_near_kernel(NearArgs a) {
                 h1 = madd(madd(h1, a2[1], y1m), a3[1], y0);
             }
         } else if (i + 2 < nb) {
-            // lags >= 3 of step i+2, from in-block steps up to i-1
-            cd part = zero;
+            // lags >= 3 of step i+2, from in-block steps up to i-1: lag
+            // c+3+C*m reads row i - c - C*m (step i+2-lag), row 0 if earlier
+            cd pa = zero, pb = zero;
 #pragma unroll
-            for (int m = 0; m < kNearLags; ++m) {
-                const int lag = c + 3 + kNearClasses * m;
-                if (lag <= i + 2) {
-                    const int s = i + 2 - lag;
-                    if (sl >= 0) part = madd(part, cl[m], gh[s][sl]);
-                    if (sr >= 0) part = madd(part, cr[m], gh[s][sr]);
+            for (int g0 = 0; g0 < kNearLags; g0 += kNearGroup) {
+                // first lag of the group: 3 + C*g0 <= i + 2 for some class
+                if (i >= 1 + kNearClasses * g0) {
+                    cd xl[kNearGroup], xr[kNearGroup];
+#pragma unroll
+                    for (int u = 0; u < kNearGroup; ++u) {
+                        const int r = max(i - c - kNearClasses * (g0 + u), 0);
+                        xl[u] = gh[r][2 * kk];
+                        xr[u] = gh[r][2 * kk + 1];
+                    }
+#pragma unroll
+                    for (int u = 0; u < kNearGroup; ++u) {
+                        pa = madd(madd(pa, wa0[g0 + u], xl[u]), wa1[g0 + u], xr[u]);
+                        pb = madd(madd(pb, wb0[g0 + u], xl[u]), wb1[g0 + u], xr[u]);
+                    }
                 }
             }
-#pragma unroll
-            for (int x = 1; x < kNearClasses; x <<= 1)
-                part = mk(part.x + __shfl_xor(part.x, x), part.y + __shfl_xor(part.y, x));
-            if (gather && c == 0) gn[(i + 2) % 3][o] = part + bb[(size_t)o * kTb + i + 2];
+            pa = quad_sum(pa);
+            pb = quad_sum(pb);
+            if (c == 0 && has_a) gh[i + 3][2 * k - 1] = gh[i + 3][2 * k - 1] + pa;   // slot 2k-2
+            if (c == 1 && has_b) gh[i + 3][2 * k + 2] = gh[i + 3][2 * k + 2] + pb;   // slot 2k+1
         }
         __syncthreads();
     }
@@ -551,18 +634,36 @@ __global__ __launch_bounds__(THREADS) void causal_near_gen_kernel(NearGenArgs a)
 #pragma unroll
     for (int q = 0; q < 8; ++q) Kc[q] = zero;
     if (lev > 0) loadK(0, Kc);
-    cd bn0 = act ? bb[(size_t)(2 * j) * TB] : zero;
-    cd bn1 = act ? bb[(size_t)(2 * j + 1) * TB] : zero;
+    // base of my two slots for every step of the block -> their entries of
+    // gh (only this thread reads them before its step overwrites them with
+    // the solution); the step loop touches no global memory
+    if (act) {
+        cd t0[TB], t1[TB];
+#pragma unroll
+        for (int i = 0; i < TB; ++i) {
+            t0[i] = zero;
+            t1[i] = zero;
+            if (i < nb) {
+                t0[i] = bb[(size_t)(2 * j) * TB + i];
+                t1[i] = bb[(size_t)(2 * j + 1) * TB + i];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < TB; ++i) {
+            if (i < nb) {
+                gh[(size_t)i * ns + 2 * j] = t0[i];
+                gh[(size_t)i * ns + 2 * j + 1] = t1[i];
+            }
+        }
+    }
 
 #pragma unroll
     for (int i = 0; i < TB; ++i) {
         if (i < nb) {
-            cd p0 = bn0, p1 = bn1;
-            if (act && i + 1 < nb) {
-                bn0 = bb[(size_t)(2 * j) * TB + i + 1];
-                bn1 = bb[(size_t)(2 * j + 1) * TB + i + 1];
-            }
+            cd p0 = zero, p1 = zero;
             if (act) {
+                p0 = gh[(size_t)i * ns + 2 * j];
+                p1 = gh[(size_t)i * ns + 2 * j + 1];
 #pragma unroll
                 for (int m = 0; m < TB - 1; ++m) {
                     const int lag = m + 1;
@@ -598,10 +699,19 @@ __global__ __launch_bounds__(THREADS) void causal_near_gen_kernel(NearGenArgs a)
                 const cd x1 = madd(di2 * p0, di3, p1);
                 gh[(size_t)i * ns + 2 * j] = x0;
                 gh[(size_t)i * ns + 2 * j + 1] = x1;
-                gb[(size_t)(2 * j) * nt + n0 + i] = x0;
-                gb[(size_t)(2 * j + 1) * nt + n0 + i] = x1;
             }
             __syncthreads();
+        }
+    }
+    // my two slots' solutions of the block -> memory (kept out of the step
+    // loop: its multiplier loads would otherwise wait for these stores)
+    if (act) {
+#pragma unroll
+        for (int i = 0; i < TB; ++i) {
+            if (i < nb) {
+                gb[(size_t)(2 * j) * nt + n0 + i] = gh[(size_t)i * ns + 2 * j];
+                gb[(size_t)(2 * j + 1) * nt + n0 + i] = gh[(size_t)i * ns + 2 * j + 1];
+            }
         }
     }
 }

@@ -133,7 +133,8 @@ __global__ __launch_bounds__(sweep_threads(HELP)) void sweep_kernel(SweepArgs a)
     if (first) {
 #pragma unroll
         for (int q = 0; q < P; ++q) {
-            u[q] = (data && s + q < n) ? u0[s + q] : zero;
+            u[q] = zero;
+            if (data && s + q < n) u[q] = u0[s + q];
             vlast[q] = u[q];
         }
     } else {
@@ -248,8 +249,12 @@ __global__ __launch_bounds__(sweep_threads(HELP)) void sweep_kernel(SweepArgs a)
                 for (int q0 = 0; q0 <= qmax; q0 += kWave) {
                     const int qn = min(kWave, qmax + 1 - q0);
                     const int bbase = n0 - q0 - (kWave - 2);   // beta index of sb[0]
-                    sha[t] = (t < qn) ? Ha[q0 + t] : zero;
-                    shb[t] = (t < qn) ? Hb[q0 + t] : zero;
+                    // (assignments, not a conditional of two lvalues: that
+                    // would put the zero constant in scratch memory)
+                    cd hta = zero, htb = zero;
+                    if (t < qn) { hta = Ha[q0 + t]; htb = Hb[q0 + t]; }
+                    sha[t] = hta;
+                    shb[t] = htb;
                     sb[t] = (bbase + t >= 0) ? a.beta[bbase + t] : 0.0;
                     sb[kWave + t] = (bbase + kWave + t >= 0) ? a.beta[bbase + kWave + t] : 0.0;
                     __syncthreads();
