@@ -30,7 +30,9 @@ namespace swr {
 
 
 // far part of the S0^2 history for outputs n0+1+lane:
-// sum_{q <= n0} beta_{n0+1+lane-q} H[q] (both ends), staged through LDS
+// sum_{q <= n0} beta_{n0+1+lane-q} H[q] (both ends), staged through LDS in
+// chunks of 64; the loads of the next chunk are issued before the current
+// one is summed
 __device__ inline void far_history(const cd* Ha, const cd* Hb, const double* beta, int n0,
                                    cd* sha, cd* shb, double* sb, cd& acc_a, cd& acc_b) {
     const int t = lane_id();
@@ -39,18 +41,30 @@ __device__ inline void far_history(const cd* Ha, const cd* Hb, const double* bet
     acc_b = zero;
     __threadfence_block();
     const int nj = n0 + 1 + t;
-    for (int q0 = 0; q0 <= n0; q0 += kWave) {
+    cd pa = zero, pb = zero;
+    double p0 = 0.0, p1 = 0.0;
+    auto fetch = [&](int q0) {
         const int qn = min(kWave, n0 + 1 - q0);
         const int bbase = n0 - q0 - (kWave - 2);
         // (assignments, not a conditional of two lvalues: that would put
         // the zero constant in scratch memory)
-        cd hta = zero, htb = zero;
-        if (t < qn) { hta = Ha[q0 + t]; htb = Hb[q0 + t]; }
-        sha[t] = hta;
-        shb[t] = htb;
+        pa = zero;
+        pb = zero;
+        if (t < qn) { pa = Ha[q0 + t]; pb = Hb[q0 + t]; }
         const int i0 = bbase + t, i1 = bbase + kWave + t;
-        sb[t] = (i0 >= 0) ? beta[i0] : 0.0;
-        sb[kWave + t] = (i1 >= 0) ? beta[i1] : 0.0;
+        p0 = 0.0;
+        p1 = 0.0;
+        if (i0 >= 0) p0 = beta[i0];
+        if (i1 >= 0) p1 = beta[i1];
+    };
+    if (n0 >= 0) fetch(0);
+    for (int q0 = 0; q0 <= n0; q0 += kWave) {
+        const int bbase = n0 - q0 - (kWave - 2);
+        sha[t] = pa;
+        shb[t] = pb;
+        sb[t] = p0;
+        sb[kWave + t] = p1;
+        if (q0 + kWave <= n0) fetch(q0 + kWave);
         __syncthreads();
         const double* bw = sb + (nj - q0 - bbase);
         // all 64 entries: the staged chunk is zero past qn and the beta

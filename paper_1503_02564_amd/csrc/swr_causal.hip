@@ -268,55 +268,6 @@ __global__ __launch_bounds__(kNearThreads) void causal_near_kernel(NearArgs a) {
     const cd* bb = a.base + (size_t)b * ns * kTb;
     const cd* cbase = a.cols + (size_t)v * a.N * 4 * nt;
 
-    // multipliers of the levels run and the matching inverse diagonal -> LDS;
-    // base (d + far part) of every step of the block -> its row of gh.  All
-    // loads of a loop are issued before its stores.
-    const int lev = a.levels;
-    const cd* prec = a.pcr + (size_t)v * kPcrRec * kWave;
-    {
-        constexpr int kIt = (kPcrLevels * 8 * kWave + kNearThreads - 1) / kNearThreads;
-        const int lim = lev * 8 * kWave;
-        cd t[kIt];
-#pragma unroll
-        for (int u = 0; u < kIt; ++u) {
-            const int e = tid + u * kNearThreads;
-            t[u] = zero;
-            if (e < lim) t[u] = prec[e];
-        }
-        cd di = zero;
-        if (tid < 4 * kWave) di = prec[(size_t)(kPcrLevels * 8 + 4 * lev) * kWave + tid];
-#pragma unroll
-        for (int u = 0; u < kIt; ++u) {
-            const int e = tid + u * kNearThreads;
-            if (e < lim) (&spcr[0][0])[e] = t[u];
-        }
-        if (tid < 4 * kWave) (&spcr[kPcrLevels * 8][0])[tid] = di;
-    }
-    {
-        constexpr int kIt = (kNearSlots * kTb + kNearThreads - 1) / kNearThreads;
-        const int lim = ns * nb;
-        cd t[kIt];
-#pragma unroll
-        for (int u = 0; u < kIt; ++u) {
-            const int e = tid + u * kNearThreads;
-            const int q = e / nb, s = e - q * nb;
-            t[u] = zero;
-            if (e < lim) t[u] = bb[(size_t)q * kTb + s];
-        }
-#pragma unroll
-        for (int u = 0; u < kIt; ++u) {
-            const int e = tid + u * kNearThreads;
-            const int q = e / nb, s = e - q * nb;
-            if (e < lim) gh[s + 1][q + 1] = t[u];
-        }
-    }
-    // zero row (steps before the block) and zero columns (no such slot)
-    for (int e = tid; e < kNearCols; e += kNearThreads) gh[0][e] = zero;
-    for (int e = tid; e < kTb; e += kNearThreads) {
-        gh[e + 1][0] = zero;
-        gh[e + 1][ns + 1] = zero;
-    }
-
     // gather role: subdomain k, lag class c (lags c+3, c+3+C, c+3+2C, ...).
     // wa*: slot 2k-2 from slots 2k-1, 2k; wb*: slot 2k+1 from the same pair.
     const int gt = tid - kWave;
@@ -358,6 +309,58 @@ __global__ __launch_bounds__(kNearThreads) void causal_near_kernel(NearArgs a) {
                 a3[q] = cbase[((size_t)j * 4 + 3) * nt + lag];                              // x0_j
             }
         }
+    }
+    // base (d + far part) of every step of the block -> its row of gh; then
+    // the multipliers of the levels run and the matching inverse diagonal ->
+    // LDS.  The lag coefficients above and the base are in flight together,
+    // so the set-up waits for one round of memory latency (two when PCR
+    // levels run).
+    const int lev = a.levels;
+    const cd* prec = a.pcr + (size_t)v * kPcrRec * kWave;
+    {
+        constexpr int kIt = (kNearSlots * kTb + kNearThreads - 1) / kNearThreads;
+        const int lim = ns * nb;
+        // q = e / nb as (e * ceil(2^32 / nb)) >> 32: exact for e < 2^32 / kTb
+        const unsigned long long rnb = (0x100000000ull + nb - 1) / nb;
+        cd t[kIt];
+#pragma unroll
+        for (int u = 0; u < kIt; ++u) {
+            const int e = tid + u * kNearThreads;
+            const int q = (int)(((unsigned long long)e * rnb) >> 32), s = e - q * nb;
+            t[u] = zero;
+            if (e < lim) t[u] = bb[(size_t)q * kTb + s];
+        }
+#pragma unroll
+        for (int u = 0; u < kIt; ++u) {
+            const int e = tid + u * kNearThreads;
+            const int q = (int)(((unsigned long long)e * rnb) >> 32), s = e - q * nb;
+            if (e < lim) gh[s + 1][q + 1] = t[u];
+        }
+    }
+    {
+        constexpr int kIt = (kPcrLevels * 8 * kWave + kNearThreads - 1) / kNearThreads;
+        const int lim = lev * 8 * kWave;
+        cd t[kIt];
+        cd di = zero;
+#pragma unroll
+        for (int u = 0; u < kIt; ++u) {
+            const int e = tid + u * kNearThreads;
+            t[u] = zero;
+            if (e < lim) t[u] = prec[e];
+        }
+        if (tid < 4 * kWave) di = prec[(size_t)(kPcrLevels * 8 + 4 * lev) * kWave + tid];
+#pragma unroll
+        for (int u = 0; u < kIt; ++u) {
+            const int e = tid + u * kNearThreads;
+            if (e < lim) (&spcr[0][0])[e] = t[u];
+        }
+        if (tid < 4 * kWave) (&spcr[kPcrLevels * 8][0])[tid] = di;
+    }
+    // zero row (steps before the block) and zero columns (no such slot)
+    for (int e = tid; e < kNearCols; e += kNearThreads) gh[0][e] = zero;
+    for (int e = tid; e < kTb; e += kNearThreads) {
+        gh[e + 1][0] = zero;
+        gh[e + 1][ns + 1] = zero;
     }
     cd x0 = zero, x1 = zero, y0 = zero, y1 = zero;   // solutions of steps i-1 and i-2
     __syncthreads();

@@ -1009,16 +1009,16 @@ static swr_status run_static_pipelined(swr_ctx* c, const cd* u0, cd* g, const Sw
         HIPCHK(hipEventRecord(es[2 + j], st));
     }
     // stage 2: causal interface solve on s2 (its set-up reads the first
-    // step of the impulse responses, i.e. chunk 0)
+    // step of the impulse responses, i.e. chunk 0), and stage 3: final sweep
+    // on s3.  Chunk j of the final sweep is queued right after chunk j of
+    // the interface solve: queued after all of stage 2, it would wait for
+    // the host to issue every interface launch first.
     for (int j = 0; j < K; ++j) {
         HIPCHK(hipStreamWaitEvent(s2, es[2 + j], 0));
         if (j == 0) HIPCHK(hipEventRecord(et[4 * K], s2));
         CHK(run_causal(c, c->L, c->dD, g, s2, cut[j], cut[j + 1]));
         HIPCHK(hipEventRecord(es[2 + K + j], s2));
-    }
-    HIPCHK(hipEventRecord(et[4 * K + 1], s2));
-    // stage 3: final sweep on s3
-    for (int j = 0; j < K; ++j) {
+        if (j == K - 1) HIPCHK(hipEventRecord(et[4 * K + 1], s2));
         HIPCHK(hipStreamWaitEvent(s3, es[2 + K + j], 0));
         af.n_begin = cut[j];
         af.n_end = cut[j + 1];

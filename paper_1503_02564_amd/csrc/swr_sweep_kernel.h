@@ -22,23 +22,71 @@ constexpr int kHelpMaxTasks = 512;
 // and hands them over through LDS (double buffer, one barrier per block, the
 // same count as the main wave's).  The main wave adds the 64 terms of the
 // block just finished, which it accumulates step by step.
+//
+// The sum itself (far_sum_s02): lane t, output step nj = n0 + 1 + t, adds
+// beta_{nj-q} x_q for q = 0 .. n0 - 64 in ascending order (one FMA chain per
+// component).  The past values come in chunks of 64 staged in LDS with one
+// coalesced load each, together with the 127-entry window of beta the chunk
+// meets; the loads of the next chunk are issued before the current one is
+// summed, so the wave waits for memory about once per chunk boundary instead
+// of once per few terms.  Only the calling wave touches the staging buffers,
+// and a wave's LDS operations complete in order, so no workgroup barrier is
+// needed (the helper wave cannot take one: the main wave does not join).
+// Positions past the last term hold zeros, which add exact zeros.
+__device__ inline void far_sum_s02(const SweepArgs& a, const cd* Ha, const cd* Hb, int n0, int t,
+                                   cd* sha, cd* shb, double* sb, cd& fa, cd& fb) {
+    const cd zero = mk(0, 0);
+    const int qmax = n0 - kWave;
+    const int nj = n0 + 1 + t;
+    fa = zero;
+    fb = zero;
+    cd pa = zero, pb = zero;
+    double p0 = 0.0, p1 = 0.0;
+    auto fetch = [&](int q0) {
+        const int qn = min(kWave, qmax + 1 - q0);
+        const int bbase = n0 - q0 - (kWave - 2);   // beta index of sb[0]
+        pa = zero;
+        pb = zero;
+        if (t < qn) { pa = Ha[q0 + t]; pb = Hb[q0 + t]; }
+        p0 = 0.0;
+        p1 = 0.0;
+        if (bbase + t >= 0) p0 = a.beta[bbase + t];
+        if (bbase + kWave + t >= 0) p1 = a.beta[bbase + kWave + t];
+    };
+    if (qmax >= 0) fetch(0);
+    for (int q0 = 0; q0 <= qmax; q0 += kWave) {
+        const int bbase = n0 - q0 - (kWave - 2);
+        sha[t] = pa;
+        shb[t] = pb;
+        sb[t] = p0;
+        sb[kWave + t] = p1;
+        if (q0 + kWave <= qmax) fetch(q0 + kWave);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const double* bw = sb + (nj - q0 - bbase);  // beta_{nj - q0 - i} = bw[-i]
+#pragma unroll 16
+        for (int i = 0; i < kWave; ++i) {
+            const double bt = bw[-i];
+            const cd ha = sha[i], hb = shb[i];
+            fa = mk(fma(bt, ha.x, fa.x), fma(bt, ha.y, fa.y));
+            fb = mk(fma(bt, hb.x, fb.x), fma(bt, hb.y, fb.y));
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
 __device__ inline void far_helper(const SweepArgs& a, const cd* Ha, const cd* Hb, int t,
-                                  cd (*ffa)[kWave], cd (*ffb)[kWave]) {
+                                  cd (*ffa)[kWave], cd (*ffb)[kWave], cd* sha, cd* shb,
+                                  double* sb) {
     const int nbeg = a.n_begin, nend = a.n_end;
     auto far = [&](int n0, int buf) {
-        const int nj = n0 + 1 + t;
-        double ax = 0.0, ay = 0.0, bx = 0.0, by = 0.0;
-#pragma unroll 8
-        for (int q = 0; q <= n0 - kWave; ++q) {
-            const double bt = a.beta[nj - q];
-            const cd xa = Ha[q], xb = Hb[q];
-            ax = fma(bt, xa.x, ax);
-            ay = fma(bt, xa.y, ay);
-            bx = fma(bt, xb.x, bx);
-            by = fma(bt, xb.y, by);
-        }
-        ffa[buf][t] = mk(ax, ay);
-        ffb[buf][t] = mk(bx, by);
+        cd fa, fb;
+        far_sum_s02(a, Ha, Hb, n0, t, sha, shb, sb, fa, fb);
+        ffa[buf][t] = fa;
+        ffb[buf][t] = fb;
     };
     far(nbeg, 0);
     __syncthreads();
@@ -85,7 +133,7 @@ __global__ __launch_bounds__(sweep_threads(HELP)) void sweep_kernel(SweepArgs a)
     cd* Ha = a.hist ? a.hist + (size_t)tix * 2 * (nt + 1) : nullptr;
     cd* Hb = Ha ? Ha + (nt + 1) : nullptr;
     if (HELP && wv == 1) {
-        far_helper(a, Ha, Hb, t, ffa, ffb);
+        far_helper(a, Ha, Hb, t, ffa, ffb, sha, shb, sb);
         return;
     }
     // higher-order operators: coefficients of the two ends (left, right)
@@ -244,30 +292,7 @@ __global__ __launch_bounds__(sweep_threads(HELP)) void sweep_kernel(SweepArgs a)
                 fb = ffb[kb & 1][t];
             } else {
                 __threadfence_block();
-                const int qmax = n0 - kWave;
-                const int nj = n0 + 1 + t;
-                for (int q0 = 0; q0 <= qmax; q0 += kWave) {
-                    const int qn = min(kWave, qmax + 1 - q0);
-                    const int bbase = n0 - q0 - (kWave - 2);   // beta index of sb[0]
-                    // (assignments, not a conditional of two lvalues: that
-                    // would put the zero constant in scratch memory)
-                    cd hta = zero, htb = zero;
-                    if (t < qn) { hta = Ha[q0 + t]; htb = Hb[q0 + t]; }
-                    sha[t] = hta;
-                    shb[t] = htb;
-                    sb[t] = (bbase + t >= 0) ? a.beta[bbase + t] : 0.0;
-                    sb[kWave + t] = (bbase + kWave + t >= 0) ? a.beta[bbase + kWave + t] : 0.0;
-                    __syncthreads();
-                    const double* bw = sb + (nj - q0 - bbase);  // beta_{nj - q0 - i} = bw[-i]
-                    #pragma unroll 16
-                    for (int i = 0; i < kWave; ++i) {
-                        const double bt = bw[-i];
-                        const cd ha = sha[i], hb = shb[i];
-                        fa = mk(fma(bt, ha.x, fa.x), fma(bt, ha.y, fa.y));
-                        fb = mk(fma(bt, hb.x, fb.x), fma(bt, hb.y, fb.y));
-                    }
-                    __syncthreads();
-                }
+                far_sum_s02(a, Ha, Hb, n0, t, sha, shb, sb, fa, fb);
             }
             acc_a = fa + nxt_a;
             acc_b = fb + nxt_b;
