@@ -153,25 +153,47 @@ __global__ __launch_bounds__(256) void causal_far_kernel(FarArgs f) {
     const cd* gl = sl >= 0 ? f.g + ((size_t)b * f.ns + sl) * f.nt : nullptr;
     const cd* gr = sr >= 0 ? f.g + ((size_t)b * f.ns + sr) * f.nt : nullptr;
     const int len = f.n0 - f.s_from;                 // < kCausalSuper
-    // lags n - s for n in [n0, n0 + TB), s in [s_from, n0): 1 .. len + TB - 1
-    for (int e = threadIdx.x; e < len; e += blockDim.x) {
-        cd x0 = mk(0, 0), x1 = mk(0, 0);
-        if (gl) x0 = gl[f.s_from + e];
-        if (gr) x1 = gr[f.s_from + e];
-        sg[0][e] = x0;
-        sg[1][e] = x1;
+    const int n = f.n0 + i;
+    // d plus the finished super-blocks' partials, in that order, loaded
+    // before the staging so their latency overlaps it
+    cd r = mk(0, 0);
+    if (sp == 0 && i < f.nb) {
+        r = f.d[((size_t)b * f.ns + o) * f.nt + n];
+        const size_t seg_stride = (size_t)gridDim.y * f.ns * kCausalSuper;
+        const cd* fp = f.facc + ((size_t)b * f.ns + o) * kCausalSuper + (n - f.s_from);
+        for (int q = 0; q < f.nseg; ++q) r = r + fp[q * seg_stride];
     }
-    for (int e = threadIdx.x; e < len + TB; e += blockDim.x) {
-        cd c0 = mk(0, 0), c1 = mk(0, 0);
-        if (e < f.nt) {
-            if (gl) c0 = cl[e];
-            if (gr) c1 = cr[e];
-        }
-        sc[0][e] = c0;
-        sc[1][e] = c1;
+    // lags n - s for n in [n0, n0 + TB), s in [s_from, n0): 1 .. len + TB - 1.
+    // 256 threads: one source and at most two coefficient entries each, all
+    // loaded before any is stored
+    static_assert(kCausalSuper == 256 && TB <= 256, "far kernel staging: two rounds of 256");
+    const int e0 = threadIdx.x, e1 = threadIdx.x + 256;
+    cd x0 = mk(0, 0), x1 = mk(0, 0), c0 = mk(0, 0), c1 = mk(0, 0), c2 = mk(0, 0), c3 = mk(0, 0);
+    if (e0 < len) {
+        if (gl) x0 = gl[f.s_from + e0];
+        if (gr) x1 = gr[f.s_from + e0];
+    }
+    if (e0 < len + TB && e0 < f.nt) {
+        if (gl) c0 = cl[e0];
+        if (gr) c1 = cr[e0];
+    }
+    if (e1 < len + TB && e1 < f.nt) {
+        if (gl) c2 = cl[e1];
+        if (gr) c3 = cr[e1];
+    }
+    if (e0 < len) {
+        sg[0][e0] = x0;
+        sg[1][e0] = x1;
+    }
+    if (e0 < len + TB) {
+        sc[0][e0] = c0;
+        sc[1][e0] = c1;
+    }
+    if (e1 < len + TB) {
+        sc[0][e1] = c2;
+        sc[1][e1] = c3;
     }
     __syncthreads();
-    const int n = f.n0 + i;
     const int per = (len + SPLITS - 1) / SPLITS;
     const int s_lo = f.s_from + sp * per, s_hi = min(f.n0, s_lo + per);
     double ax = 0, ay = 0;
@@ -193,10 +215,6 @@ __global__ __launch_bounds__(256) void causal_far_kernel(FarArgs f) {
     part[sp][i] = mk(ax, ay);
     __syncthreads();
     if (sp == 0 && i < f.nb) {
-        cd r = f.d[((size_t)b * f.ns + o) * f.nt + n];
-        const size_t seg_stride = (size_t)gridDim.y * f.ns * kCausalSuper;
-        const cd* fp = f.facc + ((size_t)b * f.ns + o) * kCausalSuper + (n - f.s_from);
-        for (int q = 0; q < f.nseg; ++q) r = r + fp[q * seg_stride];
         for (int q = 0; q < SPLITS; ++q) r = r + part[q][i];
         f.out[((size_t)b * f.ns + o) * TB + i] = r;
     }
@@ -273,6 +291,9 @@ __global__ __launch_bounds__(kNearThreads) void causal_near_kernel(NearArgs a) {
     const int gt = tid - kWave;
     const int k = gt / kNearClasses, c = gt % kNearClasses;
     const bool gather = tid >= kWave && k < a.N;
+    // a gather wave with no subdomain at all skips the sums (it would add
+    // zeros and hold its SIMD)
+    const bool gwave = tid >= kWave && ((tid & ~(kWave - 1)) - kWave) / kNearClasses < a.N;
     const bool has_a = gather && k >= 1, has_b = gather && k <= a.N - 2;
     const int kk = gather ? k : 0;
     cd wa0[kNearLags], wa1[kNearLags], wb0[kNearLags], wb1[kNearLags];
@@ -412,7 +433,7 @@ __global__ __launch_bounds__(kNearThreads) void causal_near_kernel(NearArgs a) {
                 h0 = madd(madd(h0, a0[1], y1), a1[1], y0p);
                 h1 = madd(madd(h1, a2[1], y1m), a3[1], y0);
             }
-        } else if (i + 2 < nb) {
+        } else if (gwave && i + 2 < nb) {
             // lags >= 3 of step i+2, from in-block steps up to i-1: lag
             // c+3+C*m reads row i - c - C*m (step i+2-lag), row 0 if earlier
             cd pa = zero, pb = zero;
