@@ -391,6 +391,9 @@ __global__ __launch_bounds__(kNearThreads) void causal_near_kernel(NearArgs a) {
     // lag-1 and lag-2 part of the next step's right-hand side, formed from
     // the solver's own registers before the step's barrier
     cd h0 = zero, h1 = zero;
+    // neighbour values of the previous step's solution (lane j+1's x0, lane
+    // j-1's x1): this step's lag-2 neighbours, shuffled once
+    cd x0p = zero, x1m = zero;
 
     for (int i = 0; i < nb; ++i) {
         if (tid < kWave) {
@@ -425,8 +428,9 @@ __global__ __launch_bounds__(kNearThreads) void causal_near_kernel(NearArgs a) {
                 gb[(size_t)(2 * j + 1) * nt + n0 + i] = x1;
             }
             // lags 1 (this step) and 2 (the step before) for step i+1
-            const cd x0p = lane_dn1(x0), x1m = lane_up1(x1);
-            const cd y0p = lane_dn1(y0), y1m = lane_up1(y1);
+            const cd y0p = x0p, y1m = x1m;
+            x0p = lane_dn1(x0);
+            x1m = lane_up1(x1);
             h0 = madd(a1[0] * x0p, a0[0], x1);
             h1 = madd(a3[0] * x0, a2[0], x1m);
             if (i >= 1) {

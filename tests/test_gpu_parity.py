@@ -542,6 +542,48 @@ def test_causal_solve_with_a_thousand_interfaces(dev):
     pb.close()
 
 
+def _lag0_dominance(wl, cols):
+    """max over interfaces j of ||D_j^{-1}|| (||L_j|| + ||U_j||) (inf-norms) for
+    the per-step block system (I - C_0) g_n = rhs: D_j couples the two slots of
+    interface j through the lag-0 impulse responses X^{j+1,1}, X^{j,4}; U_j and
+    L_j reach interfaces j+1 and j-1 through X^{j+1,2} and X^{j,3}.  Below 1
+    the solve runs block PCR (the one-workgroup form up to 64 interfaces)."""
+    N = wl.N
+    worst = 0.0
+    for j in range(N - 1):
+        D = np.array([[1.0, -cols[j + 1, 0, 0]], [-cols[j, 3, 0], 1.0]])
+        u = abs(cols[j + 1, 1, 0]) if j + 1 <= N - 2 else 0.0
+        low = abs(cols[j, 2, 0]) if j >= 1 else 0.0
+        worst = max(worst, np.max(np.sum(np.abs(np.linalg.inv(D)), axis=1)) * (low + u))
+    return worst
+
+
+def test_causal_solve_with_64_interfaces(dev):
+    """65 subdomains (64 interfaces, 128 slots), the largest size of the
+    one-workgroup near-block form, whose lag >= 3 gather then reads the zero
+    column past the last slot; 400 steps: a finished 256-step super-block
+    (history product), pipeline chunks, and a ragged last near block of 16
+    steps.  g against the oracle's causal solve, u(T) against the monodomain
+    solution."""
+    import torch
+    from paper_1503_02564_amd import swr
+    J = np.array([36, 44, 40, 38, 42] * 13, np.int32)
+    wl = W.small_case(J=J, nt=400, trans=W.S02, sigma=0j, seed=23, a0=-6.0, b0=6.0)
+    cols = O.impulse_columns(wl)
+    assert wl.N == 65 and _lag0_dominance(wl, cols) < 1.0
+    say("causal", "65 subdomains")
+    pb = make_problem(wl, tol=1e-13)
+    uT = torch.zeros((1, wl.nx), dtype=torch.complex128, device=dev)
+    g = torch.zeros((1, pb.ns, wl.nt), dtype=torch.complex128, device=dev)
+    st, info = swr.swr_solve(pb.ctx, to_dev(wl.u0), uT, g)
+    torch.cuda.synchronize()
+    assert st == swr.SWR_OK and info.iters == 1 and info.residual < 1e-11
+    gw = O.causal_solve(wl, cols, O.interface_d(wl, wl.u0[0]))
+    assert rel(to_np(g)[0], gw) < 1e-10
+    assert rel(to_np(uT)[0], O.mono(wl, wl.u0[0])) < 1e-10
+    pb.close()
+
+
 @pytest.mark.parametrize("pipeline", [0, 64])
 def test_causal_solve_not_offered_falls_back_to_bicgstab(dev, pipeline):
     """599 interfaces whose per-step block system is not block diagonally
