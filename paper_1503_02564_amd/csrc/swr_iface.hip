@@ -51,12 +51,19 @@ __device__ inline d4 mfma16(double a, double b, d4 c) {
 // causal solve's history products), the workgroup first stages the sources
 // and the coefficient window they meet (at most 511 lags) in LDS with
 // coalesced loads by all four waves, so the lag-block loop reads its operands
-// from LDS instead of waiting on memory every block; the MFMA sequence, and so
-// every result bit, is the same either way.
+// from LDS instead of waiting on memory every block.  The four waves then
+// share the tile: wave w takes k-slice w (sources 4w .. 4w+3 of every
+// 16-step source block) of every lag block, with one accumulator pair per
+// side (four independent MFMA chains), and the partial sums are added in a
+// fixed order (sides, then waves).  For a given output the terms and their
+// order do not depend on the output range of the call, so splitting a range
+// changes no result bit; the rounding differs from the one-wave form used
+// for longer ranges by the order of the sum.
 constexpr int kLttStage = 256;
 
 __global__ __launch_bounds__(256) void ltt_mfma_kernel(LttArgs a) {
     __shared__ cd st_x[2][kLttStage], st_c[2][2 * kLttStage];
+    __shared__ d4 red[4][2][kWave];               // staged form: the waves' accumulators
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const int tile = blockIdx.x * 4 + w;
     const int o = blockIdx.y;
@@ -97,10 +104,9 @@ __global__ __launch_bounds__(256) void ltt_mfma_kernel(LttArgs a) {
             st_c[1][e] = c1;
         }
         __syncthreads();
-        if (tile * 256 >= nlen) return;
     }
     const int r = lane & 15, kq = lane >> 4;
-    const int I0 = tile * 16;
+    const int I0 = staged ? 0 : tile * 16;
     const int slen = s_hi - s_lo;
     const int Jn = (slen + 15) / 16;
     const int delta = a.n_lo - s_lo;
@@ -110,8 +116,7 @@ __global__ __launch_bounds__(256) void ltt_mfma_kernel(LttArgs a) {
     const int m_lo = max(I0 - (Jn - 1), m_lag);
     const int m_hi = slen > 0 ? I0 + 15 : m_lo - 1;
     d4 yr = {0, 0, 0, 0}, yi = {0, 0, 0, 0};
-    // one lag-block loop, with the operands taken from LDS (staged) or from
-    // memory; the MFMA sequence is the same
+    // the lag-block loop of the one-wave form, operands from memory
     auto blocks = [&](auto opA, auto opB) {
         for (int m = m_lo; m <= m_hi; ++m) {
             const int J = I0 + r - m;               // source block of B column r
@@ -138,13 +143,44 @@ __global__ __launch_bounds__(256) void ltt_mfma_kernel(LttArgs a) {
     if (staged) {
         // a lag outside the window pairs only with sources outside [0, slen)
         // or outputs past nlen, i.e. with a zero operand or a dropped result
-        blocks([&](int side, int lag) {
-                   const int le = lag - lag0;
-                   cd c = mk(0, 0);
-                   if (le >= 0 && le < 2 * kLttStage) c = st_c[side][le];
-                   return c;
-               },
-               [&](int side, int si) { return st_x[side][si]; });
+        const int kk = 4 * w + kq;
+        d4 ar0 = {0, 0, 0, 0}, ai0 = {0, 0, 0, 0}, ar1 = {0, 0, 0, 0}, ai1 = {0, 0, 0, 0};
+        for (int m = m_lo; m <= m_hi; ++m) {
+            const int J = I0 + r - m;               // source block of B column r
+            const int le = delta + 16 * m + r - kk - lag0;
+            const int si = 16 * J + kk;
+            const bool sok = J >= 0 && si < slen;
+            const bool lok = le >= 0 && le < 2 * kLttStage;
+            if (xl) {
+                cd av = mk(0, 0), bv = mk(0, 0);
+                if (lok) av = st_c[0][le];
+                if (sok) bv = st_x[0][si];
+                ar0 = mfma16(av.x, bv.x, ar0);
+                ar0 = mfma16(-av.y, bv.y, ar0);
+                ai0 = mfma16(av.x, bv.y, ai0);
+                ai0 = mfma16(av.y, bv.x, ai0);
+            }
+            if (xr) {
+                cd av = mk(0, 0), bv = mk(0, 0);
+                if (lok) av = st_c[1][le];
+                if (sok) bv = st_x[1][si];
+                ar1 = mfma16(av.x, bv.x, ar1);
+                ar1 = mfma16(-av.y, bv.y, ar1);
+                ai1 = mfma16(av.x, bv.y, ai1);
+                ai1 = mfma16(av.y, bv.x, ai1);
+            }
+        }
+        red[w][0][lane] = ar0 + ar1;
+        red[w][1][lane] = ai0 + ai1;
+        __syncthreads();
+        if (w != 0) return;
+        yr = red[0][0][lane];
+        yi = red[0][1][lane];
+#pragma unroll
+        for (int u = 1; u < 4; ++u) {
+            yr = yr + red[u][0][lane];
+            yi = yi + red[u][1][lane];
+        }
     } else {
         blocks([&](int side, int lag) {
                    cd c = mk(0, 0);
