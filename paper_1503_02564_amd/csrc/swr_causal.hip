@@ -32,6 +32,21 @@
 namespace swr {
 
 constexpr int kTb = kNearTb;                  // near block (time steps)
+constexpr int kNearClasses = 4;                            // gather threads per subdomain
+constexpr int kNearLags = kTb / kNearClasses;              // lags per thread: c+3, c+3+C, ...
+constexpr int kNearGroup = 4;                              // lags whose loads are issued together
+// gather threads: kNearClasses per subdomain, N <= kWave + 1 subdomains
+constexpr int kNearGather = (kNearClasses * (kWave + 1) + kWave - 1) / kWave * kWave;
+constexpr int kNearThreads = kWave + kNearGather;
+constexpr int kNearCols = kNearSlots + 2;                  // slot q in column q + 1; 0 and ns + 1 stay zero
+static_assert(kTb % (kNearClasses * kNearGroup) == 0, "near block: whole lag groups");
+// per-potential record of the one-wave form: PCR multipliers and inverse
+// diagonals [kPcrRec][64], then the near kernel's lag coefficients packed by
+// thread: gather [kNearLags][4][kNearGather] (lags >= 3), solver [2][4][64]
+// (lags 1, 2), zero where the coupling does not exist
+constexpr size_t kNearPackG = (size_t)kNearLags * 4 * kNearGather;
+constexpr size_t kFastRec = (size_t)kPcrRec * kWave + kNearPackG + 2 * 4 * kWave;
+size_t causal_fast_rec() { return kFastRec; }
 
 struct C2x2 { cd a, b, c, d; };   // [[a, b], [c, d]]
 
@@ -81,7 +96,7 @@ __global__ __launch_bounds__(64) void causal_pcr_setup_kernel(int N, int nt, con
         U = m2(-x2, zero, zero, zero);
         Lm = m2(zero, zero, zero, -x3);
     }
-    cd* rec = pcr + (size_t)v * kPcrRec * kWave + j;
+    cd* rec = pcr + (size_t)v * kFastRec + j;
     // per level: the coupling measure and the inverse diagonal block of the
     // current system, then one reduction.  Runs once per solve: keep the
     // loop rolled (the unrolled chain of 2x2 products is slow to compile).
@@ -224,20 +239,12 @@ struct NearArgs {
     int N, nt, ns, per_problem;
     int n0, nb;
     const cd* cols;
-    const cd* pcr;     // [nv][kPcrRec][64]
+    const cd* pcr;     // [nv][kFastRec]
     int levels;        // PCR levels run per step (the rest of the coupling is negligible)
     const cd* base;    // [B][ns][kTb]: d + far part
     cd* g;             // [B][ns][nt]
 };
 
-constexpr int kNearClasses = 4;                            // gather threads per subdomain
-constexpr int kNearLags = kTb / kNearClasses;              // lags per thread: c+3, c+3+C, ...
-constexpr int kNearGroup = 4;                              // lags whose loads are issued together
-// gather threads: kNearClasses per subdomain, N <= kWave + 1 subdomains
-constexpr int kNearGather = (kNearClasses * (kWave + 1) + kWave - 1) / kWave * kWave;
-constexpr int kNearThreads = kWave + kNearGather;
-constexpr int kNearCols = kNearSlots + 2;                  // slot q in column q + 1; 0 and ns + 1 stay zero
-static_assert(kTb % (kNearClasses * kNearGroup) == 0, "near block: whole lag groups");
 
 // neighbour values for the lag-1/lag-2 history: lane j - 1 / j + 1 (zero outside)
 __device__ inline cd lane_up1(cd v) { return shfl_up_c(v, 1, mk(0, 0)); }
@@ -284,7 +291,8 @@ __global__ __launch_bounds__(kNearThreads) void causal_near_kernel(NearArgs a) {
     const cd zero = mk(0, 0);
     cd* gb = a.g + (size_t)b * ns * nt;
     const cd* bb = a.base + (size_t)b * ns * kTb;
-    const cd* cbase = a.cols + (size_t)v * a.N * 4 * nt;
+    const cd* prec = a.pcr + (size_t)v * kFastRec;
+    const cd* pk = prec + (size_t)kPcrRec * kWave;   // packed lag coefficients
 
     // gather role: subdomain k, lag class c (lags c+3, c+3+C, c+3+2C, ...).
     // wa*: slot 2k-2 from slots 2k-1, 2k; wb*: slot 2k+1 from the same pair.
@@ -296,39 +304,31 @@ __global__ __launch_bounds__(kNearThreads) void causal_near_kernel(NearArgs a) {
     const bool gwave = tid >= kWave && ((tid & ~(kWave - 1)) - kWave) / kNearClasses < a.N;
     const bool has_a = gather && k >= 1, has_b = gather && k <= a.N - 2;
     const int kk = gather ? k : 0;
+    // (coalesced reads of the table packed once per solve)
     cd wa0[kNearLags], wa1[kNearLags], wb0[kNearLags], wb1[kNearLags];
 #pragma unroll
     for (int m = 0; m < kNearLags; ++m) { wa0[m] = zero; wa1[m] = zero; wb0[m] = zero; wb1[m] = zero; }
-    {
-        const cd* cb = cbase + (size_t)kk * 4 * nt;
+    if (tid >= kWave) {
 #pragma unroll
         for (int m = 0; m < kNearLags; ++m) {
-            const int lag = c + 3 + kNearClasses * m;
-            if (lag < nt && lag < kTb) {
-                if (has_a) {
-                    wa0[m] = cb[lag];
-                    if (k <= a.N - 2) wa1[m] = cb[(size_t)nt + lag];
-                }
-                if (has_b) {
-                    if (k >= 1) wb0[m] = cb[(size_t)2 * nt + lag];
-                    wb1[m] = cb[(size_t)3 * nt + lag];
-                }
-            }
+            const cd* q = pk + (size_t)m * 4 * kNearGather + gt;
+            wa0[m] = q[0];
+            wa1[m] = q[kNearGather];
+            wb0[m] = q[2 * kNearGather];
+            wb1[m] = q[3 * kNearGather];
         }
     }
     // solver role: lag-1 and lag-2 coefficients of my two slots
     const int j = tid;
     cd a0[2] = {zero, zero}, a1[2] = {zero, zero}, a2[2] = {zero, zero}, a3[2] = {zero, zero};
-    if (tid < kWave && j < ni) {
+    if (tid < kWave) {
+        const cd* q = pk + kNearPackG + j;
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int lag = q + 1;
-            if (lag < nt) {
-                a0[q] = cbase[((size_t)(j + 1) * 4 + 0) * nt + lag];                        // x1_j
-                if (j + 1 <= a.N - 2) a1[q] = cbase[((size_t)(j + 1) * 4 + 1) * nt + lag];   // x0_{j+1}
-                if (j >= 1) a2[q] = cbase[((size_t)j * 4 + 2) * nt + lag];                  // x1_{j-1}
-                a3[q] = cbase[((size_t)j * 4 + 3) * nt + lag];                              // x0_j
-            }
+        for (int l = 0; l < 2; ++l) {
+            a0[l] = q[(l * 4 + 0) * kWave];
+            a1[l] = q[(l * 4 + 1) * kWave];
+            a2[l] = q[(l * 4 + 2) * kWave];
+            a3[l] = q[(l * 4 + 3) * kWave];
         }
     }
     // base (d + far part) of every step of the block -> its row of gh; then
@@ -337,7 +337,6 @@ __global__ __launch_bounds__(kNearThreads) void causal_near_kernel(NearArgs a) {
     // so the set-up waits for one round of memory latency (two when PCR
     // levels run).
     const int lev = a.levels;
-    const cd* prec = a.pcr + (size_t)v * kPcrRec * kWave;
     {
         constexpr int kIt = (kNearSlots * kTb + kNearThreads - 1) / kNearThreads;
         const int lim = ns * nb;
@@ -468,9 +467,68 @@ __global__ __launch_bounds__(kNearThreads) void causal_near_kernel(NearArgs a) {
     }
 }
 
+// The near kernel's lag coefficients of one potential, packed by thread so
+// that every launch reads them with coalesced loads: gather thread gt
+// (subdomain k = gt / C, class c) gets, for lag c+3+C*m, X^{k,1..4} (those of
+// slot 2k-2 from slots 2k-1, 2k and of slot 2k+1 from the same pair); solver
+// lane j gets the lag-1 and lag-2 values of its two slots.  Zero where the
+// slot or the source does not exist, or the lag is past nt or the near block.
+__global__ __launch_bounds__(kNearGather) void causal_near_pack_kernel(int N, int nt, const cd* cols,
+                                                                       cd* pcr) {
+    const int v = blockIdx.x, gt = threadIdx.x;
+    const cd zero = mk(0, 0);
+    const cd* cbase = cols + (size_t)v * N * 4 * nt;
+    cd* pk = pcr + (size_t)v * kFastRec + (size_t)kPcrRec * kWave;
+    const int k = gt / kNearClasses, c = gt % kNearClasses;
+    const bool gather = k < N;
+    const bool has_a = gather && k >= 1, has_b = gather && k <= N - 2;
+    const cd* cb = cbase + (size_t)(gather ? k : 0) * 4 * nt;
+    for (int m = 0; m < kNearLags; ++m) {
+        const int lag = c + 3 + kNearClasses * m;
+        cd w0 = zero, w1 = zero, w2 = zero, w3 = zero;
+        if (lag < nt && lag < kTb) {
+            if (has_a) {
+                w0 = cb[lag];
+                if (k <= N - 2) w1 = cb[(size_t)nt + lag];
+            }
+            if (has_b) {
+                if (k >= 1) w2 = cb[(size_t)2 * nt + lag];
+                w3 = cb[(size_t)3 * nt + lag];
+            }
+        }
+        cd* q = pk + (size_t)m * 4 * kNearGather + gt;
+        q[0] = w0;
+        q[kNearGather] = w1;
+        q[2 * kNearGather] = w2;
+        q[3 * kNearGather] = w3;
+    }
+    if (gt < kWave) {
+        const int j = gt, ni = N - 1;
+        cd* q = pk + kNearPackG + j;
+        for (int l = 0; l < 2; ++l) {
+            const int lag = l + 1;
+            cd x0 = zero, x1 = zero, x2 = zero, x3 = zero;
+            if (j < ni && lag < nt) {
+                x0 = cbase[((size_t)(j + 1) * 4 + 0) * nt + lag];                        // x1_j
+                if (j + 1 <= N - 2) x1 = cbase[((size_t)(j + 1) * 4 + 1) * nt + lag];   // x0_{j+1}
+                if (j >= 1) x2 = cbase[((size_t)j * 4 + 2) * nt + lag];                  // x1_{j-1}
+                x3 = cbase[((size_t)j * 4 + 3) * nt + lag];                              // x0_j
+            }
+            q[(l * 4 + 0) * kWave] = x0;
+            q[(l * 4 + 1) * kWave] = x1;
+            q[(l * 4 + 2) * kWave] = x2;
+            q[(l * 4 + 3) * kWave] = x3;
+        }
+    }
+}
+
 hipError_t launch_causal_pcr_setup(int N, int nt, int nv, const cd* cols, cd* pcr, double* eta,
                                    hipStream_t st) {
+    if (N > kWave + 1) return hipErrorInvalidValue;
     causal_pcr_setup_kernel<<<nv, 64, 0, st>>>(N, nt, cols, pcr, eta);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    causal_near_pack_kernel<<<nv, kNearGather, 0, st>>>(N, nt, cols, pcr);
     return hipGetLastError();
 }
 

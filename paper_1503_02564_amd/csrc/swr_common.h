@@ -329,6 +329,9 @@ constexpr int kPcrRec = kPcrLevels * 8 + (kPcrLevels + 1) * 4;
 // result: ||D_l^{-1}|| (||L_l|| + ||U_l||) <= 2^-60 (unit roundoff is 2^-53)
 constexpr double kPcrNegligible = 8.673617379884035e-19;
 // eta: [nv][levels + 1] coupling measure of the system before each level
+// per-potential record size (complex values) of the one-wave causal form:
+// PCR multipliers plus the near kernel's packed lag coefficients
+size_t causal_fast_rec();
 hipError_t launch_causal_pcr_setup(int N, int nt, int nv, const cd* cols, cd* pcr, double* eta,
                                    hipStream_t st);
 hipError_t launch_causal_fast(int N, int nt, int ns, int B, int per_problem, const cd* cols,

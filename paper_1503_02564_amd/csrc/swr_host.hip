@@ -718,7 +718,7 @@ static swr_status run_causal(swr_ctx* c, Iface& I, const cd* d, cd* g, hipStream
     if (I.dirty) {
         I.path = 3;
         if (fast_ok || gen_ok) {
-            const size_t rec = fast_ok ? (size_t)kPcrRec * kWave : (size_t)pcr_rec_gen(c->N);
+            const size_t rec = fast_ok ? causal_fast_rec() : (size_t)pcr_rec_gen(c->N);
             if (!I.pcr || I.pcr_size < rec * I.nv) {
                 ALLOC_LIVE(I.pcr, rec * I.nv);
                 I.pcr_size = rec * I.nv;
