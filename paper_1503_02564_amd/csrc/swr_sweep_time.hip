@@ -1,32 +1,27 @@
-// swr_sweep_time.hip -- instantiates the subdomain sweep for a time-dependent potential V(t,x).
-#include "swr_sweep_kernel.h"
+// swr_sweep_time.hip -- the subdomain sweep for a time-dependent potential
+// V(t,x): dispatch on the chunk width P to the instantiations in
+// swr_sweep_time_p1.hip .. swr_sweep_time_p8.hip.
+#include "swr_common.h"
 
 namespace swr {
 
 template <int P>
-static void launch_p(const SweepArgs& a, int trans, hipStream_t st) {
-    if (trans == TR_S02 && a.ntasks <= kHelpMaxTasks)
-        sweep_kernel<P, TR_S02, VK_TIME, true><<<a.ntasks, sweep_threads(true), 0, st>>>(a);
-    else if (trans == TR_S02)
-        sweep_kernel<P, TR_S02, VK_TIME, false><<<a.ntasks, sweep_threads(false), 0, st>>>(a);
-    else sweep_kernel<P, TR_ROBIN, VK_TIME><<<a.ntasks, sweep_threads(false), 0, st>>>(a);
-}
+hipError_t launch_sweep_time_p(const SweepArgs& a, int trans, hipStream_t st);
 
 hipError_t launch_sweep_time(const SweepArgs& a, int trans, hipStream_t st) {
     // the higher-order operators are provided for a static potential only
     if (trans != TR_S02 && trans != TR_ROBIN) return hipErrorInvalidValue;
     switch (a.P) {
-        case 1: launch_p<1>(a, trans, st); break;
-        case 2: launch_p<2>(a, trans, st); break;
-        case 3: launch_p<3>(a, trans, st); break;
-        case 4: launch_p<4>(a, trans, st); break;
-        case 5: launch_p<5>(a, trans, st); break;
-        case 6: launch_p<6>(a, trans, st); break;
-        case 7: launch_p<7>(a, trans, st); break;
-        case 8: launch_p<8>(a, trans, st); break;
+        case 1: return launch_sweep_time_p<1>(a, trans, st);
+        case 2: return launch_sweep_time_p<2>(a, trans, st);
+        case 3: return launch_sweep_time_p<3>(a, trans, st);
+        case 4: return launch_sweep_time_p<4>(a, trans, st);
+        case 5: return launch_sweep_time_p<5>(a, trans, st);
+        case 6: return launch_sweep_time_p<6>(a, trans, st);
+        case 7: return launch_sweep_time_p<7>(a, trans, st);
+        case 8: return launch_sweep_time_p<8>(a, trans, st);
         default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 }  // namespace swr
