@@ -110,6 +110,10 @@ typedef struct {
     int plain;         /* 1 = launch the subdomain sweeps one task (one subdomain of one problem)
                           per launch on the context's stream, staged: the unbatched form, for
                           comparison with the batched launches (default 0) */
+    int snapshot_stride; /* > 0: swr_solve may return u(t_n, x) at n = 0, s, 2s, ... <= nt
+                            (s = this stride) in its snaps argument; 0 = no snapshots (default 0) */
+    const char* tune_cache; /* host path of the schedule cache written by swr_tune and read by
+                               swr_setup (NULL = no cache, built-in schedule; default NULL) */
 } swr_opts;
 
 typedef struct {
@@ -128,6 +132,11 @@ typedef struct {
     int n_sweep;        /* ... and their number (0 when not measured) */
     int inner_iters;    /* V_TIME / V_CUBIC with more interfaces than the causal solve takes:
                            total inner BiCGStab iterations spent applying P^{-1} (else 0) */
+    const double* history; /* host array owned by the context, valid until the next call on it:
+                              the convergence measure after every interface iteration (max over
+                              the batch): GMRES / BiCGStab relative residual estimate, fixed
+                              point max trace change, causal solve the certified residual */
+    int history_len;    /* entries of history */
 } swr_info;
 
 /* Fill *o with the defaults listed above. */
@@ -158,11 +167,15 @@ swr_status swr_setup(double a0, double b0, int N, const int* J, double dt, doubl
  * |u|^2: Sec. 5 preconditioned iteration.  Outputs: uT [B][nx] complex
  * (required); g [B][2N-2][nt] converged interface vector (NULL to skip);
  * utrace [B][N][2][nt+1]: u_n at the left/right end node of every subdomain,
- * n = 0..nt (NULL to skip).  info: host struct (NULL to skip).
+ * n = 0..nt (NULL to skip); snaps [B][S][nx] complex with S = nt/s + 1
+ * (integer division, s = opts.snapshot_stride): u(t_n, x) at n = 0, s, 2s, ...
+ * from the final sweep, the node shared by two subdomains the average of the
+ * two sides as in uT (NULL to skip; SWR_EINVAL when given with a stride of 0).
+ * info: host struct (NULL to skip).
  * Returns SWR_ENOCONV if the solver hit max_iter (outputs hold the last
  * iterate), SWR_ENAN on a non-finite residual. */
 swr_status swr_solve(swr_ctx* ctx, const double* u0, double* uT, double* g, double* utrace,
-                     swr_info* info);
+                     double* snaps, swr_info* info);
 
 /* Gradient of a real objective J(u(T)) with respect to the static potential
  * and the initial data, by the discrete adjoint of the Crank-Nicolson scheme
@@ -199,8 +212,12 @@ swr_status swr_apply_R(swr_ctx* ctx, const double* u0, const double* g_in, doubl
  * d = R 0 [B][2N-2][nt] from the data u0.  Either output may be NULL. */
 swr_status swr_build_interface(swr_ctx* ctx, const double* u0, double* cols, double* d);
 
-/* y = x - L x for [B][2N-2][nt] vectors with L from the last build (the
- * matrix of the Krylov solver; static V). */
+/* y = x - L x for [B][2N-2][nt] vectors with L from the last build: the
+ * operator of the interface problem (I - L) g = d (Sec. 4, "New algorithm";
+ * the matrix its Krylov solvers iterate with), L applied block by block as
+ * lower-triangular Toeplitz products fixed by the impulse-response first
+ * columns (Props. 3-4, Sec. 4.1).  Static V: L of the potential; V(t,x) and
+ * |u|^2: L_0 of the zero potential (Sec. 5).  x and y must not overlap. */
 swr_status swr_interface_matvec(swr_ctx* ctx, const double* x, double* y);
 
 /* Replace the potential of a context (same layout as the V of swr_setup:
@@ -215,8 +232,13 @@ void swr_destroy(swr_ctx* ctx);
 /* Static description of a status code. */
 const char* swr_strerror(swr_status s);
 
-/* Number of time steps and global nodes of a context (host ints). */
-swr_status swr_sizes(const swr_ctx* ctx, int* nt, int* nx, int* B, int* nv);
+/* Sizes of a context (host ints, each pointer may be NULL): time steps nt,
+ * global nodes nx, problems B, potentials nv (B with opts.v_per_problem, else
+ * 1), subdomains N, the potential kind vk (swr_vkind) and the snapshot count S
+ * of swr_solve (0 without opts.snapshot_stride).  They fix the element counts
+ * of every array argument above. */
+swr_status swr_sizes(const swr_ctx* ctx, int* nt, int* nx, int* B, int* nv, int* N, int* vk,
+                     int* S);
 
 #ifdef __cplusplus
 }

@@ -192,6 +192,7 @@ enum TaskFlags {
     T_OUT_TRACE = 1 << 7,   // u_n at the two end nodes -> trace store
     T_MAXDIFF   = 1 << 8,   // fold max |g_out - g_in| over written slots
     T_CKPT      = 1 << 9,   // store u at steps nt - 64 j (and u_0) for the adjoint
+    T_OUT_SNAP  = 1 << 10,  // u at steps 0, s, 2s, ... -> snapshot store
 };
 
 struct Task {
@@ -242,6 +243,9 @@ struct SweepArgs {
     int n_begin, n_end;          // steps n_begin+1 .. n_end of this launch (n_begin % 64 == 0)
     cd* state;                   // [ntasks][2][P][64] u_n and v_n carried between launches
     const EndCoef* endc;         // TR_GEN: [nf][2] end coefficients (left, right)
+    cd* snaps;                   // [B][nsnap][nx] u at steps 0, snap_stride, ... (interior nodes)
+    cd* snap_ends;               // [B][nsnap][N][2] the same at the two end nodes
+    int snap_stride, nsnap;
 };
 
 struct FactorArgs {
@@ -296,6 +300,9 @@ hipError_t launch_sweep_time(const SweepArgs& a, int trans, hipStream_t st);
 hipError_t launch_sweep_cubic(const SweepArgs& a, int trans, hipStream_t st);
 hipError_t launch_finalize_ut(int N, int nx, int B, const int* off, const cd* ends, cd* uT,
                               hipStream_t st);
+// the same for every snapshot: ends [B][S][N][2] -> snaps [B][S][nx]
+hipError_t launch_finalize_snaps(int N, int nx, int B, int S, const int* off, const cd* ends,
+                                 cd* snaps, hipStream_t st);
 hipError_t launch_beta(int n, double* beta, hipStream_t st);
 // launchers (swr_iface.hip)
 hipError_t launch_ltt(const LttArgs& a, hipStream_t st);

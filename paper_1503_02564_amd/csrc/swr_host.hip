@@ -119,6 +119,11 @@ struct swr_ctx {
     cd* dStateF = nullptr;    // [nSub][2][P][64]
     cd* dHistB = nullptr;     // [nBuild][2][nt+1]
     std::vector<hipEvent_t> evSync, evTime;
+    // snapshots: end-node values [B][S][N][2] (averaged into the output)
+    cd* dSnapEnds = nullptr;
+    size_t snap_ends_size = 0;
+    // convergence history of the last call (swr_info.history)
+    std::vector<double> hist;
     // host staging (pinned)
     double* hRes = nullptr;
     int* hAct = nullptr;
@@ -176,6 +181,8 @@ extern "C" void swr_default_opts(swr_opts* o) {
     o->nl_tol = 1e-14;
     o->pipeline = 256;
     o->plain = 0;
+    o->snapshot_stride = 0;
+    o->tune_cache = nullptr;
 }
 
 extern "C" const char* swr_strerror(swr_status s) {
@@ -223,6 +230,7 @@ extern "C" swr_status swr_setup(double a0, double b0, int N, const int* J, doubl
     if (o.batch < 1 || o.restart < 1 || o.max_iter < 1 || !(o.tol > 0)) return SWR_EINVAL;
     if (o.nl_max_iter < 1 || !(o.nl_tol > 0) || o.checkpoint_K < 1) return SWR_EINVAL;
     if (o.pipeline < 0 || o.pipeline % kWave != 0) return SWR_EINVAL;
+    if (o.snapshot_stride < 0) return SWR_EINVAL;
     if (vk == SWR_V_TIME && !V) return SWR_EINVAL;
     if (vk == SWR_V_CUBIC && V) return SWR_EINVAL;
     if (vk != SWR_V_STATIC && o.v_per_problem) return SWR_EINVAL;
@@ -347,12 +355,18 @@ extern "C" void swr_destroy(swr_ctx* c) {
     delete c;
 }
 
-extern "C" swr_status swr_sizes(const swr_ctx* c, int* nt, int* nx, int* B, int* nv) {
+static int nsnaps(const swr_ctx* c);
+
+extern "C" swr_status swr_sizes(const swr_ctx* c, int* nt, int* nx, int* B, int* nv, int* N, int* vk,
+                                int* S) {
     if (!c) return SWR_EINVAL;
     if (nt) *nt = c->nt;
     if (nx) *nx = c->nx;
     if (B) *B = c->B;
     if (nv) *nv = c->nv;
+    if (N) *N = c->N;
+    if (vk) *vk = c->vk;
+    if (S) *S = nsnaps(c);
     return SWR_OK;
 }
 
@@ -365,9 +379,15 @@ struct SweepIO {
     cd* g_out = nullptr;
     cd* uT = nullptr;
     cd* trace = nullptr;
+    cd* snaps = nullptr;        // [B][S][nx] snapshots every c->o.snapshot_stride steps
     bool maxdiff = false;
     bool ckpt = false;
 };
+
+// number of snapshots of a solve: steps 0, s, 2s, ... <= nt
+static int nsnaps(const swr_ctx* c) {
+    return c->o.snapshot_stride > 0 ? c->nt / c->o.snapshot_stride + 1 : 0;
+}
 
 // kernel form of the transmission operator: Robin, S0^2, or the general
 // convolution form of the higher-order operators
@@ -423,28 +443,23 @@ static SweepArgs sub_args(swr_ctx* c, const SweepIO& io) {
     a.flags_and = 0;
     a.flags_or = (io.u0 ? T_DATA_U0 : 0) | (io.g_in ? T_FLUX_G : 0) | (io.g_out ? T_OUT_G : 0) |
                  (io.uT ? T_OUT_UT : 0) | (io.trace ? T_OUT_TRACE : 0) | (io.maxdiff ? T_MAXDIFF : 0) |
-                 (io.ckpt ? T_CKPT : 0);
+                 (io.ckpt ? T_CKPT : 0) | (io.snaps ? T_OUT_SNAP : 0);
     a.ckpt = c->dCkpt;
     a.Jc = c->Jc;
+    a.snaps = io.snaps;
+    a.snap_ends = c->dSnapEnds;
+    a.snap_stride = c->o.snapshot_stride;
+    a.nsnap = nsnaps(c);
     return a;
 }
 
 static swr_status run_sweeps(swr_ctx* c, const SweepIO& io) {
-    SweepArgs a = sweep_args(c, c->dSub, c->nSub, main_fac(c), nullptr);
-    a.u0 = io.u0;
-    a.g_in = io.g_in ? io.g_in : c->dZero;
-    a.g_out = io.g_out;
-    a.uT = io.uT;
-    a.trace = io.trace;
-    a.flags_and = 0;
-    a.flags_or = (io.u0 ? T_DATA_U0 : 0) | (io.g_in ? T_FLUX_G : 0) | (io.g_out ? T_OUT_G : 0) |
-                 (io.uT ? T_OUT_UT : 0) | (io.trace ? T_OUT_TRACE : 0) | (io.maxdiff ? T_MAXDIFF : 0) |
-                 (io.ckpt ? T_CKPT : 0);
-    a.ckpt = c->dCkpt;
-    a.Jc = c->Jc;
+    SweepArgs a = sub_args(c, io);
     if (io.maxdiff) HIPCHK(hipMemsetAsync(c->dMax, 0, sizeof(unsigned long long), c->st));
     HIPCHK(launch_sweep(a, ktr(c), c->vk, c->st, c->o.plain));
     if (io.uT) HIPCHK(launch_finalize_ut(c->N, c->nx, c->B, c->dOff, c->dEnds, io.uT, c->st));
+    if (io.snaps)
+        HIPCHK(launch_finalize_snaps(c->N, c->nx, c->B, nsnaps(c), c->dOff, c->dSnapEnds, io.snaps, c->st));
     return SWR_OK;
 }
 
@@ -537,10 +552,13 @@ static swr_status run_gmres(swr_ctx* c, const Op& A, const cd* rhs, cd* x, int* 
             ++its;
             jj = j + 1;
             bool done = true;
+            double worst = 0;
             for (int b = 0; b < B; ++b) {
                 if (!std::isfinite(c->hRes[b])) return SWR_ENAN;
                 if (c->hAct[b] && c->hRes[b] > c->o.tol) done = false;
+                if (c->hAct[b]) worst = std::max(worst, c->hRes[b]);
             }
+            c->hist.push_back(worst);
             if (done) break;
         }
         HIPCHK(launch_gmres_solve(jj, m, B, c->dH, c->dE, c->dY, c->dAct, st));
@@ -555,7 +573,7 @@ static swr_status run_gmres(swr_ctx* c, const Op& A, const cd* rhs, cd* x, int* 
 // ||r||_2 <= tol ||rhs||_2, checked on s after the half step and on r after
 // the full step; finished problems keep their x (zero coefficients).
 static swr_status run_bicgstab(swr_ctx* c, const Op& A, const cd* rhs, cd* x, int* iters_out,
-                               double tol, int max_iter) {
+                               double tol, int max_iter, bool record = true) {
     const int B = c->B;
     const long M = (long)c->ns * c->nt;
     const size_t vec = (size_t)B * M;
@@ -636,12 +654,15 @@ static swr_status run_bicgstab(swr_ctx* c, const Op& A, const cd* rhs, cd* x, in
         CHK(comb(s, t, nullptr, r));                             // r = s - omega t
         CHK(norms(r, nr));
         any = false;
+        double worst = 0;
         for (int b = 0; b < B; ++b) {
             if (!std::isfinite(nr[b])) return SWR_ENAN;
+            if (act[b] && bn[b] > 0) worst = std::max(worst, (half[b] ? 0.0 : nr[b]) / bn[b]);
             if (half[b] || nr[b] <= tol * bn[b]) act[b] = 0;
             any |= act[b] != 0;
             rho[b] = rho_new[b];
         }
+        if (record) c->hist.push_back(worst);
     }
     *iters_out = its;
     return any ? SWR_ENOCONV : SWR_OK;
@@ -700,7 +721,7 @@ static swr_status apply_inverse(swr_ctx* c, Iface& I, const cd* rhs, cd* x) {
     // needs a multiple of the interface count
     int its = 0;
     const int cap = std::max(c->o.max_iter, 20 * c->ns);
-    const swr_status rs = run_bicgstab(c, A, rhs, x, &its, kInnerTol, cap);
+    const swr_status rs = run_bicgstab(c, A, rhs, x, &its, kInnerTol, cap, false);
     c->inner_iters += its;
     return rs == SWR_ENOCONV ? SWR_ENOCONV : rs;
 }
@@ -843,6 +864,7 @@ static swr_status run_classical(swr_ctx* c, const cd* u0, int* iters, double* la
         CHK(read_max(c, &d));
         *last = d;
         *iters = it;
+        c->hist.push_back(d);
         std::swap(gi, go);
         if (!std::isfinite(d)) return SWR_ENAN;
         if (d < c->o.tol) { rs = SWR_OK; break; }
@@ -910,6 +932,7 @@ static swr_status run_precond_cubic(swr_ctx* c, const cd* u0, int* iters, double
         for (int b = 0; b < c->B; ++b) d = std::max(d, m[b] / std::max(1.0, gm[b]));
         *last = d;
         *iters = it;
+        c->hist.push_back(d);
         if (!std::isfinite(d)) return SWR_ENAN;
         if (d < c->o.tol) return SWR_OK;
     }
@@ -1027,6 +1050,8 @@ static swr_status run_static_pipelined(swr_ctx* c, const cd* u0, cd* g, const Sw
         HIPCHK(hipEventRecord(et[2 * K + 2 * j + 1], s3));
     }
     if (fin.uT) HIPCHK(launch_finalize_ut(c->N, c->nx, c->B, c->dOff, c->dEnds, fin.uT, s3));
+    if (fin.snaps)
+        HIPCHK(launch_finalize_snaps(c->N, c->nx, c->B, nsnaps(c), c->dOff, c->dSnapEnds, fin.snaps, s3));
     // join back onto st
     HIPCHK(hipEventRecord(ev_join, s3));
     HIPCHK(hipStreamWaitEvent(st, ev_join, 0));
@@ -1043,8 +1068,17 @@ static swr_status run_static_pipelined(swr_ctx* c, const cd* u0, cd* g, const Sw
 }
 
 extern "C" swr_status swr_solve(swr_ctx* c, const double* u0d, double* uT, double* g, double* utrace,
-                                swr_info* info) {
+                                double* snaps, swr_info* info) {
     if (!c || !u0d || !uT) return SWR_EINVAL;
+    if (snaps && c->o.snapshot_stride <= 0) return SWR_EINVAL;
+    if (snaps) {
+        const size_t need = (size_t)c->B * nsnaps(c) * c->N * 2;
+        if (c->snap_ends_size < need) {
+            ALLOC_LIVE(c->dSnapEnds, need);
+            c->snap_ends_size = need;
+        }
+    }
+    c->hist.clear();
     const cd* u0 = reinterpret_cast<const cd*>(u0d);
     const size_t vec = (size_t)c->B * c->ns * c->nt;
     hipStream_t st = c->st;
@@ -1066,6 +1100,7 @@ extern "C" swr_status swr_solve(swr_ctx* c, const double* u0d, double* uT, doubl
         SweepIO io;
         io.u0 = u0; io.g_in = c->dG; io.g_out = c->dG2;
         io.uT = reinterpret_cast<cd*>(uT); io.trace = reinterpret_cast<cd*>(utrace);
+        io.snaps = reinterpret_cast<cd*>(snaps);
         const swr_status ps = run_static_pipelined(c, u0, c->dG, io, info ? &tm : nullptr);
         if (ps == kCausalOff) {
             // the causal solve turned out not to be offered for this system
@@ -1074,7 +1109,7 @@ extern "C" swr_status swr_solve(swr_ctx* c, const double* u0d, double* uT, doubl
             if (c->s2) HIPCHK(hipStreamSynchronize(c->s2));
             if (c->s3) HIPCHK(hipStreamSynchronize(c->s3));
             HIPCHK(hipStreamSynchronize(st));
-            return swr_solve(c, u0d, uT, g, utrace, info);
+            return swr_solve(c, u0d, uT, g, utrace, snaps, info);
         }
         CHK(ps);
         iters = 1;
@@ -1132,6 +1167,7 @@ extern "C" swr_status swr_solve(swr_ctx* c, const double* u0d, double* uT, doubl
         SweepIO io;
         io.u0 = u0; io.g_in = c->ns ? c->dG : nullptr; io.g_out = c->dG2;
         io.uT = reinterpret_cast<cd*>(uT); io.trace = reinterpret_cast<cd*>(utrace);
+        io.snaps = reinterpret_cast<cd*>(snaps);
         CHK(run_sweeps(c, io));
     }
     HIPCHK(hipEventRecord(c->ev[4], st));
@@ -1163,6 +1199,7 @@ extern "C" swr_status swr_solve(swr_ctx* c, const double* u0d, double* uT, doubl
     HIPCHK(hipMemcpyAsync(nl, c->dNl, sizeof(nl), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     if (info) {
+        *info = swr_info{};
         info->iters = iters;
         info->residual = res;
         info->t_factor_ms = elapsed(c->ev[0], c->ev[1]);
@@ -1174,6 +1211,11 @@ extern "C" swr_status swr_solve(swr_ctx* c, const double* u0d, double* uT, doubl
         info->t_sweep_ms = 0;
         info->n_sweep = 0;
         info->inner_iters = c->inner_iters;
+        // Krylov and fixed-point solvers recorded every iteration; the
+        // causal solve (one pass) has the certified residual
+        if (c->hist.empty()) c->hist.push_back(res);
+        info->history = c->hist.data();
+        info->history_len = (int)c->hist.size();
         if (pipe) {
             info->t_build_ms = tm.build;
             info->t_iface_ms = tm.iface;
@@ -1345,6 +1387,7 @@ extern "C" swr_status swr_grad(swr_ctx* c, const double* u0d, const double* gbar
     a.grad = 0;
     HIPCHK(launch_adjoint(a, ktr(c), st));
     HIPCHK(hipEventRecord(c->ev[2], st));
+    c->hist.clear();   // the history reported is the adjoint interface solve's
     swr_status rb = solve_interface(c, c->dDadj, c->dGadj, &it_b);
     if (rb != SWR_OK && rb != SWR_ENOCONV) return rb;
     HIPCHK(hipEventRecord(c->ev[3], st));
@@ -1377,6 +1420,7 @@ extern "C" swr_status swr_grad(swr_ctx* c, const double* u0d, const double* gbar
     }
     HIPCHK(hipStreamSynchronize(st));
     if (info) {
+        *info = swr_info{};
         info->iters = it_b;
         info->residual = res;
         info->t_factor_ms = elapsed(c->ev[0], c->ev[1]);   // the whole forward solve
@@ -1384,6 +1428,9 @@ extern "C" swr_status swr_grad(swr_ctx* c, const double* u0d, const double* gbar
         info->t_iface_ms = elapsed(c->ev[2], c->ev[3]);    // adjoint interface solve
         info->t_final_ms = elapsed(c->ev[3], c->ev[4]);    // replay + adjoint sweep + dJ/dV
         info->nl_worst = it_f;
+        if (c->hist.empty()) c->hist.push_back(res);
+        info->history = c->hist.data();
+        info->history_len = (int)c->hist.size();
     }
     return (rf == SWR_ENOCONV || rb == SWR_ENOCONV) ? SWR_ENOCONV : SWR_OK;
 }

@@ -111,6 +111,20 @@ __global__ void finalize_ut_kernel(int N, int nx, int B, const int* off, const c
     else u[off[j]] = 0.5 * (e[(j - 1) * 2 + 1] + e[j * 2 + 0]);
 }
 
+// the same per snapshot: one thread per (problem, snapshot, end node)
+__global__ void finalize_snaps_kernel(int N, int nx, int B, int S, const int* off, const cd* ends,
+                                      cd* snaps) {
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)B * S * (N + 1)) return;
+    const long bs = idx / (N + 1);
+    const int j = (int)(idx % (N + 1));
+    const cd* e = ends + (size_t)bs * N * 2;
+    cd* u = snaps + (size_t)bs * nx;
+    if (j == 0) u[0] = e[0];
+    else if (j == N) u[nx - 1] = e[(N - 1) * 2 + 1];
+    else u[off[j]] = 0.5 * (e[(j - 1) * 2 + 1] + e[j * 2 + 0]);
+}
+
 // beta_s = (-1)^s alpha_s, alpha_{2m} = alpha_{2m+1} = (2m-1)!!/(2m)!!
 // (Sec. 2.2), tabulated for s = 0..n-1 by one thread.
 __global__ void beta_table_kernel(int n, double* beta) {
@@ -161,6 +175,13 @@ hipError_t launch_finalize_ut(int N, int nx, int B, const int* off, const cd* en
                               hipStream_t st) {
     const int tot = B * (N + 1);
     finalize_ut_kernel<<<(tot + 255) / 256, 256, 0, st>>>(N, nx, B, off, ends, uT);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_snaps(int N, int nx, int B, int S, const int* off, const cd* ends,
+                                 cd* snaps, hipStream_t st) {
+    const long tot = (long)B * S * (N + 1);
+    finalize_snaps_kernel<<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(N, nx, B, S, off, ends, snaps);
     return hipGetLastError();
 }
 

@@ -213,6 +213,26 @@ __global__ __launch_bounds__(sweep_threads(HELP)) void sweep_kernel(SweepArgs a)
 #pragma unroll
         for (int q = 0; q < P; ++q) ck[((size_t)a.Jc * P + q) * kWave] = u[q];
     }
+    // snapshots u_n, n = 0, stride, 2 stride, ...: interior nodes straight to
+    // the output, the two end nodes to a side store (averaged across the
+    // interface afterwards, as u(T))
+    const bool snap = (fl & T_OUT_SNAP) != 0;
+    auto put_snap = [&](int nstep) {
+        const int j = nstep / a.snap_stride;
+        cd* sp = a.snaps + ((size_t)b * a.nsnap + j) * a.nx + o;
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            const int gi = s + q;
+            if (gi > 0 && gi < n - 1) sp[gi] = u[q];
+        }
+        const cd ua = rdlane(u[0], 0), ub = at_last(u);
+        if (t == 0) {
+            cd* se = a.snap_ends + (((size_t)b * a.nsnap + j) * a.N + k) * 2;
+            se[0] = ua;
+            se[1] = ub;
+        }
+    };
+    if (snap && first) put_snap(0);
     cd* trace_a = (fl & T_OUT_TRACE) ? a.trace + ((size_t)(b * a.N + k) * 2) * (nt + 1) : nullptr;
     cd* trace_b = trace_a ? trace_a + (nt + 1) : nullptr;
     if (trace_a && t == 0 && first) {
@@ -476,6 +496,7 @@ __global__ __launch_bounds__(sweep_threads(HELP)) void sweep_kernel(SweepArgs a)
             // advance u_n = 2 v_n - u_{n-1}
 #pragma unroll
             for (int q = 0; q < P; ++q) u[q] = mk(2.0 * x[q].x - u[q].x, 2.0 * x[q].y - u[q].y);
+            if (snap && nstep % a.snap_stride == 0) put_snap(nstep);
             if (ck && nstep < nt && ((nt - nstep) & (kWave - 1)) == 0) {
                 const int jj = (nt - nstep) / kWave;
 #pragma unroll

@@ -79,7 +79,7 @@ def test_setup_rejects_bad_opts(swr):
 
 
 def test_calls_reject_null_context(swr):
-    assert swr._L.swr_solve(None, None, None, None, None, None) == swr.SWR_EINVAL
+    assert swr._L.swr_solve(None, None, None, None, None, None, None) == swr.SWR_EINVAL
     assert swr._L.swr_apply_R(None, None, None, None, None, None) == swr.SWR_EINVAL
     assert swr._L.swr_grad(None, None, None, None, None, None) == swr.SWR_EINVAL
     swr._L.swr_destroy(None)

@@ -203,23 +203,34 @@ def test_plain_launches_equal_batched(dev):
 
 
 def test_classical_iteration_matches_oracle_iterates(dev):
-    """Robin-window grid with S0^2: classical SWR to max change < 1e-10 (the
+    """Robin-window grid with S0^2: classical SWR to max change < 1e-12 (the
     Robin value s = 1-i on that grid does not converge by fixed point; see
-    the next test).  Converged u(T) = monodomain; iteration count = oracle's."""
+    the next test).  Converged u(T) = monodomain to 1e-10; iteration count and
+    the history of max changes = the oracle's.  (1e-12 is the parity
+    tolerance here: the traces are ~45 in size, and both sides' changes
+    stagnate near 2.5e-13, ten units in the last place, so 1e-13 is not
+    reachable in FP64 by either.)"""
     import copy
     import torch
     from paper_1503_02564_amd import swr
     wl = copy.copy(W.robin_window())
     wl.trans = W.S02
-    say("classical", "robin-window-grid-s02")
-    pb = make_problem(wl, solver=swr.SWR_SOLVER_FIXED, tol=1e-10, max_iter=2000)
+    say("classical", "robin-window-grid-s02 tol 1e-12")
+    pb = make_problem(wl, solver=swr.SWR_SOLVER_FIXED, tol=1e-12, max_iter=2000)
     uT = torch.zeros((1, wl.nx), dtype=torch.complex128, device=dev)
     st, info = swr.swr_solve(pb.ctx, to_dev(wl.u0), uT)
     torch.cuda.synchronize()
     assert st == swr.SWR_OK
-    g, it, _ = O.classical(wl, wl.u0[0], tol=1e-10, maxit=2000)
+    g, it, hist = O.classical(wl, wl.u0[0], tol=1e-12, maxit=2000)
+    say("classical", "gpu iterations", info.iters, "oracle", it, "residual", info.residual)
     assert abs(info.iters - it) <= 1
-    assert rel(to_np(uT)[0], O.mono(wl, wl.u0[0])) < 1e-9
+    h = info.history
+    assert len(h) == info.iters
+    m = min(len(h), len(hist))
+    # the first iterates are far from rounding level: same changes
+    assert np.allclose(h[:50], hist[:50], rtol=1e-9, atol=0)
+    assert h[-1] < 1e-12 and np.all(np.isfinite(h[:m]))
+    assert rel(to_np(uT)[0], O.mono(wl, wl.u0[0])) < 1e-10
     pb.close()
 
 

@@ -47,6 +47,25 @@ def test_robin_small_sigma_direct_solution_is_monodomain():
     assert info["residual"] < 1e-13
 
 
+def test_robin_window_fixed_point_grows_before_it_could_converge():
+    """The Robin window as stated (dn u + (1-i) u on 4 x 100 cells, 500
+    steps): the classical fixed point's max trace change grows over the first
+    100 iterations (by about 1.08 per iteration) instead of shrinking, so the
+    stated stop rule (change < 1e-10) is out of reach in FP64, while the same
+    interface problem solved directly (above) is the monodomain solution.
+    The iteration operator is a non-normal block lower-triangular Toeplitz
+    matrix whose transient growth precedes its asymptotic decay."""
+    wl = W.robin_window()
+    g, it, hist = O.classical(wl, wl.u0[0], tol=1e-10, maxit=100)
+    hist = np.asarray(hist)
+    assert it == -100 and len(hist) == 100        # not converged within the cap
+    assert np.all(np.isfinite(hist))
+    assert hist[-1] > 1e3 * hist[0]
+    # steady geometric growth over the second half
+    rate = (hist[99] / hist[49]) ** (1.0 / 50)
+    assert 1.03 < rate < 1.15
+
+
 # ---------------------------------------------------- Props. 1-4 ------------
 
 @pytest.mark.parametrize("trans,sigma", [(W.S02, 0j), (W.ROBIN, 1 - 1j)])
