@@ -206,6 +206,23 @@ swr_status swr_grad(swr_ctx* ctx, const double* u0, const double* gbar, double* 
 swr_status swr_apply_R(swr_ctx* ctx, const double* u0, const double* g_in, double* g_out,
                        double* uT, double* maxdiff);
 
+/* swr_apply_R for callers that cannot allocate device memory during the call
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same sweeps and the same results as swr_apply_R, but its
+ * scratch -- the S0^2 boundary history of every (problem, subdomain) sweep,
+ * the end values of u(T) and the max-change word -- is a fixed 16 MiB device
+ * array of the library (one copy per GPU, held until the process ends) instead
+ * of context memory; the call allocates nothing, never synchronises and enqueues
+ * only kernels on the context's stream.  maxdiff is a DEVICE double (NULL to
+ * skip) that receives max |g_out - g_in| when the stream reaches it.
+ * Requires 256 + 16 (B N 2 + B N 2 (nt + 1)) bytes <= 16 MiB (the history term
+ * only for the convolution-type transmissions); SWR_EINVAL beyond, and for the
+ * argument errors of swr_apply_R.  All calls on one GPU share the array: calls
+ * that overlap in time on one GPU (other streams, other threads) race and
+ * corrupt each other's results. */
+swr_status swr_apply_R_noalloc(swr_ctx* ctx, const double* u0, const double* g_in, double* g_out,
+                               double* uT, double* maxdiff);
+
 /* Build the explicit interface problem (Sec. 4.1, static V): impulse sweeps
  * give the first columns of all blocks X^{k,p}, cols [nv][N][4][nt] (p = 0..3
  * for X^{k,1..4}; entries of absent blocks are left untouched), and

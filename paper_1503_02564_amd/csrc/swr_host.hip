@@ -16,6 +16,7 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -124,6 +125,9 @@ struct swr_ctx {
     size_t snap_ends_size = 0;
     // convergence history of the last call (swr_info.history)
     std::vector<double> hist;
+    // this context's GPU and its copy of the static scratch array
+    int dev = 0;
+    void* scratch = nullptr;
     // host staging (pinned)
     double* hRes = nullptr;
     int* hAct = nullptr;
@@ -166,6 +170,41 @@ static swr_status dalloc(swr_ctx* c, T** p, size_t count) {
         swr_status s_ = dalloc(c, &(p), (size_t)(n));   \
         if (s_ != SWR_OK) return s_;                    \
     } while (0)
+
+// ---------------------------------------------------------------------------
+// Scratch of the entry point that allocates nothing (swr_apply_R_noalloc): the
+// S0^2 boundary history of every sweep task, the end values of u(T) and the
+// max-change word live in this file-scope device array of fixed size instead
+// of context memory.  Every GPU holds its own copy, at its own address, until
+// the process ends; host code never uses the array's name as an address, only
+// the pointer hipGetSymbolAddress returns for the current device, taken once
+// per device when the first context is set up on it.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = (size_t)16 << 20;   // 16 MiB per GPU
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices];
+static bool g_scratch_done[kMaxDevices];
+
+// device address of `scratch` on device `dev` (the current device), looked up
+// once per device; null if the lookup failed
+static void* scratch_address(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_done[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) p = nullptr;
+        g_scratch_ptr[dev] = p;
+        g_scratch_done[dev] = true;
+    }
+    return g_scratch_ptr[dev];
+}
+
+__global__ void zero_word_kernel(unsigned long long* w) { *w = 0ull; }
+__global__ void word_to_double_kernel(const unsigned long long* w, double* out) {
+    *out = __longlong_as_double((long long)*w);
+}
 
 extern "C" void swr_default_opts(swr_opts* o) {
     if (!o) return;
@@ -248,6 +287,8 @@ extern "C" swr_status swr_setup(double a0, double b0, int N, const int* J, doubl
     c->a0 = a0; c->b0 = b0; c->dt = dt; c->N = N; c->nt = (int)ntr; c->nc = (int)nc;
     c->nx = (int)nc + 1; c->h = (b0 - a0) / (double)nc; c->ns = 2 * N - 2; c->B = o.batch;
     c->vk = vk; c->tr = tr; c->o = o; c->st = (hipStream_t)stream;
+    if (hipGetDevice(&c->dev) != hipSuccess) { delete c; return SWR_EDEVICE; }
+    c->scratch = scratch_address(c->dev);
     c->nv = (vk == SWR_V_STATIC && o.v_per_problem) ? o.batch : 1;
     c->P = (nmax + kWave - 1) / kWave;
     c->c2 = mk(std::cos(-M_PI / 4) * std::sqrt(2.0 / dt), std::sin(-M_PI / 4) * std::sqrt(2.0 / dt));
@@ -1245,6 +1286,44 @@ extern "C" swr_status swr_apply_R(swr_ctx* c, const double* u0, const double* g_
     CHK(run_sweeps(c, io));
     if (maxdiff) CHK(read_max(c, maxdiff));
     HIPCHK(hipStreamSynchronize(c->st));
+    return SWR_OK;
+}
+
+extern "C" swr_status swr_apply_R_noalloc(swr_ctx* c, const double* u0, const double* g_in,
+                                          double* g_out, double* uT, double* maxdiff) {
+    if (!c || !g_in || !g_out) return SWR_EINVAL;
+    if (!c->scratch) return SWR_EDEVICE;
+    // scratch layout: [max word, padded to 256 B][ends B*N*2][history nSub*2*(nt+1)]
+    const size_t ends = (size_t)c->B * c->N * 2;
+    const size_t hist = c->tr != SWR_ROBIN ? (size_t)c->nSub * 2 * (c->nt + 1) : 0;
+    if (256 + (ends + hist) * sizeof(cd) > kScratchBytes) return SWR_EINVAL;
+    unsigned char* base = static_cast<unsigned char*>(c->scratch);
+    auto* word = reinterpret_cast<unsigned long long*>(base);
+    cd* dEnds = reinterpret_cast<cd*>(base + 256);
+    cd* dHist = dEnds + ends;
+    if (c->vk == SWR_V_STATIC) CHK(run_factor(c, c->dV, c->nv, c->L.fac));
+    else CHK(run_factor(c, nullptr, 1, c->L0.fac));
+    SweepIO io;
+    io.u0 = reinterpret_cast<const cd*>(u0);
+    io.g_in = reinterpret_cast<const cd*>(g_in);
+    io.g_out = reinterpret_cast<cd*>(g_out);
+    io.uT = reinterpret_cast<cd*>(uT);
+    io.maxdiff = maxdiff != nullptr;
+    SweepArgs a = sub_args(c, io);
+    a.hist = dHist;
+    a.ends = dEnds;
+    a.maxdiff = word;
+    // the max-change word starts at zero (a kernel, not a memset: capturable)
+    if (maxdiff) {
+        zero_word_kernel<<<1, 1, 0, c->st>>>(word);
+        HIPCHK(hipGetLastError());
+    }
+    HIPCHK(launch_sweep(a, ktr(c), c->vk, c->st, c->o.plain));
+    if (uT) HIPCHK(launch_finalize_ut(c->N, c->nx, c->B, c->dOff, dEnds, io.uT, c->st));
+    if (maxdiff) {
+        word_to_double_kernel<<<1, 1, 0, c->st>>>(word, maxdiff);
+        HIPCHK(hipGetLastError());
+    }
     return SWR_OK;
 }
 

@@ -68,7 +68,7 @@ class SwrInfo(ctypes.Structure):
 # exported symbols of include/swr.h
 EXPORTS = ("swr_default_opts", "swr_strerror", "swr_setup", "swr_solve", "swr_grad",
            "swr_apply_R", "swr_build_interface", "swr_interface_matvec", "swr_destroy",
-           "swr_sizes", "swr_set_potential")
+           "swr_sizes", "swr_set_potential", "swr_apply_R_noalloc")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
@@ -89,6 +89,8 @@ _L.swr_grad.argtypes = [_P, _P, _P, _P, _P, ctypes.POINTER(SwrInfo)]
 _L.swr_grad.restype = ctypes.c_int
 _L.swr_apply_R.argtypes = [_P, _P, _P, _P, _P, ctypes.POINTER(ctypes.c_double)]
 _L.swr_apply_R.restype = ctypes.c_int
+_L.swr_apply_R_noalloc.argtypes = [_P, _P, _P, _P, _P, _P]
+_L.swr_apply_R_noalloc.restype = ctypes.c_int
 _L.swr_build_interface.argtypes = [_P, _P, _P, _P]
 _L.swr_build_interface.restype = ctypes.c_int
 _L.swr_interface_matvec.argtypes = [_P, _P, _P]
@@ -244,6 +246,16 @@ def swr_apply_R(ctx, u0, g_in, g_out, uT=None, want_maxdiff=False):
                         ctypes.byref(md) if want_maxdiff else None)
     _check(st, "swr_apply_R")
     return md.value
+
+
+def swr_apply_R_noalloc(ctx, u0, g_in, g_out, uT=None, maxdiff=None):
+    """swr_apply_R with the library's static scratch (no allocation, no
+    synchronisation); maxdiff: a one-element float64 CUDA tensor or None."""
+    z = _sizes(ctx)
+    st = _L.swr_apply_R_noalloc(ctx, _arr(u0, "c", z.B * z.nx, "u0"), _arr(g_in, "c", z.vec, "g_in"),
+                                _arr(g_out, "c", z.vec, "g_out"), _arr(uT, "c", z.B * z.nx, "uT"),
+                                _arr(maxdiff, "d", 1, "maxdiff"))
+    _check(st, "swr_apply_R_noalloc")
 
 
 def swr_build_interface(ctx, u0, cols=None, d=None):
