@@ -131,14 +131,20 @@ def make_problem(wl, **kw):
                        wl.trans, wl.sigma, o, V)
 
 
-def timed_solves(wl, steps, warmup, **kw):
+def timed_solves(wl, steps, warmup, tune_ms=0.0, sched=None, **kw):
     """Wall time per solve (synchronised around `steps` solves after
-    `warmup`), the infos of the timed solves, the last u(T) and status."""
+    `warmup`), the infos of the timed solves, the last u(T) and status.  With
+    tune_ms > 0 the library's autotuner first picks the schedule (outside the
+    timed region); sched (a dict) receives the schedule the solves ran with."""
     import torch
     from paper_1503_02564_amd import swr
     pb = make_problem(wl, **kw)
     u0 = torch.from_numpy(np.ascontiguousarray(wl.u0)).cuda()
     uT = torch.zeros_like(u0)
+    if tune_ms > 0:
+        swr.swr_tune(pb.ctx, u0, tune_ms)
+    if sched is not None:
+        sched.update(swr.swr_get_schedule(pb.ctx).as_dict())
     st = None
     for _ in range(warmup):
         st, _ = swr.swr_solve(pb.ctx, u0, uT)
@@ -368,6 +374,9 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
+    ap.add_argument("--tune-ms", type=float, default=4000.0,
+                    help="autotuner budget for the 'autotune' key, run after the headline on a "
+                         "context of its own (0 = skip)")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the headline solves (profiling runs)")
     ap.add_argument("--no-paper", dest="paper", action="store_false",
@@ -396,7 +405,8 @@ def main():
 
     from paper_1503_02564_amd import workloads as W
     wl = W.batched_uneven()
-    ms, infos, uT, st = timed_solves(wl, args.steps, args.warmup)
+    sched = {}
+    ms, infos, uT, st = timed_solves(wl, args.steps, args.warmup, sched=sched)
     value = wl.pt_steps() / (1e-3 * ms)
     ph = {k: float(np.mean([i[k] for i in infos])) for k in
           ("t_factor_ms", "t_build_ms", "t_iface_ms", "t_final_ms", "t_total_ms")}
@@ -424,10 +434,17 @@ def main():
                                "dt=5e-4, S0^2, seeded bumpy harmonic V, new algorithm, causal "
                                "interface solve",
                    "nx": wl.nx, "nt": wl.nt, "N": wl.N, "B": wl.B, "solver": "causal",
-                   "pipeline": 256},
+                   "schedule": {k: sched[k] for k in ("pipeline", "help_max", "restart")}},
         "status": st, "interface_residual": resid, "phases_ms": ph,
         "max_rel_diff_vs_oracle_fixture": fixture_error(uT),
     }
+    if not args.headline_only and args.tune_ms > 0:
+        # the autotuner on the headline workload (a context of its own, after
+        # the timed region): the schedule it picks and the time it measured
+        tuned = {}
+        tms, _, _, _ = timed_solves(wl, 2, 0, tune_ms=args.tune_ms, sched=tuned)
+        out["autotune"] = {"budget_ms": args.tune_ms, "chosen": tuned, "ms_per_solve": tms,
+                           "default_schedule_ms": ms}
     if not args.headline_only:
         sp = static_packet_solvers(args.steps)
         out["static_packet"] = sp

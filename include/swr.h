@@ -106,7 +106,10 @@ typedef struct {
                           this many steps (a multiple of 64) and overlap the impulse/d sweeps,
                           the interface solve and the final sweep chunk by chunk on two extra
                           internal streams (joined back to the context's stream before the call
-                          returns); 0 = one stage after the other (default 256) */
+                          returns); 0 = one stage after the other; -1 = chosen by the library
+                          (default): 256 while the build sweeps leave CUs free for the
+                          interface solve (at most 4096 build tasks), else 0; a tuning-cache
+                          entry (tune_cache) overrides the choice */
     int plain;         /* 1 = launch the subdomain sweeps one task (one subdomain of one problem)
                           per launch on the context's stream, staged: the unbatched form, for
                           comparison with the batched launches (default 0) */
@@ -138,6 +141,18 @@ typedef struct {
                               point max trace change, causal solve the certified residual */
     int history_len;    /* entries of history */
 } swr_info;
+
+/* A schedule: parameters that change how the work is launched, not what is
+ * computed (results are bitwise the same for every pipeline chunk and helper
+ * bound; the GMRES restart changes the iterate, not the tolerance met). */
+typedef struct {
+    int pipeline;     /* pipeline chunk of the static causal solve, 0 = staged */
+    int help_max;     /* S0^2 sweeps: launches of at most this many tasks give every task a
+                         second wave that sums the far boundary history */
+    int restart;      /* GMRES restart length */
+    double ms;        /* swr_tune: wall time of the chosen schedule's solve */
+    int candidates;   /* swr_tune: schedules timed */
+} swr_schedule;
 
 /* Fill *o with the defaults listed above. */
 void swr_default_opts(swr_opts* o);
@@ -242,6 +257,22 @@ swr_status swr_interface_matvec(swr_ctx* ctx, const double* x, double* y);
  * solve refactorises and rebuilds the interface problem.  SWR_EINVAL for a
  * cubic context or a NULL V. */
 swr_status swr_set_potential(swr_ctx* ctx, const double* V);
+
+/* The autotuner: times candidate schedules (pipeline chunks 0, 128, 256, 512,
+ * 1024 for the static causal solve; helper-wave bounds 0, 512, all for S0^2;
+ * restarts 20, 30, 60, 120 for GMRES and the V(t,x) iteration) with full
+ * solves of the caller's u0 [B][nx] (one warm-up and the best of two timed
+ * solves each), until budget_ms of wall time is spent, and keeps the fastest
+ * on the context.  With opts.tune_cache the choice is written to that file
+ * under a key of the problem's shape (sizes, batch, potential kind,
+ * transmission, solver) and applied by every later swr_setup of the same
+ * shape.  chosen (host, NULL to skip) receives it.  May allocate; synchronises.
+ * SWR_EINVAL on bad arguments or an unwritable cache file, SWR_ENOCONV when no
+ * candidate solve converged. */
+swr_status swr_tune(swr_ctx* ctx, const double* u0, double budget_ms, swr_schedule* chosen);
+
+/* The schedule a context runs with (host out). */
+swr_status swr_get_schedule(const swr_ctx* ctx, swr_schedule* s);
 
 /* Release the context and all device memory it owns. */
 void swr_destroy(swr_ctx* ctx);

@@ -83,11 +83,11 @@ __device__ inline void far_history(const cd* Ha, const cd* Hb, const double* bet
 
 template <int P, int TR>
 __global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs a) {
-    using L = FacLayout<P>;
     __shared__ double sbeta[kWave + 1];
     __shared__ cd sha[kWave], shb[kWave];
     __shared__ double sb[2 * kWave];
-    const Task task = a.tasks[blockIdx.x];
+    const int tix = a.task0 + blockIdx.x;   // task index (per-task buffers)
+    const Task task = a.tasks[tix];
     const int k = task.k, b = task.b, f = task.f;
     const int t = threadIdx.x;
     const int n = a.J[k] + 1, o = a.off[k];
@@ -104,7 +104,7 @@ __global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs a) {
         __syncthreads();
     }
     LaneFac<P> F;
-    load_fac<P>(a.fac + (size_t)f * L::total * kWave + t, F);
+    load_fac<P>(a.fac + (size_t)f * a.fstride + t, F);
 
     double wl[P], wr[P], wlast[P];
 #pragma unroll
@@ -149,7 +149,7 @@ __global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs a) {
 #pragma unroll
     for (int q = 0; q < P; ++q) gv[q] = 0.0;
 
-    cd* Ha = a.hist + (size_t)blockIdx.x * 2 * (nt + 1);
+    cd* Ha = a.hist + (size_t)tix * 2 * (nt + 1);
     cd* Hb = Ha + (nt + 1);
     if (TR == TR_S02 && t == 0) { Ha[0] = zero; Hb[0] = zero; }
     const cd* gin_l = (lif && a.g_in) ? a.g_in + ((size_t)b * ns_ + 2 * k - 1) * nt : nullptr;
@@ -159,9 +159,9 @@ __global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs a) {
     // forward replay
     const cd* fw_l = (lif && a.grad) ? a.g_fwd + ((size_t)b * ns_ + 2 * k - 1) * nt : nullptr;
     const cd* fw_r = (rif && a.grad) ? a.g_fwd + ((size_t)b * ns_ + 2 * k) * nt : nullptr;
-    const cd* Fa = a.grad ? a.hist_fwd + (size_t)blockIdx.x * 2 * (nt + 1) : nullptr;
+    const cd* Fa = a.grad ? a.hist_fwd + (size_t)tix * 2 * (nt + 1) : nullptr;
     const cd* Fb = Fa ? Fa + (nt + 1) : nullptr;
-    cd* seg = a.grad ? a.seg + (size_t)blockIdx.x * kWave * P * kWave + t : nullptr;
+    cd* seg = a.grad ? a.seg + (size_t)tix * kWave * a.pstride * kWave + t : nullptr;
 
     for (int m0 = 0; m0 < nt; m0 += kWave) {
         const int nb = min(kWave, nt - m0);
@@ -171,7 +171,7 @@ __global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs a) {
             const int jj = m0 / kWave + 1;
             const int nsf = max(0, nt - kWave * jj);
             cd uf[P];
-            const cd* ck = a.ckpt + (((size_t)blockIdx.x * (a.Jc + 1) + jj) * P) * kWave + t;
+            const cd* ck = a.ckpt + (((size_t)tix * (a.Jc + 1) + jj) * a.pstride) * kWave + t;
 #pragma unroll
             for (int q = 0; q < P; ++q) uf[q] = ck[q * kWave];
             cd lf = zero, rf = zero;
@@ -199,7 +199,7 @@ __global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs a) {
 #pragma unroll
                 for (int q = 0; q < P; ++q) {
                     uf[q] = mk(2.0 * x[q].x - uf[q].x, 2.0 * x[q].y - uf[q].y);
-                    seg[((size_t)i * P + q) * kWave] = x[q];
+                    seg[((size_t)i * a.pstride + q) * kWave] = x[q];
                 }
                 if (TR == TR_S02) {
                     // boundary values by cross-lane reads: every lane must take part
@@ -245,7 +245,7 @@ __global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs a) {
                 const int is = nb - 1 - i;            // forward step ns+1+is
                 cd v[P];
 #pragma unroll
-                for (int q = 0; q < P; ++q) v[q] = seg[((size_t)is * P + q) * kWave];
+                for (int q = 0; q < P; ++q) v[q] = seg[((size_t)is * a.pstride + q) * kWave];
                 const cd xL = shfl_up_c(x[P - 1], 1, zero), xR = shfl_dn_c(x[0], 1, zero);
                 const cd vL = shfl_up_c(v[P - 1], 1, zero), vR = shfl_dn_c(v[0], 1, zero);
 #pragma unroll

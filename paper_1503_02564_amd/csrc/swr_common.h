@@ -209,6 +209,12 @@ struct Task {
 constexpr int kPcrLevels = 6;
 __host__ __device__ constexpr int fac_fields(int P) { return 5 * (P - 1) + 2 + 2 * kPcrLevels + 1; }
 constexpr int kMaxP = 8;
+// default schedule: the S0^2 helper wave up to this many tasks per launch (every
+// wave then has a SIMD of its own), the pipelined static solve up to this many
+// build tasks (beyond, the sweeps fill the GPU and the interface solve's
+// kernels only find CUs between them, so one stage after the other is faster)
+constexpr int kHelpMaxTasks = 512;
+constexpr int kPipeMaxBuild = 4096;
 
 struct SweepArgs {
     int N, nt, B, nx, ns;        // ns = 2N-2 interface slots
@@ -243,6 +249,11 @@ struct SweepArgs {
     int n_begin, n_end;          // steps n_begin+1 .. n_end of this launch (n_begin % 64 == 0)
     cd* state;                   // [ntasks][2][P][64] u_n and v_n carried between launches
     const EndCoef* endc;         // TR_GEN: [nf][2] end coefficients (left, right)
+    int help_max;                // S0^2: launches of at most this many tasks use the helper wave
+    int pstride;                 // chunk-width stride of the per-task state and checkpoint
+                                 // records (the context's largest width; a launch's own P may
+                                 // be smaller: subdomains are grouped by width)
+    size_t fstride;              // complex entries per subdomain factor record
     cd* snaps;                   // [B][nsnap][nx] u at steps 0, snap_stride, ... (interior nodes)
     cd* snap_ends;               // [B][nsnap][N][2] the same at the two end nodes
     int snap_stride, nsnap;
@@ -255,6 +266,8 @@ struct FactorArgs {
     int tr;                      // swr_transmission code; 2..5 fill endc
     cd c2;                       // e^{-i pi/4} sqrt(2/dt)
     EndCoef* endc;               // [nf][2] output for the higher-order operators
+    const int* Pk;               // [N] chunk width of each subdomain (this launch builds width P)
+    size_t fstride;              // complex entries per subdomain factor record
     const int* J;
     const int* off;
     const double* V;             // [nv][nx] static potential (nullptr = 0)
@@ -373,6 +386,8 @@ hipError_t launch_causal_gen(int N, int nt, int ns, int B, int per_problem, cons
                              int n_hi, const cd* facc, int s_from, hipStream_t st);
 struct AdjArgs {
     int N, nt, B, nx, ns, ntasks, P, Jc;
+    int task0, pstride;          // this launch runs tasks task0 ..; record stride as SweepArgs
+    size_t fstride;
     double kappa, h;
     cd sigma, c2;
     const int* J;

@@ -12,12 +12,16 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
 #include <functional>
 #include <mutex>
 #include <new>
+#include <sstream>
+#include <string>
 #include <vector>
 
 #include "swr.h"
@@ -48,6 +52,15 @@ struct Iface {
     int* piv = nullptr;
 };
 
+// A run of tasks of one chunk width: tasks [start, start + count) of a task
+// list, whose subdomains all have P = ceil((J_k + 1) / 64) nodes per lane.
+// Every task list is ordered by width (widest first), so each width is one
+// launch of the sweep kernel instantiated for it: a subdomain of 41 nodes
+// no longer runs with the registers and padded rows of the widest one.
+struct WidthRun {
+    int P, start, count;
+};
+
 struct swr_ctx {
     // problem
     double a0 = 0, b0 = 0, h = 0, dt = 0;
@@ -68,6 +81,10 @@ struct swr_ctx {
     int nBuild = 0;
     Task* dSub = nullptr;     // one task per (problem, subdomain)
     int nSub = 0;
+    std::vector<int> Pk;      // chunk width of each subdomain (c->P is the largest)
+    int* dPk = nullptr;
+    std::vector<WidthRun> runs_build, runs_sub, runs_L0;
+    int n_launch_sweep = 0;   // sweep kernel launches of the current call
     Iface L, L0;              // interface operator of V and of V = 0
     cd* dD = nullptr;
     cd* dG = nullptr;
@@ -125,6 +142,11 @@ struct swr_ctx {
     size_t snap_ends_size = 0;
     // convergence history of the last call (swr_info.history)
     std::vector<double> hist;
+    // schedule (swr_tune / the tuning cache): pipeline chunk of the static
+    // causal solve (0 = staged), S0^2 helper-wave task bound, GMRES restart
+    int pipe_chunk = 0;
+    int help_max = kHelpMaxTasks;
+    std::string cache_path;   // opts.tune_cache, copied (the caller's string may not outlive setup)
     // this context's GPU and its copy of the static scratch array
     int dev = 0;
     void* scratch = nullptr;
@@ -218,7 +240,7 @@ extern "C" void swr_default_opts(swr_opts* o) {
     o->checkpoint_K = 64;
     o->nl_max_iter = 100;
     o->nl_tol = 1e-14;
-    o->pipeline = 256;
+    o->pipeline = -1;
     o->plain = 0;
     o->snapshot_stride = 0;
     o->tune_cache = nullptr;
@@ -248,6 +270,8 @@ static std::vector<Task> impulse_tasks(int N, int nv) {
     return t;
 }
 
+static void load_schedule(swr_ctx* c, const char* path);
+
 extern "C" swr_status swr_setup(double a0, double b0, int N, const int* J, double dt, double T,
                                 int vk, const double* V, int tr, double s_re, double s_im,
                                 const swr_opts* opts, void* stream, swr_ctx** out) {
@@ -268,7 +292,7 @@ extern "C" swr_status swr_setup(double a0, double b0, int N, const int* J, doubl
     if (!std::isfinite(s_re) || !std::isfinite(s_im)) return SWR_EINVAL;
     if (o.batch < 1 || o.restart < 1 || o.max_iter < 1 || !(o.tol > 0)) return SWR_EINVAL;
     if (o.nl_max_iter < 1 || !(o.nl_tol > 0) || o.checkpoint_K < 1) return SWR_EINVAL;
-    if (o.pipeline < 0 || o.pipeline % kWave != 0) return SWR_EINVAL;
+    if (o.pipeline < -1 || (o.pipeline > 0 && o.pipeline % kWave != 0)) return SWR_EINVAL;
     if (o.snapshot_stride < 0) return SWR_EINVAL;
     if (vk == SWR_V_TIME && !V) return SWR_EINVAL;
     if (vk == SWR_V_CUBIC && V) return SWR_EINVAL;
@@ -299,19 +323,42 @@ extern "C" swr_status swr_setup(double a0, double b0, int N, const int* J, doubl
     for (int k = 0, acc = 0; k < N; ++k) { c->off[k] = acc; acc += J[k]; }
 
     const int nt = c->nt, B = c->B, ns = c->ns, nv = c->nv;
-    // task lists
+    c->Pk.resize(N);
+    for (int k = 0; k < N; ++k) c->Pk[k] = (J[k] + 1 + kWave - 1) / kWave;
+    // task lists, each ordered by chunk width (widest first; stable within a width)
     std::vector<Task> build = impulse_tasks(N, nv), sub, imp0 = impulse_tasks(N, 1);
     for (int b = 0; b < B; ++b)
         for (int k = 0; k < N; ++k) build.push_back(Task{k, b, vof(c, b) * N + k, T_DATA_U0 | T_OUT_G});
     for (int b = 0; b < B; ++b)
         for (int k = 0; k < N; ++k) sub.push_back(Task{k, b, vof(c, b) * N + k, 0});
+    auto by_width = [c](std::vector<Task>& list, std::vector<WidthRun>& runs) {
+        std::stable_sort(list.begin(), list.end(),
+                         [c](const Task& x, const Task& y) { return c->Pk[x.k] > c->Pk[y.k]; });
+        runs.clear();
+        for (int i = 0; i < (int)list.size(); ++i) {
+            const int P = c->Pk[list[i].k];
+            if (runs.empty() || runs.back().P != P) runs.push_back(WidthRun{P, i, 0});
+            ++runs.back().count;
+        }
+    };
+    by_width(build, c->runs_build);
+    by_width(sub, c->runs_sub);
+    by_width(imp0, c->runs_L0);
     c->nBuild = (int)build.size();
+    // default schedule; a tuning cache entry for this problem replaces it
+    c->pipe_chunk = o.pipeline >= 0 ? o.pipeline : (c->nBuild <= kPipeMaxBuild ? 256 : 0);
+    if (o.tune_cache) {
+        c->cache_path = o.tune_cache;
+        load_schedule(c, o.tune_cache);
+    }
+    c->o.tune_cache = nullptr;
     c->nSub = (int)sub.size();
     const size_t vec = (size_t)B * ns * nt;
     const size_t max_tasks = std::max(build.size(), std::max(sub.size(), imp0.size()));
     const int fields = fac_fields(c->P);
     ALLOC(c->dJ, N);
     ALLOC(c->dOff, N);
+    ALLOC(c->dPk, N);
     // beta_0 .. beta_{nt+64}, and at least beta_0 .. beta_{2*64-1} (the
     // sweep's LDS copy of the first 128 weights)
     const int nbeta = std::max(nt, kWave) + kWave + 1;
@@ -365,6 +412,7 @@ extern "C" swr_status swr_setup(double a0, double b0, int N, const int* J, doubl
         if (hipEventCreate(&e) != hipSuccess) { swr_destroy(c); return SWR_EDEVICE; }
     HIPCHK(hipMemcpyAsync(c->dJ, c->J.data(), N * sizeof(int), hipMemcpyHostToDevice, c->st));
     HIPCHK(hipMemcpyAsync(c->dOff, c->off.data(), N * sizeof(int), hipMemcpyHostToDevice, c->st));
+    HIPCHK(hipMemcpyAsync(c->dPk, c->Pk.data(), N * sizeof(int), hipMemcpyHostToDevice, c->st));
     HIPCHK(hipMemcpyAsync(c->dBuild, build.data(), build.size() * sizeof(Task), hipMemcpyHostToDevice, c->st));
     HIPCHK(hipMemcpyAsync(c->dSub, sub.data(), sub.size() * sizeof(Task), hipMemcpyHostToDevice, c->st));
     if (c->L0.tasks)
@@ -453,6 +501,9 @@ static SweepArgs sweep_args(swr_ctx* c, const Task* tasks, int ntasks, const cd*
     a.nl_stats = c->dNl;
     a.flags_and = ~0;
     a.flags_or = 0;
+    a.help_max = c->help_max;
+    a.pstride = c->P;
+    a.fstride = (size_t)fac_fields(c->P) * kWave;
     a.task0 = 0;
     a.n_begin = 0;
     a.n_end = c->nt;
@@ -466,7 +517,16 @@ static swr_status run_factor(swr_ctx* c, const double* V, int nv, cd* fac) {
     f.N = c->N; f.nx = c->nx; f.nf = nv * c->N; f.P = c->P; f.h = c->h; f.dt = c->dt;
     f.sigma = c->sigma; f.J = c->dJ; f.off = c->dOff; f.V = V; f.fac = fac;
     f.tr = c->tr; f.c2 = c->c2; f.endc = c->dEndc;
-    HIPCHK(launch_factor(f, c->st));
+    f.Pk = c->dPk;
+    f.fstride = (size_t)fac_fields(c->P) * kWave;
+    // one launch per chunk width present; each builds the records of its width
+    std::vector<int> widths(c->Pk);
+    std::sort(widths.begin(), widths.end());
+    widths.erase(std::unique(widths.begin(), widths.end()), widths.end());
+    for (int P : widths) {
+        f.P = P;
+        HIPCHK(launch_factor(f, c->st));
+    }
     return SWR_OK;
 }
 
@@ -494,10 +554,32 @@ static SweepArgs sub_args(swr_ctx* c, const SweepIO& io) {
     return a;
 }
 
+// the width runs of a task list
+static const std::vector<WidthRun>& runs_of(const swr_ctx* c, const Task* tasks) {
+    if (tasks == c->dBuild) return c->runs_build;
+    if (tasks == c->dSub) return c->runs_sub;
+    return c->runs_L0;
+}
+
+// all tasks of a's list (a.task0 = 0, a.ntasks = the whole list), one launch
+// per chunk width, in order on one stream; *launches counts the kernels
+static hipError_t launch_widths(const swr_ctx* c, SweepArgs a, int vk, hipStream_t st, bool plain,
+                                int* launches = nullptr) {
+    for (const WidthRun& r : runs_of(c, a.tasks)) {
+        a.P = r.P;
+        a.task0 = r.start;
+        a.ntasks = r.count;
+        const hipError_t e = launch_sweep(a, ktr(c), vk, st, plain);
+        if (e != hipSuccess) return e;
+        if (launches) *launches += plain ? r.count : 1;
+    }
+    return hipSuccess;
+}
+
 static swr_status run_sweeps(swr_ctx* c, const SweepIO& io) {
     SweepArgs a = sub_args(c, io);
     if (io.maxdiff) HIPCHK(hipMemsetAsync(c->dMax, 0, sizeof(unsigned long long), c->st));
-    HIPCHK(launch_sweep(a, ktr(c), c->vk, c->st, c->o.plain));
+    HIPCHK(launch_widths(c, a, c->vk, c->st, c->o.plain, &c->n_launch_sweep));
     if (io.uT) HIPCHK(launch_finalize_ut(c->N, c->nx, c->B, c->dOff, c->dEnds, io.uT, c->st));
     if (io.snaps)
         HIPCHK(launch_finalize_snaps(c->N, c->nx, c->B, nsnaps(c), c->dOff, c->dSnapEnds, io.snaps, c->st));
@@ -510,7 +592,7 @@ static swr_status run_build(swr_ctx* c, const double* u0) {
     a.u0 = reinterpret_cast<const cd*>(u0);
     a.g_in = c->dZero;
     a.g_out = c->dD;
-    HIPCHK(launch_sweep(a, ktr(c), SWR_V_STATIC, c->st, c->o.plain));
+    HIPCHK(launch_widths(c, a, SWR_V_STATIC, c->st, c->o.plain, &c->n_launch_sweep));
     c->L.dirty = true;
     return SWR_OK;
 }
@@ -520,7 +602,7 @@ static swr_status run_build_L0(swr_ctx* c) {
     CHK(run_factor(c, nullptr, 1, c->L0.fac));
     SweepArgs a = sweep_args(c, c->L0.tasks, c->L0.ntasks, c->L0.fac, c->L0.cols);
     a.g_in = c->dZero;
-    HIPCHK(launch_sweep(a, ktr(c), SWR_V_STATIC, c->st, c->o.plain));
+    HIPCHK(launch_widths(c, a, SWR_V_STATIC, c->st, c->o.plain));
     c->L0.dirty = true;
     return SWR_OK;
 }
@@ -1003,9 +1085,9 @@ struct PipeTimes {
 };
 
 static bool pipelined(const swr_ctx* c) {
-    return c->vk == SWR_V_STATIC && c->o.solver == SWR_SOLVER_CAUSAL && c->o.pipeline > 0 &&
+    return c->vk == SWR_V_STATIC && c->o.solver == SWR_SOLVER_CAUSAL && c->pipe_chunk > 0 &&
            !c->o.plain && causal_sized(c) &&
-           c->ns > 0 && c->nt > c->o.pipeline;
+           c->ns > 0 && c->nt > c->pipe_chunk;
 }
 
 static swr_status pipe_resources(swr_ctx* c, int K) {
@@ -1032,7 +1114,7 @@ static swr_status pipe_resources(swr_ctx* c, int K) {
 
 static swr_status run_static_pipelined(swr_ctx* c, const cd* u0, cd* g, const SweepIO& fin,
                                        PipeTimes* tm) {
-    const int nt = c->nt, ch = c->o.pipeline;
+    const int nt = c->nt, ch = c->pipe_chunk;
     // chunk boundaries: a short first chunk (64 steps) so the interface solve
     // starts early, then multiples of ch, and a short last chunk so the final
     // sweep ends soon after the interface solve (all multiples of 64)
@@ -1062,13 +1144,14 @@ static swr_status run_static_pipelined(swr_ctx* c, const cd* u0, cd* g, const Sw
     SweepArgs af = sub_args(c, fin);
     af.state = c->dStateF;
     c->L.dirty = true;
+    int launches = 0;
 
     // stage 1: impulse + d sweeps, chunk by chunk on st
     for (int j = 0; j < K; ++j) {
         ab.n_begin = cut[j];
         ab.n_end = cut[j + 1];
         HIPCHK(hipEventRecord(et[2 * j], st));
-        HIPCHK(launch_sweep(ab, ktr(c), SWR_V_STATIC, st));
+        HIPCHK(launch_widths(c, ab, SWR_V_STATIC, st, false, &launches));
         HIPCHK(hipEventRecord(et[2 * j + 1], st));
         HIPCHK(hipEventRecord(es[2 + j], st));
     }
@@ -1087,7 +1170,7 @@ static swr_status run_static_pipelined(swr_ctx* c, const cd* u0, cd* g, const Sw
         af.n_begin = cut[j];
         af.n_end = cut[j + 1];
         HIPCHK(hipEventRecord(et[2 * K + 2 * j], s3));
-        HIPCHK(launch_sweep(af, ktr(c), c->vk, s3));
+        HIPCHK(launch_widths(c, af, c->vk, s3, false, &launches));
         HIPCHK(hipEventRecord(et[2 * K + 2 * j + 1], s3));
     }
     if (fin.uT) HIPCHK(launch_finalize_ut(c->N, c->nx, c->B, c->dOff, c->dEnds, fin.uT, s3));
@@ -1103,7 +1186,7 @@ static swr_status run_static_pipelined(swr_ctx* c, const cd* u0, cd* g, const Sw
         tm->fin = elapsed(et[2 * K], et[4 * K - 1]);
         tm->sweep_sum = 0;
         for (int j = 0; j < 2 * K; ++j) tm->sweep_sum += elapsed(et[2 * j], et[2 * j + 1]);
-        tm->n_sweep = 2 * K;
+        tm->n_sweep = launches;
     }
     return SWR_OK;
 }
@@ -1120,6 +1203,7 @@ extern "C" swr_status swr_solve(swr_ctx* c, const double* u0d, double* uT, doubl
         }
     }
     c->hist.clear();
+    c->n_launch_sweep = 0;
     const cd* u0 = reinterpret_cast<const cd*>(u0d);
     const size_t vec = (size_t)c->B * c->ns * c->nt;
     hipStream_t st = c->st;
@@ -1265,7 +1349,7 @@ extern "C" swr_status swr_solve(swr_ctx* c, const double* u0d, double* uT, doubl
             info->n_sweep = tm.n_sweep;
         } else if (c->vk == SWR_V_STATIC && !fixed) {
             info->t_sweep_ms = info->t_build_ms + info->t_final_ms;
-            info->n_sweep = 2;
+            info->n_sweep = c->n_launch_sweep;
         }
     }
     if (nl[1]) return SWR_ENOCONV;
@@ -1318,12 +1402,138 @@ extern "C" swr_status swr_apply_R_noalloc(swr_ctx* c, const double* u0, const do
         zero_word_kernel<<<1, 1, 0, c->st>>>(word);
         HIPCHK(hipGetLastError());
     }
-    HIPCHK(launch_sweep(a, ktr(c), c->vk, c->st, c->o.plain));
+    HIPCHK(launch_widths(c, a, c->vk, c->st, c->o.plain));
     if (uT) HIPCHK(launch_finalize_ut(c->N, c->nx, c->B, c->dOff, dEnds, io.uT, c->st));
     if (maxdiff) {
         word_to_double_kernel<<<1, 1, 0, c->st>>>(word, maxdiff);
         HIPCHK(hipGetLastError());
     }
+    return SWR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Schedule tuning.  The schedule parameters change no arithmetic of any
+// result (the pipelined and staged solves, and both sweep workgroup forms,
+// are bitwise equal; the GMRES restart changes the iterate, not the
+// tolerance it meets): pipeline chunk of the static causal solve, the task
+// bound of the S0^2 helper wave, the GMRES restart.  swr_tune times candidate
+// schedules on the caller's input and keeps the fastest; the tuning cache
+// (opts.tune_cache, a text file of "key value..." lines) remembers it per
+// problem shape so a later swr_setup starts from it.
+// ---------------------------------------------------------------------------
+static std::string schedule_key(const swr_ctx* c) {
+    uint64_t h = 1469598103934665603ull;                 // FNV-1a over the subdomain sizes
+    for (int j : c->J) {
+        for (int b = 0; b < 4; ++b) { h ^= (uint64_t)((j >> (8 * b)) & 0xff); h *= 1099511628211ull; }
+    }
+    std::ostringstream k;
+    k << "N" << c->N << "_nt" << c->nt << "_B" << c->B << "_nv" << c->nv << "_vk" << c->vk << "_tr"
+      << c->tr << "_solver" << c->o.solver << "_J" << std::hex << h;
+    return k.str();
+}
+
+static void load_schedule(swr_ctx* c, const char* path) {
+    std::ifstream f(path);
+    if (!f) return;
+    const std::string key = schedule_key(c);
+    std::string line;
+    while (std::getline(f, line)) {
+        std::istringstream in(line);
+        std::string k;
+        int pipe = 0, help = 0, restart = 0;
+        if (!(in >> k >> pipe >> help >> restart) || k != key) continue;
+        if (pipe < 0 || (pipe > 0 && pipe % kWave != 0) || help < 0 || restart < 1) continue;
+        c->pipe_chunk = pipe;
+        c->help_max = help;
+        c->o.restart = restart;
+    }
+}
+
+static bool store_schedule(const swr_ctx* c, const char* path, double ms) {
+    const std::string key = schedule_key(c);
+    std::vector<std::string> keep;
+    {
+        std::ifstream f(path);
+        std::string line;
+        while (f && std::getline(f, line)) {
+            std::istringstream in(line);
+            std::string k;
+            if ((in >> k) && k == key) continue;
+            if (!line.empty()) keep.push_back(line);
+        }
+    }
+    std::ofstream f(path, std::ios::trunc);
+    if (!f) return false;
+    for (const auto& l : keep) f << l << "\n";
+    f << key << " " << c->pipe_chunk << " " << c->help_max << " " << c->o.restart << " " << ms << "\n";
+    return (bool)f;
+}
+
+extern "C" swr_status swr_tune(swr_ctx* c, const double* u0, double budget_ms, swr_schedule* chosen) {
+    if (!c || !u0 || !(budget_ms > 0)) return SWR_EINVAL;
+    if (!c->dUT) ALLOC_LIVE(c->dUT, (size_t)c->B * c->nx);
+    double* uT = reinterpret_cast<double*>(c->dUT);
+    // candidate values (the current schedule first)
+    std::vector<int> pipes{c->pipe_chunk}, helps{c->help_max}, restarts{c->o.restart};
+    if (c->vk == SWR_V_STATIC && c->o.solver == SWR_SOLVER_CAUSAL)
+        for (int p : {0, 128, 256, 512, 1024})
+            if (p < c->nt && std::find(pipes.begin(), pipes.end(), p) == pipes.end()) pipes.push_back(p);
+    if (c->tr == SWR_S02)
+        for (int h : {0, kHelpMaxTasks, 1 << 30})
+            if (std::find(helps.begin(), helps.end(), h) == helps.end()) helps.push_back(h);
+    if (c->o.solver == SWR_SOLVER_GMRES || c->vk == SWR_V_TIME)
+        for (int m : {20, 30, 60, 120})
+            if (std::find(restarts.begin(), restarts.end(), m) == restarts.end()) restarts.push_back(m);
+    const int p0 = c->pipe_chunk, h0 = c->help_max, m0 = c->o.restart;
+    double best = INFINITY;
+    int bp = p0, bh = h0, bm = m0, tried = 0;
+    double spent = 0;
+    auto t_now = [] { return std::chrono::steady_clock::now(); };
+    const auto t_start = t_now();
+    for (int m : restarts)
+        for (int p : pipes)
+            for (int h : helps) {
+                if (tried > 0 && spent > budget_ms) break;
+                c->pipe_chunk = p;
+                c->help_max = h;
+                c->o.restart = m;
+                swr_status rs = swr_solve(c, u0, uT, nullptr, nullptr, nullptr, nullptr);   // warm-up
+                if (rs != SWR_OK) continue;
+                double ms = INFINITY;
+                for (int r = 0; r < 2; ++r) {
+                    HIPCHK(hipStreamSynchronize(c->st));
+                    const auto t0 = t_now();
+                    rs = swr_solve(c, u0, uT, nullptr, nullptr, nullptr, nullptr);
+                    HIPCHK(hipStreamSynchronize(c->st));
+                    if (rs != SWR_OK) break;
+                    ms = std::min(ms, std::chrono::duration<double, std::milli>(t_now() - t0).count());
+                }
+                ++tried;
+                if (ms < best) { best = ms; bp = p; bh = h; bm = m; }
+                spent = std::chrono::duration<double, std::milli>(t_now() - t_start).count();
+            }
+    c->pipe_chunk = bp;
+    c->help_max = bh;
+    c->o.restart = bm;
+    if (chosen) {
+        chosen->pipeline = bp;
+        chosen->help_max = bh;
+        chosen->restart = bm;
+        chosen->ms = best;
+        chosen->candidates = tried;
+    }
+    if (!std::isfinite(best)) return SWR_ENOCONV;
+    if (!c->cache_path.empty() && !store_schedule(c, c->cache_path.c_str(), best)) return SWR_EINVAL;
+    return SWR_OK;
+}
+
+extern "C" swr_status swr_get_schedule(const swr_ctx* c, swr_schedule* s) {
+    if (!c || !s) return SWR_EINVAL;
+    s->pipeline = c->pipe_chunk;
+    s->help_max = c->help_max;
+    s->restart = c->o.restart;
+    s->ms = 0;
+    s->candidates = 0;
     return SWR_OK;
 }
 
@@ -1405,7 +1615,22 @@ static AdjArgs adj_args(swr_ctx* c) {
     a.hist = c->dHist2;
     a.ckpt = c->dCkpt; a.g_fwd = c->dGfwd; a.hist_fwd = c->dHist; a.seg = c->dSeg;
     a.gends = c->dGends; a.wends = c->dWends;
+    a.task0 = 0;
+    a.pstride = c->P;
+    a.fstride = (size_t)fac_fields(c->P) * kWave;
     return a;
+}
+
+// the adjoint sweep over every (problem, subdomain), one launch per chunk width
+static hipError_t launch_adjoint_widths(const swr_ctx* c, AdjArgs a, hipStream_t st) {
+    for (const WidthRun& r : c->runs_sub) {
+        a.P = r.P;
+        a.task0 = r.start;
+        a.ntasks = r.count;
+        const hipError_t e = launch_adjoint(a, ktr(c), st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 extern "C" swr_status swr_grad(swr_ctx* c, const double* u0d, const double* gbar, double* dJdV,
@@ -1464,7 +1689,7 @@ extern "C" swr_status swr_grad(swr_ctx* c, const double* u0d, const double* gbar
     a.g_in = nullptr;
     a.g_out = c->ns ? c->dDadj : nullptr;
     a.grad = 0;
-    HIPCHK(launch_adjoint(a, ktr(c), st));
+    HIPCHK(launch_adjoint_widths(c, a, st));
     HIPCHK(hipEventRecord(c->ev[2], st));
     c->hist.clear();   // the history reported is the adjoint interface solve's
     swr_status rb = solve_interface(c, c->dDadj, c->dGadj, &it_b);
@@ -1476,7 +1701,7 @@ extern "C" swr_status swr_grad(swr_ctx* c, const double* u0d, const double* gbar
     a.grad = 1;
     a.dV = dJdV;
     a.du0 = reinterpret_cast<cd*>(dJdu0);
-    HIPCHK(launch_adjoint(a, ktr(c), st));
+    HIPCHK(launch_adjoint_widths(c, a, st));
     HIPCHK(launch_finalize_grad(c->N, c->nx, c->B, c->dOff, c->dGends, c->dWends, dJdV,
                                 reinterpret_cast<cd*>(dJdu0), st));
     HIPCHK(hipEventRecord(c->ev[4], st));

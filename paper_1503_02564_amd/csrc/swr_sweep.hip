@@ -41,9 +41,9 @@ namespace swr {
 // ---------------------------------------------------------------------------
 template <int P>
 __global__ __launch_bounds__(64) void factor_kernel(FactorArgs a) {
-    using L = FacLayout<P>;
     const int f = blockIdx.x;
     const int k = f % a.N, v = f / a.N;
+    if (a.Pk && a.Pk[k] != P) return;    // another width's launch builds this record
     const int t = threadIdx.x;
     const int n = a.J[k] + 1, o = a.off[k];
     const bool lif = k > 0, rif = k < a.N - 1;
@@ -94,7 +94,7 @@ __global__ __launch_bounds__(64) void factor_kernel(FactorArgs a) {
     chunk_rows<P>(s, n, lif, rif, a.h, kap, sigL, sigR, w, wL, wR, ra, rb, rc);
     LaneFac<P> F;
     lane_factor<P>(ra, rb, rc, F);
-    store_fac<P>(a.fac + (size_t)f * L::total * kWave + t, F);
+    store_fac<P>(a.fac + (size_t)f * a.fstride + t, F);
 }
 
 

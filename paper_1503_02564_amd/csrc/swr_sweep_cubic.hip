@@ -5,7 +5,7 @@ namespace swr {
 
 template <int P>
 static void launch_p(const SweepArgs& a, int trans, hipStream_t st) {
-    if (trans == TR_S02 && a.ntasks <= kHelpMaxTasks)
+    if (trans == TR_S02 && a.ntasks <= a.help_max)
         sweep_kernel<P, TR_S02, VK_CUBIC, true><<<a.ntasks, sweep_threads(true), 0, st>>>(a);
     else if (trans == TR_S02)
         sweep_kernel<P, TR_S02, VK_CUBIC, false><<<a.ntasks, sweep_threads(false), 0, st>>>(a);

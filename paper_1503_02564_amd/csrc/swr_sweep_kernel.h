@@ -8,11 +8,11 @@
 namespace swr {
 
 // Threads per workgroup of the sweep: with HELP (S0^2, launches of at most
-// kHelpMaxTasks tasks, so every wave has a SIMD of its own) a second wave
-// sums the far history beside the sweep (far_helper below); otherwise one
-// wave does everything, with the same arithmetic in the same order.
+// SweepArgs::help_max tasks -- by default kHelpMaxTasks, so that every wave
+// has a SIMD of its own; a schedule parameter) a second wave sums the far
+// history beside the sweep (far_helper below); otherwise one wave does
+// everything, with the same arithmetic in the same order.
 __host__ __device__ constexpr int sweep_threads(bool help) { return help ? 2 * kWave : kWave; }
-constexpr int kHelpMaxTasks = 512;
 
 // The far part of the S0^2 history on the workgroup's second wave.  The main
 // wave marches blocks of 64 steps, n0 = nbeg, nbeg + 64, ...; for block n0 it
@@ -104,7 +104,6 @@ __device__ inline void far_helper(const SweepArgs& a, const cd* Ha, const cd* Hb
 // ---------------------------------------------------------------------------
 template <int P, int TR, int VK, bool HELP = false>
 __global__ __launch_bounds__(sweep_threads(HELP)) void sweep_kernel(SweepArgs a) {
-    using L = FacLayout<P>;
     static_assert(!HELP || TR == TR_S02, "the helper wave serves S0^2");
     __shared__ double sbeta[2 * kWave];       // beta_0 .. beta_127
     __shared__ cd ffa[2][kWave], ffb[2][kWave];   // S0^2: far sums from the helper wave
@@ -148,7 +147,7 @@ __global__ __launch_bounds__(sweep_threads(HELP)) void sweep_kernel(SweepArgs a)
     // start at step 0 resumes from the state the previous one saved
     const int nbeg = a.n_begin, nend = a.n_end;
     const bool first = nbeg == 0, last = nend == nt;
-    cd* stp = a.state ? a.state + (size_t)tix * 2 * P * kWave + t : nullptr;
+    cd* stp = a.state ? a.state + (size_t)tix * 2 * a.pstride * kWave + t : nullptr;
 
     // time-dependent potential: rows n and n+1 of V at my nodes
     double vprev[P], vnext[P];
@@ -160,7 +159,7 @@ __global__ __launch_bounds__(sweep_threads(HELP)) void sweep_kernel(SweepArgs a)
             vnext[q] = (s + q < n) ? Vt[(size_t)(nbeg + 1) * a.nx + s + q] : 0.0;
         }
     } else {
-        load_fac<P>(a.fac + (size_t)f * L::total * kWave + t, F);
+        load_fac<P>(a.fac + (size_t)f * a.fstride + t, F);
     }
 
     // per-node constants: mass stencil weights (P1 mass: 1,4,1 inside,
@@ -189,7 +188,7 @@ __global__ __launch_bounds__(sweep_threads(HELP)) void sweep_kernel(SweepArgs a)
 #pragma unroll
         for (int q = 0; q < P; ++q) {
             u[q] = stp[q * kWave];
-            vlast[q] = (VK == VK_CUBIC) ? stp[(P + q) * kWave] : u[q];
+            vlast[q] = (VK == VK_CUBIC) ? stp[(a.pstride + q) * kWave] : u[q];
         }
     }
     auto at_last = [&](const cd (&arr)[P]) {
@@ -208,10 +207,10 @@ __global__ __launch_bounds__(sweep_threads(HELP)) void sweep_kernel(SweepArgs a)
         Hb[0] = vb0;
     }
     // checkpoints for the adjoint: u at forward steps max(0, nt - 64 jj), jj = 1..Jc
-    cd* ck = (fl & T_CKPT) ? a.ckpt + ((size_t)tix * (a.Jc + 1) * P) * kWave + t : nullptr;
+    cd* ck = (fl & T_CKPT) ? a.ckpt + ((size_t)tix * (a.Jc + 1) * a.pstride) * kWave + t : nullptr;
     if (ck && first) {
 #pragma unroll
-        for (int q = 0; q < P; ++q) ck[((size_t)a.Jc * P + q) * kWave] = u[q];
+        for (int q = 0; q < P; ++q) ck[((size_t)a.Jc * a.pstride + q) * kWave] = u[q];
     }
     // snapshots u_n, n = 0, stride, 2 stride, ...: interior nodes straight to
     // the output, the two end nodes to a side store (averaged across the
@@ -500,7 +499,7 @@ __global__ __launch_bounds__(sweep_threads(HELP)) void sweep_kernel(SweepArgs a)
             if (ck && nstep < nt && ((nt - nstep) & (kWave - 1)) == 0) {
                 const int jj = (nt - nstep) / kWave;
 #pragma unroll
-                for (int q = 0; q < P; ++q) ck[((size_t)jj * P + q) * kWave] = u[q];
+                for (int q = 0; q < P; ++q) ck[((size_t)jj * a.pstride + q) * kWave] = u[q];
             }
             const cd va = rdlane(x[0], 0);
             const cd vb = at_last(x);
@@ -567,7 +566,7 @@ __global__ __launch_bounds__(sweep_threads(HELP)) void sweep_kernel(SweepArgs a)
 #pragma unroll
         for (int q = 0; q < P; ++q) {
             stp[q * kWave] = u[q];
-            if (VK == VK_CUBIC) stp[(P + q) * kWave] = vlast[q];
+            if (VK == VK_CUBIC) stp[(a.pstride + q) * kWave] = vlast[q];
         }
     }
     if ((fl & T_OUT_UT) && last) {

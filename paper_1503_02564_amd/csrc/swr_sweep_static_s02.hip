@@ -1,14 +1,14 @@
 // swr_sweep_static_s02.hip -- instantiates the subdomain sweep for a
 // time-independent potential with the S0^2 transmission, in both workgroup
 // forms (with the far-history helper wave for launches of at most
-// kHelpMaxTasks tasks, one wave otherwise; same arithmetic).
+// help_max tasks (a schedule parameter), one wave otherwise; same arithmetic).
 #include "swr_sweep_kernel.h"
 
 namespace swr {
 
 template <int P>
 static void launch_p(const SweepArgs& a, hipStream_t st) {
-    if (a.ntasks <= kHelpMaxTasks)
+    if (a.ntasks <= a.help_max)
         sweep_kernel<P, TR_S02, VK_STATIC, true><<<a.ntasks, sweep_threads(true), 0, st>>>(a);
     else
         sweep_kernel<P, TR_S02, VK_STATIC, false><<<a.ntasks, sweep_threads(false), 0, st>>>(a);

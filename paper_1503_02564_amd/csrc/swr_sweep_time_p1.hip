@@ -8,7 +8,7 @@ namespace swr {
 
 template <int P>
 hipError_t launch_sweep_time_p(const SweepArgs& a, int trans, hipStream_t st) {
-    if (trans == TR_S02 && a.ntasks <= kHelpMaxTasks)
+    if (trans == TR_S02 && a.ntasks <= a.help_max)
         sweep_kernel<P, TR_S02, VK_TIME, true><<<a.ntasks, sweep_threads(true), 0, st>>>(a);
     else if (trans == TR_S02)
         sweep_kernel<P, TR_S02, VK_TIME, false><<<a.ntasks, sweep_threads(false), 0, st>>>(a);

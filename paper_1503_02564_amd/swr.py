@@ -65,10 +65,19 @@ class SwrInfo(ctypes.Structure):
         return d
 
 
+class SwrSchedule(ctypes.Structure):
+    _fields_ = [("pipeline", ctypes.c_int), ("help_max", ctypes.c_int), ("restart", ctypes.c_int),
+                ("ms", ctypes.c_double), ("candidates", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 # exported symbols of include/swr.h
 EXPORTS = ("swr_default_opts", "swr_strerror", "swr_setup", "swr_solve", "swr_grad",
            "swr_apply_R", "swr_build_interface", "swr_interface_matvec", "swr_destroy",
-           "swr_sizes", "swr_set_potential", "swr_apply_R_noalloc")
+           "swr_sizes", "swr_set_potential", "swr_tune", "swr_get_schedule",
+           "swr_apply_R_noalloc")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
@@ -101,6 +110,10 @@ _L.swr_sizes.argtypes = [_P] + [_I] * 7
 _L.swr_sizes.restype = ctypes.c_int
 _L.swr_set_potential.argtypes = [_P, _P]
 _L.swr_set_potential.restype = ctypes.c_int
+_L.swr_tune.argtypes = [_P, _P, ctypes.c_double, ctypes.POINTER(SwrSchedule)]
+_L.swr_tune.restype = ctypes.c_int
+_L.swr_get_schedule.argtypes = [_P, ctypes.POINTER(SwrSchedule)]
+_L.swr_get_schedule.restype = ctypes.c_int
 
 
 class SwrError(RuntimeError):
@@ -275,6 +288,22 @@ def swr_interface_matvec(ctx, x, y):
 def swr_set_potential(ctx, V):
     z = _sizes(ctx)
     _check(_L.swr_set_potential(ctx, _arr(V, "d", z.v_count(), "V")), "swr_set_potential")
+
+
+def swr_tune(ctx, u0, budget_ms=2000.0):
+    """Time candidate schedules on u0 and keep the fastest (see swr_tune in
+    include/swr.h); returns the chosen SwrSchedule."""
+    z = _sizes(ctx)
+    out = SwrSchedule()
+    _check(_L.swr_tune(ctx, _arr(u0, "c", z.B * z.nx, "u0"), float(budget_ms), ctypes.byref(out)),
+           "swr_tune")
+    return out
+
+
+def swr_get_schedule(ctx):
+    out = SwrSchedule()
+    _check(_L.swr_get_schedule(ctx, ctypes.byref(out)), "swr_get_schedule")
+    return out
 
 
 def swr_sizes(ctx):

@@ -40,7 +40,7 @@ def test_defaults_and_strerror(swr):
     o = swr.swr_default_opts()
     assert o.tol == 1e-10 and o.restart == 30 and o.batch == 1
     assert o.solver == swr.SWR_SOLVER_CAUSAL and o.checkpoint_K == 64
-    assert o.pipeline == 256 and o.plain == 0 and o.nl_max_iter == 100
+    assert o.pipeline == -1 and o.plain == 0 and o.nl_max_iter == 100
     for s in range(6):
         assert swr.swr_strerror(s)
     assert swr.swr_strerror(99) == "unknown status"

@@ -155,7 +155,9 @@ def test_pipelined_solve_equals_staged_solve(dev, label, J, nt, trans, sigma, B,
         torch.cuda.synchronize()
         assert st == swr.SWR_OK and info.residual < 1e-11
         if ch:
-            assert info.n_sweep == 2 * _pipeline_chunks(nt, ch)
+            # one sweep launch per chunk and chunk width (ceil((J + 1) / 64) nodes per lane)
+            widths = len({(int(j) + 64) // 64 for j in J})
+            assert info.n_sweep == 2 * _pipeline_chunks(nt, ch) * widths
         out[ch] = (to_np(uT), to_np(g), to_np(tr))
         pb.close()
     for a, b in zip(out[0], out[chunk]):

@@ -1,0 +1,70 @@
+"""The autotuner (swr_tune) and its cache.  Schedules change how the work is
+launched, never the arithmetic of a result: the solve with the tuned
+schedule equals the default one bit for bit (pipeline chunk, helper-wave
+bound).  The cache written by swr_tune is read back by a later swr_setup of
+the same problem shape and ignored by another shape."""
+import numpy as np
+import pytest
+
+from paper_1503_02564_amd import workloads as W
+from tests.gpu_util import say, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+def _problem(wl, cache=None, **kw):
+    from paper_1503_02564_amd import swr
+    o = swr.swr_default_opts()
+    o.batch = wl.B
+    if cache is not None:
+        o.tune_cache = cache.encode()
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return swr.Problem(wl.a0, wl.b0, tuple(int(j) for j in wl.J), wl.dt, wl.dt * wl.nt, wl.vkind,
+                       wl.trans, wl.sigma, o, to_dev(np.asarray(wl.V, np.float64)))
+
+
+def test_tuned_schedule_gives_the_same_result_and_is_cached(dev, tmp_path):
+    import torch
+    from paper_1503_02564_amd import swr
+    wl = W.static_packet(N=16, cells=96, nt=600)
+    cache = str(tmp_path / "swr_schedules.txt")
+    pb = _problem(wl, cache)
+    default = swr.swr_get_schedule(pb.ctx).as_dict()
+    say("tune", "default schedule", default)
+    assert default["pipeline"] == 256            # 46 build tasks: the pipelined form
+    u0 = to_dev(wl.u0)
+    u_def = torch.zeros_like(u0)
+    st, _ = swr.swr_solve(pb.ctx, u0, u_def)
+    assert st == swr.SWR_OK
+    chosen = swr.swr_tune(pb.ctx, u0, budget_ms=3000.0)
+    say("tune", "chosen", chosen.as_dict())
+    assert chosen.candidates >= 2 and np.isfinite(chosen.ms)
+    assert chosen.pipeline in (0, 128, 256, 512) and chosen.help_max >= 0
+    assert swr.swr_get_schedule(pb.ctx).as_dict()["pipeline"] == chosen.pipeline
+    u_tuned = torch.zeros_like(u0)
+    st, _ = swr.swr_solve(pb.ctx, u0, u_tuned)
+    assert st == swr.SWR_OK
+    assert np.array_equal(to_np(u_def), to_np(u_tuned))
+    pb.close()
+    text = open(cache).read()
+    assert text.count("\n") == 1
+    # a later setup of the same shape starts from the cached schedule ...
+    pb2 = _problem(wl, cache)
+    s2 = swr.swr_get_schedule(pb2.ctx)
+    assert (s2.pipeline, s2.help_max, s2.restart) == (chosen.pipeline, chosen.help_max, chosen.restart)
+    pb2.close()
+    # ... another shape does not
+    other = W.static_packet(N=12, cells=96, nt=600)
+    pb3 = _problem(other, cache)
+    assert swr.swr_get_schedule(pb3.ctx).as_dict() == swr.swr_get_schedule(
+        _problem(other).ctx).as_dict()
+    pb3.close()
+
+
+def test_default_schedule_is_staged_when_sweeps_fill_the_gpu(dev):
+    from paper_1503_02564_amd import swr
+    wl = W.batched_uneven(N=100, B=48, nt=128)   # 100 * 48 + 198 build tasks > 4096
+    pb = _problem(wl)
+    assert swr.swr_get_schedule(pb.ctx).pipeline == 0
+    pb.close()
