@@ -150,6 +150,9 @@ typedef struct {
     int help_max;     /* S0^2 sweeps: launches of at most this many tasks give every task a
                          second wave that sums the far boundary history */
     int restart;      /* GMRES restart length */
+    int pair_from;    /* static Robin / S0^2 sweeps: launches that fill the GPU with one-wave
+                         tasks run two tasks of one subdomain per wave from this chunk width
+                         (ceil((J_k + 1) / 64) nodes per lane) on; 9 = never (default) */
     double ms;        /* swr_tune: wall time of the chosen schedule's solve */
     int candidates;   /* swr_tune: schedules timed */
 } swr_schedule;
@@ -260,6 +263,7 @@ swr_status swr_set_potential(swr_ctx* ctx, const double* V);
 
 /* The autotuner: times candidate schedules (pipeline chunks 0, 128, 256, 512,
  * 1024 for the static causal solve; helper-wave bounds 0, 512, all for S0^2;
+ * two-task waves from widths 1, 4 or never for static Robin / S0^2 sweeps;
  * restarts 20, 30, 60, 120 for GMRES and the V(t,x) iteration) with full
  * solves of the caller's u0 [B][nx] (one warm-up and the best of two timed
  * solves each), until budget_ms of wall time is spent, and keeps the fastest
@@ -273,6 +277,11 @@ swr_status swr_tune(swr_ctx* ctx, const double* u0, double budget_ms, swr_schedu
 
 /* The schedule a context runs with (host out). */
 swr_status swr_get_schedule(const swr_ctx* ctx, swr_schedule* s);
+
+/* Set the schedule of a context (host in; ms and candidates are ignored).
+ * SWR_EINVAL for a pipeline chunk that is negative or not a multiple of 64, a
+ * negative helper bound, a restart or pair width below 1. */
+swr_status swr_set_schedule(swr_ctx* ctx, const swr_schedule* s);
 
 /* Release the context and all device memory it owns. */
 void swr_destroy(swr_ctx* ctx);

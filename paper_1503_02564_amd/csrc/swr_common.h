@@ -215,6 +215,13 @@ constexpr int kMaxP = 8;
 // kernels only find CUs between them, so one stage after the other is faster)
 constexpr int kHelpMaxTasks = 512;
 constexpr int kPipeMaxBuild = 4096;
+// chunk width from which filled launches run two tasks per wave (a schedule
+// parameter; kMaxP + 1 = never).  Measured on the batched-uneven workload the
+// one-task sweep is bound by instruction issue, not by its dependency chain:
+// two tasks per wave take twice as long per step (widths 4-7: 14.1-16.2 ms
+// per launch of two-task waves against 10.3-12.8 ms of one-task waves for
+// the same tasks), so the default is never
+constexpr int kPairFrom = kMaxP + 1;
 
 struct SweepArgs {
     int N, nt, B, nx, ns;        // ns = 2N-2 interface slots
@@ -250,6 +257,7 @@ struct SweepArgs {
     cd* state;                   // [ntasks][2][P][64] u_n and v_n carried between launches
     const EndCoef* endc;         // TR_GEN: [nf][2] end coefficients (left, right)
     int help_max;                // S0^2: launches of at most this many tasks use the helper wave
+    const int2* pairs;           // two-task waves: [.] task indices (second -1 for a single)
     int pstride;                 // chunk-width stride of the per-task state and checkpoint
                                  // records (the context's largest width; a launch's own P may
                                  // be smaller: subdomains are grouped by width)
@@ -311,6 +319,9 @@ hipError_t launch_sweep_static(const SweepArgs& a, int trans, hipStream_t st);
 hipError_t launch_sweep_static_s02(const SweepArgs& a, hipStream_t st);
 hipError_t launch_sweep_time(const SweepArgs& a, int trans, hipStream_t st);
 hipError_t launch_sweep_cubic(const SweepArgs& a, int trans, hipStream_t st);
+// static potential, Robin or S0^2: a.ntasks waves of two tasks each, the
+// pairs a.pairs[a.task0 ..] (swr_sweep_pair.hip)
+hipError_t launch_sweep_pairs(const SweepArgs& a, int trans, hipStream_t st);
 hipError_t launch_finalize_ut(int N, int nx, int B, const int* off, const cd* ends, cd* uT,
                               hipStream_t st);
 // the same for every snapshot: ends [B][S][N][2] -> snaps [B][S][nx]

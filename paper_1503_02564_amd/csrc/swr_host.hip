@@ -59,6 +59,7 @@ struct Iface {
 // no longer runs with the registers and padded rows of the widest one.
 struct WidthRun {
     int P, start, count;
+    int pstart, pcount;   // its waves of two tasks in the list's pair table
 };
 
 struct swr_ctx {
@@ -84,6 +85,8 @@ struct swr_ctx {
     std::vector<int> Pk;      // chunk width of each subdomain (c->P is the largest)
     int* dPk = nullptr;
     std::vector<WidthRun> runs_build, runs_sub, runs_L0;
+    int2* dPairsB = nullptr;  // pair tables of the build and the per-(problem, subdomain) lists
+    int2* dPairsS = nullptr;
     int n_launch_sweep = 0;   // sweep kernel launches of the current call
     Iface L, L0;              // interface operator of V and of V = 0
     cd* dD = nullptr;
@@ -146,6 +149,7 @@ struct swr_ctx {
     // causal solve (0 = staged), S0^2 helper-wave task bound, GMRES restart
     int pipe_chunk = 0;
     int help_max = kHelpMaxTasks;
+    int pair_from = kPairFrom;   // two tasks per wave from this chunk width on (9: never)
     std::string cache_path;   // opts.tune_cache, copied (the caller's string may not outlive setup)
     // this context's GPU and its copy of the static scratch array
     int dev = 0;
@@ -331,19 +335,36 @@ extern "C" swr_status swr_setup(double a0, double b0, int N, const int* J, doubl
         for (int k = 0; k < N; ++k) build.push_back(Task{k, b, vof(c, b) * N + k, T_DATA_U0 | T_OUT_G});
     for (int b = 0; b < B; ++b)
         for (int k = 0; k < N; ++k) sub.push_back(Task{k, b, vof(c, b) * N + k, 0});
-    auto by_width = [c](std::vector<Task>& list, std::vector<WidthRun>& runs) {
-        std::stable_sort(list.begin(), list.end(),
-                         [c](const Task& x, const Task& y) { return c->Pk[x.k] > c->Pk[y.k]; });
+    // ordered by width, then by factor record, so that tasks sharing a record
+    // are neighbours; each run of a width is cut into waves of two tasks of
+    // one record (a record with an odd count leaves a single)
+    auto by_width = [c](std::vector<Task>& list, std::vector<WidthRun>& runs, std::vector<int2>* pairs) {
+        std::stable_sort(list.begin(), list.end(), [c](const Task& x, const Task& y) {
+            if (c->Pk[x.k] != c->Pk[y.k]) return c->Pk[x.k] > c->Pk[y.k];
+            return x.f < y.f;
+        });
         runs.clear();
         for (int i = 0; i < (int)list.size(); ++i) {
             const int P = c->Pk[list[i].k];
-            if (runs.empty() || runs.back().P != P) runs.push_back(WidthRun{P, i, 0});
+            if (runs.empty() || runs.back().P != P) runs.push_back(WidthRun{P, i, 0, 0, 0});
             ++runs.back().count;
         }
+        if (!pairs) return;
+        pairs->clear();
+        for (WidthRun& r : runs) {
+            r.pstart = (int)pairs->size();
+            for (int i = r.start; i < r.start + r.count;) {
+                const bool two = i + 1 < r.start + r.count && list[i + 1].f == list[i].f;
+                pairs->push_back(make_int2(i, two ? i + 1 : -1));
+                i += two ? 2 : 1;
+            }
+            r.pcount = (int)pairs->size() - r.pstart;
+        }
     };
-    by_width(build, c->runs_build);
-    by_width(sub, c->runs_sub);
-    by_width(imp0, c->runs_L0);
+    std::vector<int2> pairs_build, pairs_sub;
+    by_width(build, c->runs_build, &pairs_build);
+    by_width(sub, c->runs_sub, &pairs_sub);
+    by_width(imp0, c->runs_L0, nullptr);
     c->nBuild = (int)build.size();
     // default schedule; a tuning cache entry for this problem replaces it
     c->pipe_chunk = o.pipeline >= 0 ? o.pipeline : (c->nBuild <= kPipeMaxBuild ? 256 : 0);
@@ -368,6 +389,8 @@ extern "C" swr_status swr_setup(double a0, double b0, int N, const int* J, doubl
     ALLOC(c->dEnds, (size_t)B * N * 2);
     ALLOC(c->dBuild, build.size());
     ALLOC(c->dSub, sub.size());
+    ALLOC(c->dPairsB, pairs_build.size());
+    ALLOC(c->dPairsS, pairs_sub.size());
     ALLOC(c->dD, vec);
     ALLOC(c->dG, vec);
     ALLOC(c->dG2, vec);
@@ -415,6 +438,10 @@ extern "C" swr_status swr_setup(double a0, double b0, int N, const int* J, doubl
     HIPCHK(hipMemcpyAsync(c->dPk, c->Pk.data(), N * sizeof(int), hipMemcpyHostToDevice, c->st));
     HIPCHK(hipMemcpyAsync(c->dBuild, build.data(), build.size() * sizeof(Task), hipMemcpyHostToDevice, c->st));
     HIPCHK(hipMemcpyAsync(c->dSub, sub.data(), sub.size() * sizeof(Task), hipMemcpyHostToDevice, c->st));
+    HIPCHK(hipMemcpyAsync(c->dPairsB, pairs_build.data(), pairs_build.size() * sizeof(int2),
+                          hipMemcpyHostToDevice, c->st));
+    HIPCHK(hipMemcpyAsync(c->dPairsS, pairs_sub.data(), pairs_sub.size() * sizeof(int2),
+                          hipMemcpyHostToDevice, c->st));
     if (c->L0.tasks)
         HIPCHK(hipMemcpyAsync(c->L0.tasks, imp0.data(), imp0.size() * sizeof(Task), hipMemcpyHostToDevice, c->st));
     HIPCHK(hipMemsetAsync(c->dZero, 0, vec * sizeof(cd), c->st));
@@ -561,15 +588,36 @@ static const std::vector<WidthRun>& runs_of(const swr_ctx* c, const Task* tasks)
     return c->runs_L0;
 }
 
+static const int2* pairs_of(const swr_ctx* c, const Task* tasks) {
+    if (tasks == c->dBuild) return c->dPairsB;
+    if (tasks == c->dSub) return c->dPairsS;
+    return nullptr;
+}
+
 // all tasks of a's list (a.task0 = 0, a.ntasks = the whole list), one launch
-// per chunk width, in order on one stream; *launches counts the kernels
+// per chunk width, in order on one stream; *launches counts the kernels.  A
+// run that fills the GPU with one-wave tasks (more than help_max of them) of
+// a width >= pair_from runs two tasks per wave where it has pairs (static
+// potential, Robin or S0^2): the same arithmetic per task.
 static hipError_t launch_widths(const swr_ctx* c, SweepArgs a, int vk, hipStream_t st, bool plain,
                                 int* launches = nullptr) {
+    const int2* pairs = pairs_of(c, a.tasks);
+    const int tr = ktr(c);
     for (const WidthRun& r : runs_of(c, a.tasks)) {
         a.P = r.P;
-        a.task0 = r.start;
-        a.ntasks = r.count;
-        const hipError_t e = launch_sweep(a, ktr(c), vk, st, plain);
+        const bool two = !plain && pairs && vk == SWR_V_STATIC && (tr == TR_S02 || tr == TR_ROBIN) &&
+                         r.P >= c->pair_from && r.count > c->help_max && 4 * r.pcount <= 3 * r.count;
+        hipError_t e;
+        if (two) {
+            a.pairs = pairs;
+            a.task0 = r.pstart;
+            a.ntasks = r.pcount;
+            e = launch_sweep_pairs(a, tr, st);
+        } else {
+            a.task0 = r.start;
+            a.ntasks = r.count;
+            e = launch_sweep(a, tr, vk, st, plain);
+        }
         if (e != hipSuccess) return e;
         if (launches) *launches += plain ? r.count : 1;
     }
@@ -1440,12 +1488,13 @@ static void load_schedule(swr_ctx* c, const char* path) {
     while (std::getline(f, line)) {
         std::istringstream in(line);
         std::string k;
-        int pipe = 0, help = 0, restart = 0;
-        if (!(in >> k >> pipe >> help >> restart) || k != key) continue;
-        if (pipe < 0 || (pipe > 0 && pipe % kWave != 0) || help < 0 || restart < 1) continue;
+        int pipe = 0, help = 0, restart = 0, pair = 0;
+        if (!(in >> k >> pipe >> help >> restart >> pair) || k != key) continue;
+        if (pipe < 0 || (pipe > 0 && pipe % kWave != 0) || help < 0 || restart < 1 || pair < 1) continue;
         c->pipe_chunk = pipe;
         c->help_max = help;
         c->o.restart = restart;
+        c->pair_from = pair;
     }
 }
 
@@ -1465,7 +1514,8 @@ static bool store_schedule(const swr_ctx* c, const char* path, double ms) {
     std::ofstream f(path, std::ios::trunc);
     if (!f) return false;
     for (const auto& l : keep) f << l << "\n";
-    f << key << " " << c->pipe_chunk << " " << c->help_max << " " << c->o.restart << " " << ms << "\n";
+    f << key << " " << c->pipe_chunk << " " << c->help_max << " " << c->o.restart << " " << c->pair_from
+      << " " << ms << "\n";
     return (bool)f;
 }
 
@@ -1474,7 +1524,7 @@ extern "C" swr_status swr_tune(swr_ctx* c, const double* u0, double budget_ms, s
     if (!c->dUT) ALLOC_LIVE(c->dUT, (size_t)c->B * c->nx);
     double* uT = reinterpret_cast<double*>(c->dUT);
     // candidate values (the current schedule first)
-    std::vector<int> pipes{c->pipe_chunk}, helps{c->help_max}, restarts{c->o.restart};
+    std::vector<int> pipes{c->pipe_chunk}, helps{c->help_max}, restarts{c->o.restart}, pairs{c->pair_from};
     if (c->vk == SWR_V_STATIC && c->o.solver == SWR_SOLVER_CAUSAL)
         for (int p : {0, 128, 256, 512, 1024})
             if (p < c->nt && std::find(pipes.begin(), pipes.end(), p) == pipes.end()) pipes.push_back(p);
@@ -1484,19 +1534,24 @@ extern "C" swr_status swr_tune(swr_ctx* c, const double* u0, double budget_ms, s
     if (c->o.solver == SWR_SOLVER_GMRES || c->vk == SWR_V_TIME)
         for (int m : {20, 30, 60, 120})
             if (std::find(restarts.begin(), restarts.end(), m) == restarts.end()) restarts.push_back(m);
-    const int p0 = c->pipe_chunk, h0 = c->help_max, m0 = c->o.restart;
+    if (c->vk == SWR_V_STATIC && c->tr <= SWR_S02)
+        for (int w : {1, 4, kMaxP + 1})
+            if (std::find(pairs.begin(), pairs.end(), w) == pairs.end()) pairs.push_back(w);
+    const int p0 = c->pipe_chunk, h0 = c->help_max, m0 = c->o.restart, w0 = c->pair_from;
     double best = INFINITY;
-    int bp = p0, bh = h0, bm = m0, tried = 0;
+    int bp = p0, bh = h0, bm = m0, bw = w0, tried = 0;
     double spent = 0;
     auto t_now = [] { return std::chrono::steady_clock::now(); };
     const auto t_start = t_now();
     for (int m : restarts)
+        for (int w : pairs)
         for (int p : pipes)
             for (int h : helps) {
                 if (tried > 0 && spent > budget_ms) break;
                 c->pipe_chunk = p;
                 c->help_max = h;
                 c->o.restart = m;
+                c->pair_from = w;
                 swr_status rs = swr_solve(c, u0, uT, nullptr, nullptr, nullptr, nullptr);   // warm-up
                 if (rs != SWR_OK) continue;
                 double ms = INFINITY;
@@ -1509,16 +1564,18 @@ extern "C" swr_status swr_tune(swr_ctx* c, const double* u0, double budget_ms, s
                     ms = std::min(ms, std::chrono::duration<double, std::milli>(t_now() - t0).count());
                 }
                 ++tried;
-                if (ms < best) { best = ms; bp = p; bh = h; bm = m; }
+                if (ms < best) { best = ms; bp = p; bh = h; bm = m; bw = w; }
                 spent = std::chrono::duration<double, std::milli>(t_now() - t_start).count();
             }
     c->pipe_chunk = bp;
     c->help_max = bh;
     c->o.restart = bm;
+    c->pair_from = bw;
     if (chosen) {
         chosen->pipeline = bp;
         chosen->help_max = bh;
         chosen->restart = bm;
+        chosen->pair_from = bw;
         chosen->ms = best;
         chosen->candidates = tried;
     }
@@ -1527,11 +1584,24 @@ extern "C" swr_status swr_tune(swr_ctx* c, const double* u0, double budget_ms, s
     return SWR_OK;
 }
 
+extern "C" swr_status swr_set_schedule(swr_ctx* c, const swr_schedule* s) {
+    if (!c || !s) return SWR_EINVAL;
+    if (s->pipeline < 0 || (s->pipeline > 0 && s->pipeline % kWave != 0) || s->help_max < 0 ||
+        s->restart < 1 || s->pair_from < 1)
+        return SWR_EINVAL;
+    c->pipe_chunk = s->pipeline;
+    c->help_max = s->help_max;
+    c->o.restart = s->restart;
+    c->pair_from = s->pair_from;
+    return SWR_OK;
+}
+
 extern "C" swr_status swr_get_schedule(const swr_ctx* c, swr_schedule* s) {
     if (!c || !s) return SWR_EINVAL;
     s->pipeline = c->pipe_chunk;
     s->help_max = c->help_max;
     s->restart = c->o.restart;
+    s->pair_from = c->pair_from;
     s->ms = 0;
     s->candidates = 0;
     return SWR_OK;

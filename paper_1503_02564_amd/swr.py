@@ -67,7 +67,7 @@ class SwrInfo(ctypes.Structure):
 
 class SwrSchedule(ctypes.Structure):
     _fields_ = [("pipeline", ctypes.c_int), ("help_max", ctypes.c_int), ("restart", ctypes.c_int),
-                ("ms", ctypes.c_double), ("candidates", ctypes.c_int)]
+                ("pair_from", ctypes.c_int), ("ms", ctypes.c_double), ("candidates", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -76,7 +76,7 @@ class SwrSchedule(ctypes.Structure):
 # exported symbols of include/swr.h
 EXPORTS = ("swr_default_opts", "swr_strerror", "swr_setup", "swr_solve", "swr_grad",
            "swr_apply_R", "swr_build_interface", "swr_interface_matvec", "swr_destroy",
-           "swr_sizes", "swr_set_potential", "swr_tune", "swr_get_schedule",
+           "swr_sizes", "swr_set_potential", "swr_tune", "swr_get_schedule", "swr_set_schedule",
            "swr_apply_R_noalloc")
 
 if not os.path.exists(LIB_PATH):
@@ -114,6 +114,8 @@ _L.swr_tune.argtypes = [_P, _P, ctypes.c_double, ctypes.POINTER(SwrSchedule)]
 _L.swr_tune.restype = ctypes.c_int
 _L.swr_get_schedule.argtypes = [_P, ctypes.POINTER(SwrSchedule)]
 _L.swr_get_schedule.restype = ctypes.c_int
+_L.swr_set_schedule.argtypes = [_P, ctypes.POINTER(SwrSchedule)]
+_L.swr_set_schedule.restype = ctypes.c_int
 
 
 class SwrError(RuntimeError):
@@ -304,6 +306,17 @@ def swr_get_schedule(ctx):
     out = SwrSchedule()
     _check(_L.swr_get_schedule(ctx, ctypes.byref(out)), "swr_get_schedule")
     return out
+
+
+def swr_set_schedule(ctx, pipeline=None, help_max=None, restart=None, pair_from=None):
+    """Change some parameters of the context's schedule (the rest stay)."""
+    cur = swr_get_schedule(ctx)
+    for k, v in (("pipeline", pipeline), ("help_max", help_max), ("restart", restart),
+                 ("pair_from", pair_from)):
+        if v is not None:
+            setattr(cur, k, int(v))
+    _check(_L.swr_set_schedule(ctx, ctypes.byref(cur)), "swr_set_schedule")
+    return cur
 
 
 def swr_sizes(ctx):

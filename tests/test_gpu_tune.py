@@ -68,3 +68,50 @@ def test_default_schedule_is_staged_when_sweeps_fill_the_gpu(dev):
     pb = _problem(wl)
     assert swr.swr_get_schedule(pb.ctx).pipeline == 0
     pb.close()
+
+
+PAIR_CASES = [
+    # (label, J, nt, trans, sigma, B, pipeline): odd batches leave single tasks
+    ("s02-staged", [60, 90, 75, 128, 200, 47, 250], 300, W.S02, 0j, 3, 0),
+    ("s02-pipelined", [60, 90, 75, 128, 200, 47, 250], 300, W.S02, 0j, 4, 64),
+    ("robin-staged", [50, 70, 300, 33], 200, W.ROBIN, 1 - 1j, 3, 0),
+]
+
+
+@pytest.mark.parametrize("label,J,nt,trans,sigma,B,pipeline", PAIR_CASES)
+def test_two_task_waves_equal_one_task_waves(dev, label, J, nt, trans, sigma, B, pipeline):
+    """Sweeps that run two tasks of one subdomain per wave (forced here for
+    every width and launch size) perform each task's arithmetic exactly as
+    the one-task waves: u(T), g, end-node traces, snapshots and the adjoint's
+    gradients are bitwise equal; u(T) matches the monodomain oracle."""
+    import torch
+    import oracle as O
+    from paper_1503_02564_amd import swr
+    from tests.gpu_util import rel
+    wl = W.small_case(J=J, nt=nt, trans=trans, sigma=sigma, B=B, seed=29, a0=-12.0, b0=12.0)
+    out = {}
+    for pair in (False, True):
+        say("two-task waves", label, "pairs", pair)
+        pb = _problem(wl, pipeline=pipeline, snapshot_stride=50)
+        if pair:
+            swr.swr_set_schedule(pb.ctx, help_max=0, pair_from=1)
+        else:
+            swr.swr_set_schedule(pb.ctx, pair_from=9)
+        u0 = to_dev(wl.u0)
+        uT = torch.zeros_like(u0)
+        g = torch.zeros((B, pb.ns, nt), dtype=torch.complex128, device=dev)
+        tr = torch.zeros((B, wl.N, 2, nt + 1), dtype=torch.complex128, device=dev)
+        sn = torch.zeros((B, nt // 50 + 1, wl.nx), dtype=torch.complex128, device=dev)
+        st, info = swr.swr_solve(pb.ctx, u0, uT, g, tr, sn)
+        assert st == swr.SWR_OK and info.residual < 1e-10
+        dV = torch.zeros((B, wl.nx), dtype=torch.float64, device=dev)
+        du0 = torch.zeros_like(u0)
+        st2, _ = swr.swr_grad(pb.ctx, u0, (2.0 * uT).contiguous(), dV, du0)
+        assert st2 == swr.SWR_OK
+        torch.cuda.synchronize()
+        out[pair] = [to_np(x) for x in (uT, g, tr, sn, dV, du0)]
+        pb.close()
+    for x, y in zip(out[False], out[True]):
+        assert np.array_equal(x, y)
+    for b in range(B):
+        assert rel(out[True][0][b], O.mono(wl, wl.u0[b])) < 1e-10
