@@ -153,6 +153,10 @@ typedef struct {
     int pair_from;    /* static Robin / S0^2 sweeps: launches that fill the GPU with one-wave
                          tasks run two tasks of one subdomain per wave from this chunk width
                          (ceil((J_k + 1) / 64) nodes per lane) on; 9 = never (default) */
+    int graph;        /* static causal solve: 1 = from the second solve with the same potential,
+                         output pointers and schedule, replay the whole solve as one HIP graph
+                         captured on the context's streams (bitwise the same results; no
+                         per-stage timings in swr_info); 0 = launch kernel by kernel (default) */
     double ms;        /* swr_tune: wall time of the chosen schedule's solve */
     int candidates;   /* swr_tune: schedules timed */
 } swr_schedule;
@@ -264,7 +268,8 @@ swr_status swr_set_potential(swr_ctx* ctx, const double* V);
 /* The autotuner: times candidate schedules (pipeline chunks 0, 128, 256, 512,
  * 1024 for the static causal solve; helper-wave bounds 0, 512, all for S0^2;
  * two-task waves from widths 1, 4 or never for static Robin / S0^2 sweeps;
- * restarts 20, 30, 60, 120 for GMRES and the V(t,x) iteration) with full
+ * graph replay on and off for the static causal solve; restarts 20, 30, 60,
+ * 120 for GMRES and the V(t,x) iteration) with full
  * solves of the caller's u0 [B][nx] (one warm-up and the best of two timed
  * solves each), until budget_ms of wall time is spent, and keeps the fastest
  * on the context.  With opts.tune_cache the choice is written to that file

@@ -50,6 +50,7 @@ struct Iface {
     cd* Minv = nullptr;
     cd* Mwork = nullptr;
     int* piv = nullptr;
+    int built_version = -1;  // potential version the causal set-up above was built from
 };
 
 // A run of tasks of one chunk width: tasks [start, start + count) of a task
@@ -150,6 +151,25 @@ struct swr_ctx {
     int pipe_chunk = 0;
     int help_max = kHelpMaxTasks;
     int pair_from = kPairFrom;   // two tasks per wave from this chunk width on (9: never)
+    int graph = 0;               // 1: capture the static causal solve once, replay it
+    int v_version = 0;           // bumped whenever the potential changes
+    // the captured solve and the arguments it was captured with
+    hipGraph_t g_graph = nullptr;
+    hipGraphExec_t g_exec = nullptr;
+    hipStream_t gs = nullptr;    // capture stream (the caller's may be the null stream)
+    struct GraphKey {
+        const void* u0;
+        void *uT, *g, *tr, *sn;
+        int pipe, help, pair, vver;
+        bool operator==(const GraphKey& o) const {
+            return u0 == o.u0 && uT == o.uT && g == o.g && tr == o.tr && sn == o.sn && pipe == o.pipe &&
+                   help == o.help && pair == o.pair && vver == o.vver;
+        }
+    } g_key{};
+    // arguments of the last uncaptured static causal solve that succeeded:
+    // every buffer, stream and event a capture with them uses exists
+    GraphKey warm_key{};
+    bool warm = false;
     std::string cache_path;   // opts.tune_cache, copied (the caller's string may not outlive setup)
     // this context's GPU and its copy of the static scratch array
     int dev = 0;
@@ -228,6 +248,21 @@ static void* scratch_address(int dev) {
 }
 
 __global__ void zero_word_kernel(unsigned long long* w) { *w = 0ull; }
+// graph-safe fills and copies (kernels, not memset/memcpy nodes)
+__global__ void zero_ints_kernel(int* p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+__global__ void copy_cd_kernel(const cd* src, cd* dst, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+static hipError_t launch_copy_cd(const cd* src, cd* dst, size_t n, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    const size_t blocks = std::min<size_t>((n + 255) / 256, 4096);
+    copy_cd_kernel<<<(unsigned)blocks, 256, 0, st>>>(src, dst, n);
+    return hipGetLastError();
+}
 __global__ void word_to_double_kernel(const unsigned long long* w, double* out) {
     *out = __longlong_as_double((long long)*w);
 }
@@ -457,6 +492,9 @@ extern "C" void swr_destroy(swr_ctx* c) {
     if (!c) return;
     if (c->st) hipStreamSynchronize(c->st);
     else hipDeviceSynchronize();
+    if (c->g_exec) hipGraphExecDestroy(c->g_exec);
+    if (c->g_graph) hipGraphDestroy(c->g_graph);
+    if (c->gs) hipStreamDestroy(c->gs);
     if (c->s2) hipStreamSynchronize(c->s2);
     if (c->s3) hipStreamSynchronize(c->s3);
     for (void* p : c->allocs) hipFree(p);
@@ -907,7 +945,13 @@ static swr_status run_causal(swr_ctx* c, Iface& I, const cd* d, cd* g, hipStream
     const int ns = c->ns, nt = c->nt, B = c->B, ni = c->N - 1;
     const bool fast_ok = causal_fast_ok(c);
     const bool gen_ok = causal_gen_ok(c);
+    // the impulse responses were rebuilt from the same potential as at the
+    // last set-up: same columns bit for bit, so the PCR records, the level
+    // count and the path stay valid (no set-up kernels, no host read-back)
+    const int ver = (&I == &c->L) ? c->v_version : 0;
+    if (I.dirty && I.built_version == ver) I.dirty = false;
     if (I.dirty) {
+        I.built_version = ver;
         I.path = 3;
         if (fast_ok || gen_ok) {
             const size_t rec = fast_ok ? causal_fast_rec() : (size_t)pcr_rec_gen(c->N);
@@ -1161,7 +1205,7 @@ static swr_status pipe_resources(swr_ctx* c, int K) {
 }
 
 static swr_status run_static_pipelined(swr_ctx* c, const cd* u0, cd* g, const SweepIO& fin,
-                                       PipeTimes* tm) {
+                                       PipeTimes* tm, bool timing = true) {
     const int nt = c->nt, ch = c->pipe_chunk;
     // chunk boundaries: a short first chunk (64 steps) so the interface solve
     // starts early, then multiples of ch, and a short last chunk so the final
@@ -1198,9 +1242,9 @@ static swr_status run_static_pipelined(swr_ctx* c, const cd* u0, cd* g, const Sw
     for (int j = 0; j < K; ++j) {
         ab.n_begin = cut[j];
         ab.n_end = cut[j + 1];
-        HIPCHK(hipEventRecord(et[2 * j], st));
+        if (timing) HIPCHK(hipEventRecord(et[2 * j], st));
         HIPCHK(launch_widths(c, ab, SWR_V_STATIC, st, false, &launches));
-        HIPCHK(hipEventRecord(et[2 * j + 1], st));
+        if (timing) HIPCHK(hipEventRecord(et[2 * j + 1], st));
         HIPCHK(hipEventRecord(es[2 + j], st));
     }
     // stage 2: causal interface solve on s2 (its set-up reads the first
@@ -1210,16 +1254,16 @@ static swr_status run_static_pipelined(swr_ctx* c, const cd* u0, cd* g, const Sw
     // the host to issue every interface launch first.
     for (int j = 0; j < K; ++j) {
         HIPCHK(hipStreamWaitEvent(s2, es[2 + j], 0));
-        if (j == 0) HIPCHK(hipEventRecord(et[4 * K], s2));
+        if (timing && j == 0) HIPCHK(hipEventRecord(et[4 * K], s2));
         CHK(run_causal(c, c->L, c->dD, g, s2, cut[j], cut[j + 1]));
         HIPCHK(hipEventRecord(es[2 + K + j], s2));
-        if (j == K - 1) HIPCHK(hipEventRecord(et[4 * K + 1], s2));
+        if (timing && j == K - 1) HIPCHK(hipEventRecord(et[4 * K + 1], s2));
         HIPCHK(hipStreamWaitEvent(s3, es[2 + K + j], 0));
         af.n_begin = cut[j];
         af.n_end = cut[j + 1];
-        HIPCHK(hipEventRecord(et[2 * K + 2 * j], s3));
+        if (timing) HIPCHK(hipEventRecord(et[2 * K + 2 * j], s3));
         HIPCHK(launch_widths(c, af, c->vk, s3, false, &launches));
-        HIPCHK(hipEventRecord(et[2 * K + 2 * j + 1], s3));
+        if (timing) HIPCHK(hipEventRecord(et[2 * K + 2 * j + 1], s3));
     }
     if (fin.uT) HIPCHK(launch_finalize_ut(c->N, c->nx, c->B, c->dOff, c->dEnds, fin.uT, s3));
     if (fin.snaps)
@@ -1227,7 +1271,7 @@ static swr_status run_static_pipelined(swr_ctx* c, const cd* u0, cd* g, const Sw
     // join back onto st
     HIPCHK(hipEventRecord(ev_join, s3));
     HIPCHK(hipStreamWaitEvent(st, ev_join, 0));
-    if (tm) {
+    if (tm && timing) {
         HIPCHK(hipEventSynchronize(ev_join));
         tm->build = elapsed(et[0], et[2 * K - 1]);
         tm->iface = elapsed(et[4 * K], et[4 * K + 1]);
@@ -1237,6 +1281,112 @@ static swr_status run_static_pipelined(swr_ctx* c, const cd* u0, cd* g, const Sw
         tm->n_sweep = launches;
     }
     return SWR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// The static causal solve as one HIP graph (schedule option graph).  Once the
+// causal set-up is cached (the second solve with the same potential), every
+// step of the solve -- factorisation, impulse and d sweeps, causal interface
+// solve, final sweep, the residual's norms -- is a kernel on the context's
+// streams with no host decision in between, so it is captured once per set of
+// output pointers and schedule and replayed; only the residual's read-back
+// stays outside.  Same kernels, same arguments, same order: the replay is
+// bitwise the uncaptured solve.  The graph holds kernels and event waits only
+// (no memset or memcpy nodes).
+// ---------------------------------------------------------------------------
+static swr_ctx::GraphKey graph_key(const swr_ctx* c, const double* u0, double* uT, double* g,
+                                   double* tr, double* sn) {
+    return swr_ctx::GraphKey{u0, uT, g, tr, sn, c->pipe_chunk, c->help_max, c->pair_from, c->v_version};
+}
+
+static bool graph_ready(const swr_ctx* c, const swr_ctx::GraphKey& key) {
+    const bool shape = c->graph && c->vk == SWR_V_STATIC && c->o.solver == SWR_SOLVER_CAUSAL &&
+                       !c->o.plain && c->ns > 0 && c->L.built_version == c->v_version &&
+                       (c->L.path == 1 || c->L.path == 2 || c->L.path == 3);
+    return shape && ((c->warm && key == c->warm_key) || (c->g_exec && key == c->g_key));
+}
+
+// everything of a static causal solve up to the residual's norms (dNrm, dBn)
+static swr_status enqueue_static_causal(swr_ctx* c, const cd* u0, cd* uT, cd* g, cd* utrace, cd* snaps) {
+    const size_t vec = (size_t)c->B * c->ns * c->nt;
+    hipStream_t st = c->st;
+    CHK(run_factor(c, c->dV, c->nv, c->L.fac));
+    SweepIO io;
+    io.u0 = u0; io.g_in = c->dG; io.g_out = c->dG2;
+    io.uT = uT; io.trace = utrace; io.snaps = snaps;
+    if (pipelined(c)) {
+        CHK(run_static_pipelined(c, u0, c->dG, io, nullptr, false));
+    } else {
+        CHK(run_build(c, reinterpret_cast<const double*>(u0)));
+        const swr_status rs = run_causal(c, c->L, c->dD, c->dG, st, 0, c->nt);
+        if (rs != SWR_OK) return rs == kCausalOff ? SWR_EINVAL : rs;
+        CHK(run_sweeps(c, io));
+    }
+    if (g) HIPCHK(launch_copy_cd(c->dG, g, vec, st));
+    const long M = (long)c->ns * c->nt;
+    HIPCHK(launch_axpby(c->dG, 1.0, c->dG2, -1.0, c->dT1, (long)vec, st));
+    HIPCHK(launch_norm(c->dT1, M, c->B, c->dPart, c->dNrm, st));
+    HIPCHK(launch_norm(c->dD, M, c->B, c->dPart, c->dBn, st));
+    return SWR_OK;
+}
+
+static swr_status solve_graph(swr_ctx* c, const swr_ctx::GraphKey& key, const double* u0d, double* uT,
+                              double* g, double* utrace, double* snaps, swr_info* info) {
+    hipStream_t st = c->st;
+    if (!c->g_exec || !(key == c->g_key)) {
+        if (c->g_exec) { hipGraphExecDestroy(c->g_exec); c->g_exec = nullptr; }
+        if (c->g_graph) { hipGraphDestroy(c->g_graph); c->g_graph = nullptr; }
+        // captured on a stream of the context's own (the null stream cannot
+        // be captured): every helper enqueues on c->st, so it points there
+        // while the capture runs; nothing executes until the launch below
+        if (!c->gs) HIPCHK(hipStreamCreateWithFlags(&c->gs, hipStreamNonBlocking));
+        HIPCHK(hipStreamBeginCapture(c->gs, hipStreamCaptureModeRelaxed));
+        c->st = c->gs;
+        const swr_status es = enqueue_static_causal(c, reinterpret_cast<const cd*>(u0d), reinterpret_cast<cd*>(uT),
+                                                    reinterpret_cast<cd*>(g), reinterpret_cast<cd*>(utrace),
+                                                    reinterpret_cast<cd*>(snaps));
+        c->st = st;
+        hipGraph_t graph = nullptr;
+        const hipError_t ee = hipStreamEndCapture(c->gs, &graph);
+        if (es != SWR_OK || ee != hipSuccess || !graph) {
+            if (graph) hipGraphDestroy(graph);
+            return es != SWR_OK ? es : SWR_EDEVICE;
+        }
+        if (hipGraphInstantiate(&c->g_exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+            hipGraphDestroy(graph);
+            c->g_exec = nullptr;
+            return SWR_EDEVICE;
+        }
+        c->g_graph = graph;
+        c->g_key = key;
+    }
+    HIPCHK(hipEventRecord(c->ev[0], st));
+    HIPCHK(hipGraphLaunch(c->g_exec, st));
+    HIPCHK(hipEventRecord(c->ev[4], st));
+    std::vector<double> a(c->B), bnv(c->B);
+    int nl[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(a.data(), c->dNrm, sizeof(double) * c->B, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(bnv.data(), c->dBn, sizeof(double) * c->B, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(nl, c->dNl, sizeof(nl), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    double res = 0;
+    for (int b = 0; b < c->B; ++b) {
+        const double r = bnv[b] > 0 ? a[b] / bnv[b] : a[b];
+        if (!std::isfinite(r)) return SWR_ENAN;
+        res = std::max(res, r);
+    }
+    c->hist.push_back(res);
+    if (info) {
+        // one pass, timed as a whole (no per-stage events inside the graph)
+        *info = swr_info{};
+        info->iters = 1;
+        info->residual = res;
+        info->nl_worst = nl[0];
+        info->t_total_ms = elapsed(c->ev[0], c->ev[4]);
+        info->history = c->hist.data();
+        info->history_len = (int)c->hist.size();
+    }
+    return nl[1] ? SWR_ENOCONV : SWR_OK;
 }
 
 extern "C" swr_status swr_solve(swr_ctx* c, const double* u0d, double* uT, double* g, double* utrace,
@@ -1259,7 +1409,10 @@ extern "C" swr_status swr_solve(swr_ctx* c, const double* u0d, double* uT, doubl
     int iters = 0;
     double fixed_last = 0;
     c->inner_iters = 0;
-    HIPCHK(hipMemsetAsync(c->dNl, 0, 2 * sizeof(int), st));
+    zero_ints_kernel<<<1, 2, 0, st>>>(c->dNl, 2);
+    HIPCHK(hipGetLastError());
+    const swr_ctx::GraphKey gkey = graph_key(c, u0d, uT, g, utrace, snaps);
+    if (graph_ready(c, gkey)) return solve_graph(c, gkey, u0d, uT, g, utrace, snaps, info);
     HIPCHK(hipEventRecord(c->ev[0], st));
     // 1. assembly + factorisation
     if (c->vk == SWR_V_STATIC) CHK(run_factor(c, c->dV, c->nv, c->L.fac));
@@ -1401,6 +1554,10 @@ extern "C" swr_status swr_solve(swr_ctx* c, const double* u0d, double* uT, doubl
         }
     }
     if (nl[1]) return SWR_ENOCONV;
+    if (rs == SWR_OK && c->vk == SWR_V_STATIC && c->o.solver == SWR_SOLVER_CAUSAL) {
+        c->warm_key = gkey;
+        c->warm = true;
+    }
     return rs;
 }
 
@@ -1491,10 +1648,14 @@ static void load_schedule(swr_ctx* c, const char* path) {
         int pipe = 0, help = 0, restart = 0, pair = 0;
         if (!(in >> k >> pipe >> help >> restart >> pair) || k != key) continue;
         if (pipe < 0 || (pipe > 0 && pipe % kWave != 0) || help < 0 || restart < 1 || pair < 1) continue;
+        // then "graph ms", or "ms" alone in lines written before the graph option
+        std::vector<std::string> rest;
+        for (std::string t; in >> t;) rest.push_back(t);
         c->pipe_chunk = pipe;
         c->help_max = help;
         c->o.restart = restart;
         c->pair_from = pair;
+        c->graph = rest.size() >= 2 && rest[0] == "1" ? 1 : 0;
     }
 }
 
@@ -1515,7 +1676,7 @@ static bool store_schedule(const swr_ctx* c, const char* path, double ms) {
     if (!f) return false;
     for (const auto& l : keep) f << l << "\n";
     f << key << " " << c->pipe_chunk << " " << c->help_max << " " << c->o.restart << " " << c->pair_from
-      << " " << ms << "\n";
+      << " " << c->graph << " " << ms << "\n";
     return (bool)f;
 }
 
@@ -1524,7 +1685,9 @@ extern "C" swr_status swr_tune(swr_ctx* c, const double* u0, double budget_ms, s
     if (!c->dUT) ALLOC_LIVE(c->dUT, (size_t)c->B * c->nx);
     double* uT = reinterpret_cast<double*>(c->dUT);
     // candidate values (the current schedule first)
-    std::vector<int> pipes{c->pipe_chunk}, helps{c->help_max}, restarts{c->o.restart}, pairs{c->pair_from};
+    std::vector<int> pipes{c->pipe_chunk}, helps{c->help_max}, restarts{c->o.restart}, pairs{c->pair_from},
+        graphs{c->graph};
+    if (c->vk == SWR_V_STATIC && c->o.solver == SWR_SOLVER_CAUSAL) graphs.push_back(1 - c->graph);
     if (c->vk == SWR_V_STATIC && c->o.solver == SWR_SOLVER_CAUSAL)
         for (int p : {0, 128, 256, 512, 1024})
             if (p < c->nt && std::find(pipes.begin(), pipes.end(), p) == pipes.end()) pipes.push_back(p);
@@ -1537,14 +1700,15 @@ extern "C" swr_status swr_tune(swr_ctx* c, const double* u0, double budget_ms, s
     if (c->vk == SWR_V_STATIC && c->tr <= SWR_S02)
         for (int w : {1, 4, kMaxP + 1})
             if (std::find(pairs.begin(), pairs.end(), w) == pairs.end()) pairs.push_back(w);
-    const int p0 = c->pipe_chunk, h0 = c->help_max, m0 = c->o.restart, w0 = c->pair_from;
+    const int p0 = c->pipe_chunk, h0 = c->help_max, m0 = c->o.restart, w0 = c->pair_from, q0 = c->graph;
     double best = INFINITY;
-    int bp = p0, bh = h0, bm = m0, bw = w0, tried = 0;
+    int bp = p0, bh = h0, bm = m0, bw = w0, bq = q0, tried = 0;
     double spent = 0;
     auto t_now = [] { return std::chrono::steady_clock::now(); };
     const auto t_start = t_now();
     for (int m : restarts)
         for (int w : pairs)
+        for (int q : graphs)
         for (int p : pipes)
             for (int h : helps) {
                 if (tried > 0 && spent > budget_ms) break;
@@ -1552,7 +1716,10 @@ extern "C" swr_status swr_tune(swr_ctx* c, const double* u0, double budget_ms, s
                 c->help_max = h;
                 c->o.restart = m;
                 c->pair_from = w;
-                swr_status rs = swr_solve(c, u0, uT, nullptr, nullptr, nullptr, nullptr);   // warm-up
+                c->graph = q;
+                // warm-up (with a graph: the uncaptured solve, then the capture)
+                swr_status rs = swr_solve(c, u0, uT, nullptr, nullptr, nullptr, nullptr);
+                if (rs == SWR_OK && q) rs = swr_solve(c, u0, uT, nullptr, nullptr, nullptr, nullptr);
                 if (rs != SWR_OK) continue;
                 double ms = INFINITY;
                 for (int r = 0; r < 2; ++r) {
@@ -1564,18 +1731,20 @@ extern "C" swr_status swr_tune(swr_ctx* c, const double* u0, double budget_ms, s
                     ms = std::min(ms, std::chrono::duration<double, std::milli>(t_now() - t0).count());
                 }
                 ++tried;
-                if (ms < best) { best = ms; bp = p; bh = h; bm = m; bw = w; }
+                if (ms < best) { best = ms; bp = p; bh = h; bm = m; bw = w; bq = q; }
                 spent = std::chrono::duration<double, std::milli>(t_now() - t_start).count();
             }
     c->pipe_chunk = bp;
     c->help_max = bh;
     c->o.restart = bm;
     c->pair_from = bw;
+    c->graph = bq;
     if (chosen) {
         chosen->pipeline = bp;
         chosen->help_max = bh;
         chosen->restart = bm;
         chosen->pair_from = bw;
+        chosen->graph = bq;
         chosen->ms = best;
         chosen->candidates = tried;
     }
@@ -1593,6 +1762,7 @@ extern "C" swr_status swr_set_schedule(swr_ctx* c, const swr_schedule* s) {
     c->help_max = s->help_max;
     c->o.restart = s->restart;
     c->pair_from = s->pair_from;
+    c->graph = s->graph ? 1 : 0;
     return SWR_OK;
 }
 
@@ -1602,6 +1772,7 @@ extern "C" swr_status swr_get_schedule(const swr_ctx* c, swr_schedule* s) {
     s->help_max = c->help_max;
     s->restart = c->o.restart;
     s->pair_from = c->pair_from;
+    s->graph = c->graph;
     s->ms = 0;
     s->candidates = 0;
     return SWR_OK;
@@ -1635,6 +1806,7 @@ extern "C" swr_status swr_set_potential(swr_ctx* c, const double* V) {
                                             : (size_t)c->nx * (c->o.v_per_problem ? c->B : 1);
     HIPCHK(hipMemcpyAsync(c->dV, V, vn * sizeof(double), hipMemcpyDeviceToDevice, c->st));
     c->L.dirty = true;
+    ++c->v_version;
     return SWR_OK;
 }
 
