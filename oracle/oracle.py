@@ -39,7 +39,8 @@ __all__ = [
     "sweep", "slot_map", "apply_R", "apply_R0", "local_solution", "classical",
     "impulse_columns", "ltt_apply", "brute_L", "gmres", "bicgstab", "causal_solve",
     "interface_d", "new_algorithm", "preconditioned_time", "preconditioned_cubic",
-    "adjoint_mono", "potential_of", "end_data", "sbar", "mono_ld",
+    "adjoint_mono", "potential_of", "end_data", "sbar", "mono_ld", "pade_coef", "pade_eval",
+    "pade_apply",
 ]
 
 _LIB = None
@@ -63,7 +64,7 @@ def lib():
         L.orc_mono_cn.argtypes = [_I, _D, _D, _I, _I, _C, _C, _C, _C, _C, _I, _D, _C]
         L.orc_mono_cn.restype = _I
         L.orc_sub_sweep.argtypes = [_I, _D, _D, _I, _I, _C, _I, _I, _I, _I, _I, _D, _D, _C,
-                                    _C, _C, _C, _C, _C, _C, _C, _C, _C, _C, _I, _D, _C]
+                                    _C, _C, _C, _C, _C, _C, _C, _C, _C, _C, _I, _D, _C, _I, _D]
         L.orc_sub_sweep.restype = _I
         L.orc_mono_adjoint.argtypes = [_I, _D, _D, _I, _C, _C, _C, _C, _C]
         L.orc_mono_adjoint.restype = _I
@@ -71,6 +72,10 @@ def lib():
         L.orc_mono_cn_ld.argtypes = [_I, _D, _D, _I, _I, _C, _C, _C, _I, _D, _C]
         L.orc_mono_cn_ld.restype = _I
         L.orc_sbar_apply.argtypes = [_I, _I, _D, _C, _C, _C, _C, _C, _C]
+        L.orc_pade_coef.argtypes = [_I, _D, _C, _C]
+        L.orc_pade_eval.argtypes = [_I, _D, _D, _D, _C]
+        L.orc_pade_apply.argtypes = [_I, _I, _D, _I, _D, _C, _C, _C, _C, _C]
+        L.orc_pade_apply.restype = _I
         _LIB = L
     return _LIB
 
@@ -222,6 +227,36 @@ def mono_ld(wl: Workload, u0, V=None, nl_maxit=100, nl_tol=1e-17):
     return uT
 
 
+def pade_coef(m: int, theta: float):
+    """(a[0..m], d[0..m]) of the Pade strategy: sqrt(z) ~ sum_s a_s -
+    sum_{s>=1} a_s d_s / (z + d_s) (Sec. 2.2; reading in swr_oracle.c)."""
+    a = np.zeros(m + 1, np.complex128)
+    d = np.zeros(m + 1, np.complex128)
+    lib().orc_pade_coef(m, theta, _p(a), _p(d))
+    return a, d
+
+
+def pade_eval(m: int, theta: float, z: complex) -> complex:
+    """The rational approximation of sqrt(z) above at one point."""
+    out = np.zeros(2)
+    lib().orc_pade_eval(m, theta, float(np.real(z)), float(np.imag(z)), _p(out))
+    return complex(out[0], out[1])
+
+
+def pade_apply(order: int, m: int, theta: float, dt: float, v, W, dW):
+    """Sbar v_n, n = 1..nt, of S2^{order,m} on a given sequence v (index 0 is
+    returned as 0): returns (full, without the order-4 term)."""
+    v = _cvec(v)
+    nt = len(v) - 1
+    W, dW = (np.ascontiguousarray(np.broadcast_to(x, (nt + 1,)), np.float64) for x in (W, dW))
+    out = np.zeros(nt + 1, np.complex128)
+    out_s = np.zeros(nt + 1, np.complex128)
+    rc = lib().orc_pade_apply(order, m, theta, nt, dt, _p(v), _p(W), _p(dW), _p(out), _p(out_s))
+    if rc:
+        raise ValueError(f"pade_apply rc={rc}")
+    return out, out_s
+
+
 # ---------------------------------------------------------------------------
 # One subdomain over the whole window (eq. AvML / AvMNL, eq. TransmissionCond_disc)
 # ---------------------------------------------------------------------------
@@ -253,7 +288,8 @@ def sweep(wl: Workload, k: int, u0=None, l=None, r=None, hist0=None, V=None,
                              wl.sigma.real, wl.sigma.imag, _p(bt), _p(u0l), _p(h0),
                              _p(la), _p(ra), _p(out["rhoL"]), _p(out["rhoR"]), _p(out["uT"]),
                              _p(out["va"]), _p(out["vb"]), _p(out["v_all"]),
-                             nl_maxit, nl_tol, ctypes.byref(worst))
+                             nl_maxit, nl_tol, ctypes.byref(worst), int(wl.pade_m),
+                             float(wl.pade_theta))
     if rc:
         raise RuntimeError(f"sub_sweep failed rc={rc}")
     out["nl_worst"] = worst.value

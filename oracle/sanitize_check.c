@@ -40,7 +40,11 @@ int orc_sub_sweep(int n, double h, double dt, int nt, int vkind, const double *V
                   int trans, double sigma_re, double sigma_im, const double *beta,
                   const cplx *u0, const cplx *hist0, const cplx *l, const cplx *r,
                   cplx *rhoL, cplx *rhoR, cplx *uT, cplx *va, cplx *vb, cplx *v_all,
-                  int nl_maxit, double nl_tol, int *nl_worst);
+                  int nl_maxit, double nl_tol, int *nl_worst, int pade_m, double pade_theta);
+void orc_pade_coef(int m, double theta, cplx *a, cplx *d);
+void orc_pade_eval(int m, double theta, double zr, double zi, double *out);
+int orc_pade_apply(int order, int m, double theta, int nt, double dt, const cplx *v,
+                   const double *W, const double *dW, cplx *out, cplx *out_s);
 int orc_mono_adjoint(int nx, double h, double dt, int nt, const double *V,
                      const cplx *v_all, const cplx *gbar, double *dV, cplx *du0);
 
@@ -92,6 +96,15 @@ int main(void)
     for (int vk = 0; vk <= 1; ++vk) {
         orc_end_data(vk, vk ? Vt : Vs, NX, NSUB, +1, h, dt, NT, W, dW, calW);
         for (int kind = 1; kind <= 5; ++kind) orc_sbar_apply(kind, NT, dt, vend, W, dW, calW, out, out_s);
+        for (int order = 2; order <= 4; order += 2)
+            EXPECT(orc_pade_apply(order, 7, M_PI / 4, NT, dt, vend, W, dW, out, out_s) == 0);
+    }
+    EXPECT(orc_pade_apply(3, 7, M_PI / 4, NT, dt, vend, W, dW, out, out_s) == -5);
+    {
+        cplx pa[8], pd[8];
+        double z[2];
+        orc_pade_coef(7, M_PI / 4, pa, pd);
+        orc_pade_eval(7, M_PI / 4, 1.0, 2000.0, z);
     }
 
     /* one subdomain sweep per operator and potential kind: nodes NSUB..NSUB+NSUB
@@ -100,19 +113,22 @@ int main(void)
     const int n = NSUB + 1;
     cplx l[NT], r[NT], rhoL[NT], rhoR[NT], uTs[NSUB + 1], va[NT + 1], vb[NT + 1], vsub[NT * (NSUB + 1)];
     for (int i = 0; i < NT; ++i) { l[i] = 0.1 * i + 0.2 * I; r[i] = -0.05 * i + 0.1 * I; }
-    for (int trans = 0; trans <= 5; ++trans)
+    for (int trans = 0; trans <= 7; ++trans)
         for (int vk = 0; vk <= 2; ++vk) {
             const double *V = vk == 0 ? Vs : (vk == 1 ? Vt : NULL);
             const int rc = orc_sub_sweep(n, h, dt, NT, vk, V, NX, NSUB, 1, 1, trans, 1.0, -1.0, beta,
                                          u0 + NSUB, NULL, l, r, rhoL, rhoR, uTs, va, vb, vsub,
-                                         100, 1e-14, &worst);
+                                         100, 1e-14, &worst, 7, M_PI / 4);
             /* the operators beyond S0^2 are refused with |u|^2 */
             EXPECT(rc == ((trans > 1 && vk == 2) ? -4 : 0));
         }
     EXPECT(orc_sub_sweep(n, h, dt, NT, 0, Vs, NX, 0, 0, 1, 1, 0.0, 0.0, beta, NULL, NULL, NULL,
-                         NULL, NULL, NULL, uTs, NULL, NULL, NULL, 100, 1e-14, &worst) == 0);
+                         NULL, NULL, NULL, uTs, NULL, NULL, NULL, 100, 1e-14, &worst, 0, 0.0) == 0);
     EXPECT(orc_sub_sweep(n, h, dt, NT, 0, Vs, NX, NX - n, 1, 0, 1, 0.0, 0.0, beta, NULL, NULL, NULL,
-                         NULL, NULL, NULL, uTs, NULL, NULL, NULL, 100, 1e-14, &worst) == 0);
+                         NULL, NULL, NULL, uTs, NULL, NULL, NULL, 100, 1e-14, &worst, 0, 0.0) == 0);
+    /* a Pade sweep with no auxiliary functions is refused */
+    EXPECT(orc_sub_sweep(n, h, dt, NT, 0, Vs, NX, NSUB, 1, 1, 6, 0.0, 0.0, beta, NULL, NULL, NULL,
+                         NULL, NULL, NULL, uTs, NULL, NULL, NULL, 100, 1e-14, &worst, 0, 0.0) == -5);
     if (fails) return 1;
     printf("ok\n");
     return 0;

@@ -23,6 +23,8 @@
  *   S1^4 : adds - i sgn(dn W_n) q_n e^{i calW_n} (dt/2) sum gamma_{n-s} q_s e^{-i calW_s} v_s,
  *          q_n = sqrt(|dn W_n|)/2
  *   Robin: Sbar v_n = sigma v_n (the caller passes the complex sigma of dn + sigma)
+ *   S2^{2,m}, S2^{4,m} (Pade strategy): Sbar v_n from m auxiliary functions
+ *          phi^s (and psi for order 4), see orc_pade_coef / pade_parts
  */
 #define _GNU_SOURCE
 #include <complex.h>
@@ -136,7 +138,9 @@ int orc_thomas(int n, const cplx *diag, const cplx *off, const cplx *rhs, cplx *
 /* Potential kinds */
 enum { ORC_V_STATIC = 0, ORC_V_TIME = 1, ORC_V_CUBIC = 2 };
 /* Transmission kinds */
-enum { ORC_ROBIN = 0, ORC_S02 = 1, ORC_S03 = 2, ORC_S04 = 3, ORC_S12 = 4, ORC_S14 = 5 };
+enum { ORC_ROBIN = 0, ORC_S02 = 1, ORC_S03 = 2, ORC_S04 = 3, ORC_S12 = 4, ORC_S14 = 5,
+       ORC_P22 = 6, ORC_P24 = 7 };
+#define ORC_PADE_MAX 1024
 
 /* W_n on n nodes starting at global node offset `off0`.
  * Static: W = V(x).  Time dependent: W_n = (V_n + V_{n-1})/2 (eq. CNS_L),
@@ -358,6 +362,134 @@ void orc_sbar_apply(int kind, int nt, double dt, const cplx *v, const double *W,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Pade approximation strategy (Sec. 2.1 "l=2", Sec. 2.2).  S2^2 is           */
+/* -i sqrt(i d_t + V) with the square root replaced by the rational function  */
+/*     sqrt(z) ~ sum_{s=0}^m a_s - sum_{s=1}^m a_s d_s / (z + d_s),           */
+/* whose coefficients the paper takes from its references without stating   */
+/* them.  Reading: the diagonal [m/m] Pade approximant of sqrt(1 + w) at     */
+/* w = 0 in its partial-fraction form                                        */
+/*     R_m(w) = 1 + sum_{s=1}^m A_s w / (1 + B_s w),                           */
+/*     A_s = 2/(2m+1) sin^2(s pi/(2m+1)),  B_s = cos^2(s pi/(2m+1))            */
+/* (Baker & Graves-Morris, "Pade Approximants"; Milinazzo, Zala & Brooke,    */
+/* J. Acoust. Soc. Am. 101 (1997), which also rotates the branch cut), with  */
+/* the cut rotated by theta: sqrt(z) = e^{i theta/2} sqrt(1 + w),            */
+/* w = e^{-i theta} z - 1.  From w/(1 + B w) = (1 - 1/(1 + B w))/B and       */
+/* 1 + B w = B e^{-i theta} (z + e^{i theta}(1 - B)/B) the paper's form has  */
+/*     d_s = e^{i theta} (1 - B_s) / B_s,                                      */
+/*     a_s = e^{i theta/2} A_s / (B_s (1 - B_s))            (s >= 1),          */
+/*     a_0 = e^{i theta/2} R_m(-1)            (the value of the form at z = 0).*/
+/* a[0..m], d[0..m] (d[0] = 0, unused).                                      */
+/* ------------------------------------------------------------------------ */
+void orc_pade_coef(int m, double theta, cplx *a, cplx *d)
+{
+    const cplx rot = cexp(I * theta / 2.0);
+    double r_at_minus1 = 1.0;
+    a[0] = 0;
+    d[0] = 0;
+    for (int s = 1; s <= m; ++s) {
+        const double ang = s * M_PI / (2.0 * m + 1.0);
+        const double A = 2.0 / (2.0 * m + 1.0) * sin(ang) * sin(ang);
+        const double B = cos(ang) * cos(ang);
+        d[s] = cexp(I * theta) * (1.0 - B) / B;
+        a[s] = rot * A / (B * (1.0 - B));
+        r_at_minus1 += A * (-1.0) / (1.0 - B);
+    }
+    a[0] = rot * r_at_minus1;
+}
+
+/* The rational function above at z (test access to the coefficients). */
+void orc_pade_eval(int m, double theta, double zr, double zi, double *out)
+{
+    cplx *a = malloc(sizeof(cplx) * (size_t)(m + 1)), *d = malloc(sizeof(cplx) * (size_t)(m + 1));
+    orc_pade_coef(m, theta, a, d);
+    const cplx z = zr + I * zi;
+    cplx r = 0;
+    for (int s = 0; s <= m; ++s) r += a[s];
+    for (int s = 1; s <= m; ++s) r -= a[s] * d[s] / (z + d[s]);
+    out[0] = creal(r);
+    out[1] = cimag(r);
+    free(a); free(d);
+}
+
+/* Sbar_2^{2,m} / Sbar_2^{4,m} at step n and one end (Sec. 2.2), with c =     */
+/* 2i/dt, W = W_n and dW = dn W_n at the end:                                 */
+/*   Sbar_2^2 v_n = -i (sum_{s=0}^m a_s) v_n                                  */
+/*                  + i sum_s a_s d_s [ v_n + c phi^s_{n-1} ] / (c + W + d_s)  */
+/*   Sbar_2^4 v_n = Sbar_2^2 v_n + (dW/4) v_n / (c + W)                       */
+/*                  + sgn(dW) (sqrt|dW|/2) c psi_{n-1} / (c + W)              */
+/* written as sig v_n + hist; (sig_s, hist_s) drops the order-4 terms, which  */
+/* change sign with the normal (as for S0^4).  The paper's third term writes  */
+/* d_k^m in its denominator: read as d_s^m.                                   */
+static void pade_parts(int order, int m, const cplx *a, const cplx *d, double dt, double W,
+                       double dW, const cplx *phi, cplx psi, cplx *sig, cplx *hist, cplx *sig_s,
+                       cplx *hist_s)
+{
+    const cplx c = 2.0 * I / dt;
+    cplx asum = 0, s2, h2 = 0;
+    for (int s = 0; s <= m; ++s) asum += a[s];
+    s2 = -I * asum;
+    for (int s = 1; s <= m; ++s) {
+        const cplx den = c + W + d[s];
+        s2 += I * a[s] * d[s] * (1.0 / den);
+        h2 += I * a[s] * d[s] * (c / den) * phi[s];
+    }
+    *sig_s = s2;
+    *hist_s = h2;
+    if (order == 4) {
+        const double q = sqrt(fabs(dW)) / 2.0;
+        s2 += (dW / 4.0) * (1.0 / (c + W));
+        h2 += sgn(dW) * q * (c / (c + W)) * psi;
+    }
+    *sig = s2;
+    *hist = h2;
+}
+
+/* The auxiliary functions once v_n is known (Sec. 2.2):                      */
+/*   phi^s_{n-1/2} = v_n/(c + W + d_s) + c phi^s_{n-1}/(c + W + d_s),         */
+/*   phi^s_n = 2 phi^s_{n-1/2} - phi^s_{n-1},  phi^s_0 = 0;                    */
+/*   psi_{n-1/2} = (sqrt|dW|/2) v_n/(c + W) + c psi_{n-1}/(c + W),             */
+/*   psi_n = 2 psi_{n-1/2} - psi_{n-1},  psi_0 = 0.                            */
+static void pade_advance(int order, int m, const cplx *d, double dt, double W, double dW, cplx v,
+                         cplx *phi, cplx *psi)
+{
+    const cplx c = 2.0 * I / dt;
+    for (int s = 1; s <= m; ++s) {
+        const cplx den = c + W + d[s];
+        const cplx half = v * (1.0 / den) + (c / den) * phi[s];
+        phi[s] = 2.0 * half - phi[s];
+    }
+    if (order == 4) {
+        const double q = sqrt(fabs(dW)) / 2.0;
+        const cplx half = q * v * (1.0 / (c + W)) + (c / (c + W)) * *psi;
+        *psi = 2.0 * half - *psi;
+    }
+}
+
+/* Sbar v_n, n = 1..nt, of S2^{order,m} on a given sequence v (test access;   */
+/* v_0 plays no part: phi_0 = psi_0 = 0); out[0] = out_s[0] = 0.  W, dW as    */
+/* orc_end_data.  Returns -5 for a bad order or m.                            */
+int orc_pade_apply(int order, int m, double theta, int nt, double dt, const cplx *v,
+                   const double *W, const double *dW, cplx *out, cplx *out_s)
+{
+    if ((order != 2 && order != 4) || m < 1 || m > ORC_PADE_MAX) return -5;
+    cplx *a = malloc(sizeof(cplx) * (size_t)(m + 1)), *d = malloc(sizeof(cplx) * (size_t)(m + 1));
+    cplx *phi = calloc((size_t)(m + 1), sizeof(cplx));
+    cplx psi = 0;
+    orc_pade_coef(m, theta, a, d);
+    out[0] = 0;
+    out_s[0] = 0;
+    for (int n = 1; n <= nt; ++n) {
+        cplx sg, hs, sgs, hss;
+        pade_parts(order, m, a, d, dt, W[n], dW[n], phi, psi, &sg, &hs, &sgs, &hss);
+        out[n] = sg * v[n] + hs;
+        out_s[n] = sgs * v[n] + hss;
+        pade_advance(order, m, d, dt, W[n], dW[n], v[n], phi, &psi);
+    }
+    free(a); free(d); free(phi);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* One subdomain over the whole time window (eq. AvML for linear V,          */
 /* eq. AvMNL for f(u) = |u|^2), with the transmission conditions written by  */
 /* fluxes (eq. TransmissionCondlocal) and the exchange of                    */
@@ -370,9 +502,10 @@ void orc_sbar_apply(int kind, int nt, double dt, const cplx *v, const double *W,
 /*  b_n = Q^T (h_n(a), h_n(b))                                               */
 /*  outgoing fluxes:  rhoL_n = -l_n + 2 (sig'_n v_n(a) + h'_n(a))            */
 /*                    rhoR_n = -r_n + 2 (sig'_n v_n(b) + h'_n(b))            */
-/*  where ' drops the order-4 normal-derivative term (S0^4, S1^4).           */
-/*  trans: 0 Robin, 1 S0^2, 2 S0^3, 3 S0^4, 4 S1^2, 5 S1^4; the last four    */
-/*  need a linear potential (returns -4 with |u|^2).                         */
+/*  where ' drops the order-4 normal-derivative term (S0^4, S1^4, S2^4).     */
+/*  trans: 0 Robin, 1 S0^2, 2 S0^3, 3 S0^4, 4 S1^2, 5 S1^4, 6 S2^{2,m},      */
+/*  7 S2^{4,m} (pade_m auxiliary functions, branch rotation pade_theta); the */
+/*  operators after S0^2 need a linear potential (returns -4 with |u|^2).    */
 /*                                                                           */
 /* The subdomain has n nodes starting at global node `off0` of a mesh with   */
 /* nx_global nodes (V is indexed globally).  left_iface/right_iface say      */
@@ -389,14 +522,17 @@ int orc_sub_sweep(int n, double h, double dt, int nt, int vkind, const double *V
                   const cplx *u0, const cplx *hist0,
                   const cplx *l, const cplx *r,
                   cplx *rhoL, cplx *rhoR, cplx *uT, cplx *va, cplx *vb, cplx *v_all,
-                  int nl_maxit, double nl_tol, int *nl_worst)
+                  int nl_maxit, double nl_tol, int *nl_worst, int pade_m, double pade_theta)
 {
     const cplx c = 2.0 * I / dt;
-    const int conv = trans != ORC_ROBIN;     /* a convolution-type Sbar */
+    const int pade = trans == ORC_P22 || trans == ORC_P24;
+    const int conv = trans != ORC_ROBIN && !pade;     /* a convolution-type Sbar */
+    const int porder = trans == ORC_P24 ? 4 : 2;
     /* the operators beyond S0^2 carry W_n; with f(u) = |u|^2 the paper gives
        no discretisation of them that keeps the interface continuity */
     if (trans > ORC_S02 && vkind == ORC_V_CUBIC) return -4;
-    if (trans < ORC_ROBIN || trans > ORC_S14) return -5;
+    if (trans < ORC_ROBIN || trans > ORC_P24) return -5;
+    if (pade && (pade_m < 1 || pade_m > ORC_PADE_MAX)) return -5;
     cplx *diag = malloc(sizeof(cplx) * (size_t)n), *off = malloc(sizeof(cplx) * (size_t)(n > 1 ? n - 1 : 1));
     cplx *u = malloc(sizeof(cplx) * (size_t)n), *v = malloc(sizeof(cplx) * (size_t)n);
     cplx *rhs = malloc(sizeof(cplx) * (size_t)n), *w1 = malloc(sizeof(cplx) * (size_t)n);
@@ -408,6 +544,12 @@ int orc_sub_sweep(int n, double h, double dt, int nt, int vkind, const double *V
     double *Wa = ed, *dWa = ed + (nt + 1), *cWa = ed + 2 * (nt + 1);
     double *Wb = ed + 3 * (nt + 1), *dWb = ed + 4 * (nt + 1), *cWb = ed + 5 * (nt + 1);
     int rc = 0, worst = 0;
+    /* Pade: coefficients and the auxiliary functions of the two ends */
+    const int pm = pade ? pade_m : 0;
+    cplx *pa = malloc(sizeof(cplx) * (size_t)(pm + 1)), *pd = malloc(sizeof(cplx) * (size_t)(pm + 1));
+    cplx *phiA = calloc((size_t)(pm + 1), sizeof(cplx)), *phiB = calloc((size_t)(pm + 1), sizeof(cplx));
+    cplx psiA = 0, psiB = 0;
+    if (pade) orc_pade_coef(pm, pade_theta, pa, pd);
 
     orc_alpha(nt + 1, alpha);
     memset(ed, 0, sizeof(double) * (size_t)(nt + 1) * 6);
@@ -432,6 +574,10 @@ int orc_sub_sweep(int n, double h, double dt, int nt, int vkind, const double *V
             orc_sbar_parts(trans, step, dt, ta, Wa, dWa, cWa, alpha, beta, &sgA, &hA, &sgAs, &hAs);
             orc_sbar_parts(trans, step, dt, tb, Wb, dWb, cWb, alpha, beta, &sgB, &hB, &sgBs, &hBs);
         }
+        if (pade) {
+            pade_parts(porder, pm, pa, pd, dt, Wa[step], dWa[step], phiA, psiA, &sgA, &hA, &sgAs, &hAs);
+            pade_parts(porder, pm, pa, pd, dt, Wb[step], dWb[step], phiB, psiB, &sgB, &hB, &sgBs, &hBs);
+        }
         if (left_iface)  diag[0]     -= sgA;
         if (right_iface) diag[n - 1] -= sgB;
         cplx ln = l ? l[step - 1] : 0, rn = r ? r[step - 1] : 0;
@@ -448,6 +594,10 @@ int orc_sub_sweep(int n, double h, double dt, int nt, int vkind, const double *V
         }
         for (int i = 0; i < n; ++i) u[i] = 2.0 * v[i] - u[i];
         ta[step] = v[0]; tb[step] = v[n - 1];
+        if (pade) {
+            pade_advance(porder, pm, pd, dt, Wa[step], dWa[step], v[0], phiA, &psiA);
+            pade_advance(porder, pm, pd, dt, Wb[step], dWb[step], v[n - 1], phiB, &psiB);
+        }
         if (rhoL) rhoL[step - 1] = left_iface  ? -ln + 2.0 * (sgAs * v[0] + hAs) : 0;
         if (rhoR) rhoR[step - 1] = right_iface ? -rn + 2.0 * (sgBs * v[n - 1] + hBs) : 0;
         if (v_all) memcpy(v_all + (size_t)(step - 1) * n, v, sizeof(cplx) * (size_t)n);
@@ -460,6 +610,7 @@ int orc_sub_sweep(int n, double h, double dt, int nt, int vkind, const double *V
     if (nl_worst) *nl_worst = worst;
     free(diag); free(off); free(u); free(v); free(rhs); free(w1); free(w2); free(w3);
     free(W); free(ta); free(tb); free(alpha); free(ed);
+    free(pa); free(pd); free(phiA); free(phiB);
     return rc;
 }
 

@@ -14,8 +14,10 @@ Conventions
 * Potential kinds: ``V_STATIC`` (``V[nx]``), ``V_TIME`` (``V[nt+1][nx]``,
   row ``n`` at ``t_n = n*dt``), ``V_CUBIC`` (``|u|^2``, no array).
 * Transmission: ``ROBIN`` (``dn u + sigma u``, complex ``sigma``), ``S02``,
-  ``S03``, ``S04`` (potential strategy of order 2, 3, 4) or ``S12``, ``S14``
-  (gauge change strategy of order 2, 4).
+  ``S03``, ``S04`` (potential strategy of order 2, 3, 4), ``S12``, ``S14``
+  (gauge change strategy of order 2, 4) or ``P22``, ``P24`` (Pade strategy of
+  order 2, 4 with ``pade_m`` auxiliary functions and branch rotation
+  ``pade_theta``).
 * Complex arrays are ``complex128`` (interleaved re/im doubles).
 * Random numbers: ``numpy.random.default_rng(seed)``, fixed draw order.
 """
@@ -27,7 +29,7 @@ from typing import Optional
 import numpy as np
 
 V_STATIC, V_TIME, V_CUBIC = 0, 1, 2
-ROBIN, S02, S03, S04, S12, S14 = 0, 1, 2, 3, 4, 5
+ROBIN, S02, S03, S04, S12, S14, P22, P24 = 0, 1, 2, 3, 4, 5, 6, 7
 
 
 @dataclass
@@ -48,6 +50,8 @@ class Workload:
     tol: float = 1e-10
     seed: int = 0
     extras: dict = field(default_factory=dict)
+    pade_m: int = 20                 # Pade strategy: auxiliary functions per end
+    pade_theta: float = np.pi / 4    # and the rotation of the square root's branch cut
 
     @property
     def N(self) -> int:
