@@ -64,13 +64,21 @@ typedef enum {
  *   SWR_S04    order 4: S0^3 - i (dn W / 4) I_t
  *   SWR_S12    gauge change strategy, order 2: e^{-i pi/4} e^{i calW} d_t^{1/2} e^{-i calW}
  *   SWR_S14    order 4: S1^2 - i sgn(dn W) (|dn W|^{1/2}/2) e^{i calW} I_t (|dn W|^{1/2}/2) e^{-i calW}
+ *   SWR_P22    Pade approximation strategy, order 2: -i sqrt(i d_t + W) with the square
+ *              root replaced by sum_{s=0}^m a_s - sum_{s=1}^m a_s d_s / (z + d_s), applied
+ *              through m auxiliary functions per interface end (Sec. 2.2); a_s, d_s are the
+ *              partial fractions of the diagonal [m/m] Pade approximant of sqrt(1 + w) with
+ *              the branch cut rotated by theta (opts.pade_m, opts.pade_theta)
+ *   SWR_P24    order 4: S2^2 + sgn(dn W) (|dn W|^{1/2}/2) (i d_t + W)^{-1} (|dn W|^{1/2}/2)
+ *              (one more auxiliary function)
  * W is the potential at the interface node, dn W its outward normal derivative
  * (centred difference on the mesh), calW the gauge phase (time integral of V by
- * the trapezoid rule, averaged over the two ends of the step).  S03..S14 need a
+ * the trapezoid rule, averaged over the two ends of the step).  S03..P24 need a
  * static potential (SWR_V_STATIC); the order-4 terms flip sign with the normal
  * and cancel in the exchange, which transmits S without them. */
 typedef enum {
-    SWR_ROBIN = 0, SWR_S02 = 1, SWR_S03 = 2, SWR_S04 = 3, SWR_S12 = 4, SWR_S14 = 5
+    SWR_ROBIN = 0, SWR_S02 = 1, SWR_S03 = 2, SWR_S04 = 3, SWR_S12 = 4, SWR_S14 = 5,
+    SWR_P22 = 6, SWR_P24 = 7
 } swr_transmission;
 
 /* potential: static V(x) [nx] | time dependent V(t,x) [nt+1][nx] | |u|^2 (V NULL) */
@@ -117,6 +125,10 @@ typedef struct {
                             (s = this stride) in its snaps argument; 0 = no snapshots (default 0) */
     const char* tune_cache; /* host path of the schedule cache written by swr_tune and read by
                                swr_setup (NULL = no cache, built-in schedule; default NULL) */
+    int pade_m;        /* SWR_P22 / SWR_P24: auxiliary functions per interface end, 1..128
+                          (default 20; the paper runs 20, 50 and 100) */
+    double pade_theta; /* SWR_P22 / SWR_P24: rotation of the square root's branch cut in
+                          (0, pi) (default pi/4) */
 } swr_opts;
 
 typedef struct {

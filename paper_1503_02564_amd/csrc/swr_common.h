@@ -159,9 +159,12 @@ __device__ inline double wave_sum(double v) {
 // ---------------------------------------------------------------------------
 // Problem-wide constants handed to every kernel.
 // ---------------------------------------------------------------------------
-// kernel forms of the transmission operator: Robin, S0^2, and the general
-// convolution form that carries S0^3, S0^4, S1^2 and S1^4 (EndCoef)
-enum Trans { TR_ROBIN = 0, TR_S02 = 1, TR_GEN = 2 };
+// kernel forms of the transmission operator: Robin, S0^2, the general
+// convolution form that carries S0^3, S0^4, S1^2 and S1^4 (EndCoef), and the
+// Pade strategy's auxiliary-function form (S2^{2,m}, S2^{4,m})
+enum Trans { TR_ROBIN = 0, TR_S02 = 1, TR_GEN = 2, TR_PADE = 3 };
+// Pade strategy: at most two auxiliary functions of each end per lane
+constexpr int kPadeMax = 2 * 64;
 
 // Coefficients of the higher-order transmission operators at one interface
 // end for a time-independent potential (Sec. 2.2).  With x_s = e^{-i calW_s}
@@ -174,6 +177,10 @@ enum Trans { TR_ROBIN = 0, TR_S02 = 1, TR_GEN = 2 };
 // alpha_k = +-beta_k splits the alpha sum by parity), a = -i (dn W/4)(dt/2)
 // (S0^4, S1^4), sig = c2 + d + a.  The part that crosses the interface drops
 // the a terms: sig_s = c2 + d.
+// Pade strategy (c = 2i/dt, W and dn W at the end node):
+//   sig_s = -i sum_{s=0}^m a_s + i sum_{s=1}^m a_s d_s / (c + W + d_s),
+//   sig = sig_s + (dn W/4) / (c + W) at order 4 (else sig_s),
+//   cp = 1/(c + W), omega = W, pad = dn W.
 struct EndCoef {
     cd sig, sig_s, cp, cm, a;
     double omega, pad;
@@ -265,13 +272,19 @@ struct SweepArgs {
     cd* snaps;                   // [B][nsnap][nx] u at steps 0, snap_stride, ... (interior nodes)
     cd* snap_ends;               // [B][nsnap][N][2] the same at the two end nodes
     int snap_stride, nsnap;
+    // Pade strategy
+    double dt;
+    const cd* pade;              // [2][m+1]: a_0..a_m, then d_0..d_m (d_0 unused)
+    int pade_m, pade_order;      // auxiliary functions per end; 2 or 4
+    cd* pstate;                  // [ntasks][6][64] auxiliary functions carried between launches
+                                 // (phi of the left end: slots 0, 1; right end: 2, 3; psi: 4, 5)
 };
 
 struct FactorArgs {
     int N, nx, nf, P;
     double h, dt;
     cd sigma;                    // Robin / S0^2: implicit coefficient at both ends
-    int tr;                      // swr_transmission code; 2..5 fill endc
+    int tr;                      // swr_transmission code; 2..7 fill endc
     cd c2;                       // e^{-i pi/4} sqrt(2/dt)
     EndCoef* endc;               // [nf][2] output for the higher-order operators
     const int* Pk;               // [N] chunk width of each subdomain (this launch builds width P)
@@ -280,6 +293,8 @@ struct FactorArgs {
     const int* off;
     const double* V;             // [nv][nx] static potential (nullptr = 0)
     cd* fac;
+    const cd* pade;              // Pade strategy: [2][m+1] coefficients a, d
+    int pade_m;
 };
 
 struct LttArgs {
@@ -317,6 +332,7 @@ hipError_t launch_factor(const FactorArgs& a, hipStream_t st);
 hipError_t launch_sweep(const SweepArgs& a, int trans, int vk, hipStream_t st, bool plain = false);
 hipError_t launch_sweep_static(const SweepArgs& a, int trans, hipStream_t st);
 hipError_t launch_sweep_static_s02(const SweepArgs& a, hipStream_t st);
+hipError_t launch_sweep_static_pade(const SweepArgs& a, hipStream_t st);
 hipError_t launch_sweep_time(const SweepArgs& a, int trans, hipStream_t st);
 hipError_t launch_sweep_cubic(const SweepArgs& a, int trans, hipStream_t st);
 // static potential, Robin or S0^2: a.ntasks waves of two tasks each, the

@@ -78,6 +78,9 @@ struct swr_ctx {
     double* dBeta = nullptr;
     cd* dHist = nullptr;
     EndCoef* dEndc = nullptr; // [nv][N][2] higher-order transmission coefficients
+    cd* dPade = nullptr;      // Pade strategy: [2][m+1] coefficients a_s, d_s
+    cd* dPadeStB = nullptr;   // ... its auxiliary functions between chunk launches (build, final)
+    cd* dPadeStF = nullptr;
     cd* dEnds = nullptr;
     Task* dBuild = nullptr;   // impulses + d sweeps of the potential (static V)
     int nBuild = 0;
@@ -283,6 +286,8 @@ extern "C" void swr_default_opts(swr_opts* o) {
     o->plain = 0;
     o->snapshot_stride = 0;
     o->tune_cache = nullptr;
+    o->pade_m = 20;
+    o->pade_theta = M_PI / 4;
 }
 
 extern "C" const char* swr_strerror(swr_status s) {
@@ -311,6 +316,34 @@ static std::vector<Task> impulse_tasks(int N, int nv) {
 
 static void load_schedule(swr_ctx* c, const char* path);
 
+// transmissions whose history is a convolution over the stored boundary values
+static bool conv_hist(int tr) { return tr != SWR_ROBIN && tr <= SWR_S14; }
+
+// Pade strategy (Sec. 2.2): sqrt(z) ~ sum_{s=0}^m a_s - sum_{s=1}^m a_s d_s/(z + d_s)
+// from the partial fractions of the diagonal [m/m] Pade approximant of
+// sqrt(1 + w), R_m(w) = 1 + sum_s A_s w/(1 + B_s w) with A_s = 2/(2m+1)
+// sin^2(s pi/(2m+1)) and B_s = cos^2(s pi/(2m+1)), used as
+// sqrt(z) = e^{i theta/2} sqrt(1 + w), w = e^{-i theta} z - 1 (branch cut
+// rotated by theta): d_s = e^{i theta}(1 - B_s)/B_s, a_s = e^{i theta/2}
+// A_s/(B_s(1 - B_s)), a_0 = e^{i theta/2} R_m(-1).  Returns [a_0..a_m, d_0..d_m].
+static std::vector<cd> pade_coefficients(int m, double theta) {
+    std::vector<cd> out(2 * (size_t)(m + 1), mk(0, 0));
+    const double ch = std::cos(theta / 2), sh = std::sin(theta / 2);
+    const double ct = std::cos(theta), st = std::sin(theta);
+    double r_m1 = 1.0;   // R_m(-1)
+    for (int s = 1; s <= m; ++s) {
+        const double ang = s * M_PI / (2.0 * m + 1.0);
+        const double A = 2.0 / (2.0 * m + 1.0) * std::sin(ang) * std::sin(ang);
+        const double B = std::cos(ang) * std::cos(ang);
+        const double as = A / (B * (1.0 - B)), ds = (1.0 - B) / B;
+        out[s] = mk(ch * as, sh * as);
+        out[m + 1 + s] = mk(ct * ds, st * ds);
+        r_m1 -= A / (1.0 - B);
+    }
+    out[0] = mk(ch * r_m1, sh * r_m1);
+    return out;
+}
+
 extern "C" swr_status swr_setup(double a0, double b0, int N, const int* J, double dt, double T,
                                 int vk, const double* V, int tr, double s_re, double s_im,
                                 const swr_opts* opts, void* stream, swr_ctx** out) {
@@ -324,7 +357,10 @@ extern "C" swr_status swr_setup(double a0, double b0, int N, const int* J, doubl
     const double ntd = T / dt;
     const double ntr = std::round(ntd);
     if (ntr < 1 || std::fabs(ntd - ntr) > 1e-9 * ntd || ntr > 1e8) return SWR_EINVAL;
-    if (vk < SWR_V_STATIC || vk > SWR_V_CUBIC || tr < SWR_ROBIN || tr > SWR_S14) return SWR_EINVAL;
+    if (vk < SWR_V_STATIC || vk > SWR_V_CUBIC || tr < SWR_ROBIN || tr > SWR_P24) return SWR_EINVAL;
+    if (tr >= SWR_P22 && (o.pade_m < 1 || o.pade_m > kPadeMax || !(o.pade_theta > 0) ||
+                          !(o.pade_theta < M_PI)))
+        return SWR_EINVAL;
     // the operators beyond S0^2 depend on W: provided for a static potential
     if (tr > SWR_S02 && vk != SWR_V_STATIC) return SWR_EINVAL;
     if (tr == SWR_ROBIN && s_re == 0.0 && s_im == 0.0) return SWR_EINVAL;
@@ -419,8 +455,13 @@ extern "C" swr_status swr_setup(double a0, double b0, int N, const int* J, doubl
     // sweep's LDS copy of the first 128 weights)
     const int nbeta = std::max(nt, kWave) + kWave + 1;
     ALLOC(c->dBeta, nbeta);
-    ALLOC(c->dHist, (tr != SWR_ROBIN) ? max_tasks * 2 * (nt + 1) : 1);
+    ALLOC(c->dHist, conv_hist(tr) ? max_tasks * 2 * (nt + 1) : 1);
     if (tr > SWR_S02) ALLOC(c->dEndc, (size_t)nv * N * 2);
+    std::vector<cd> pade;
+    if (tr >= SWR_P22) {
+        pade = pade_coefficients(o.pade_m, o.pade_theta);
+        ALLOC(c->dPade, pade.size());
+    }
     ALLOC(c->dEnds, (size_t)B * N * 2);
     ALLOC(c->dBuild, build.size());
     ALLOC(c->dSub, sub.size());
@@ -483,6 +524,8 @@ extern "C" swr_status swr_setup(double a0, double b0, int N, const int* J, doubl
     if (c->L.cols) HIPCHK(hipMemsetAsync(c->L.cols, 0, (size_t)nv * N * 4 * nt * sizeof(cd), c->st));
     if (c->L0.cols) HIPCHK(hipMemsetAsync(c->L0.cols, 0, (size_t)N * 4 * nt * sizeof(cd), c->st));
     HIPCHK(launch_beta(nbeta, c->dBeta, c->st));
+    if (c->dPade)
+        HIPCHK(hipMemcpyAsync(c->dPade, pade.data(), pade.size() * sizeof(cd), hipMemcpyHostToDevice, c->st));
     HIPCHK(hipStreamSynchronize(c->st));
     *out = c;
     return SWR_OK;
@@ -546,6 +589,7 @@ static int nsnaps(const swr_ctx* c) {
 // kernel form of the transmission operator: Robin, S0^2, or the general
 // convolution form of the higher-order operators
 static int ktr(const swr_ctx* c) {
+    if (c->tr >= SWR_P22) return TR_PADE;
     return c->tr == SWR_ROBIN ? TR_ROBIN : (c->tr == SWR_S02 ? TR_S02 : TR_GEN);
 }
 
@@ -560,6 +604,11 @@ static SweepArgs sweep_args(swr_ctx* c, const Task* tasks, int ntasks, const cd*
     a.J = c->dJ; a.off = c->dOff; a.tasks = tasks; a.fac = fac; a.beta = c->dBeta;
     a.cols = cols; a.hist = c->dHist; a.ends = c->dEnds; a.maxdiff = c->dMax;
     a.endc = c->dEndc;
+    a.dt = c->dt;
+    a.pade = c->dPade;
+    a.pade_m = c->o.pade_m;
+    a.pade_order = c->tr == SWR_P24 ? 4 : 2;
+    a.pstate = nullptr;
     a.Vt = (c->vk == SWR_V_TIME) ? c->dV : nullptr;
     a.nl_maxit = c->o.nl_max_iter;
     a.nl_tol = c->o.nl_tol;
@@ -582,6 +631,7 @@ static swr_status run_factor(swr_ctx* c, const double* V, int nv, cd* fac) {
     f.N = c->N; f.nx = c->nx; f.nf = nv * c->N; f.P = c->P; f.h = c->h; f.dt = c->dt;
     f.sigma = c->sigma; f.J = c->dJ; f.off = c->dOff; f.V = V; f.fac = fac;
     f.tr = c->tr; f.c2 = c->c2; f.endc = c->dEndc;
+    f.pade = c->dPade; f.pade_m = c->o.pade_m;
     f.Pk = c->dPk;
     f.fstride = (size_t)fac_fields(c->P) * kWave;
     // one launch per chunk width present; each builds the records of its width
@@ -1188,7 +1238,11 @@ static swr_status pipe_resources(swr_ctx* c, int K) {
     const size_t st_rec = (size_t)2 * c->P * kWave;
     if (!c->dStateB) ALLOC_LIVE(c->dStateB, (size_t)c->nBuild * st_rec);
     if (!c->dStateF) ALLOC_LIVE(c->dStateF, (size_t)c->nSub * st_rec);
-    if (!c->dHistB && c->tr != SWR_ROBIN) ALLOC_LIVE(c->dHistB, (size_t)c->nBuild * 2 * (c->nt + 1));
+    if (!c->dHistB && conv_hist(c->tr)) ALLOC_LIVE(c->dHistB, (size_t)c->nBuild * 2 * (c->nt + 1));
+    if (c->tr >= SWR_P22) {
+        if (!c->dPadeStB) ALLOC_LIVE(c->dPadeStB, (size_t)c->nBuild * 6 * kWave);
+        if (!c->dPadeStF) ALLOC_LIVE(c->dPadeStF, (size_t)c->nSub * 6 * kWave);
+    }
     // sync events: fork, build j, causal j, join; timing events: 2 per sweep
     // launch plus the two ends of the interface solve
     while ((int)c->evSync.size() < 2 * K + 2) {
@@ -1232,9 +1286,11 @@ static swr_status run_static_pipelined(swr_ctx* c, const cd* u0, cd* g, const Sw
     ab.g_in = c->dZero;
     ab.g_out = c->dD;
     ab.state = c->dStateB;
+    ab.pstate = c->dPadeStB;
     if (c->dHistB) ab.hist = c->dHistB;
     SweepArgs af = sub_args(c, fin);
     af.state = c->dStateF;
+    af.pstate = c->dPadeStF;
     c->L.dirty = true;
     int launches = 0;
 
@@ -1584,7 +1640,7 @@ extern "C" swr_status swr_apply_R_noalloc(swr_ctx* c, const double* u0, const do
     if (!c->scratch) return SWR_EDEVICE;
     // scratch layout: [max word, padded to 256 B][ends B*N*2][history nSub*2*(nt+1)]
     const size_t ends = (size_t)c->B * c->N * 2;
-    const size_t hist = c->tr != SWR_ROBIN ? (size_t)c->nSub * 2 * (c->nt + 1) : 0;
+    const size_t hist = conv_hist(c->tr) ? (size_t)c->nSub * 2 * (c->nt + 1) : 0;
     if (256 + (ends + hist) * sizeof(cd) > kScratchBytes) return SWR_EINVAL;
     unsigned char* base = static_cast<unsigned char*>(c->scratch);
     auto* word = reinterpret_cast<unsigned long long*>(base);
@@ -1633,7 +1689,9 @@ static std::string schedule_key(const swr_ctx* c) {
     }
     std::ostringstream k;
     k << "N" << c->N << "_nt" << c->nt << "_B" << c->B << "_nv" << c->nv << "_vk" << c->vk << "_tr"
-      << c->tr << "_solver" << c->o.solver << "_J" << std::hex << h;
+      << c->tr << "_solver" << c->o.solver;
+    if (c->tr >= SWR_P22) k << "_m" << c->o.pade_m;
+    k << "_J" << std::hex << h;
     return k.str();
 }
 

@@ -57,7 +57,7 @@ __global__ __launch_bounds__(64) void factor_kernel(FactorArgs a) {
     neighbour_w(w, wL, wR);
     cd sigL = a.sigma, sigR = a.sigma;
     if (a.tr >= 2) {
-        // higher-order operators (Sec. 2.2) at the two interface ends: W and
+        // higher-order and Pade operators (Sec. 2.2) at the two interface ends: W and
         // its outward normal derivative (centred difference on the global
         // mesh) at the end node
         const double* Vg = a.V ? a.V + (size_t)v * a.nx : nullptr;
@@ -71,6 +71,28 @@ __global__ __launch_bounds__(64) void factor_kernel(FactorArgs a) {
             if (Vg && iface) {
                 We = Vg[g];
                 dWe = (side ? 1.0 : -1.0) * (Vg[g + 1] - Vg[g - 1]) / (2.0 * a.h);
+            }
+            if (a.tr >= 6) {
+                // Pade strategy: the implicit part of Sbar v_n (see EndCoef)
+                const cd cc = mk(0.0, 2.0 / a.dt);
+                const cd* pa = a.pade;
+                const cd* pd = a.pade + a.pade_m + 1;
+                cd asum = mk(0, 0);
+                for (int q = 0; q <= a.pade_m; ++q) asum = asum + pa[q];
+                cd s2 = -mul_i(asum);
+                for (int q = 1; q <= a.pade_m; ++q) {
+                    const cd den = mk(cc.x + We + pd[q].x, cc.y + pd[q].y);
+                    s2 = s2 + mul_i(pa[q] * pd[q]) * inv(den);
+                }
+                const cd rho = inv(mk(cc.x + We, cc.y));
+                e[side].cp = rho;
+                e[side].cm = mk(0, 0);
+                e[side].a = mk(0, 0);
+                e[side].sig_s = s2;
+                e[side].sig = (a.tr == 7) ? s2 + (dWe / 4.0) * rho : s2;
+                e[side].omega = We;
+                e[side].pad = dWe;
+                continue;
             }
             const bool pot = a.tr == 2 || a.tr == 3, ord4 = a.tr == 3 || a.tr == 5;
             const cd d = pot ? (-(sqrt(0.5 * a.dt) * 0.5 * We)) * eP : mk(0, 0);

@@ -135,9 +135,9 @@ __global__ __launch_bounds__(sweep_threads(HELP)) void sweep_kernel(SweepArgs a)
         far_helper(a, Ha, Hb, t, ffa, ffb, sha, shb, sb);
         return;
     }
-    // higher-order operators: coefficients of the two ends (left, right)
+    // higher-order and Pade operators: coefficients of the two ends (left, right)
     EndCoef ea{}, eb{};
-    if (TR == TR_GEN) {
+    if (TR == TR_GEN || TR == TR_PADE) {
         ea = a.endc[(size_t)f * 2 + 0];
         eb = a.endc[(size_t)f * 2 + 1];
     }
@@ -148,6 +148,45 @@ __global__ __launch_bounds__(sweep_threads(HELP)) void sweep_kernel(SweepArgs a)
     const int nbeg = a.n_begin, nend = a.n_end;
     const bool first = nbeg == 0, last = nend == nt;
     cd* stp = a.state ? a.state + (size_t)tix * 2 * a.pstride * kWave + t : nullptr;
+
+    // Pade strategy (Sec. 2.2): lane t carries the auxiliary functions
+    // s = t + 1 and s = t + 65 of both ends, with r_s = 1/(c + W + d_s),
+    // c r_s, and the history weight w_s = i a_s d_s c r_s (c = 2i/dt); psi of
+    // the order-4 operator is wave-uniform.  ph[e] = sum_s w_s phi^s_{n-1}
+    // (a wave sum, every lane holds it) is ready before each step.
+    cd pr[2][2], pkr[2][2], pw[2][2], pphi[2][2], ppsi[2], ph[2];
+    double pq[2] = {0.0, 0.0};
+    cd pkrho[2];
+    const bool ord4 = TR == TR_PADE && a.pade_order == 4;
+    cd* pst = (TR == TR_PADE && a.pstate) ? a.pstate + (size_t)tix * 6 * kWave + t : nullptr;
+    auto pade_sum = [&](int e) {
+        const cd p = pw[e][0] * pphi[e][0] + pw[e][1] * pphi[e][1];
+        return mk(wave_sum(p.x), wave_sum(p.y));
+    };
+    if (TR == TR_PADE) {
+        const cd cc = mk(0.0, 2.0 / a.dt);
+        const cd* pa = a.pade;
+        const cd* pd = a.pade + a.pade_m + 1;
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const EndCoef& ec = e ? eb : ea;
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int sl = t + 1 + j * kWave;
+                pr[e][j] = pkr[e][j] = pw[e][j] = pphi[e][j] = zero;
+                if (sl <= a.pade_m) {
+                    pr[e][j] = inv(mk(cc.x + ec.omega + pd[sl].x, cc.y + pd[sl].y));
+                    pkr[e][j] = cc * pr[e][j];
+                    pw[e][j] = mul_i(pa[sl] * pd[sl]) * pkr[e][j];
+                    if (!first && pst) pphi[e][j] = pst[(2 * e + j) * kWave];
+                }
+            }
+            pq[e] = ord4 ? 0.5 * sqrt(fabs(ec.pad)) : 0.0;
+            pkrho[e] = cc * ec.cp;
+            ppsi[e] = (ord4 && !first && pst) ? pst[(4 + e) * kWave] : zero;
+            ph[e] = pade_sum(e);
+        }
+    }
 
     // time-dependent potential: rows n and n+1 of V at my nodes
     double vprev[P], vnext[P];
@@ -420,6 +459,19 @@ __global__ __launch_bounds__(sweep_threads(HELP)) void sweep_kernel(SweepArgs a)
                 hA = hAs + ea.a * (phA * Ga);
                 hB = hBs + eb.a * (phB * Gb);
             }
+            if (TR == TR_PADE) {
+                hAs = ph[0];
+                hBs = ph[1];
+                hA = hAs;
+                hB = hBs;
+                if (ord4) {
+                    // + sgn(dn W) (sqrt|dn W|/2) c psi_{n-1} / (c + W)
+                    const double gA = (ea.pad > 0.0 ? 1.0 : (ea.pad < 0.0 ? -1.0 : 0.0)) * pq[0];
+                    const double gB = (eb.pad > 0.0 ? 1.0 : (eb.pad < 0.0 ? -1.0 : 0.0)) * pq[1];
+                    hA = hA + gA * (pkrho[0] * ppsi[0]);
+                    hB = hB + gB * (pkrho[1] * ppsi[1]);
+                }
+            }
             // right-hand side c M u_{n-1} + boundary terms
             const cd uL = shfl_up_c(u[P - 1], 1, zero);
             const cd uR = shfl_dn_c(u[0], 1, zero);
@@ -503,8 +555,8 @@ __global__ __launch_bounds__(sweep_threads(HELP)) void sweep_kernel(SweepArgs a)
             }
             const cd va = rdlane(x[0], 0);
             const cd vb = at_last(x);
-            const cd sgA = (TR == TR_GEN) ? ea.sig_s : a.sigma;
-            const cd sgB = (TR == TR_GEN) ? eb.sig_s : a.sigma;
+            const cd sgA = (TR == TR_GEN || TR == TR_PADE) ? ea.sig_s : a.sigma;
+            const cd sgB = (TR == TR_GEN || TR == TR_PADE) ? eb.sig_s : a.sigma;
             const cd rhoL = (2.0 * madd(hAs, sgA, va)) - ln;
             const cd rhoR = (2.0 * madd(hBs, sgB, vb)) - rn;
             // stored history value: x_n = e^{-i calW_n} v_n (= v_n for S0^2)
@@ -530,6 +582,25 @@ __global__ __launch_bounds__(sweep_threads(HELP)) void sweep_kernel(SweepArgs a)
                 const double bn = sbeta[kWave + t - i];
                 nxt_a = mk(fma(bn, va.x, nxt_a.x), fma(bn, va.y, nxt_a.y));
                 nxt_b = mk(fma(bn, vb.x, nxt_b.x), fma(bn, vb.y, nxt_b.y));
+            }
+            if (TR == TR_PADE) {
+                // phi^s_n = 2 r_s (v_n + c phi^s_{n-1}) - phi^s_{n-1}, psi alike;
+                // then the history sums of the next step
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const cd ve = e ? vb : va;
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        const cd half = pr[e][j] * ve + pkr[e][j] * pphi[e][j];
+                        pphi[e][j] = 2.0 * half - pphi[e][j];
+                    }
+                    if (ord4) {
+                        const EndCoef& ec = e ? eb : ea;
+                        const cd half = (pq[e] * ve) * ec.cp + pkrho[e] * ppsi[e];
+                        ppsi[e] = 2.0 * half - ppsi[e];
+                    }
+                    ph[e] = pade_sum(e);
+                }
             }
             if (TR == TR_GEN) {
                 if (t > i) {
@@ -567,6 +638,14 @@ __global__ __launch_bounds__(sweep_threads(HELP)) void sweep_kernel(SweepArgs a)
         for (int q = 0; q < P; ++q) {
             stp[q * kWave] = u[q];
             if (VK == VK_CUBIC) stp[(a.pstride + q) * kWave] = vlast[q];
+        }
+    }
+    if (TR == TR_PADE && !last && pst) {
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+#pragma unroll
+            for (int j = 0; j < 2; ++j) pst[(2 * e + j) * kWave] = pphi[e][j];
+            pst[(4 + e) * kWave] = ppsi[e];
         }
     }
     if ((fl & T_OUT_UT) && last) {

@@ -1,6 +1,6 @@
 // swr_sweep_static.hip -- instantiates the subdomain sweep for a time-independent
 // potential with the Robin and higher-order transmissions (S0^2 is in
-// swr_sweep_static_s02.hip).
+// swr_sweep_static_s02.hip, the Pade strategy in swr_sweep_static_pade.hip).
 #include "swr_sweep_kernel.h"
 
 namespace swr {
@@ -13,6 +13,7 @@ static void launch_p(const SweepArgs& a, int trans, hipStream_t st) {
 
 hipError_t launch_sweep_static(const SweepArgs& a, int trans, hipStream_t st) {
     if (trans == TR_S02) return launch_sweep_static_s02(a, st);
+    if (trans == TR_PADE) return launch_sweep_static_pade(a, st);
     if (trans == TR_GEN && !a.endc) return hipErrorInvalidValue;
     switch (a.P) {
         case 1: launch_p<1>(a, trans, st); break;

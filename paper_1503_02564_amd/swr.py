@@ -27,7 +27,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "_swr_hip.so")
 
 SWR_OK, SWR_EINVAL, SWR_ENOMEM, SWR_EDEVICE, SWR_ENOCONV, SWR_ENAN = range(6)
-SWR_ROBIN, SWR_S02, SWR_S03, SWR_S04, SWR_S12, SWR_S14 = 0, 1, 2, 3, 4, 5
+SWR_ROBIN, SWR_S02, SWR_S03, SWR_S04, SWR_S12, SWR_S14, SWR_P22, SWR_P24 = 0, 1, 2, 3, 4, 5, 6, 7
 SWR_V_STATIC, SWR_V_TIME, SWR_V_CUBIC = 0, 1, 2
 SWR_SOLVER_FIXED, SWR_SOLVER_GMRES, SWR_SOLVER_CAUSAL, SWR_SOLVER_BICGSTAB = 0, 1, 2, 3
 
@@ -38,7 +38,8 @@ class SwrOpts(ctypes.Structure):
                 ("v_per_problem", ctypes.c_int), ("checkpoint_K", ctypes.c_int),
                 ("nl_max_iter", ctypes.c_int), ("nl_tol", ctypes.c_double),
                 ("pipeline", ctypes.c_int), ("plain", ctypes.c_int),
-                ("snapshot_stride", ctypes.c_int), ("tune_cache", ctypes.c_char_p)]
+                ("snapshot_stride", ctypes.c_int), ("tune_cache", ctypes.c_char_p),
+                ("pade_m", ctypes.c_int), ("pade_theta", ctypes.c_double)]
 
 
 class SwrInfo(ctypes.Structure):

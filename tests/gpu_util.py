@@ -47,6 +47,8 @@ def make_problem(wl, solver=None, tol=None, restart=None, max_iter=None, v_per_p
         o.precond = int(precond)
     if pipeline is not None:
         o.pipeline = int(pipeline)
+    o.pade_m = int(wl.pade_m)
+    o.pade_theta = float(wl.pade_theta)
     V = None if wl.V is None else to_dev(np.asarray(wl.V, np.float64))
     return swr.Problem(wl.a0, wl.b0, tuple(int(j) for j in wl.J), wl.dt, wl.dt * wl.nt, wl.vkind,
                        wl.trans, wl.sigma, o, V)

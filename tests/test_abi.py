@@ -41,6 +41,7 @@ def test_defaults_and_strerror(swr):
     assert o.tol == 1e-10 and o.restart == 30 and o.batch == 1
     assert o.solver == swr.SWR_SOLVER_CAUSAL and o.checkpoint_K == 64
     assert o.pipeline == -1 and o.plain == 0 and o.nl_max_iter == 100
+    assert o.pade_m == 20 and abs(o.pade_theta - np.pi / 4) < 1e-15
     for s in range(6):
         assert swr.swr_strerror(s)
     assert swr.swr_strerror(99) == "unknown status"
@@ -56,8 +57,8 @@ def _setup_raw(swr, a0=-1.0, b0=1.0, J=(4, 4), dt=0.1, T=1.0, vk=0, tr=1, s=(1.0
 
 @pytest.mark.parametrize("kw", [
     dict(a0=1.0, b0=-1.0), dict(J=()), dict(J=(4, 0)), dict(dt=0.0), dict(T=-1.0),
-    dict(dt=0.3, T=1.0), dict(vk=7), dict(tr=6), dict(tr=-1), dict(tr=0, s=(0.0, 0.0)),
-    dict(tr=2, vk=1), dict(tr=5, vk=2), dict(tr=4, vk=1),
+    dict(dt=0.3, T=1.0), dict(vk=7), dict(tr=8), dict(tr=-1), dict(tr=0, s=(0.0, 0.0)),
+    dict(tr=2, vk=1), dict(tr=5, vk=2), dict(tr=4, vk=1), dict(tr=6, vk=1), dict(tr=7, vk=2),
     dict(J=(600,)), dict(vk=1), dict(dt=float("nan")),
 ])
 def test_setup_rejects_invalid_arguments(swr, kw):
@@ -75,6 +76,13 @@ def test_setup_rejects_bad_opts(swr):
         o = swr.swr_default_opts()
         setattr(o, field, val)
         st, _ = _setup_raw(swr, opts=o)
+        assert st == swr.SWR_EINVAL, field
+    # Pade strategy: 1..128 auxiliary functions, branch rotation in (0, pi)
+    for field, val in (("pade_m", 0), ("pade_m", 129), ("pade_theta", 0.0), ("pade_theta", np.pi),
+                       ("pade_theta", float("nan"))):
+        o = swr.swr_default_opts()
+        setattr(o, field, val)
+        st, _ = _setup_raw(swr, tr=swr.SWR_P22, opts=o)
         assert st == swr.SWR_EINVAL, field
 
 
