@@ -272,6 +272,7 @@ struct SweepArgs {
     cd* snaps;                   // [B][nsnap][nx] u at steps 0, snap_stride, ... (interior nodes)
     cd* snap_ends;               // [B][nsnap][N][2] the same at the two end nodes
     int snap_stride, nsnap;
+    int tr;                      // swr_transmission code (time-dependent end coefficients)
     // Pade strategy
     double dt;
     const cd* pade;              // [2][m+1]: a_0..a_m, then d_0..d_m (d_0 unused)

@@ -361,8 +361,9 @@ extern "C" swr_status swr_setup(double a0, double b0, int N, const int* J, doubl
     if (tr >= SWR_P22 && (o.pade_m < 1 || o.pade_m > kPadeMax || !(o.pade_theta > 0) ||
                           !(o.pade_theta < M_PI)))
         return SWR_EINVAL;
-    // the operators beyond S0^2 depend on W: provided for a static potential
-    if (tr > SWR_S02 && vk != SWR_V_STATIC) return SWR_EINVAL;
+    // the operators beyond S0^2 depend on W: provided for linear potentials
+    // (with |u|^2 the paper gives no discretisation of W = f(u) in them)
+    if (tr > SWR_S02 && vk == SWR_V_CUBIC) return SWR_EINVAL;
     if (tr == SWR_ROBIN && s_re == 0.0 && s_im == 0.0) return SWR_EINVAL;
     if (!std::isfinite(s_re) || !std::isfinite(s_im)) return SWR_EINVAL;
     if (o.batch < 1 || o.restart < 1 || o.max_iter < 1 || !(o.tol > 0)) return SWR_EINVAL;
@@ -604,6 +605,7 @@ static SweepArgs sweep_args(swr_ctx* c, const Task* tasks, int ntasks, const cd*
     a.J = c->dJ; a.off = c->dOff; a.tasks = tasks; a.fac = fac; a.beta = c->dBeta;
     a.cols = cols; a.hist = c->dHist; a.ends = c->dEnds; a.maxdiff = c->dMax;
     a.endc = c->dEndc;
+    a.tr = c->tr;
     a.dt = c->dt;
     a.pade = c->dPade;
     a.pade_m = c->o.pade_m;

@@ -97,6 +97,36 @@ __device__ inline void far_helper(const SweepArgs& a, const cd* Ha, const cd* Hb
     }
 }
 
+// Coefficients of the higher-order operators at one interface end for end
+// data W, dn W (Sec. 2.2; the EndCoef form, see swr_common.h): cp, cm of the
+// parity-split beta/alpha sums, the order-4 prefactor aa of e^{i calW_n} G_n
+// with the weight gw of each stored value in G (S0^4: aa = -i (dn W/4)(dt/2),
+// gw = 1; S1^4: aa = -i sgn(dn W) q (dt/2), gw = q = sqrt|dn W|/2), the
+// implicit coefficient sig and the exchanged sig_s (without order-4 terms).
+__device__ inline void gen_end_coef(int tr, double W, double dW, double dt, cd c2, cd& cp, cd& cm,
+                                    cd& aa, cd& sig, cd& sig_s, double& gw) {
+    const bool pot = tr == 2 || tr == 3, ord4 = tr == 3 || tr == 5;
+    const cd eP = mk(M_SQRT1_2, M_SQRT1_2);                 // e^{i pi/4}
+    const cd d = pot ? (-(sqrt(0.5 * dt) * 0.5 * W)) * eP : mk(0, 0);
+    cp = c2 + d;
+    cm = c2 - d;
+    sig_s = c2 + d;
+    aa = mk(0, 0);
+    gw = 1.0;
+    cd s4 = mk(0, 0);
+    if (ord4 && pot) {
+        aa = mk(0.0, -(dW / 4.0) * (0.5 * dt));
+        s4 = aa;
+    } else if (ord4) {
+        const double q = 0.5 * sqrt(fabs(dW));
+        const double sg = dW > 0.0 ? 1.0 : (dW < 0.0 ? -1.0 : 0.0);
+        aa = mk(0.0, -(sg * q) * (0.5 * dt));
+        s4 = q * aa;
+        gw = q;
+    }
+    sig = sig_s + s4;
+}
+
 // ---------------------------------------------------------------------------
 // The sweep.  VK selects the potential: static (factors loaded once), time
 // dependent (rows rebuilt and refactored every step from the streamed V rows)
@@ -154,37 +184,77 @@ __global__ __launch_bounds__(sweep_threads(HELP)) void sweep_kernel(SweepArgs a)
     // c r_s, and the history weight w_s = i a_s d_s c r_s (c = 2i/dt); psi of
     // the order-4 operator is wave-uniform.  ph[e] = sum_s w_s phi^s_{n-1}
     // (a wave sum, every lane holds it) is ready before each step.
-    cd pr[2][2], pkr[2][2], pw[2][2], pphi[2][2], ppsi[2], ph[2];
-    double pq[2] = {0.0, 0.0};
-    cd pkrho[2];
+    // Time-dependent potential with the higher-order or Pade operators
+    // (Sec. 2.2 with W_n = (V_n + V_{n-1})/2 at the end node): the end
+    // coefficients change every step.  Lane j computes those of step n0+1+j
+    // at each block start from rows n and n-1 of V; the gauge phase is
+    // advanced step by step (calV_n = calV_{n-1} + dt W_n, calW_n the mean of
+    // the two, as in the oracle) and the order-4 sum G_n = 2 sum_{s<n} q_s x_s
+    // (q_s = sqrt|dn W_s|/2 for S1^4, 1 for S0^4) is a running sum; both are
+    // carried across launches in the second half of the state record.
+    constexpr bool TEND = VK == VK_TIME && (TR == TR_GEN || TR == TR_PADE);
+    const int trc = a.tr;
+    const bool g_gauge = trc == 4 || trc == 5;
+    cd Ga = zero, Gb = zero;          // TR_GEN: G_n of the two ends
+    double cvA = 0.0, cvB = 0.0;      // TEND gauge: calV_{n-1} of the two ends
+    // W_n and dn W_n at global node g (outward sign ns), rows n and n-1 of V
+    auto end_data = [&](int nj, int g, double ns, double& W, double& dW) {
+        const double* Vn = a.Vt + (size_t)nj * a.nx;
+        const double* Vm = a.Vt + (size_t)(nj > 0 ? nj - 1 : 0) * a.nx;
+        W = 0.5 * (Vn[g] + Vm[g]);
+        const double wm = 0.5 * (Vn[g - 1] + Vm[g - 1]), wp = 0.5 * (Vn[g + 1] + Vm[g + 1]);
+        dW = ns * (wp - wm) / (2.0 * a.h);
+    };
+
+    cd pr[2][2], pkr[2][2], pw[2][2], pphi[2][2], ppsi[2], ph[2], pad[2];
+    double pq[2] = {0.0, 0.0}, psg[2] = {0.0, 0.0};
+    cd pkrho[2], prho[2], pasum = zero;
     const bool ord4 = TR == TR_PADE && a.pade_order == 4;
     cd* pst = (TR == TR_PADE && a.pstate) ? a.pstate + (size_t)tix * 6 * kWave + t : nullptr;
+    const cd pcc = mk(0.0, 2.0 / a.dt);
     auto pade_sum = [&](int e) {
         const cd p = pw[e][0] * pphi[e][0] + pw[e][1] * pphi[e][1];
         return mk(wave_sum(p.x), wave_sum(p.y));
     };
+    // r_s = 1/(c + W + d_s), c r_s, w_s = i a_s d_s c r_s at end e for the
+    // end potential W; rho = 1/(c + W) and the order-4 weight from dn W
+    auto pade_coef = [&](int e, double W, double dW) {
+        const cd* pd = a.pade + a.pade_m + 1;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int sl = t + 1 + j * kWave;
+            pr[e][j] = pkr[e][j] = pw[e][j] = zero;
+            if (sl <= a.pade_m) {
+                pr[e][j] = inv(mk(pcc.x + W + pd[sl].x, pcc.y + pd[sl].y));
+                pkr[e][j] = pcc * pr[e][j];
+                pw[e][j] = pad[j] * pkr[e][j];
+            }
+        }
+        prho[e] = inv(mk(pcc.x + W, pcc.y));
+        pkrho[e] = pcc * prho[e];
+        pq[e] = ord4 ? 0.5 * sqrt(fabs(dW)) : 0.0;
+        psg[e] = dW > 0.0 ? 1.0 : (dW < 0.0 ? -1.0 : 0.0);
+    };
     if (TR == TR_PADE) {
-        const cd cc = mk(0.0, 2.0 / a.dt);
         const cd* pa = a.pade;
         const cd* pd = a.pade + a.pade_m + 1;
 #pragma unroll
-        for (int e = 0; e < 2; ++e) {
-            const EndCoef& ec = e ? eb : ea;
+        for (int j = 0; j < 2; ++j) {
+            const int sl = t + 1 + j * kWave;
+            pad[j] = (sl <= a.pade_m) ? mul_i(pa[sl] * pd[sl]) : zero;
+        }
+        for (int q = 0; q <= a.pade_m; ++q) pasum = pasum + pa[q];
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const int sl = t + 1 + j * kWave;
-                pr[e][j] = pkr[e][j] = pw[e][j] = pphi[e][j] = zero;
-                if (sl <= a.pade_m) {
-                    pr[e][j] = inv(mk(cc.x + ec.omega + pd[sl].x, cc.y + pd[sl].y));
-                    pkr[e][j] = cc * pr[e][j];
-                    pw[e][j] = mul_i(pa[sl] * pd[sl]) * pkr[e][j];
-                    if (!first && pst) pphi[e][j] = pst[(2 * e + j) * kWave];
-                }
-            }
-            pq[e] = ord4 ? 0.5 * sqrt(fabs(ec.pad)) : 0.0;
-            pkrho[e] = cc * ec.cp;
+        for (int e = 0; e < 2; ++e) {
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                pphi[e][j] = (!first && pst && t + 1 + j * kWave <= a.pade_m) ? pst[(2 * e + j) * kWave] : zero;
             ppsi[e] = (ord4 && !first && pst) ? pst[(4 + e) * kWave] : zero;
-            ph[e] = pade_sum(e);
+            if (!TEND) {
+                const EndCoef& ec = e ? eb : ea;
+                pade_coef(e, ec.omega, ec.pad);
+                ph[e] = pade_sum(e);
+            }
         }
     }
 
@@ -320,6 +390,26 @@ __global__ __launch_bounds__(sweep_threads(HELP)) void sweep_kernel(SweepArgs a)
         if (HELP) __syncthreads();
     }
 
+    // TEND: G and calV at the launch start (the state record's second half
+    // carries them across launches: lane 0 G of the left end, lane 1 of the
+    // right end, lane 2 the two calV)
+    if (TEND && TR == TR_GEN) {
+        if (first) {
+            double w0, dw0, gw0a = 1.0, gw0b = 1.0;
+            if (trc == 5 && lif) { end_data(0, o, -1.0, w0, dw0); gw0a = 0.5 * sqrt(fabs(dw0)); }
+            if (trc == 5 && rif) { end_data(0, o + n - 1, 1.0, w0, dw0); gw0b = 0.5 * sqrt(fabs(dw0)); }
+            Ga = (2.0 * gw0a) * va0;
+            Gb = (2.0 * gw0b) * vb0;
+        } else if (stp) {
+            const cd sv = stp[a.pstride * kWave];
+            Ga = rdlane(sv, 0);
+            Gb = rdlane(sv, 1);
+            const cd cv = rdlane(sv, 2);
+            cvA = cv.x;
+            cvB = cv.y;
+        }
+    }
+
     int kb = 0;
     for (int n0 = nbeg; n0 < nend; n0 += kWave, ++kb) {
         const int nb = min(kWave, nend - n0);
@@ -404,24 +494,86 @@ __global__ __launch_bounds__(sweep_threads(HELP)) void sweep_kernel(SweepArgs a)
         // nj = n0+1+j (lag nj - q0 - i has the parity of nj - i, q0 being a
         // multiple of 64), its phase e^{i calW_nj}, and the wave-uniform
         // G = 2 sum_{s <= n0} x_s
-        cd Hl_a = zero, Hl_b = zero, Ga = zero, Gb = zero, pha = mk(1, 0), phb = mk(1, 0);
+        cd Hl_a = zero, Hl_b = zero, pha = mk(1, 0), phb = mk(1, 0);
+        // end coefficients of lane j's step (static potential: the EndCoef values)
+        cd cpA = ea.cp, cmA = ea.cm, cpB = eb.cp, cmB = eb.cm;
+        cd aAl = ea.a, aBl = eb.a, sgAl = ea.sig, sgBl = eb.sig, sgsAl = ea.sig_s, sgsBl = eb.sig_s;
+        double gwA = 1.0, gwB = 1.0;
+        double eWa = 0.0, edWa = 0.0, eWb = 0.0, edWb = 0.0;
+        if (TEND) {
+            const int nj = min(n0 + 1 + t, nt);
+            if (lif) end_data(nj, o, -1.0, eWa, edWa);
+            if (rif) end_data(nj, o + n - 1, 1.0, eWb, edWb);
+            if (TR == TR_GEN) {
+                gen_end_coef(trc, eWa, edWa, a.dt, a.c2, cpA, cmA, aAl, sgAl, sgsAl, gwA);
+                gen_end_coef(trc, eWb, edWb, a.dt, a.c2, cpB, cmB, aBl, sgBl, sgsBl, gwB);
+            }
+        }
         if (TR == TR_GEN) {
             const int nj = n0 + 1 + t;
             const bool odd = (nj & 1) != 0;
-            Hl_a = ea.cp * (odd ? acc_a1 : acc_a) + ea.cm * (odd ? acc_a : acc_a1);
-            Hl_b = eb.cp * (odd ? acc_b1 : acc_b) + eb.cm * (odd ? acc_b : acc_b1);
-            Ga = 2.0 * mk(wave_sum(gs_a.x), wave_sum(gs_a.y));
-            Gb = 2.0 * mk(wave_sum(gs_b.x), wave_sum(gs_b.y));
-            double sn, cs;
-            sincos(((double)nj - 0.5) * ea.omega, &sn, &cs);
-            pha = mk(cs, sn);
-            sincos(((double)nj - 0.5) * eb.omega, &sn, &cs);
-            phb = mk(cs, sn);
+            Hl_a = cpA * (odd ? acc_a1 : acc_a) + cmA * (odd ? acc_a : acc_a1);
+            Hl_b = cpB * (odd ? acc_b1 : acc_b) + cmB * (odd ? acc_b : acc_b1);
+            if (!TEND) {
+                Ga = 2.0 * mk(wave_sum(gs_a.x), wave_sum(gs_a.y));
+                Gb = 2.0 * mk(wave_sum(gs_b.x), wave_sum(gs_b.y));
+                double sn, cs;
+                sincos(((double)nj - 0.5) * ea.omega, &sn, &cs);
+                pha = mk(cs, sn);
+                sincos(((double)nj - 0.5) * eb.omega, &sn, &cs);
+                phb = mk(cs, sn);
+            }
         }
         cd rl_b = zero, rr_b = zero, va_b = zero, vb_b = zero, ua_b = zero, ub_b = zero;
 
         for (int i = 0; i < nb; ++i) {
             const int nstep = n0 + 1 + i;
+            // implicit coefficients of this step's boundary rows and of the
+            // exchange (static potential: constant)
+            cd sgA_n = a.sigma, sgB_n = a.sigma, sgsA_n = a.sigma, sgsB_n = a.sigma;
+            cd phA = mk(1, 0), phB = mk(1, 0);
+            if (TR == TR_GEN) {
+                sgsA_n = TEND ? rdlane(sgsAl, i) : ea.sig_s;
+                sgsB_n = TEND ? rdlane(sgsBl, i) : eb.sig_s;
+                sgA_n = TEND ? rdlane(sgAl, i) : ea.sig;
+                sgB_n = TEND ? rdlane(sgBl, i) : eb.sig;
+                if (TEND) {
+                    if (g_gauge) {
+                        // calV_n = calV_{n-1} + dt W_n, calW_n = (calV_n + calV_{n-1})/2
+                        const double wa = rdlane(eWa, i), wb = rdlane(eWb, i);
+                        const double na = cvA + a.dt * wa, nbv = cvB + a.dt * wb;
+                        double sn, cs;
+                        sincos(0.5 * (na + cvA), &sn, &cs);
+                        phA = mk(cs, sn);
+                        sincos(0.5 * (nbv + cvB), &sn, &cs);
+                        phB = mk(cs, sn);
+                        cvA = na;
+                        cvB = nbv;
+                    }
+                } else {
+                    phA = rdlane(pha, i);
+                    phB = rdlane(phb, i);
+                }
+            }
+            if (TR == TR_PADE) {
+                if (TEND) {
+                    // this step's r_s, w_s from W_n; history sums; implicit part
+                    // -i sum a_s + i sum a_s d_s r_s (+ (dn W/4) rho at order 4)
+#pragma unroll
+                    for (int e = 0; e < 2; ++e) {
+                        const double we = rdlane(e ? eWb : eWa, i), dwe = rdlane(e ? edWb : edWa, i);
+                        pade_coef(e, we, dwe);
+                        ph[e] = pade_sum(e);
+                        const cd p = pad[0] * pr[e][0] + pad[1] * pr[e][1];
+                        const cd ss = mk(wave_sum(p.x), wave_sum(p.y)) - mul_i(pasum);
+                        const cd sg = ord4 ? ss + (dwe / 4.0) * prho[e] : ss;
+                        if (e) { sgsB_n = ss; sgB_n = sg; } else { sgsA_n = ss; sgA_n = sg; }
+                    }
+                } else {
+                    sgsA_n = ea.sig_s;
+                    sgsB_n = eb.sig_s;
+                }
+            }
             if (VK == VK_TIME) {
                 // W_n = (V_n + V_{n-1})/2 (eq. CNS_L); refactor for this step
                 double w[P];
@@ -438,13 +590,13 @@ __global__ __launch_bounds__(sweep_threads(HELP)) void sweep_kernel(SweepArgs a)
                 double wL, wR;
                 neighbour_w(w, wL, wR);
                 cd ra[P], rbr[P], rc[P];
-                chunk_rows<P>(s, n, lif, rif, a.h, kap, a.sigma, a.sigma, w, wL, wR, ra, rbr, rc);
+                chunk_rows<P>(s, n, lif, rif, a.h, kap, sgA_n, sgB_n, w, wL, wR, ra, rbr, rc);
                 lane_factor<P>(ra, rbr, rc, F);
             }
             const cd ln = rdlane(lb, i), rn = rdlane(rb, i);
             // history part of Sbar v_n at each end: hA (all terms, boundary
             // condition) and hAs (without the order-4 term, the exchange)
-            cd hA = zero, hB = zero, hAs = zero, hBs = zero, phA = mk(1, 0), phB = mk(1, 0);
+            cd hA = zero, hB = zero, hAs = zero, hBs = zero;
             if (TR == TR_S02) {
                 hA = a.c2 * rdlane(acc_a, i);
                 hB = a.c2 * rdlane(acc_b, i);
@@ -452,12 +604,11 @@ __global__ __launch_bounds__(sweep_threads(HELP)) void sweep_kernel(SweepArgs a)
                 hBs = hB;
             }
             if (TR == TR_GEN) {
-                phA = rdlane(pha, i);
-                phB = rdlane(phb, i);
                 hAs = phA * rdlane(Hl_a, i);
                 hBs = phB * rdlane(Hl_b, i);
-                hA = hAs + ea.a * (phA * Ga);
-                hB = hBs + eb.a * (phB * Gb);
+                const cd aA = TEND ? rdlane(aAl, i) : ea.a, aB = TEND ? rdlane(aBl, i) : eb.a;
+                hA = hAs + aA * (phA * Ga);
+                hB = hBs + aB * (phB * Gb);
             }
             if (TR == TR_PADE) {
                 hAs = ph[0];
@@ -466,10 +617,8 @@ __global__ __launch_bounds__(sweep_threads(HELP)) void sweep_kernel(SweepArgs a)
                 hB = hBs;
                 if (ord4) {
                     // + sgn(dn W) (sqrt|dn W|/2) c psi_{n-1} / (c + W)
-                    const double gA = (ea.pad > 0.0 ? 1.0 : (ea.pad < 0.0 ? -1.0 : 0.0)) * pq[0];
-                    const double gB = (eb.pad > 0.0 ? 1.0 : (eb.pad < 0.0 ? -1.0 : 0.0)) * pq[1];
-                    hA = hA + gA * (pkrho[0] * ppsi[0]);
-                    hB = hB + gB * (pkrho[1] * ppsi[1]);
+                    hA = hA + (psg[0] * pq[0]) * (pkrho[0] * ppsi[0]);
+                    hB = hB + (psg[1] * pq[1]) * (pkrho[1] * ppsi[1]);
                 }
             }
             // right-hand side c M u_{n-1} + boundary terms
@@ -555,8 +704,8 @@ __global__ __launch_bounds__(sweep_threads(HELP)) void sweep_kernel(SweepArgs a)
             }
             const cd va = rdlane(x[0], 0);
             const cd vb = at_last(x);
-            const cd sgA = (TR == TR_GEN || TR == TR_PADE) ? ea.sig_s : a.sigma;
-            const cd sgB = (TR == TR_GEN || TR == TR_PADE) ? eb.sig_s : a.sigma;
+            const cd sgA = sgsA_n;
+            const cd sgB = sgsB_n;
             const cd rhoL = (2.0 * madd(hAs, sgA, va)) - ln;
             const cd rhoR = (2.0 * madd(hBs, sgB, vb)) - rn;
             // stored history value: x_n = e^{-i calW_n} v_n (= v_n for S0^2)
@@ -595,22 +744,26 @@ __global__ __launch_bounds__(sweep_threads(HELP)) void sweep_kernel(SweepArgs a)
                         pphi[e][j] = 2.0 * half - pphi[e][j];
                     }
                     if (ord4) {
-                        const EndCoef& ec = e ? eb : ea;
-                        const cd half = (pq[e] * ve) * ec.cp + pkrho[e] * ppsi[e];
+                        const cd half = (pq[e] * ve) * prho[e] + pkrho[e] * ppsi[e];
                         ppsi[e] = 2.0 * half - ppsi[e];
                     }
-                    ph[e] = pade_sum(e);
+                    if (!TEND) ph[e] = pade_sum(e);
                 }
             }
             if (TR == TR_GEN) {
                 if (t > i) {
                     const int lag = t - i;
                     const double bt = sbeta[lag];
-                    Hl_a = Hl_a + (bt * ((lag & 1) ? ea.cm : ea.cp)) * xa;
-                    Hl_b = Hl_b + (bt * ((lag & 1) ? eb.cm : eb.cp)) * xb;
+                    Hl_a = Hl_a + (bt * ((lag & 1) ? cmA : cpA)) * xa;
+                    Hl_b = Hl_b + (bt * ((lag & 1) ? cmB : cpB)) * xb;
                 }
-                Ga = Ga + 2.0 * xa;
-                Gb = Gb + 2.0 * xb;
+                if (TEND) {
+                    Ga = Ga + (2.0 * rdlane(gwA, i)) * xa;
+                    Gb = Gb + (2.0 * rdlane(gwB, i)) * xb;
+                } else {
+                    Ga = Ga + 2.0 * xa;
+                    Gb = Gb + 2.0 * xb;
+                }
             }
         }
         // block epilogue: coalesced stores
@@ -640,6 +793,8 @@ __global__ __launch_bounds__(sweep_threads(HELP)) void sweep_kernel(SweepArgs a)
             if (VK == VK_CUBIC) stp[(a.pstride + q) * kWave] = vlast[q];
         }
     }
+    if (TEND && TR == TR_GEN && !last && stp)
+        stp[a.pstride * kWave] = (t == 0) ? Ga : ((t == 1) ? Gb : mk(cvA, cvB));
     if (TR == TR_PADE && !last && pst) {
 #pragma unroll
         for (int e = 0; e < 2; ++e) {

@@ -1,6 +1,7 @@
 """GPU parity of the higher-order transmission operators (Sec. 2.2: potential
-strategy of orders 3 and 4, gauge change strategy of orders 2 and 4) against
-the CPU oracle, through the C ABI.
+strategy of orders 3 and 4, gauge change strategy of orders 2 and 4; with a
+time-dependent potential also the Pade strategy) against the CPU oracle,
+through the C ABI.
 
 Tolerances as in test_gpu_parity: 1e-12 relative for one sweep or one
 interface build (rounding order only; the gauge phase is formed as
@@ -150,4 +151,59 @@ def test_gradient_refuses_higher_order_operators(dev):
     with pytest.raises(swr.SwrError) as e:
         swr.swr_grad(pb.ctx, u0, gbar, dV, du0)
     assert e.value.status == swr.SWR_EINVAL
+    pb.close()
+
+
+# ---------------------------------------------------------------------------
+# time-dependent potential V(t,x): the end coefficients change every step
+# ---------------------------------------------------------------------------
+TIME_KINDS = KINDS + [("p22", W.P22), ("p24", W.P24)]
+
+
+def _tcase(J, nt, trans, B=1, seed=3):
+    wl = W.small_case(J=J, nt=nt, trans=trans, sigma=0j, B=B, seed=seed, a0=-12.0, b0=12.0,
+                      vkind=W.V_TIME)
+    wl.pade_m = 20
+    return wl
+
+
+@pytest.mark.parametrize("name,trans", TIME_KINDS)
+@pytest.mark.parametrize("with_data", [True, False])
+def test_time_dependent_one_sweep_matches_oracle(dev, name, trans, with_data):
+    """One iteration g -> R g with V(t,x): W_n, dn W_n, the gauge phase and
+    the order-4 sums follow the potential step by step."""
+    import torch
+    from paper_1503_02564_amd import swr
+    wl = _tcase(RAGGED, 150, trans)
+    say("time one_sweep", name, "data" if with_data else "zero-data")
+    pb = make_problem(wl)
+    rng = np.random.default_rng(12)
+    g = rng.standard_normal((pb.ns, wl.nt)) + 1j * rng.standard_normal((pb.ns, wl.nt))
+    u0 = wl.u0[0] if with_data else None
+    g_out = torch.zeros((1, pb.ns, wl.nt), dtype=torch.complex128, device=dev)
+    uT = torch.zeros((1, wl.nx), dtype=torch.complex128, device=dev)
+    swr.swr_apply_R(pb.ctx, to_dev(wl.u0) if with_data else None, to_dev(g[None]), g_out, uT)
+    torch.cuda.synchronize()
+    want = O.apply_R(wl, u0, g, hist0_zero=not with_data)
+    assert rel(to_np(g_out)[0], want) < 1e-12
+    if with_data:
+        assert rel(to_np(uT)[0], O.local_solution(wl, u0, g)[0]) < 1e-12
+    pb.close()
+
+
+@pytest.mark.parametrize("name,trans", TIME_KINDS)
+def test_time_dependent_solve_matches_monodomain(dev, name, trans):
+    """The preconditioned iteration (P = I - L_0, L_0 of the same operator at
+    zero potential, Sec. 5) reaches the monodomain solution."""
+    import torch
+    from paper_1503_02564_amd import swr
+    wl = _tcase([40, 63, 64, 100, 127, 200, 31], 130, trans, B=2)
+    say("time solve", name)
+    pb = make_problem(wl, tol=1e-13, restart=60, max_iter=400)
+    uT = torch.zeros((2, wl.nx), dtype=torch.complex128, device=dev)
+    st, info = swr.swr_solve(pb.ctx, to_dev(wl.u0), uT)
+    torch.cuda.synchronize()
+    assert st == swr.SWR_OK
+    for b in range(2):
+        assert rel(to_np(uT)[b], O.mono(wl, wl.u0[b])) < 1e-10
     pb.close()
