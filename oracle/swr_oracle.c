@@ -505,7 +505,8 @@ int orc_pade_apply(int order, int m, double theta, int nt, double dt, const cplx
 /*  where ' drops the order-4 normal-derivative term (S0^4, S1^4, S2^4).     */
 /*  trans: 0 Robin, 1 S0^2, 2 S0^3, 3 S0^4, 4 S1^2, 5 S1^4, 6 S2^{2,m},      */
 /*  7 S2^{4,m} (pade_m auxiliary functions, branch rotation pade_theta); the */
-/*  operators after S0^2 need a linear potential (returns -4 with |u|^2).    */
+/*  order-4 operators need a linear potential (returns -4 with |u|^2); with  */
+/*  |u|^2 the others take W_n = |v_{n-1}|^2 at the end node.                 */
 /*                                                                           */
 /* The subdomain has n nodes starting at global node `off0` of a mesh with   */
 /* nx_global nodes (V is indexed globally).  left_iface/right_iface say      */
@@ -528,9 +529,9 @@ int orc_sub_sweep(int n, double h, double dt, int nt, int vkind, const double *V
     const int pade = trans == ORC_P22 || trans == ORC_P24;
     const int conv = trans != ORC_ROBIN && !pade;     /* a convolution-type Sbar */
     const int porder = trans == ORC_P24 ? 4 : 2;
-    /* the operators beyond S0^2 carry W_n; with f(u) = |u|^2 the paper gives
-       no discretisation of them that keeps the interface continuity */
-    if (trans > ORC_S02 && vkind == ORC_V_CUBIC) return -4;
+    /* the order-4 operators carry dn W_n; with f(u) = |u|^2 the paper finds
+       no discretisation of dn f(u) that keeps the interfaces continuous */
+    if ((trans == ORC_S04 || trans == ORC_S14 || trans == ORC_P24) && vkind == ORC_V_CUBIC) return -4;
     if (trans < ORC_ROBIN || trans > ORC_P24) return -5;
     if (pade && (pade_m < 1 || pade_m > ORC_PADE_MAX)) return -5;
     cplx *diag = malloc(sizeof(cplx) * (size_t)n), *off = malloc(sizeof(cplx) * (size_t)(n > 1 ? n - 1 : 1));
@@ -562,7 +563,21 @@ int orc_sub_sweep(int n, double h, double dt, int nt, int vkind, const double *V
     ta[0] = hist0 ? hist0[0] : u[0];
     tb[0] = hist0 ? hist0[1] : u[n - 1];
 
+    double cvA = 0.0, cvB = 0.0;     /* |u|^2: calV_{n-1} at the two ends */
     for (int step = 1; step <= nt && rc == 0; ++step) {
+        if (vkind == ORC_V_CUBIC && trans > ORC_S02) {
+            /* W_n = f(u) at the end node, taken at the start of the step's
+               inner fixed point (zeta^0 = v_{n-1}), so that B_n stays fixed
+               over the inner iteration as eq. AvMNL writes it; dn W is not
+               used (order 2 and 3 only); calV, calW as for a linear potential */
+            Wa[step] = creal(v[0]) * creal(v[0]) + cimag(v[0]) * cimag(v[0]);
+            Wb[step] = creal(v[n - 1]) * creal(v[n - 1]) + cimag(v[n - 1]) * cimag(v[n - 1]);
+            const double nA = cvA + dt * Wa[step], nB = cvB + dt * Wb[step];
+            cWa[step] = 0.5 * (nA + cvA);
+            cWb[step] = 0.5 * (nB + cvB);
+            cvA = nA;
+            cvB = nB;
+        }
         /* A_n = cM - S + M_{W_n} (rebuilt every step: W_n and the implicit
            part of Sbar may change with n) */
         weight_at_step(vkind, V, nx_global, off0, n, vkind == ORC_V_TIME ? step : 0, W);

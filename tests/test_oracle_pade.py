@@ -124,7 +124,10 @@ def test_swr_with_pade_converges_to_the_monodomain_solution(trans, vkind):
         assert np.max(abs(O.ltt_apply(wl, cols, x).ravel() - Lb @ x)) < 1e-12 * np.max(abs(Lb @ x))
 
 
-def test_pade_with_the_cubic_potential_is_refused():
-    wl = W.small_case(N=2, nt=6, vkind=W.V_CUBIC, trans=W.P22, cells=6)
+def test_order_four_pade_with_the_cubic_potential_is_refused():
+    """S2^{4,m} carries dn f(u) (refused with |u|^2, as S0^4 and S1^4); S2^{2,m}
+    with |u|^2 is pinned with the other order-2 operators in
+    test_oracle_transmission.py."""
+    wl = W.small_case(N=2, nt=6, vkind=W.V_CUBIC, trans=W.P24, cells=6)
     with pytest.raises(RuntimeError):
         O.sweep(wl, 0, wl.u0[0])

@@ -13,7 +13,8 @@ formulas:
 * the normal derivative and gauge phase of the potential against closed forms;
 * the converged SWR solution equals the monodomain solution for every
   operator (the exchange cancels the order-4 terms, which flip sign with the
-  normal), for static and time-dependent potentials.
+  normal), for static and time-dependent potentials, and for the order-2 and
+  order-3 operators with |u|^2.
 """
 import math
 
@@ -156,10 +157,31 @@ def test_classical_swr_converges_to_the_monodomain_solution(trans, vkind):
         assert np.max(abs(O.ltt_apply(wl, cols, x).ravel() - Lb @ x)) < 1e-12 * np.max(abs(Lb @ x))
 
 
-def test_higher_order_operators_with_the_cubic_potential_are_refused():
-    """The paper gives no discretisation of the potential-dependent operators
-    with f(u) = |u|^2 that keeps the interfaces continuous: the oracle
-    refuses them."""
-    wl = W.small_case(N=2, nt=6, vkind=W.V_CUBIC, trans=W.S03, cells=6)
+@pytest.mark.parametrize("trans", [W.S04, W.S14, W.P24])
+def test_order_four_operators_with_the_cubic_potential_are_refused(trans):
+    """The paper finds no discretisation of dn f(u) in the order-4 operators
+    that keeps the interfaces continuous (Sec. 6): the oracle refuses them."""
+    wl = W.small_case(N=2, nt=6, vkind=W.V_CUBIC, trans=trans, cells=6)
     with pytest.raises(RuntimeError):
         O.sweep(wl, 0, wl.u0[0])
+
+
+@pytest.mark.parametrize("trans", [W.S03, W.S12, W.P22])
+def test_order_two_and_three_operators_with_the_cubic_potential(trans):
+    """With f(u) = |u|^2 the operators that carry W_n take it at the end node
+    from the start of the step's inner fixed point, W_n = |v_{n-1}|^2: both
+    sides of an interface see the same value once the iteration has
+    converged, so the classical fixed point reaches the monodomain solution;
+    and W_n really enters (the result differs from S0^2's iterates)."""
+    wl = W.small_case(N=3, nt=24, vkind=W.V_CUBIC, trans=trans, cells=8, seed=9)
+    wl.pade_m = 8
+    u0 = 1.5 * wl.u0[0]
+    um = O.mono(wl, u0)
+    g, it, _ = O.classical(wl, u0, tol=1e-12, maxit=600)
+    assert it > 0
+    uT, _ = O.local_solution(wl, u0, g)
+    assert np.max(abs(uT - um)) < 1e-11 * np.max(abs(um))
+    # the first iterate from g = 0 differs from that of S0^2 (W_n is used)
+    w2 = W.small_case(N=3, nt=24, vkind=W.V_CUBIC, trans=W.S02, cells=8, seed=9)
+    z = np.zeros((2 * wl.N - 2, wl.nt), np.complex128)
+    assert np.max(abs(O.apply_R(wl, u0, z) - O.apply_R(w2, u0, z))) > 1e-6
