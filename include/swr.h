@@ -74,9 +74,11 @@ typedef enum {
  * W is the potential at the interface node, dn W its outward normal derivative
  * (centred difference on the mesh), calW the gauge phase (time integral of V by
  * the trapezoid rule, averaged over the two ends of the step); with V(t,x) all of
- * them follow W_n = (V_n + V_{n-1})/2 step by step.  S03..P24 need a linear
- * potential (SWR_V_STATIC or SWR_V_TIME, not |u|^2); the order-4 terms flip sign
- * with the normal and cancel in the exchange, which transmits S without them. */
+ * them follow W_n = (V_n + V_{n-1})/2 step by step; with |u|^2 (SWR_V_CUBIC)
+ * W_n = |v_{n-1}|^2 at the end node (the inner fixed point's starting value) and
+ * the order-4 operators S04, S14, P24 are refused (they carry dn f(u)).  The
+ * order-4 terms flip sign with the normal and cancel in the exchange, which
+ * transmits S without them. */
 typedef enum {
     SWR_ROBIN = 0, SWR_S02 = 1, SWR_S03 = 2, SWR_S04 = 3, SWR_S12 = 4, SWR_S14 = 5,
     SWR_P22 = 6, SWR_P24 = 7

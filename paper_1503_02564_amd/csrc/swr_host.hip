@@ -361,9 +361,9 @@ extern "C" swr_status swr_setup(double a0, double b0, int N, const int* J, doubl
     if (tr >= SWR_P22 && (o.pade_m < 1 || o.pade_m > kPadeMax || !(o.pade_theta > 0) ||
                           !(o.pade_theta < M_PI)))
         return SWR_EINVAL;
-    // the operators beyond S0^2 depend on W: provided for linear potentials
-    // (with |u|^2 the paper gives no discretisation of W = f(u) in them)
-    if (tr > SWR_S02 && vk == SWR_V_CUBIC) return SWR_EINVAL;
+    // the order-4 operators carry dn W; with |u|^2 the paper finds no
+    // discretisation of dn f(u) that keeps the interfaces continuous
+    if ((tr == SWR_S04 || tr == SWR_S14 || tr == SWR_P24) && vk == SWR_V_CUBIC) return SWR_EINVAL;
     if (tr == SWR_ROBIN && s_re == 0.0 && s_im == 0.0) return SWR_EINVAL;
     if (!std::isfinite(s_re) || !std::isfinite(s_im)) return SWR_EINVAL;
     if (o.batch < 1 || o.restart < 1 || o.max_iter < 1 || !(o.tol > 0)) return SWR_EINVAL;

@@ -1,4 +1,5 @@
-// swr_sweep_cubic.hip -- instantiates the subdomain sweep for the |u|^2 potential.
+// swr_sweep_cubic.hip -- instantiates the subdomain sweep for the |u|^2 potential
+// (Robin and S0^2; the W-dependent operators are in swr_sweep_cubic_hi.hip).
 #include "swr_sweep_kernel.h"
 
 namespace swr {
@@ -12,8 +13,11 @@ static void launch_p(const SweepArgs& a, int trans, hipStream_t st) {
     else sweep_kernel<P, TR_ROBIN, VK_CUBIC><<<a.ntasks, sweep_threads(false), 0, st>>>(a);
 }
 
+hipError_t launch_sweep_cubic_hi(const SweepArgs& a, int trans, hipStream_t st);
+
 hipError_t launch_sweep_cubic(const SweepArgs& a, int trans, hipStream_t st) {
-    // the higher-order operators are provided for a static potential only
+    // the W-dependent operators (swr_sweep_cubic_hi.hip)
+    if (trans == TR_GEN || trans == TR_PADE) return launch_sweep_cubic_hi(a, trans, st);
     if (trans != TR_S02 && trans != TR_ROBIN) return hipErrorInvalidValue;
     switch (a.P) {
         case 1: launch_p<1>(a, trans, st); break;

@@ -184,15 +184,19 @@ __global__ __launch_bounds__(sweep_threads(HELP)) void sweep_kernel(SweepArgs a)
     // c r_s, and the history weight w_s = i a_s d_s c r_s (c = 2i/dt); psi of
     // the order-4 operator is wave-uniform.  ph[e] = sum_s w_s phi^s_{n-1}
     // (a wave sum, every lane holds it) is ready before each step.
-    // Time-dependent potential with the higher-order or Pade operators
-    // (Sec. 2.2 with W_n = (V_n + V_{n-1})/2 at the end node): the end
-    // coefficients change every step.  Lane j computes those of step n0+1+j
-    // at each block start from rows n and n-1 of V; the gauge phase is
-    // advanced step by step (calV_n = calV_{n-1} + dt W_n, calW_n the mean of
-    // the two, as in the oracle) and the order-4 sum G_n = 2 sum_{s<n} q_s x_s
-    // (q_s = sqrt|dn W_s|/2 for S1^4, 1 for S0^4) is a running sum; both are
-    // carried across launches in the second half of the state record.
-    constexpr bool TEND = VK == VK_TIME && (TR == TR_GEN || TR == TR_PADE);
+    // Time-dependent or |u|^2 potential with the higher-order or Pade
+    // operators (Sec. 2.2): the end coefficients change every step and are
+    // formed per step, wave-uniform, from W_n and dn W_n at the end node --
+    // V(t,x): W_n = (V_n + V_{n-1})/2, which lane j reads for step n0+1+j at
+    // each block start; |u|^2: W_n = |v_{n-1}|^2 at the end node, the inner
+    // fixed point's starting value (dn W unused: order 2 and 3 only).  The
+    // history keeps its even- and odd-lag beta sums apart (E, O) until the
+    // step's coefficients are known; the gauge phase is advanced step by step
+    // (calV_n = calV_{n-1} + dt W_n, calW_n the mean of the two, as in the
+    // oracle) and the order-4 sum G_n = 2 sum_{s<n} q_s x_s (q_s =
+    // sqrt|dn W_s|/2 for S1^4, 1 for S0^4) is a running sum; both are carried
+    // across launches in the second half of the state record.
+    constexpr bool TEND = (VK == VK_TIME || VK == VK_CUBIC) && (TR == TR_GEN || TR == TR_PADE);
     const int trc = a.tr;
     const bool g_gauge = trc == 4 || trc == 5;
     cd Ga = zero, Gb = zero;          // TR_GEN: G_n of the two ends
@@ -494,26 +498,26 @@ __global__ __launch_bounds__(sweep_threads(HELP)) void sweep_kernel(SweepArgs a)
         // nj = n0+1+j (lag nj - q0 - i has the parity of nj - i, q0 being a
         // multiple of 64), its phase e^{i calW_nj}, and the wave-uniform
         // G = 2 sum_{s <= n0} x_s
-        cd Hl_a = zero, Hl_b = zero, pha = mk(1, 0), phb = mk(1, 0);
-        // end coefficients of lane j's step (static potential: the EndCoef values)
-        cd cpA = ea.cp, cmA = ea.cm, cpB = eb.cp, cmB = eb.cm;
-        cd aAl = ea.a, aBl = eb.a, sgAl = ea.sig, sgBl = eb.sig, sgsAl = ea.sig_s, sgsBl = eb.sig_s;
-        double gwA = 1.0, gwB = 1.0;
-        double eWa = 0.0, edWa = 0.0, eWb = 0.0, edWb = 0.0;
-        if (TEND) {
+        // static: Hl = cp E + cm O; TEND: Hl = E and Ho = O (coefficients per step)
+        cd Hl_a = zero, Hl_b = zero, Ho_a = zero, Ho_b = zero, pha = mk(1, 0), phb = mk(1, 0);
+        double eWa = 0.0, edWa = 0.0, eWb = 0.0, edWb = 0.0;   // V(t,x): lane j's step
+        if (TEND && VK == VK_TIME) {
             const int nj = min(n0 + 1 + t, nt);
             if (lif) end_data(nj, o, -1.0, eWa, edWa);
             if (rif) end_data(nj, o + n - 1, 1.0, eWb, edWb);
-            if (TR == TR_GEN) {
-                gen_end_coef(trc, eWa, edWa, a.dt, a.c2, cpA, cmA, aAl, sgAl, sgsAl, gwA);
-                gen_end_coef(trc, eWb, edWb, a.dt, a.c2, cpB, cmB, aBl, sgBl, sgsBl, gwB);
-            }
         }
         if (TR == TR_GEN) {
             const int nj = n0 + 1 + t;
             const bool odd = (nj & 1) != 0;
-            Hl_a = cpA * (odd ? acc_a1 : acc_a) + cmA * (odd ? acc_a : acc_a1);
-            Hl_b = cpB * (odd ? acc_b1 : acc_b) + cmB * (odd ? acc_b : acc_b1);
+            if (TEND) {
+                Hl_a = odd ? acc_a1 : acc_a;
+                Ho_a = odd ? acc_a : acc_a1;
+                Hl_b = odd ? acc_b1 : acc_b;
+                Ho_b = odd ? acc_b : acc_b1;
+            } else {
+                Hl_a = ea.cp * (odd ? acc_a1 : acc_a) + ea.cm * (odd ? acc_a : acc_a1);
+                Hl_b = eb.cp * (odd ? acc_b1 : acc_b) + eb.cm * (odd ? acc_b : acc_b1);
+            }
             if (!TEND) {
                 Ga = 2.0 * mk(wave_sum(gs_a.x), wave_sum(gs_a.y));
                 Gb = 2.0 * mk(wave_sum(gs_b.x), wave_sum(gs_b.y));
@@ -532,15 +536,31 @@ __global__ __launch_bounds__(sweep_threads(HELP)) void sweep_kernel(SweepArgs a)
             // exchange (static potential: constant)
             cd sgA_n = a.sigma, sgB_n = a.sigma, sgsA_n = a.sigma, sgsB_n = a.sigma;
             cd phA = mk(1, 0), phB = mk(1, 0);
+            // end data of this step (TEND)
+            double WA_n = 0.0, dWA_n = 0.0, WB_n = 0.0, dWB_n = 0.0;
+            if (TEND && VK == VK_TIME) {
+                WA_n = rdlane(eWa, i);
+                dWA_n = rdlane(edWa, i);
+                WB_n = rdlane(eWb, i);
+                dWB_n = rdlane(edWb, i);
+            }
+            if (TEND && VK == VK_CUBIC) {
+                WA_n = abs2(rdlane(vlast[0], 0));
+                WB_n = abs2(at_last(vlast));
+            }
+            cd cpA_n = ea.cp, cmA_n = ea.cm, cpB_n = eb.cp, cmB_n = eb.cm, aA_n = ea.a, aB_n = eb.a;
+            double gwA_n = 1.0, gwB_n = 1.0;
             if (TR == TR_GEN) {
-                sgsA_n = TEND ? rdlane(sgsAl, i) : ea.sig_s;
-                sgsB_n = TEND ? rdlane(sgsBl, i) : eb.sig_s;
-                sgA_n = TEND ? rdlane(sgAl, i) : ea.sig;
-                sgB_n = TEND ? rdlane(sgBl, i) : eb.sig;
+                sgsA_n = ea.sig_s;
+                sgsB_n = eb.sig_s;
+                sgA_n = ea.sig;
+                sgB_n = eb.sig;
                 if (TEND) {
+                    gen_end_coef(trc, WA_n, dWA_n, a.dt, a.c2, cpA_n, cmA_n, aA_n, sgA_n, sgsA_n, gwA_n);
+                    gen_end_coef(trc, WB_n, dWB_n, a.dt, a.c2, cpB_n, cmB_n, aB_n, sgB_n, sgsB_n, gwB_n);
                     if (g_gauge) {
                         // calV_n = calV_{n-1} + dt W_n, calW_n = (calV_n + calV_{n-1})/2
-                        const double wa = rdlane(eWa, i), wb = rdlane(eWb, i);
+                        const double wa = WA_n, wb = WB_n;
                         const double na = cvA + a.dt * wa, nbv = cvB + a.dt * wb;
                         double sn, cs;
                         sincos(0.5 * (na + cvA), &sn, &cs);
@@ -561,7 +581,7 @@ __global__ __launch_bounds__(sweep_threads(HELP)) void sweep_kernel(SweepArgs a)
                     // -i sum a_s + i sum a_s d_s r_s (+ (dn W/4) rho at order 4)
 #pragma unroll
                     for (int e = 0; e < 2; ++e) {
-                        const double we = rdlane(e ? eWb : eWa, i), dwe = rdlane(e ? edWb : edWa, i);
+                        const double we = e ? WB_n : WA_n, dwe = e ? dWB_n : dWA_n;
                         pade_coef(e, we, dwe);
                         ph[e] = pade_sum(e);
                         const cd p = pad[0] * pr[e][0] + pad[1] * pr[e][1];
@@ -593,6 +613,16 @@ __global__ __launch_bounds__(sweep_threads(HELP)) void sweep_kernel(SweepArgs a)
                 chunk_rows<P>(s, n, lif, rif, a.h, kap, sgA_n, sgB_n, w, wL, wR, ra, rbr, rc);
                 lane_factor<P>(ra, rbr, rc, F);
             }
+            if (VK == VK_CUBIC && TEND) {
+                // |u|^2 with a W-dependent operator: the V-free matrix with this
+                // step's implicit coefficients, fixed over the inner iteration
+                double w[P];
+#pragma unroll
+                for (int q = 0; q < P; ++q) w[q] = 0.0;
+                cd ra[P], rbr[P], rc[P];
+                chunk_rows<P>(s, n, lif, rif, a.h, kap, sgA_n, sgB_n, w, 0.0, 0.0, ra, rbr, rc);
+                lane_factor<P>(ra, rbr, rc, F);
+            }
             const cd ln = rdlane(lb, i), rn = rdlane(rb, i);
             // history part of Sbar v_n at each end: hA (all terms, boundary
             // condition) and hAs (without the order-4 term, the exchange)
@@ -604,11 +634,15 @@ __global__ __launch_bounds__(sweep_threads(HELP)) void sweep_kernel(SweepArgs a)
                 hBs = hB;
             }
             if (TR == TR_GEN) {
-                hAs = phA * rdlane(Hl_a, i);
-                hBs = phB * rdlane(Hl_b, i);
-                const cd aA = TEND ? rdlane(aAl, i) : ea.a, aB = TEND ? rdlane(aBl, i) : eb.a;
-                hA = hAs + aA * (phA * Ga);
-                hB = hBs + aB * (phB * Gb);
+                if (TEND) {
+                    hAs = phA * (cpA_n * rdlane(Hl_a, i) + cmA_n * rdlane(Ho_a, i));
+                    hBs = phB * (cpB_n * rdlane(Hl_b, i) + cmB_n * rdlane(Ho_b, i));
+                } else {
+                    hAs = phA * rdlane(Hl_a, i);
+                    hBs = phB * rdlane(Hl_b, i);
+                }
+                hA = hAs + aA_n * (phA * Ga);
+                hB = hBs + aB_n * (phB * Gb);
             }
             if (TR == TR_PADE) {
                 hAs = ph[0];
@@ -754,12 +788,22 @@ __global__ __launch_bounds__(sweep_threads(HELP)) void sweep_kernel(SweepArgs a)
                 if (t > i) {
                     const int lag = t - i;
                     const double bt = sbeta[lag];
-                    Hl_a = Hl_a + (bt * ((lag & 1) ? cmA : cpA)) * xa;
-                    Hl_b = Hl_b + (bt * ((lag & 1) ? cmB : cpB)) * xb;
+                    if (TEND) {
+                        if (lag & 1) {
+                            Ho_a = Ho_a + bt * xa;
+                            Ho_b = Ho_b + bt * xb;
+                        } else {
+                            Hl_a = Hl_a + bt * xa;
+                            Hl_b = Hl_b + bt * xb;
+                        }
+                    } else {
+                        Hl_a = Hl_a + (bt * ((lag & 1) ? ea.cm : ea.cp)) * xa;
+                        Hl_b = Hl_b + (bt * ((lag & 1) ? eb.cm : eb.cp)) * xb;
+                    }
                 }
                 if (TEND) {
-                    Ga = Ga + (2.0 * rdlane(gwA, i)) * xa;
-                    Gb = Gb + (2.0 * rdlane(gwB, i)) * xb;
+                    Ga = Ga + (2.0 * gwA_n) * xa;
+                    Gb = Gb + (2.0 * gwB_n) * xb;
                 } else {
                     Ga = Ga + 2.0 * xa;
                     Gb = Gb + 2.0 * xb;

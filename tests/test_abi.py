@@ -58,7 +58,7 @@ def _setup_raw(swr, a0=-1.0, b0=1.0, J=(4, 4), dt=0.1, T=1.0, vk=0, tr=1, s=(1.0
 @pytest.mark.parametrize("kw", [
     dict(a0=1.0, b0=-1.0), dict(J=()), dict(J=(4, 0)), dict(dt=0.0), dict(T=-1.0),
     dict(dt=0.3, T=1.0), dict(vk=7), dict(tr=8), dict(tr=-1), dict(tr=0, s=(0.0, 0.0)),
-    dict(tr=2, vk=2), dict(tr=5, vk=2), dict(tr=4, vk=2), dict(tr=6, vk=2), dict(tr=7, vk=2),
+    dict(tr=3, vk=2), dict(tr=5, vk=2), dict(tr=7, vk=2),
     dict(J=(600,)), dict(vk=1), dict(dt=float("nan")),
 ])
 def test_setup_rejects_invalid_arguments(swr, kw):

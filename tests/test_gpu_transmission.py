@@ -207,3 +207,56 @@ def test_time_dependent_solve_matches_monodomain(dev, name, trans):
     for b in range(2):
         assert rel(to_np(uT)[b], O.mono(wl, wl.u0[b])) < 1e-10
     pb.close()
+
+
+# ---------------------------------------------------------------------------
+# |u|^2: the order-2 and order-3 W-dependent operators, W_n = |v_{n-1}|^2 at
+# the end node (the inner fixed point's starting value); order 4 is refused
+# ---------------------------------------------------------------------------
+CUBIC_KINDS = [("s03", W.S03), ("s12", W.S12), ("p22", W.P22)]
+
+
+def _ccase(J, nt, trans, seed=23):
+    wl = W.small_case(J=J, nt=nt, trans=trans, sigma=0j, seed=seed, a0=-12.0, b0=12.0,
+                      vkind=W.V_CUBIC)
+    wl.u0 = 1.5 * wl.u0
+    wl.pade_m = 20
+    return wl
+
+
+@pytest.mark.parametrize("name,trans", CUBIC_KINDS)
+def test_cubic_one_sweep_matches_oracle(dev, name, trans):
+    """One iteration with the inner fixed point every step (both sides to
+    1e-14, hence the 1e-11 bar of the other |u|^2 sweeps)."""
+    import torch
+    from paper_1503_02564_amd import swr
+    wl = _ccase([40, 63, 100, 31, 128, 200], 90, trans)
+    say("cubic one_sweep", name)
+    pb = make_problem(wl)
+    rng = np.random.default_rng(3)
+    g = 0.3 * (rng.standard_normal((pb.ns, wl.nt)) + 1j * rng.standard_normal((pb.ns, wl.nt)))
+    g_out = torch.zeros((1, pb.ns, wl.nt), dtype=torch.complex128, device=dev)
+    uT = torch.zeros((1, wl.nx), dtype=torch.complex128, device=dev)
+    swr.swr_apply_R(pb.ctx, to_dev(wl.u0), to_dev(g[None]), g_out, uT)
+    torch.cuda.synchronize()
+    assert rel(to_np(g_out)[0], O.apply_R(wl, wl.u0[0], g)) < 1e-11
+    assert rel(to_np(uT)[0], O.local_solution(wl, wl.u0[0], g)[0]) < 1e-11
+    pb.close()
+
+
+@pytest.mark.parametrize("name,trans", CUBIC_KINDS)
+def test_cubic_solve_matches_monodomain(dev, name, trans):
+    """The preconditioned fixed point (P = I - L_0, Sec. 5) reaches the
+    monodomain solution with each operator."""
+    import torch
+    from paper_1503_02564_amd import swr
+    wl = _ccase([40, 63, 100, 31], 90, trans)
+    say("cubic solve", name)
+    pb = make_problem(wl, tol=1e-13, max_iter=3000)
+    uT = torch.zeros((1, wl.nx), dtype=torch.complex128, device=dev)
+    st, info = swr.swr_solve(pb.ctx, to_dev(wl.u0), uT)
+    torch.cuda.synchronize()
+    say("cubic solve", name, info.iters, info.nl_worst)
+    assert st == swr.SWR_OK
+    assert rel(to_np(uT)[0], O.mono(wl, wl.u0[0])) < 1e-10
+    pb.close()
