@@ -216,6 +216,9 @@ struct Task {
 constexpr int kPcrLevels = 6;
 __host__ __device__ constexpr int fac_fields(int P) { return 5 * (P - 1) + 2 + 2 * kPcrLevels + 1; }
 constexpr int kMaxP = 8;
+// subdomains of more than 64 * kMaxP nodes run the long-chunk sweep
+// (swr_sweep_long.hip) with up to this many nodes per lane
+constexpr int kLongMaxQ = 8192;
 // default schedule: the S0^2 helper wave up to this many tasks per launch (every
 // wave then has a SIMD of its own), the pipelined static solve up to this many
 // build tasks (beyond, the sweeps fill the GPU and the interface solve's
@@ -279,6 +282,11 @@ struct SweepArgs {
     int pade_m, pade_order;      // auxiliary functions per end; 2 or 4
     cd* pstate;                  // [ntasks][6][64] auxiliary functions carried between launches
                                  // (phi of the left end: slots 0, 1; right end: 2, 3; psi: 4, 5)
+    // long-chunk sweep (subdomains of more than 64 * kMaxP nodes)
+    int lq;                      // nodes per lane of this launch
+    cd* lfac;                    // [nf][fac_fields(lq max)][64] factor records (static, |u|^2)
+    size_t lfstride;             // complex entries per long factor record
+    cd* lwork;                   // [ntasks][3 Q (+ fac_fields(Q) for V(t,x))][64] per-task arrays
 };
 
 struct FactorArgs {
@@ -334,6 +342,9 @@ hipError_t launch_sweep(const SweepArgs& a, int trans, int vk, hipStream_t st, b
 hipError_t launch_sweep_static(const SweepArgs& a, int trans, hipStream_t st);
 hipError_t launch_sweep_static_s02(const SweepArgs& a, hipStream_t st);
 hipError_t launch_sweep_static_pade(const SweepArgs& a, hipStream_t st);
+// subdomains of more than 64 * kMaxP nodes (swr_sweep_long.hip): a.lq nodes per lane
+hipError_t launch_sweep_long(const SweepArgs& a, int trans, int vk, hipStream_t st);
+hipError_t launch_factor_long(const FactorArgs& a, int Q, hipStream_t st);
 hipError_t launch_sweep_time(const SweepArgs& a, int trans, hipStream_t st);
 hipError_t launch_sweep_cubic(const SweepArgs& a, int trans, hipStream_t st);
 // static potential, Robin or S0^2: a.ntasks waves of two tasks each, the

@@ -36,6 +36,7 @@ using namespace swr;
 struct Iface {
     cd* cols = nullptr;     // [nv][N][4][nt]
     cd* fac = nullptr;      // factor records [nv*N][fields][64]
+    cd* lfac = nullptr;     // long-chunk factor records [nv*N][fac_fields(Qmax)][64]
     Task* tasks = nullptr;  // impulse tasks
     int ntasks = 0;
     int nv = 1;
@@ -86,7 +87,12 @@ struct swr_ctx {
     int nBuild = 0;
     Task* dSub = nullptr;     // one task per (problem, subdomain)
     int nSub = 0;
-    std::vector<int> Pk;      // chunk width of each subdomain (c->P is the largest)
+    std::vector<int> Pk;      // chunk width of each subdomain (c->P is the largest up to kMaxP;
+                              // wider subdomains run the long-chunk sweep)
+    int Qlong = 0;            // largest long-chunk width (0: none)
+    size_t lfstride = 0;      // complex entries per long factor record
+    size_t lwrec = 0;         // complex entries per task work record of the long sweep
+    cd* dLwork = nullptr;     // [max tasks][lwrec]
     int* dPk = nullptr;
     std::vector<WidthRun> runs_build, runs_sub, runs_L0;
     int2* dPairsB = nullptr;  // pair tables of the build and the per-(problem, subdomain) lists
@@ -380,7 +386,9 @@ extern "C" swr_status swr_setup(double a0, double b0, int N, const int* J, doubl
         nc += J[k];
         nmax = J[k] + 1 > nmax ? J[k] + 1 : nmax;
     }
-    if (nmax > kWave * kMaxP || nc > (1L << 30)) return SWR_EINVAL;
+    if (nmax > kWave * kLongMaxQ || nc > (1L << 30)) return SWR_EINVAL;
+    // subdomains beyond 64 * kMaxP nodes (long-chunk sweep): Robin and S0^2
+    if (nmax > kWave * kMaxP && tr != SWR_ROBIN && tr != SWR_S02) return SWR_EINVAL;
 
     swr_ctx* c = new (std::nothrow) swr_ctx();
     if (!c) return SWR_ENOMEM;
@@ -390,7 +398,8 @@ extern "C" swr_status swr_setup(double a0, double b0, int N, const int* J, doubl
     if (hipGetDevice(&c->dev) != hipSuccess) { delete c; return SWR_EDEVICE; }
     c->scratch = scratch_address(c->dev);
     c->nv = (vk == SWR_V_STATIC && o.v_per_problem) ? o.batch : 1;
-    c->P = (nmax + kWave - 1) / kWave;
+    c->P = std::min((nmax + kWave - 1) / kWave, kMaxP);
+    c->Qlong = nmax > kWave * kMaxP ? (nmax + kWave - 1) / kWave : 0;
     c->c2 = mk(std::cos(-M_PI / 4) * std::sqrt(2.0 / dt), std::sin(-M_PI / 4) * std::sqrt(2.0 / dt));
     // S0^2: the implicit coefficient of c2 sum beta_{n-s} v_s is c2 beta_0 = c2
     c->sigma = (tr == SWR_ROBIN) ? mk(s_re, s_im) : c->c2;
@@ -449,6 +458,11 @@ extern "C" swr_status swr_setup(double a0, double b0, int N, const int* J, doubl
     const size_t vec = (size_t)B * ns * nt;
     const size_t max_tasks = std::max(build.size(), std::max(sub.size(), imp0.size()));
     const int fields = fac_fields(c->P);
+    if (c->Qlong) {
+        c->lfstride = (size_t)fac_fields(c->Qlong) * kWave;
+        c->lwrec = (size_t)(3 * c->Qlong + (vk == SWR_V_TIME ? fac_fields(c->Qlong) : 0)) * kWave;
+        ALLOC(c->dLwork, max_tasks * c->lwrec);
+    }
     ALLOC(c->dJ, N);
     ALLOC(c->dOff, N);
     ALLOC(c->dPk, N);
@@ -488,6 +502,7 @@ extern "C" swr_status swr_setup(double a0, double b0, int N, const int* J, doubl
     if (vk == SWR_V_STATIC) {
         ALLOC(c->L.fac, (size_t)nv * N * fields * kWave);
         ALLOC(c->L.cols, (size_t)nv * N * 4 * nt);
+        if (c->Qlong) ALLOC(c->L.lfac, (size_t)nv * N * c->lfstride);
     }
     // ... and of the zero potential (preconditioner; also the V-free factors
     // of the |u|^2 scheme)
@@ -496,6 +511,7 @@ extern "C" swr_status swr_setup(double a0, double b0, int N, const int* J, doubl
         c->L0.ntasks = (int)imp0.size();
         ALLOC(c->L0.fac, (size_t)N * fields * kWave);
         ALLOC(c->L0.cols, (size_t)N * 4 * nt);
+        if (c->Qlong) ALLOC(c->L0.lfac, (size_t)N * c->lfstride);
         ALLOC(c->L0.tasks, imp0.size());
     }
     if (vk != SWR_V_CUBIC) {
@@ -620,6 +636,10 @@ static SweepArgs sweep_args(swr_ctx* c, const Task* tasks, int ntasks, const cd*
     a.help_max = c->help_max;
     a.pstride = c->P;
     a.fstride = (size_t)fac_fields(c->P) * kWave;
+    a.lfac = fac == c->L.fac ? c->L.lfac : (fac == c->L0.fac ? c->L0.lfac : nullptr);
+    a.lfstride = c->lfstride;
+    a.lwork = c->dLwork;
+    a.lq = 0;
     a.task0 = 0;
     a.n_begin = 0;
     a.n_end = c->nt;
@@ -640,9 +660,19 @@ static swr_status run_factor(swr_ctx* c, const double* V, int nv, cd* fac) {
     std::vector<int> widths(c->Pk);
     std::sort(widths.begin(), widths.end());
     widths.erase(std::unique(widths.begin(), widths.end()), widths.end());
+    cd* lfac = fac == c->L.fac ? c->L.lfac : (fac == c->L0.fac ? c->L0.lfac : nullptr);
     for (int P : widths) {
         f.P = P;
-        HIPCHK(launch_factor(f, c->st));
+        if (P <= kMaxP) {
+            HIPCHK(launch_factor(f, c->st));
+        } else {
+            // long-chunk records (swr_sweep_long.hip)
+            if (!lfac) return SWR_EINVAL;
+            FactorArgs fl = f;
+            fl.fac = lfac;
+            fl.fstride = c->lfstride;
+            HIPCHK(launch_factor_long(fl, P, c->st));
+        }
     }
     return SWR_OK;
 }
@@ -695,6 +725,16 @@ static hipError_t launch_widths(const swr_ctx* c, SweepArgs a, int vk, hipStream
     const int tr = ktr(c);
     for (const WidthRun& r : runs_of(c, a.tasks)) {
         a.P = r.P;
+        if (r.P > kMaxP) {
+            // subdomains beyond 64 * kMaxP nodes: the long-chunk sweep, one launch
+            a.task0 = r.start;
+            a.ntasks = r.count;
+            a.lq = r.P;
+            const hipError_t e = launch_sweep_long(a, tr, vk, st);
+            if (e != hipSuccess) return e;
+            if (launches) *launches += 1;
+            continue;
+        }
         const bool two = !plain && pairs && vk == SWR_V_STATIC && (tr == TR_S02 || tr == TR_ROBIN) &&
                          r.P >= c->pair_from && r.count > c->help_max && 4 * r.pcount <= 3 * r.count;
         hipError_t e;
@@ -1229,7 +1269,8 @@ struct PipeTimes {
 };
 
 static bool pipelined(const swr_ctx* c) {
-    return c->vk == SWR_V_STATIC && c->o.solver == SWR_SOLVER_CAUSAL && c->pipe_chunk > 0 &&
+    // (the long-chunk sweep runs the whole window in one launch)
+    return c->vk == SWR_V_STATIC && c->o.solver == SWR_SOLVER_CAUSAL && c->pipe_chunk > 0 && !c->Qlong &&
            !c->o.plain && causal_sized(c) &&
            c->ns > 0 && c->nt > c->pipe_chunk;
 }
@@ -1941,6 +1982,7 @@ extern "C" swr_status swr_grad(swr_ctx* c, const double* u0d, const double* gbar
     if (c->vk != SWR_V_STATIC || c->o.solver == SWR_SOLVER_FIXED || c->o.checkpoint_K != kWave)
         return SWR_EINVAL;
     if (c->tr > SWR_S02) return SWR_EINVAL;   // adjoint provided for Robin and S0^2
+    if (c->Qlong) return SWR_EINVAL;          // ... and subdomains of at most 64 * kMaxP nodes
     const cd* u0 = reinterpret_cast<const cd*>(u0d);
     const size_t vec = (size_t)c->B * c->ns * c->nt;
     hipStream_t st = c->st;

@@ -59,7 +59,7 @@ def _setup_raw(swr, a0=-1.0, b0=1.0, J=(4, 4), dt=0.1, T=1.0, vk=0, tr=1, s=(1.0
     dict(a0=1.0, b0=-1.0), dict(J=()), dict(J=(4, 0)), dict(dt=0.0), dict(T=-1.0),
     dict(dt=0.3, T=1.0), dict(vk=7), dict(tr=8), dict(tr=-1), dict(tr=0, s=(0.0, 0.0)),
     dict(tr=3, vk=2), dict(tr=5, vk=2), dict(tr=7, vk=2),
-    dict(J=(600,)), dict(vk=1), dict(dt=float("nan")),
+    dict(J=(600000,)), dict(J=(600,), tr=2), dict(vk=1), dict(dt=float("nan")),
 ])
 def test_setup_rejects_invalid_arguments(swr, kw):
     if kw.get("J") == ():
