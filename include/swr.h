@@ -172,6 +172,9 @@ typedef struct {
                          output pointers and schedule, replay the whole solve as one HIP graph
                          captured on the context's streams (bitwise the same results; no
                          per-stage timings in swr_info); 0 = launch kernel by kernel (default) */
+    int check;        /* GMRES: read the inner residual estimates back every this many steps
+                         (default 4); the iterate and the iteration count are those of a check
+                         after every step, the steps between reads need no host round trip */
     double ms;        /* swr_tune: wall time of the chosen schedule's solve */
     int candidates;   /* swr_tune: schedules timed */
 } swr_schedule;
@@ -284,7 +287,8 @@ swr_status swr_set_potential(swr_ctx* ctx, const double* V);
  * 1024 for the static causal solve; helper-wave bounds 0, 512, all for S0^2;
  * two-task waves from widths 1, 4 or never for static Robin / S0^2 sweeps;
  * graph replay on and off for the static causal solve; restarts 20, 30, 60,
- * 120 for GMRES and the V(t,x) iteration) with full
+ * 120 and residual read-back periods 1, 4, 16 for GMRES and the V(t,x)
+ * iteration) with full
  * solves of the caller's u0 [B][nx] (one warm-up and the best of two timed
  * solves each), until budget_ms of wall time is spent, and keeps the fastest
  * on the context.  With opts.tune_cache the choice is written to that file
@@ -300,7 +304,7 @@ swr_status swr_get_schedule(const swr_ctx* ctx, swr_schedule* s);
 
 /* Set the schedule of a context (host in; ms and candidates are ignored).
  * SWR_EINVAL for a pipeline chunk that is negative or not a multiple of 64, a
- * negative helper bound, a restart or pair width below 1. */
+ * negative helper bound, a restart, pair width or check period below 1. */
 swr_status swr_set_schedule(swr_ctx* ctx, const swr_schedule* s);
 
 /* Release the context and all device memory it owns. */

@@ -15,6 +15,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <fstream>
 #include <functional>
@@ -161,6 +162,9 @@ struct swr_ctx {
     int help_max = kHelpMaxTasks;
     int pair_from = kPairFrom;   // two tasks per wave from this chunk width on (9: never)
     int graph = 0;               // 1: capture the static causal solve once, replay it
+    int gm_check = 4;            // GMRES: read the residual estimates back every this many steps
+    double* dResHist = nullptr;  // GMRES: [restart][B] residual estimate after every inner step
+    std::vector<double> hResHist;
     int v_version = 0;           // bumped whenever the potential changes
     // the captured solve and the arguments it was captured with
     hipGraph_t g_graph = nullptr;
@@ -815,6 +819,8 @@ static swr_status run_gmres(swr_ctx* c, const Op& A, const cd* rhs, cd* x, int* 
         ALLOC_LIVE(c->dHp, (size_t)B * (m + 1));
         ALLOC_LIVE(c->dHp2, (size_t)B * (m + 1));
         ALLOC_LIVE(c->dY, (size_t)B * (m + 1));
+        ALLOC_LIVE(c->dResHist, (size_t)B * m);
+        c->hResHist.assign((size_t)B * m, 0.0);
         c->gm_m = m;
     }
     hipStream_t st = c->st;
@@ -828,14 +834,27 @@ static swr_status run_gmres(swr_ctx* c, const Op& A, const cd* rhs, cd* x, int* 
         HIPCHK(launch_norm(c->dBasis, M, B, c->dPart, c->dNrm, st));
         HIPCHK(launch_gmres_init(m, B, c->dNrm, c->dE, c->dAct, c->dBn, c->o.tol, c->dRes, st));
         HIPCHK(hipMemcpyAsync(c->hAct, c->dAct, sizeof(int) * B, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(c->hRes, c->dRes, sizeof(double) * B, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         bool any = false;
-        for (int b = 0; b < B; ++b) any |= c->hAct[b] != 0;
+        for (int b = 0; b < B; ++b) {
+            if (!std::isfinite(c->hRes[b])) return SWR_ENAN;
+            any |= c->hAct[b] != 0;
+        }
         if (!any) { conv = true; break; }
         if (its >= c->o.max_iter) break;
         HIPCHK(launch_scale(c->dBasis, c->dNrm, c->dBasis, M, B, nullptr, st));
-        int jj = 0;
-        for (int j = 0; j < m && its < c->o.max_iter; ++j) {
+        // The residual estimates of the inner steps are read back every
+        // gm_check steps (and at the cycle's and the budget's end), not after
+        // each: the steps between two reads run without a host round trip.
+        // The first step at which every active problem has converged is found
+        // among them afterwards, and the solve uses exactly the columns up to
+        // it (later steps only add Hessenberg columns and rotate e below it),
+        // so the iterate is the one of a check after every step.
+        int jj = 0, j0 = 0;
+        bool done = false;
+        for (int j = 0; j < m; ++j) {
+            if (its + (j - j0) >= c->o.max_iter) break;
             cd* vj = c->dBasis + (size_t)j * B * M;
             cd* vn = c->dBasis + (size_t)(j + 1) * B * M;
             CHK(A(vj, c->dW));
@@ -847,19 +866,27 @@ static swr_status run_gmres(swr_ctx* c, const Op& A, const cd* rhs, cd* x, int* 
             HIPCHK(launch_norm(c->dW, M, B, c->dPart, c->dNrm, st));
             HIPCHK(launch_scale(c->dW, c->dNrm, vn, M, B, nullptr, st));
             HIPCHK(launch_givens(j, m, B, c->dHp, c->dNrm, c->dH, c->dCs, c->dSn, c->dE, c->dBn,
-                                 c->dRes, c->dAct, st));
-            HIPCHK(hipMemcpyAsync(c->hRes, c->dRes, sizeof(double) * B, hipMemcpyDeviceToHost, st));
+                                 c->dResHist + (size_t)j * B, c->dAct, st));
+            const int pending = j + 1 - j0;
+            if (pending < c->gm_check && j < m - 1 && its + pending < c->o.max_iter) continue;
+            HIPCHK(hipMemcpyAsync(c->hResHist.data(), c->dResHist + (size_t)j0 * B,
+                                  sizeof(double) * B * pending, hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
-            ++its;
-            jj = j + 1;
-            bool done = true;
-            double worst = 0;
-            for (int b = 0; b < B; ++b) {
-                if (!std::isfinite(c->hRes[b])) return SWR_ENAN;
-                if (c->hAct[b] && c->hRes[b] > c->o.tol) done = false;
-                if (c->hAct[b]) worst = std::max(worst, c->hRes[b]);
+            for (int q = 0; q < pending && !done; ++q) {
+                const double* r = c->hResHist.data() + (size_t)q * B;
+                ++its;
+                jj = j0 + q + 1;
+                done = true;
+                double worst = 0;
+                for (int b = 0; b < B; ++b) {
+                    // (inactive problems' slots are not written in this cycle)
+                    if (c->hAct[b] && !std::isfinite(r[b])) return SWR_ENAN;
+                    if (c->hAct[b] && r[b] > c->o.tol) done = false;
+                    if (c->hAct[b]) worst = std::max(worst, r[b]);
+                }
+                c->hist.push_back(worst);
             }
-            c->hist.push_back(worst);
+            j0 = j + 1;
             if (done) break;
         }
         HIPCHK(launch_gmres_solve(jj, m, B, c->dH, c->dE, c->dY, c->dAct, st));
@@ -1749,7 +1776,8 @@ static void load_schedule(swr_ctx* c, const char* path) {
         int pipe = 0, help = 0, restart = 0, pair = 0;
         if (!(in >> k >> pipe >> help >> restart >> pair) || k != key) continue;
         if (pipe < 0 || (pipe > 0 && pipe % kWave != 0) || help < 0 || restart < 1 || pair < 1) continue;
-        // then "graph ms", or "ms" alone in lines written before the graph option
+        // then "graph check ms"; lines written before those options have
+        // "graph ms" or "ms" alone
         std::vector<std::string> rest;
         for (std::string t; in >> t;) rest.push_back(t);
         c->pipe_chunk = pipe;
@@ -1757,6 +1785,10 @@ static void load_schedule(swr_ctx* c, const char* path) {
         c->o.restart = restart;
         c->pair_from = pair;
         c->graph = rest.size() >= 2 && rest[0] == "1" ? 1 : 0;
+        if (rest.size() >= 3) {
+            const int chk = std::atoi(rest[1].c_str());
+            if (chk >= 1) c->gm_check = chk;
+        }
     }
 }
 
@@ -1777,7 +1809,7 @@ static bool store_schedule(const swr_ctx* c, const char* path, double ms) {
     if (!f) return false;
     for (const auto& l : keep) f << l << "\n";
     f << key << " " << c->pipe_chunk << " " << c->help_max << " " << c->o.restart << " " << c->pair_from
-      << " " << c->graph << " " << ms << "\n";
+      << " " << c->graph << " " << c->gm_check << " " << ms << "\n";
     return (bool)f;
 }
 
@@ -1787,7 +1819,10 @@ extern "C" swr_status swr_tune(swr_ctx* c, const double* u0, double budget_ms, s
     double* uT = reinterpret_cast<double*>(c->dUT);
     // candidate values (the current schedule first)
     std::vector<int> pipes{c->pipe_chunk}, helps{c->help_max}, restarts{c->o.restart}, pairs{c->pair_from},
-        graphs{c->graph};
+        graphs{c->graph}, checks{c->gm_check};
+    if (c->o.solver == SWR_SOLVER_GMRES || c->vk == SWR_V_TIME)
+        for (int q : {1, 4, 16})
+            if (std::find(checks.begin(), checks.end(), q) == checks.end()) checks.push_back(q);
     if (c->vk == SWR_V_STATIC && c->o.solver == SWR_SOLVER_CAUSAL) graphs.push_back(1 - c->graph);
     if (c->vk == SWR_V_STATIC && c->o.solver == SWR_SOLVER_CAUSAL)
         for (int p : {0, 128, 256, 512, 1024})
@@ -1801,13 +1836,15 @@ extern "C" swr_status swr_tune(swr_ctx* c, const double* u0, double budget_ms, s
     if (c->vk == SWR_V_STATIC && c->tr <= SWR_S02)
         for (int w : {1, 4, kMaxP + 1})
             if (std::find(pairs.begin(), pairs.end(), w) == pairs.end()) pairs.push_back(w);
-    const int p0 = c->pipe_chunk, h0 = c->help_max, m0 = c->o.restart, w0 = c->pair_from, q0 = c->graph;
+    const int p0 = c->pipe_chunk, h0 = c->help_max, m0 = c->o.restart, w0 = c->pair_from, q0 = c->graph,
+              k0 = c->gm_check;
     double best = INFINITY;
-    int bp = p0, bh = h0, bm = m0, bw = w0, bq = q0, tried = 0;
+    int bp = p0, bh = h0, bm = m0, bw = w0, bq = q0, bk = k0, tried = 0;
     double spent = 0;
     auto t_now = [] { return std::chrono::steady_clock::now(); };
     const auto t_start = t_now();
     for (int m : restarts)
+        for (int kc : checks)
         for (int w : pairs)
         for (int q : graphs)
         for (int p : pipes)
@@ -1818,6 +1855,7 @@ extern "C" swr_status swr_tune(swr_ctx* c, const double* u0, double budget_ms, s
                 c->o.restart = m;
                 c->pair_from = w;
                 c->graph = q;
+                c->gm_check = kc;
                 // warm-up (with a graph: the uncaptured solve, then the capture)
                 swr_status rs = swr_solve(c, u0, uT, nullptr, nullptr, nullptr, nullptr);
                 if (rs == SWR_OK && q) rs = swr_solve(c, u0, uT, nullptr, nullptr, nullptr, nullptr);
@@ -1832,7 +1870,7 @@ extern "C" swr_status swr_tune(swr_ctx* c, const double* u0, double budget_ms, s
                     ms = std::min(ms, std::chrono::duration<double, std::milli>(t_now() - t0).count());
                 }
                 ++tried;
-                if (ms < best) { best = ms; bp = p; bh = h; bm = m; bw = w; bq = q; }
+                if (ms < best) { best = ms; bp = p; bh = h; bm = m; bw = w; bq = q; bk = kc; }
                 spent = std::chrono::duration<double, std::milli>(t_now() - t_start).count();
             }
     c->pipe_chunk = bp;
@@ -1840,12 +1878,14 @@ extern "C" swr_status swr_tune(swr_ctx* c, const double* u0, double budget_ms, s
     c->o.restart = bm;
     c->pair_from = bw;
     c->graph = bq;
+    c->gm_check = bk;
     if (chosen) {
         chosen->pipeline = bp;
         chosen->help_max = bh;
         chosen->restart = bm;
         chosen->pair_from = bw;
         chosen->graph = bq;
+        chosen->check = bk;
         chosen->ms = best;
         chosen->candidates = tried;
     }
@@ -1857,13 +1897,14 @@ extern "C" swr_status swr_tune(swr_ctx* c, const double* u0, double budget_ms, s
 extern "C" swr_status swr_set_schedule(swr_ctx* c, const swr_schedule* s) {
     if (!c || !s) return SWR_EINVAL;
     if (s->pipeline < 0 || (s->pipeline > 0 && s->pipeline % kWave != 0) || s->help_max < 0 ||
-        s->restart < 1 || s->pair_from < 1)
+        s->restart < 1 || s->pair_from < 1 || s->check < 1)
         return SWR_EINVAL;
     c->pipe_chunk = s->pipeline;
     c->help_max = s->help_max;
     c->o.restart = s->restart;
     c->pair_from = s->pair_from;
     c->graph = s->graph ? 1 : 0;
+    c->gm_check = s->check;
     return SWR_OK;
 }
 
@@ -1874,6 +1915,7 @@ extern "C" swr_status swr_get_schedule(const swr_ctx* c, swr_schedule* s) {
     s->restart = c->o.restart;
     s->pair_from = c->pair_from;
     s->graph = c->graph;
+    s->check = c->gm_check;
     s->ms = 0;
     s->candidates = 0;
     return SWR_OK;

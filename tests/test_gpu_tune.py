@@ -115,3 +115,33 @@ def test_two_task_waves_equal_one_task_waves(dev, label, J, nt, trans, sigma, B,
         assert np.array_equal(x, y)
     for b in range(B):
         assert rel(out[True][0][b], O.mono(wl, wl.u0[b])) < 1e-10
+
+
+@pytest.mark.parametrize("vkind", [W.V_STATIC, W.V_TIME])
+def test_gmres_readback_period_changes_nothing(dev, vkind):
+    """GMRES reads its residual estimates back every `check` inner steps:
+    u(T), g, the iteration count and the residual history are bitwise those of
+    a read-back after every step (static GMRES and the V(t,x) iteration)."""
+    import torch
+    from paper_1503_02564_amd import swr
+    wl = W.small_case(J=[60, 90, 75, 128, 200, 47, 250], nt=200, vkind=vkind, trans=W.S02, sigma=0j,
+                      B=3, seed=17, a0=-12.0, b0=12.0)
+    out = {}
+    for chk in (1, 3, 16):
+        say("gmres check", vkind, chk)
+        kw = dict(solver=swr.SWR_SOLVER_GMRES) if vkind == W.V_STATIC else {}
+        pb = _problem(wl, tol=1e-12, **kw)
+        swr.swr_set_schedule(pb.ctx, check=chk, restart=9)
+        assert swr.swr_get_schedule(pb.ctx).check == chk
+        u0 = to_dev(wl.u0)
+        uT = torch.zeros_like(u0)
+        g = torch.zeros((wl.B, pb.ns, wl.nt), dtype=torch.complex128, device=dev)
+        st, info = swr.swr_solve(pb.ctx, u0, uT, g)
+        assert st == swr.SWR_OK
+        torch.cuda.synchronize()
+        out[chk] = (to_np(uT), to_np(g), info.iters, info.history)
+        pb.close()
+    for chk in (3, 16):
+        assert np.array_equal(out[1][0], out[chk][0]) and np.array_equal(out[1][1], out[chk][1])
+        assert out[1][2] == out[chk][2] and np.array_equal(out[1][3], out[chk][3])
+    assert out[1][2] > 9      # more than one restart cycle
