@@ -391,6 +391,10 @@ def main():
                     help="only run a plain MIB-MiB device copy (counter calibration)")
     ap.add_argument("--source-hash", action="store_true",
                     help="print the sweep kernel source hash and exit")
+    ap.add_argument("--profile", choices=["static_packet", "adjoint_batch"],
+                    help="only timed solves of this workload (profiling runs): static_packet with "
+                         "--solver, adjoint_batch forward solve and gradient")
+    ap.add_argument("--solver", choices=["causal", "gmres", "bicgstab"], default="causal")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "only --gpus 1 is supported: the solver runs on one GPU "
@@ -401,6 +405,20 @@ def main():
         return
     if args.calibrate_copy:
         calibrate_copy(args.calibrate_copy)
+        return
+    if args.profile:
+        from paper_1503_02564_amd import swr
+        from paper_1503_02564_amd import workloads as W
+        if args.profile == "static_packet":
+            sv = dict(causal=swr.SWR_SOLVER_CAUSAL, gmres=swr.SWR_SOLVER_GMRES,
+                      bicgstab=swr.SWR_SOLVER_BICGSTAB)[args.solver]
+            sched = {}
+            ms, infos, _, st = timed_solves(W.static_packet(), args.steps, args.warmup, sched=sched,
+                                            solver=sv)
+            print(json.dumps({"profile": "static_packet", "solver": args.solver, "ms_per_solve": ms,
+                              "iterations": infos[-1]["iters"], "status": st, "schedule": sched}))
+        else:
+            print(json.dumps({"profile": "adjoint_batch", **adjoint_ratio(args.steps, args.warmup)}))
         return
 
     from paper_1503_02564_amd import workloads as W
@@ -434,7 +452,8 @@ def main():
                                "dt=5e-4, S0^2, seeded bumpy harmonic V, new algorithm, causal "
                                "interface solve",
                    "nx": wl.nx, "nt": wl.nt, "N": wl.N, "B": wl.B, "solver": "causal",
-                   "schedule": {k: sched[k] for k in ("pipeline", "help_max", "restart", "pair_from")}},
+                   "schedule": {k: sched[k] for k in ("pipeline", "help_max", "restart", "pair_from",
+                                                      "graph", "check")}},
         "status": st, "interface_residual": resid, "phases_ms": ph,
         "max_rel_diff_vs_oracle_fixture": fixture_error(uT),
     }

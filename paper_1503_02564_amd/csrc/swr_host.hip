@@ -194,10 +194,17 @@ struct swr_ctx {
     std::vector<void*> allocs;
 };
 
+// with SWR_DEBUG set in the environment, a failing HIP call is reported on
+// stderr (call, file, line, HIP error) before the status is returned
+static void report_hip_error(hipError_t e, const char* what, const char* file, int line) {
+    static const bool on = std::getenv("SWR_DEBUG") != nullptr;
+    if (on) std::fprintf(stderr, "swr: %s failed at %s:%d: %s\n", what, file, line, hipGetErrorName(e));
+}
 #define HIPCHK(x)                                      \
     do {                                               \
         hipError_t e_ = (x);                           \
         if (e_ != hipSuccess) {                        \
+            report_hip_error(e_, #x, __FILE__, __LINE__); \
             return SWR_EDEVICE;                        \
         }                                              \
     } while (0)
@@ -253,7 +260,12 @@ static void* scratch_address(int dev) {
     std::lock_guard<std::mutex> lk(g_scratch_mu);
     if (!g_scratch_done[dev]) {
         void* p = nullptr;
-        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) {
+            report_hip_error(e, "hipGetSymbolAddress(scratch)", __FILE__, __LINE__);
+            (void)hipGetLastError();   // the failure must not surface in a later error check
+            p = nullptr;
+        }
         g_scratch_ptr[dev] = p;
         g_scratch_done[dev] = true;
     }
@@ -399,7 +411,11 @@ extern "C" swr_status swr_setup(double a0, double b0, int N, const int* J, doubl
     c->a0 = a0; c->b0 = b0; c->dt = dt; c->N = N; c->nt = (int)ntr; c->nc = (int)nc;
     c->nx = (int)nc + 1; c->h = (b0 - a0) / (double)nc; c->ns = 2 * N - 2; c->B = o.batch;
     c->vk = vk; c->tr = tr; c->o = o; c->st = (hipStream_t)stream;
-    if (hipGetDevice(&c->dev) != hipSuccess) { delete c; return SWR_EDEVICE; }
+    if (const hipError_t e = hipGetDevice(&c->dev); e != hipSuccess) {
+        report_hip_error(e, "hipGetDevice", __FILE__, __LINE__);
+        delete c;
+        return SWR_EDEVICE;
+    }
     c->scratch = scratch_address(c->dev);
     c->nv = (vk == SWR_V_STATIC && o.v_per_problem) ? o.batch : 1;
     c->P = std::min((nmax + kWave - 1) / kWave, kMaxP);
@@ -529,7 +545,11 @@ extern "C" swr_status swr_setup(double a0, double b0, int N, const int* J, doubl
     if (hipHostMalloc(&c->hRes, sizeof(double) * B) != hipSuccess ||
         hipHostMalloc(&c->hAct, sizeof(int) * B) != hipSuccess) { swr_destroy(c); return SWR_ENOMEM; }
     for (auto& e : c->ev)
-        if (hipEventCreate(&e) != hipSuccess) { swr_destroy(c); return SWR_EDEVICE; }
+        if (const hipError_t er = hipEventCreate(&e); er != hipSuccess) {
+            report_hip_error(er, "hipEventCreate", __FILE__, __LINE__);
+            swr_destroy(c);
+            return SWR_EDEVICE;
+        }
     HIPCHK(hipMemcpyAsync(c->dJ, c->J.data(), N * sizeof(int), hipMemcpyHostToDevice, c->st));
     HIPCHK(hipMemcpyAsync(c->dOff, c->off.data(), N * sizeof(int), hipMemcpyHostToDevice, c->st));
     HIPCHK(hipMemcpyAsync(c->dPk, c->Pk.data(), N * sizeof(int), hipMemcpyHostToDevice, c->st));

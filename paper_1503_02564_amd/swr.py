@@ -84,6 +84,10 @@ EXPORTS = ("swr_default_opts", "swr_strerror", "swr_setup", "swr_solve", "swr_gr
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
+# PyTorch's HIP runtime first: the library then binds to the same runtime
+# (one per process).  Loaded the other way round, the library's own copy of
+# the runtime comes first and reports no device to the calls made through it.
+import torch  # noqa: E402,F401
 _L = ctypes.CDLL(LIB_PATH)
 _P = ctypes.c_void_p
 _I = ctypes.POINTER(ctypes.c_int)
