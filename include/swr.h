@@ -35,6 +35,8 @@
  *   - Interface vectors g are [B][2N-2][nt]: slot 2k-1 holds l_k (k >= 1),
  *     slot 2k holds r_k (k <= N-2); entry n-1 of a slot is time step n.
  *   - A context is not thread-safe; separate contexts are independent.
+ *   - With SWR_DEBUG set in the environment a failing HIP call is reported on
+ *     stderr (call, source line, HIP error name) before SWR_EDEVICE is returned.
  *   - Errors are status codes; nothing is thrown across the ABI.  After any
  *     status other than SWR_OK or SWR_ENOCONV the context remains valid for
  *     swr_destroy.
