@@ -122,8 +122,8 @@ __global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs a) {
     };
     // c M x at my nodes (local P1 mass: 1,4,1 inside, 2,1 / 1,2 at the ends)
     auto mass = [&](const cd (&xx)[P], cd (&out)[P]) {
-        const cd xL = shfl_up_c(xx[P - 1], 1, zero);
-        const cd xR = shfl_dn_c(xx[0], 1, zero);
+        const cd xL = shfl_up1z(xx[P - 1]);
+        const cd xR = shfl_dn1z(xx[0]);
 #pragma unroll
         for (int q = 0; q < P; ++q) {
             const cd up = (q == 0) ? xL : xx[q - 1];
@@ -246,8 +246,8 @@ __global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs a) {
                 cd v[P];
 #pragma unroll
                 for (int q = 0; q < P; ++q) v[q] = seg[((size_t)is * a.pstride + q) * kWave];
-                const cd xL = shfl_up_c(x[P - 1], 1, zero), xR = shfl_dn_c(x[0], 1, zero);
-                const cd vL = shfl_up_c(v[P - 1], 1, zero), vR = shfl_dn_c(v[0], 1, zero);
+                const cd xL = shfl_up1z(x[P - 1]), xR = shfl_dn1z(x[0]);
+                const cd vL = shfl_up1z(v[P - 1]), vR = shfl_dn1z(v[0]);
 #pragma unroll
                 for (int q = 0; q < P; ++q) {
                     const cd qm = (q == 0) ? xL : x[q - 1], qp = (q + 1 < P) ? x[q + 1] : xR;

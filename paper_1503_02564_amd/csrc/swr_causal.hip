@@ -247,8 +247,8 @@ struct NearArgs {
 
 
 // neighbour values for the lag-1/lag-2 history: lane j - 1 / j + 1 (zero outside)
-__device__ inline cd lane_up1(cd v) { return shfl_up_c(v, 1, mk(0, 0)); }
-__device__ inline cd lane_dn1(cd v) { return shfl_dn_c(v, 1, mk(0, 0)); }
+__device__ inline cd lane_up1(cd v) { return shfl_up1z(v); }
+__device__ inline cd lane_dn1(cd v) { return shfl_dn1z(v); }
 
 // sum over the four lanes of a quad (DPP quad permutations); every lane of
 // the quad gets the same bits

@@ -47,12 +47,12 @@ __device__ inline cd rdlane(cd v, int l) { return mk(rdlane(v.x, l), rdlane(v.y,
 
 // whole-wave shift of one double by one lane through DPP (CTRL 0x138: lane
 // i reads lane i - 1; 0x130: lane i reads lane i + 1); the lane without a
-// source keeps 0
+// source reads 0 (bound_ctrl: no old value to materialise)
 template <int CTRL>
 __device__ inline double dpp_shift(double v) {
     int2 t = *reinterpret_cast<int2*>(&v);
-    t.x = __builtin_amdgcn_update_dpp(0, t.x, CTRL, 0xf, 0xf, false);
-    t.y = __builtin_amdgcn_update_dpp(0, t.y, CTRL, 0xf, 0xf, false);
+    t.x = __builtin_amdgcn_mov_dpp(t.x, CTRL, 0xf, 0xf, true);
+    t.y = __builtin_amdgcn_mov_dpp(t.y, CTRL, 0xf, 0xf, true);
     return *reinterpret_cast<double*>(&t);
 }
 
@@ -128,6 +128,11 @@ __device__ inline cd shfl_dn_c(cd v, int d, cd fill) {
     cd r = mk(__shfl(v.x, src > 63 ? 63 : src), __shfl(v.y, src > 63 ? 63 : src));
     return src > 63 ? fill : r;
 }
+
+// Value of lane - 1 / lane + 1 with zero where there is none: the DPP shift
+// already reads zero there, so no select is needed
+__device__ inline cd shfl_up1z(cd v) { return mk(dpp_shift<0x138>(v.x), dpp_shift<0x138>(v.y)); }
+__device__ inline cd shfl_dn1z(cd v) { return mk(dpp_shift<0x130>(v.x), dpp_shift<0x130>(v.y)); }
 
 // The same moves without the fill: lanes with no source get some other
 // lane's (finite) value.  For reductions whose multiplier is exactly zero on

@@ -120,8 +120,8 @@ __device__ inline void lane_factor(const cd (&ra)[P], const cd (&rb)[P], const c
     const cd gL = (P > 1) ? F.ga[PI - 1] : zero;
     const cd aF = (P > 1) ? F.al[0] : zero;     // right neighbour's first node
     const cd gF = (P > 1) ? F.ga[0] : one;
-    const cd aR = shfl_dn_c(aF, 1, zero);
-    const cd gR = shfl_dn_c(gF, 1, zero);
+    const cd aR = shfl_dn1z(aF);
+    const cd gR = shfl_dn1z(gF);
     cd At = ae * aL;
     cd Bt = madd(madd(rbs, ae, gL), ce, aR);
     cd Ct = ce * gR;
@@ -200,7 +200,7 @@ __device__ inline void lane_solve(const LaneFac<P>& F, const cd (&d)[P], cd (&x)
 #pragma unroll
     for (int q = P - 3; q >= 0; --q) y[q] = msub(y[q], F.cp[q], y[q + 1]);
     const cd yL = (P > 1) ? y[PI - 1] : zero;
-    const cd yR = (P > 1) ? shfl_dn_c(y[0], 1, zero) : zero;
+    const cd yR = (P > 1) ? shfl_dn1z(y[0]) : zero;
     cd D = msub(msub(d[P - 1], F.ae, yL), F.ce, yR);
 #pragma unroll
     for (int l = 0; l < kPcrLevels; ++l) {
@@ -210,7 +210,7 @@ __device__ inline void lane_solve(const LaneFac<P>& F, const cd (&d)[P], cd (&x)
         D = msub(msub(D, F.k1[l], Dm), F.k2[l], Dp);
     }
     const cd X = D * F.invB;
-    const cd Xm = shfl_up_c(X, 1, zero);
+    const cd Xm = shfl_up1z(X);
 #pragma unroll
     for (int q = 0; q < P - 1; ++q) x[q] = madd(madd(y[q], F.al[q], Xm), F.ga[q], X);
     x[P - 1] = X;

@@ -656,8 +656,8 @@ __global__ __launch_bounds__(sweep_threads(HELP)) void sweep_kernel(SweepArgs a)
                 }
             }
             // right-hand side c M u_{n-1} + boundary terms
-            const cd uL = shfl_up_c(u[P - 1], 1, zero);
-            const cd uR = shfl_dn_c(u[0], 1, zero);
+            const cd uL = shfl_up1z(u[P - 1]);
+            const cd uR = shfl_dn1z(u[0]);
             const cd tb = rif ? (hB - rn) : zero;
             cd d[P];
 #pragma unroll
@@ -685,7 +685,7 @@ __global__ __launch_bounds__(sweep_threads(HELP)) void sweep_kernel(SweepArgs a)
                     double Fz[P];
 #pragma unroll
                     for (int q = 0; q < P; ++q) Fz[q] = abs2(z[q]);
-                    const cd zL = shfl_up_c(z[P - 1], 1, zero), zR = shfl_dn_c(z[0], 1, zero);
+                    const cd zL = shfl_up1z(z[P - 1]), zR = shfl_dn1z(z[0]);
                     // neighbours' |zeta|^2: the shuffles run on every lane
                     // (a lane left out of a permute hands zero to its reader)
                     const double FLs = __shfl(Fz[P - 1], t > 0 ? t - 1 : 0);

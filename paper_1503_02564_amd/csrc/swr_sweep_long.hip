@@ -99,8 +99,8 @@ __device__ inline void long_factor(cd* R, int Q, int n, int o, bool lif, bool ri
     // separator row and the reduced system
     long_row(s + Q - 1, n, o, lif, rif, h, kap, sigL, sigR, W, ra, rb, rc);
     const cd ae = ra, rbs = rb, ce = rc;
-    const cd aR = shfl_dn_c(aF, 1, zero);
-    const cd gR = shfl_dn_c(gF, 1, zero);
+    const cd aR = shfl_dn1z(aF);
+    const cd gR = shfl_dn1z(gF);
     cd At = ae * aL;
     cd Bt = madd(madd(rbs, ae, gL), ce, aR);
     cd Ct = ce * gR;
@@ -349,7 +349,7 @@ __global__ __launch_bounds__(64) void sweep_long_kernel(SweepArgs a) {
                     yn = msub(at(Y, q), at(R, 5 * q + 2), yn);
                     at(Y, q) = yn;
                 }
-                const cd yR = (Q > 1) ? shfl_dn_c(yn, 1, zero) : zero;
+                const cd yR = (Q > 1) ? shfl_dn1z(yn) : zero;
                 cd D = msub(msub(dsep, at(R, ae_f), yL), at(R, ce_f), yR);
 #pragma unroll
                 for (int l = 0; l < kPcrLevels; ++l) {
@@ -366,7 +366,7 @@ __global__ __launch_bounds__(64) void sweep_long_kernel(SweepArgs a) {
                 bool conv = false;
                 for (; it <= a.nl_maxit; ++it) {
                     solve(true, X);
-                    const cd Xm = shfl_up_c(X, 1, zero);
+                    const cd Xm = shfl_up1z(X);
                     double dm = 0.0, zm2 = 0.0;
                     for (int q = 0; q < Q; ++q) {
                         const cd x = (q < Q - 1) ? madd(madd(at(Y, q), at(R, 5 * q + 3), Xm), at(R, 5 * q + 4), X) : X;
@@ -384,7 +384,7 @@ __global__ __launch_bounds__(64) void sweep_long_kernel(SweepArgs a) {
                 nl_worst = max(nl_worst, conv ? it : a.nl_maxit);
             } else {
                 solve(false, X);
-                const cd Xm = shfl_up_c(X, 1, zero);
+                const cd Xm = shfl_up1z(X);
                 for (int q = 0; q < Q; ++q)
                     at(Z, q) = (q < Q - 1) ? madd(madd(at(Y, q), at(R, 5 * q + 3), Xm), at(R, 5 * q + 4), X) : X;
             }

@@ -239,8 +239,8 @@ __global__ __launch_bounds__(kWave) void sweep_pair_kernel(SweepArgs a) {
                     hA = a.c2 * rdlane(acc_a[c], i);
                     hB = a.c2 * rdlane(acc_b[c], i);
                 }
-                const cd uL = shfl_up_c(u[c][P - 1], 1, zero);
-                const cd uR = shfl_dn_c(u[c][0], 1, zero);
+                const cd uL = shfl_up1z(u[c][P - 1]);
+                const cd uR = shfl_dn1z(u[c][0]);
                 const cd tb = rif ? (hB - rn) : zero;
                 cd d[P];
 #pragma unroll
