@@ -120,9 +120,8 @@ typedef struct {
                           the interface solve and the final sweep chunk by chunk on two extra
                           internal streams (joined back to the context's stream before the call
                           returns); 0 = one stage after the other; -1 = chosen by the library
-                          (default): 256 while the build sweeps leave CUs free for the
-                          interface solve (at most 4096 build tasks), else 0; a tuning-cache
-                          entry (tune_cache) overrides the choice */
+                          (default): 256; a tuning-cache entry (tune_cache) overrides the
+                          choice */
     int plain;         /* 1 = launch the subdomain sweeps one task (one subdomain of one problem)
                           per launch on the context's stream, staged: the unbatched form, for
                           comparison with the batched launches (default 0) */

@@ -225,11 +225,12 @@ constexpr int kMaxP = 8;
 // (swr_sweep_long.hip) with up to this many nodes per lane
 constexpr int kLongMaxQ = 8192;
 // default schedule: the S0^2 helper wave up to this many tasks per launch (every
-// wave then has a SIMD of its own), the pipelined static solve up to this many
-// build tasks (beyond, the sweeps fill the GPU and the interface solve's
-// kernels only find CUs between them, so one stage after the other is faster)
+// wave then has a SIMD of its own); the static causal solve pipelined in
+// chunks of this many steps (measured on batched-uneven, whose sweeps fill the
+// GPU: 172 ms per solve pipelined, 175.5 ms staged, 202 ms with 128-step and
+// 176 ms with 512-step chunks)
 constexpr int kHelpMaxTasks = 512;
-constexpr int kPipeMaxBuild = 4096;
+constexpr int kPipeChunk = 256;
 // chunk width from which filled launches run two tasks per wave (a schedule
 // parameter; kMaxP + 1 = never).  Measured on the batched-uneven workload the
 // one-task sweep is bound by instruction issue, not by its dependency chain:

@@ -468,7 +468,7 @@ extern "C" swr_status swr_setup(double a0, double b0, int N, const int* J, doubl
     by_width(imp0, c->runs_L0, nullptr);
     c->nBuild = (int)build.size();
     // default schedule; a tuning cache entry for this problem replaces it
-    c->pipe_chunk = o.pipeline >= 0 ? o.pipeline : (c->nBuild <= kPipeMaxBuild ? 256 : 0);
+    c->pipe_chunk = o.pipeline >= 0 ? o.pipeline : kPipeChunk;
     if (o.tune_cache) {
         c->cache_path = o.tune_cache;
         load_schedule(c, o.tune_cache);

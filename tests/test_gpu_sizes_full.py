@@ -1,8 +1,7 @@
 """GPU parity at the full sizes of the differentiation, time-dependent,
 nonlinear and batched uneven workloads, in the launch configuration of the
-library's default schedule (the pipelined causal solve for static potentials
-while the build sweeps leave CUs free, staged for the batched uneven workload
-whose sweeps fill the GPU), as the benchmark runs them.
+library's default schedule (the pipelined causal solve for static
+potentials), as the benchmark runs them.
 
 Where the monodomain oracle finishes in seconds the state is compared with it
 (1e-10 relative).  Where it takes about a minute (the 110k-node, 32-problem

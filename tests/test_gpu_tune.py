@@ -62,11 +62,11 @@ def test_tuned_schedule_gives_the_same_result_and_is_cached(dev, tmp_path):
     pb3.close()
 
 
-def test_default_schedule_is_staged_when_sweeps_fill_the_gpu(dev):
+def test_default_schedule_pipelines_filled_batches(dev):
     from paper_1503_02564_amd import swr
-    wl = W.batched_uneven(N=100, B=48, nt=128)   # 100 * 48 + 198 build tasks > 4096
+    wl = W.batched_uneven(N=100, B=48, nt=128)   # 100 * 48 + 198 build tasks: sweeps fill the GPU
     pb = _problem(wl)
-    assert swr.swr_get_schedule(pb.ctx).pipeline == 0
+    assert swr.swr_get_schedule(pb.ctx).pipeline == 256
     pb.close()
 
 
