@@ -452,7 +452,7 @@ def main():
                                "dt=5e-4, S0^2, seeded bumpy harmonic V, new algorithm, causal "
                                "interface solve",
                    "nx": wl.nx, "nt": wl.nt, "N": wl.N, "B": wl.B, "solver": "causal",
-                   "schedule": {k: sched[k] for k in ("pipeline", "help_max", "restart", "pair_from",
+                   "schedule": {k: sched[k] for k in ("pipeline", "help_max", "restart", "pair_from", "group",
                                                       "graph", "check")}},
         "status": st, "interface_residual": resid, "phases_ms": ph,
         "max_rel_diff_vs_oracle_fixture": fixture_error(uT),

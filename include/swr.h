@@ -36,7 +36,10 @@
  *     slot 2k holds r_k (k <= N-2); entry n-1 of a slot is time step n.
  *   - A context is not thread-safe; separate contexts are independent.
  *   - With SWR_DEBUG set in the environment a failing HIP call is reported on
- *     stderr (call, source line, HIP error name) before SWR_EDEVICE is returned.
+ *     stderr (call, source line, HIP error name) before SWR_EDEVICE is returned;
+ *     with SWR_DEBUG_POISON set, every device buffer the library allocates is
+ *     filled with all-ones bytes (NaN as a double) when it is allocated, so a
+ *     read before the first write shows in the results.
  *   - Errors are status codes; nothing is thrown across the ABI.  After any
  *     status other than SWR_OK or SWR_ENOCONV the context remains valid for
  *     swr_destroy.
@@ -176,6 +179,11 @@ typedef struct {
     int check;        /* GMRES: read the inner residual estimates back every this many steps
                          (default 4); the iterate and the iteration count are those of a check
                          after every step, the steps between reads need no host round trip */
+    int group;        /* static Robin / S0^2 sweeps: launches that fill the GPU with one-wave
+                         tasks run up to this many tasks of one subdomain and one potential (the
+                         problems of a batch) as the waves of one workgroup, reading one LDS
+                         copy of the subdomain's factors; 1..8, 1 = one task per workgroup
+                         (default 4); bitwise the same results */
     double ms;        /* swr_tune: wall time of the chosen schedule's solve */
     int candidates;   /* swr_tune: schedules timed */
 } swr_schedule;

@@ -86,6 +86,12 @@ __global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs a) {
     __shared__ double sbeta[kWave + 1];
     __shared__ cd sha[kWave], shb[kWave];
     __shared__ double sb[2 * kWave];
+    // widths 7 and 8: the factor record is read from an LDS copy every step
+    // instead of being held in VGPRs, where it would not fit beside the rest
+    // of the state without spilling to scratch memory (bitwise the same
+    // solve: the two forms of lane_solve_with round alike)
+    constexpr bool kFacLds = P >= 7;
+    __shared__ cd sfac[kFacLds ? fac_fields(P) * kWave : 1];
     const int tix = a.task0 + blockIdx.x;   // task index (per-task buffers)
     const Task task = a.tasks[tix];
     const int k = task.k, b = task.b, f = task.f;
@@ -104,7 +110,23 @@ __global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs a) {
         __syncthreads();
     }
     LaneFac<P> F;
-    load_fac<P>(a.fac + (size_t)f * a.fstride + t, F);
+    if (kFacLds) {
+        const cd* src = a.fac + (size_t)f * a.fstride;
+        for (int i = t; i < fac_fields(P) * kWave; i += kWave) sfac[i] = src[i];
+        __syncthreads();
+    } else {
+        load_fac<P>(a.fac + (size_t)f * a.fstride + t, F);
+    }
+    // one solve of the step (kFacLds: the record is read anew every step --
+    // the compiler would otherwise keep it in VGPRs across the time loop)
+    auto solve = [&](const cd (&dd)[P], cd (&xx)[P]) {
+        if constexpr (kFacLds) {
+            asm volatile("" ::: "memory");
+            lane_solve_with<P>(FacLds<P>{sfac + t}, dd, xx);
+        } else {
+            lane_solve<P>(F, dd, xx);
+        }
+    };
 
     double wl[P], wr[P], wlast[P];
 #pragma unroll
@@ -195,7 +217,7 @@ __global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs a) {
                 for (int q = 0; q < P; ++q) d[q] = mk(d[q].x + wlast[q] * tb.x, d[q].y + wlast[q] * tb.y);
                 if (lif && t == 0) d[0] = d[0] + (hA - ln);
                 cd x[P];
-                lane_solve<P>(F, d, x);
+                solve(d, x);
 #pragma unroll
                 for (int q = 0; q < P; ++q) {
                     uf[q] = mk(2.0 * x[q].x - uf[q].x, 2.0 * x[q].y - uf[q].y);
@@ -234,7 +256,7 @@ __global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs a) {
             for (int q = 0; q < P; ++q) d[q] = mk(w[q].x + wlast[q] * tb.x, w[q].y + wlast[q] * tb.y);
             if (lif && t == 0) d[0] = d[0] + (hA - ln);
             cd x[P];
-            lane_solve<P>(F, d, x);
+            solve(d, x);
             // w_m = 2 c M Q - w_{m-1}
             cd cm[P];
             mass(x, cm);

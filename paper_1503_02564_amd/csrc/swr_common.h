@@ -238,6 +238,11 @@ constexpr int kPipeChunk = 256;
 // per launch of two-task waves against 10.3-12.8 ms of one-task waves for
 // the same tasks), so the default is never
 constexpr int kPairFrom = kMaxP + 1;
+// largest group of tasks (one subdomain, one potential) that run as the
+// waves of one workgroup sharing an LDS copy of their factor record, and the
+// default group size (a schedule parameter; 1 = one task per workgroup)
+constexpr int kGroupMax = 8;
+constexpr int kGroupDefault = 4;
 
 struct SweepArgs {
     int N, nt, B, nx, ns;        // ns = 2N-2 interface slots
@@ -274,6 +279,7 @@ struct SweepArgs {
     const EndCoef* endc;         // TR_GEN: [nf][2] end coefficients (left, right)
     int help_max;                // S0^2: launches of at most this many tasks use the helper wave
     const int2* pairs;           // two-task waves: [.] task indices (second -1 for a single)
+    const int2* groups;          // shared-factor workgroups: [.] (first task, task count)
     int pstride;                 // chunk-width stride of the per-task state and checkpoint
                                  // records (the context's largest width; a launch's own P may
                                  // be smaller: subdomains are grouped by width)
@@ -356,6 +362,9 @@ hipError_t launch_sweep_cubic(const SweepArgs& a, int trans, hipStream_t st);
 // static potential, Robin or S0^2: a.ntasks waves of two tasks each, the
 // pairs a.pairs[a.task0 ..] (swr_sweep_pair.hip)
 hipError_t launch_sweep_pairs(const SweepArgs& a, int trans, hipStream_t st);
+// static potential, Robin or S0^2: a.ntasks workgroups of gsize waves, the
+// task groups a.groups[a.task0 ..] (swr_sweep_group.hip)
+hipError_t launch_sweep_groups(const SweepArgs& a, int trans, int gsize, hipStream_t st);
 hipError_t launch_finalize_ut(int N, int nx, int B, const int* off, const cd* ends, cd* uT,
                               hipStream_t st);
 // the same for every snapshot: ends [B][S][N][2] -> snaps [B][S][nx]

@@ -63,6 +63,9 @@ struct Iface {
 struct WidthRun {
     int P, start, count;
     int pstart, pcount;   // its waves of two tasks in the list's pair table
+    // its workgroups of at most g tasks of one factor record in the list's
+    // group table of size g (g = 2 .. kGroupMax)
+    int gstart[kGroupMax + 1], gcount[kGroupMax + 1];
 };
 
 struct swr_ctx {
@@ -98,6 +101,8 @@ struct swr_ctx {
     std::vector<WidthRun> runs_build, runs_sub, runs_L0;
     int2* dPairsB = nullptr;  // pair tables of the build and the per-(problem, subdomain) lists
     int2* dPairsS = nullptr;
+    int2* dGroupsB[kGroupMax + 1] = {};   // group tables of the two lists, by group size
+    int2* dGroupsS[kGroupMax + 1] = {};
     int n_launch_sweep = 0;   // sweep kernel launches of the current call
     Iface L, L0;              // interface operator of V and of V = 0
     cd* dD = nullptr;
@@ -161,6 +166,7 @@ struct swr_ctx {
     int pipe_chunk = 0;
     int help_max = kHelpMaxTasks;
     int pair_from = kPairFrom;   // two tasks per wave from this chunk width on (9: never)
+    int group = kGroupDefault;   // tasks of one factor record per workgroup (1: one per wave)
     int graph = 0;               // 1: capture the static causal solve once, replay it
     int gm_check = 4;            // GMRES: read the residual estimates back every this many steps
     double* dResHist = nullptr;  // GMRES: [restart][B] residual estimate after every inner step
@@ -173,10 +179,10 @@ struct swr_ctx {
     struct GraphKey {
         const void* u0;
         void *uT, *g, *tr, *sn;
-        int pipe, help, pair, vver;
+        int pipe, help, pair, group, vver;
         bool operator==(const GraphKey& o) const {
             return u0 == o.u0 && uT == o.uT && g == o.g && tr == o.tr && sn == o.sn && pipe == o.pipe &&
-                   help == o.help && pair == o.pair && vver == o.vver;
+                   help == o.help && pair == o.pair && group == o.group && vver == o.vver;
         }
     } g_key{};
     // arguments of the last uncaptured static causal solve that succeeded:
@@ -221,6 +227,10 @@ static swr_status dalloc(swr_ctx* c, T** p, size_t count) {
     void* q = nullptr;
     if (hipMalloc(&q, count * sizeof(T)) != hipSuccess) return SWR_ENOMEM;
     c->allocs.push_back(q);
+    // SWR_DEBUG_POISON: every buffer starts as all-ones bytes (NaN as a
+    // double), so a read before the first write shows up in the results
+    static const bool poison = std::getenv("SWR_DEBUG_POISON") != nullptr;
+    if (poison && hipMemset(q, 0xff, count * sizeof(T)) != hipSuccess) return SWR_EDEVICE;
     *p = static_cast<T*>(q);
     return SWR_OK;
 }
@@ -462,10 +472,29 @@ extern "C" swr_status swr_setup(double a0, double b0, int N, const int* J, doubl
             r.pcount = (int)pairs->size() - r.pstart;
         }
     };
-    std::vector<int2> pairs_build, pairs_sub;
+    // ... and, for every group size g, into workgroups of at most g tasks of
+    // one record
+    auto by_group = [](const std::vector<Task>& list, std::vector<WidthRun>& runs, std::vector<int2>* groups) {
+        for (int g = 2; g <= kGroupMax; ++g) {
+            groups[g].clear();
+            for (WidthRun& r : runs) {
+                r.gstart[g] = (int)groups[g].size();
+                for (int i = r.start; i < r.start + r.count;) {
+                    int j = i + 1;
+                    while (j < r.start + r.count && j - i < g && list[j].f == list[i].f) ++j;
+                    groups[g].push_back(make_int2(i, j - i));
+                    i = j;
+                }
+                r.gcount[g] = (int)groups[g].size() - r.gstart[g];
+            }
+        }
+    };
+    std::vector<int2> pairs_build, pairs_sub, groups_build[kGroupMax + 1], groups_sub[kGroupMax + 1];
     by_width(build, c->runs_build, &pairs_build);
     by_width(sub, c->runs_sub, &pairs_sub);
     by_width(imp0, c->runs_L0, nullptr);
+    by_group(build, c->runs_build, groups_build);
+    by_group(sub, c->runs_sub, groups_sub);
     c->nBuild = (int)build.size();
     // default schedule; a tuning cache entry for this problem replaces it
     c->pipe_chunk = o.pipeline >= 0 ? o.pipeline : kPipeChunk;
@@ -502,6 +531,10 @@ extern "C" swr_status swr_setup(double a0, double b0, int N, const int* J, doubl
     ALLOC(c->dSub, sub.size());
     ALLOC(c->dPairsB, pairs_build.size());
     ALLOC(c->dPairsS, pairs_sub.size());
+    for (int g = 2; g <= kGroupMax; ++g) {
+        ALLOC(c->dGroupsB[g], groups_build[g].size());
+        ALLOC(c->dGroupsS[g], groups_sub[g].size());
+    }
     ALLOC(c->dD, vec);
     ALLOC(c->dG, vec);
     ALLOC(c->dG2, vec);
@@ -559,6 +592,12 @@ extern "C" swr_status swr_setup(double a0, double b0, int N, const int* J, doubl
                           hipMemcpyHostToDevice, c->st));
     HIPCHK(hipMemcpyAsync(c->dPairsS, pairs_sub.data(), pairs_sub.size() * sizeof(int2),
                           hipMemcpyHostToDevice, c->st));
+    for (int g = 2; g <= kGroupMax; ++g) {
+        HIPCHK(hipMemcpyAsync(c->dGroupsB[g], groups_build[g].data(), groups_build[g].size() * sizeof(int2),
+                              hipMemcpyHostToDevice, c->st));
+        HIPCHK(hipMemcpyAsync(c->dGroupsS[g], groups_sub[g].data(), groups_sub[g].size() * sizeof(int2),
+                              hipMemcpyHostToDevice, c->st));
+    }
     if (c->L0.tasks)
         HIPCHK(hipMemcpyAsync(c->L0.tasks, imp0.data(), imp0.size() * sizeof(Task), hipMemcpyHostToDevice, c->st));
     HIPCHK(hipMemsetAsync(c->dZero, 0, vec * sizeof(cd), c->st));
@@ -738,11 +777,31 @@ static const int2* pairs_of(const swr_ctx* c, const Task* tasks) {
     return nullptr;
 }
 
+static const int2* groups_of(const swr_ctx* c, const Task* tasks, int g) {
+    if (tasks == c->dBuild) return c->dGroupsB[g];
+    if (tasks == c->dSub) return c->dGroupsS[g];
+    return nullptr;
+}
+
+// largest group size at most g whose workgroup (the width-P factor record and
+// the waves' staging) fits the 64 KiB of LDS a workgroup may use by default
+static int group_fit(int P, int g) {
+    auto lds = [P](int q) {
+        return sizeof(cd) * ((size_t)fac_fields(P) * kWave + (size_t)q * 2 * kWave) +
+               sizeof(double) * (size_t)q * 2 * kWave + sizeof(double) * 2 * kWave;
+    };
+    while (g > 1 && lds(g) > 65536) --g;
+    return g;
+}
+
 // all tasks of a's list (a.task0 = 0, a.ntasks = the whole list), one launch
 // per chunk width, in order on one stream; *launches counts the kernels.  A
 // run that fills the GPU with one-wave tasks (more than help_max of them) of
-// a width >= pair_from runs two tasks per wave where it has pairs (static
-// potential, Robin or S0^2): the same arithmetic per task.
+// a static potential with Robin or S0^2 runs two tasks per wave where it has
+// pairs from width pair_from on, else, with group >= 2 and tasks that share
+// factor records (two or more per record on average), workgroups of up to
+// group tasks of one record reading one LDS copy of it: the same arithmetic
+// per task in every form.
 static hipError_t launch_widths(const swr_ctx* c, SweepArgs a, int vk, hipStream_t st, bool plain,
                                 int* launches = nullptr) {
     const int2* pairs = pairs_of(c, a.tasks);
@@ -761,12 +820,20 @@ static hipError_t launch_widths(const swr_ctx* c, SweepArgs a, int vk, hipStream
         }
         const bool two = !plain && pairs && vk == SWR_V_STATIC && (tr == TR_S02 || tr == TR_ROBIN) &&
                          r.P >= c->pair_from && r.count > c->help_max && 4 * r.pcount <= 3 * r.count;
+        const int gsz = group_fit(r.P, c->group);
+        const bool grp = !two && !plain && gsz >= 2 && vk == SWR_V_STATIC && (tr == TR_S02 || tr == TR_ROBIN) &&
+                         r.count > c->help_max && groups_of(c, a.tasks, gsz) && 2 * r.gcount[gsz] <= r.count;
         hipError_t e;
         if (two) {
             a.pairs = pairs;
             a.task0 = r.pstart;
             a.ntasks = r.pcount;
             e = launch_sweep_pairs(a, tr, st);
+        } else if (grp) {
+            a.groups = groups_of(c, a.tasks, gsz);
+            a.task0 = r.gstart[gsz];
+            a.ntasks = r.gcount[gsz];
+            e = launch_sweep_groups(a, tr, gsz, st);
         } else {
             a.task0 = r.start;
             a.ntasks = r.count;
@@ -1442,7 +1509,8 @@ static swr_status run_static_pipelined(swr_ctx* c, const cd* u0, cd* g, const Sw
 // ---------------------------------------------------------------------------
 static swr_ctx::GraphKey graph_key(const swr_ctx* c, const double* u0, double* uT, double* g,
                                    double* tr, double* sn) {
-    return swr_ctx::GraphKey{u0, uT, g, tr, sn, c->pipe_chunk, c->help_max, c->pair_from, c->v_version};
+    return swr_ctx::GraphKey{u0, uT, g, tr, sn, c->pipe_chunk, c->help_max, c->pair_from, c->group,
+                             c->v_version};
 }
 
 static bool graph_ready(const swr_ctx* c, const swr_ctx::GraphKey& key) {
@@ -1796,8 +1864,8 @@ static void load_schedule(swr_ctx* c, const char* path) {
         int pipe = 0, help = 0, restart = 0, pair = 0;
         if (!(in >> k >> pipe >> help >> restart >> pair) || k != key) continue;
         if (pipe < 0 || (pipe > 0 && pipe % kWave != 0) || help < 0 || restart < 1 || pair < 1) continue;
-        // then "graph check ms"; lines written before those options have
-        // "graph ms" or "ms" alone
+        // then "graph check group ms"; lines written before those options
+        // have "graph check ms", "graph ms" or "ms" alone
         std::vector<std::string> rest;
         for (std::string t; in >> t;) rest.push_back(t);
         c->pipe_chunk = pipe;
@@ -1808,6 +1876,10 @@ static void load_schedule(swr_ctx* c, const char* path) {
         if (rest.size() >= 3) {
             const int chk = std::atoi(rest[1].c_str());
             if (chk >= 1) c->gm_check = chk;
+        }
+        if (rest.size() >= 4) {
+            const int grp = std::atoi(rest[2].c_str());
+            if (grp >= 1 && grp <= kGroupMax) c->group = grp;
         }
     }
 }
@@ -1829,7 +1901,7 @@ static bool store_schedule(const swr_ctx* c, const char* path, double ms) {
     if (!f) return false;
     for (const auto& l : keep) f << l << "\n";
     f << key << " " << c->pipe_chunk << " " << c->help_max << " " << c->o.restart << " " << c->pair_from
-      << " " << c->graph << " " << c->gm_check << " " << ms << "\n";
+      << " " << c->graph << " " << c->gm_check << " " << c->group << " " << ms << "\n";
     return (bool)f;
 }
 
@@ -1839,7 +1911,10 @@ extern "C" swr_status swr_tune(swr_ctx* c, const double* u0, double budget_ms, s
     double* uT = reinterpret_cast<double*>(c->dUT);
     // candidate values (the current schedule first)
     std::vector<int> pipes{c->pipe_chunk}, helps{c->help_max}, restarts{c->o.restart}, pairs{c->pair_from},
-        graphs{c->graph}, checks{c->gm_check};
+        graphs{c->graph}, checks{c->gm_check}, groups{c->group};
+    if (c->vk == SWR_V_STATIC && c->tr <= SWR_S02)
+        for (int g : {1, 2, 4, 8})
+            if (std::find(groups.begin(), groups.end(), g) == groups.end()) groups.push_back(g);
     if (c->o.solver == SWR_SOLVER_GMRES || c->vk == SWR_V_TIME)
         for (int q : {1, 4, 16})
             if (std::find(checks.begin(), checks.end(), q) == checks.end()) checks.push_back(q);
@@ -1857,14 +1932,15 @@ extern "C" swr_status swr_tune(swr_ctx* c, const double* u0, double budget_ms, s
         for (int w : {1, 4, kMaxP + 1})
             if (std::find(pairs.begin(), pairs.end(), w) == pairs.end()) pairs.push_back(w);
     const int p0 = c->pipe_chunk, h0 = c->help_max, m0 = c->o.restart, w0 = c->pair_from, q0 = c->graph,
-              k0 = c->gm_check;
+              k0 = c->gm_check, g0 = c->group;
     double best = INFINITY;
-    int bp = p0, bh = h0, bm = m0, bw = w0, bq = q0, bk = k0, tried = 0;
+    int bp = p0, bh = h0, bm = m0, bw = w0, bq = q0, bk = k0, bg = g0, tried = 0;
     double spent = 0;
     auto t_now = [] { return std::chrono::steady_clock::now(); };
     const auto t_start = t_now();
     for (int m : restarts)
         for (int kc : checks)
+        for (int gz : groups)
         for (int w : pairs)
         for (int q : graphs)
         for (int p : pipes)
@@ -1876,6 +1952,7 @@ extern "C" swr_status swr_tune(swr_ctx* c, const double* u0, double budget_ms, s
                 c->pair_from = w;
                 c->graph = q;
                 c->gm_check = kc;
+                c->group = gz;
                 // warm-up (with a graph: the uncaptured solve, then the capture)
                 swr_status rs = swr_solve(c, u0, uT, nullptr, nullptr, nullptr, nullptr);
                 if (rs == SWR_OK && q) rs = swr_solve(c, u0, uT, nullptr, nullptr, nullptr, nullptr);
@@ -1890,7 +1967,7 @@ extern "C" swr_status swr_tune(swr_ctx* c, const double* u0, double budget_ms, s
                     ms = std::min(ms, std::chrono::duration<double, std::milli>(t_now() - t0).count());
                 }
                 ++tried;
-                if (ms < best) { best = ms; bp = p; bh = h; bm = m; bw = w; bq = q; bk = kc; }
+                if (ms < best) { best = ms; bp = p; bh = h; bm = m; bw = w; bq = q; bk = kc; bg = gz; }
                 spent = std::chrono::duration<double, std::milli>(t_now() - t_start).count();
             }
     c->pipe_chunk = bp;
@@ -1899,6 +1976,7 @@ extern "C" swr_status swr_tune(swr_ctx* c, const double* u0, double budget_ms, s
     c->pair_from = bw;
     c->graph = bq;
     c->gm_check = bk;
+    c->group = bg;
     if (chosen) {
         chosen->pipeline = bp;
         chosen->help_max = bh;
@@ -1906,6 +1984,7 @@ extern "C" swr_status swr_tune(swr_ctx* c, const double* u0, double budget_ms, s
         chosen->pair_from = bw;
         chosen->graph = bq;
         chosen->check = bk;
+        chosen->group = bg;
         chosen->ms = best;
         chosen->candidates = tried;
     }
@@ -1917,7 +1996,7 @@ extern "C" swr_status swr_tune(swr_ctx* c, const double* u0, double budget_ms, s
 extern "C" swr_status swr_set_schedule(swr_ctx* c, const swr_schedule* s) {
     if (!c || !s) return SWR_EINVAL;
     if (s->pipeline < 0 || (s->pipeline > 0 && s->pipeline % kWave != 0) || s->help_max < 0 ||
-        s->restart < 1 || s->pair_from < 1 || s->check < 1)
+        s->restart < 1 || s->pair_from < 1 || s->check < 1 || s->group < 1 || s->group > kGroupMax)
         return SWR_EINVAL;
     c->pipe_chunk = s->pipeline;
     c->help_max = s->help_max;
@@ -1925,6 +2004,7 @@ extern "C" swr_status swr_set_schedule(swr_ctx* c, const swr_schedule* s) {
     c->pair_from = s->pair_from;
     c->graph = s->graph ? 1 : 0;
     c->gm_check = s->check;
+    c->group = s->group;
     return SWR_OK;
 }
 
@@ -1936,6 +2016,7 @@ extern "C" swr_status swr_get_schedule(const swr_ctx* c, swr_schedule* s) {
     s->pair_from = c->pair_from;
     s->graph = c->graph;
     s->check = c->gm_check;
+    s->group = c->group;
     s->ms = 0;
     s->candidates = 0;
     return SWR_OK;

@@ -185,35 +185,93 @@ __device__ inline void load_fac(const cd* Fp, LaneFac<P>& F) {
     F.invB = Fp[L::invB * kWave];
 }
 
-// Solve (A - sigma E) x = d for my chunk (all lanes take part).
+// Where a right-hand-side solve reads the factor record: the lane's VGPRs
+// (FacRegs) or the workgroup's LDS copy of the record (FacLds, p = the copy +
+// lane id, fields kWave apart as in global memory).  Both hand the solve the
+// same values, so the two forms are bitwise equal.
 template <int P>
-__device__ inline void lane_solve(const LaneFac<P>& F, const cd (&d)[P], cd (&x)[P]) {
+struct FacRegs {
+    const LaneFac<P>& F;
+    __device__ cd inv(int q) const { return F.inv[q]; }
+    __device__ cd ainv(int q) const { return F.ainv[q]; }
+    __device__ cd cp(int q) const { return F.cp[q]; }
+    __device__ cd al(int q) const { return F.al[q]; }
+    __device__ cd ga(int q) const { return F.ga[q]; }
+    __device__ cd ae() const { return F.ae; }
+    __device__ cd ce() const { return F.ce; }
+    __device__ cd k1(int l) const { return F.k1[l]; }
+    __device__ cd k2(int l) const { return F.k2[l]; }
+    __device__ cd invB() const { return F.invB; }
+};
+
+template <int P>
+struct FacLds {
+    using L = FacLayout<P>;
+    const cd* p;
+    __device__ cd inv(int q) const { return p[L::inv(q) * kWave]; }
+    __device__ cd ainv(int q) const { return p[L::ainv(q) * kWave]; }
+    __device__ cd cp(int q) const { return p[L::cp(q) * kWave]; }
+    __device__ cd al(int q) const { return p[L::al(q) * kWave]; }
+    __device__ cd ga(int q) const { return p[L::ga(q) * kWave]; }
+    __device__ cd ae() const { return p[L::ae * kWave]; }
+    __device__ cd ce() const { return p[L::ce * kWave]; }
+    __device__ cd k1(int l) const { return p[L::k1(l) * kWave]; }
+    __device__ cd k2(int l) const { return p[L::k2(l) * kWave]; }
+    __device__ cd invB() const { return p[L::invB * kWave]; }
+};
+
+// Complex products of the right-hand-side solve with every rounding fixed by
+// explicit fused multiply-adds.  Left to the compiler, a*b - c*d may be fused
+// around either product, and which one it picks depends on how the operands
+// reach the expression (a factor held in a VGPR across the time loop, whose
+// negation is hoisted out of it, or one read from LDS every step); with the
+// roundings spelled out, the VGPR and LDS forms of the solve are bitwise equal.
+__device__ inline cd cmul_x(cd a, cd b) {
+#pragma clang fp contract(off)
+    const double yy = a.y * b.y, yx = a.y * b.x;
+    return mk(fma(a.x, b.x, -yy), fma(a.x, b.y, yx));
+}
+__device__ inline cd msub_x(cd a, cd b, cd c) {   // a - b c
+    return mk(fma(b.y, c.y, fma(-b.x, c.x, a.x)), fma(-b.y, c.x, fma(-b.x, c.y, a.y)));
+}
+__device__ inline cd madd_x(cd a, cd b, cd c) {   // a + b c
+    return mk(fma(-b.y, c.y, fma(b.x, c.x, a.x)), fma(b.y, c.x, fma(b.x, c.y, a.y)));
+}
+
+// Solve (A - sigma E) x = d for my chunk (all lanes take part).
+template <int P, class FA>
+__device__ inline void lane_solve_with(const FA& F, const cd (&d)[P], cd (&x)[P]) {
     constexpr int PI = LaneFac<P>::PI;
     const cd zero = mk(0, 0);
     cd y[PI];
     cd yp = zero;
 #pragma unroll
     for (int q = 0; q < P - 1; ++q) {
-        yp = msub(d[q] * F.inv[q], F.ainv[q], yp);
+        yp = msub_x(cmul_x(d[q], F.inv(q)), F.ainv(q), yp);
         y[q] = yp;
     }
 #pragma unroll
-    for (int q = P - 3; q >= 0; --q) y[q] = msub(y[q], F.cp[q], y[q + 1]);
+    for (int q = P - 3; q >= 0; --q) y[q] = msub_x(y[q], F.cp(q), y[q + 1]);
     const cd yL = (P > 1) ? y[PI - 1] : zero;
     const cd yR = (P > 1) ? shfl_dn1z(y[0]) : zero;
-    cd D = msub(msub(d[P - 1], F.ae, yL), F.ce, yR);
+    cd D = msub_x(msub_x(d[P - 1], F.ae(), yL), F.ce(), yR);
 #pragma unroll
     for (int l = 0; l < kPcrLevels; ++l) {
         // k1 (k2) is zero on lanes without a partner at -dd (+dd)
         const int dd = 1 << l;
         const cd Dm = shfl_up_raw(D, dd), Dp = shfl_dn_raw(D, dd);
-        D = msub(msub(D, F.k1[l], Dm), F.k2[l], Dp);
+        D = msub_x(msub_x(D, F.k1(l), Dm), F.k2(l), Dp);
     }
-    const cd X = D * F.invB;
+    const cd X = cmul_x(D, F.invB());
     const cd Xm = shfl_up1z(X);
 #pragma unroll
-    for (int q = 0; q < P - 1; ++q) x[q] = madd(madd(y[q], F.al[q], Xm), F.ga[q], X);
+    for (int q = 0; q < P - 1; ++q) x[q] = madd_x(madd_x(y[q], F.al(q), Xm), F.ga(q), X);
     x[P - 1] = X;
+}
+
+template <int P>
+__device__ inline void lane_solve(const LaneFac<P>& F, const cd (&d)[P], cd (&x)[P]) {
+    lane_solve_with<P>(FacRegs<P>{F}, d, x);
 }
 
 // W at my nodes and at the two neighbouring nodes from a nodal array (static

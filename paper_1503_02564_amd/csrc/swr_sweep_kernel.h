@@ -132,19 +132,37 @@ __device__ inline void gen_end_coef(int tr, double W, double dW, double dt, cd c
 // dependent (rows rebuilt and refactored every step from the streamed V rows)
 // or |u|^2 (V-free factors, inner fixed point of eq. AvMNL every step).
 // ---------------------------------------------------------------------------
-template <int P, int TR, int VK, bool HELP = false>
-__global__ __launch_bounds__(sweep_threads(HELP)) void sweep_kernel(SweepArgs a) {
+//
+// GRP: the workgroup's waves run a group of tasks that share one factor record
+// (one subdomain, one potential: the problems of a batch, the impulse tasks),
+// a.groups[task0 + blockIdx.x] = (first task, count); the record is copied
+// once into LDS and every wave's solve reads it from there instead of holding
+// it in VGPRs, which leaves room for more waves per SIMD.  The arithmetic is
+// the one-wave form's, term for term.  Dynamic LDS: the record, then per wave
+// the staging of the far history (2 * 64 complex + 2 * 64 doubles).
+template <int P, int TR, int VK, bool HELP = false, bool GRP = false>
+__global__ __launch_bounds__(GRP ? kGroupMax * kWave : sweep_threads(HELP)) void sweep_kernel(SweepArgs a) {
     static_assert(!HELP || TR == TR_S02, "the helper wave serves S0^2");
+    static_assert(!GRP || (!HELP && VK == VK_STATIC && (TR == TR_S02 || TR == TR_ROBIN)),
+                  "shared-factor groups: static potential, Robin or S0^2");
     __shared__ double sbeta[2 * kWave];       // beta_0 .. beta_127
     __shared__ cd ffa[2][kWave], ffb[2][kWave];   // S0^2: far sums from the helper wave
     __shared__ cd sha[kWave], shb[kWave];     // staged chunk of the boundary history
     __shared__ double sb[2 * kWave];          // beta window of that chunk
-    const int tix = a.task0 + blockIdx.x;   // task index (per-task buffers)
+    extern __shared__ cd sgrp[];              // GRP: factor record, then per-wave staging
+    constexpr int kFacN = fac_fields(P) * kWave;
+    const int t = threadIdx.x & (kWave - 1);
+    const int wv = threadIdx.x / kWave;     // 1: the S0^2 helper wave; GRP: the group member
+    int tix = a.task0 + blockIdx.x;         // task index (per-task buffers)
+    int gcount = 1;
+    if (GRP) {
+        const int2 g = a.groups[a.task0 + blockIdx.x];
+        gcount = g.y;
+        tix = g.x + min(wv, g.y - 1);
+    }
     const Task task = a.tasks[tix];
     const int k = task.k, b = task.b, f = task.f;
     const int fl = (task.flags & a.flags_and) | a.flags_or;
-    const int t = threadIdx.x & (kWave - 1);
-    const int wv = threadIdx.x / kWave;     // 1: the S0^2 helper wave
     const int n = a.J[k] + 1, o = a.off[k];
     const int nt = a.nt;
     const bool lif = k > 0, rif = k < a.N - 1;
@@ -152,12 +170,27 @@ __global__ __launch_bounds__(sweep_threads(HELP)) void sweep_kernel(SweepArgs a)
     const int lastl = (n - 1) / P;          // lane holding node n-1
     const cd zero = mk(0, 0);
 
-    if (TR == TR_S02 || TR == TR_GEN) {
-        if (wv == 0) {
+    if (GRP) {
+        // every task of the group has this record (f)
+        const cd* src = a.fac + (size_t)f * a.fstride;
+        for (int i = threadIdx.x; i < kFacN; i += blockDim.x) sgrp[i] = src[i];
+    }
+    if (TR == TR_S02 || TR == TR_GEN || GRP) {
+        if (wv == 0 && (TR == TR_S02 || TR == TR_GEN)) {
             sbeta[t] = a.beta[t];
             sbeta[kWave + t] = a.beta[kWave + t];
         }
         __syncthreads();
+    }
+    if (GRP && wv >= gcount) return;        // a short group: no later workgroup barrier
+    // this wave's staging of the far history
+    cd* wsha = sha;
+    cd* wshb = shb;
+    double* wsb = sb;
+    if (GRP) {
+        wsha = sgrp + kFacN + wv * 2 * kWave;
+        wshb = wsha + kWave;
+        wsb = reinterpret_cast<double*>(sgrp + kFacN + (blockDim.x / kWave) * 2 * kWave) + wv * 2 * kWave;
     }
     cd* Ha = a.hist ? a.hist + (size_t)tix * 2 * (nt + 1) : nullptr;
     cd* Hb = Ha ? Ha + (nt + 1) : nullptr;
@@ -271,7 +304,7 @@ __global__ __launch_bounds__(sweep_threads(HELP)) void sweep_kernel(SweepArgs a)
             vprev[q] = (s + q < n) ? Vt[(size_t)nbeg * a.nx + s + q] : 0.0;
             vnext[q] = (s + q < n) ? Vt[(size_t)(nbeg + 1) * a.nx + s + q] : 0.0;
         }
-    } else {
+    } else if (!GRP) {
         load_fac<P>(a.fac + (size_t)f * a.fstride + t, F);
     }
 
@@ -444,7 +477,7 @@ __global__ __launch_bounds__(sweep_threads(HELP)) void sweep_kernel(SweepArgs a)
                 fb = ffb[kb & 1][t];
             } else {
                 __threadfence_block();
-                far_sum_s02(a, Ha, Hb, n0, t, sha, shb, sb, fa, fb);
+                far_sum_s02(a, Ha, Hb, n0, t, wsha, wshb, wsb, fa, fb);
             }
             acc_a = fa + nxt_a;
             acc_b = fb + nxt_b;
@@ -532,6 +565,9 @@ __global__ __launch_bounds__(sweep_threads(HELP)) void sweep_kernel(SweepArgs a)
 
         for (int i = 0; i < nb; ++i) {
             const int nstep = n0 + 1 + i;
+            // GRP: read the LDS factor record anew every step (the compiler
+            // would otherwise keep it in VGPRs across the loop)
+            if (GRP) asm volatile("" ::: "memory");
             // implicit coefficients of this step's boundary rows and of the
             // exchange (static potential: constant)
             cd sgA_n = a.sigma, sgB_n = a.sigma, sgsA_n = a.sigma, sgsB_n = a.sigma;
@@ -724,6 +760,8 @@ __global__ __launch_bounds__(sweep_threads(HELP)) void sweep_kernel(SweepArgs a)
                 nl_worst = max(nl_worst, conv ? it : a.nl_maxit);
 #pragma unroll
                 for (int q = 0; q < P; ++q) vlast[q] = x[q];
+            } else if (GRP) {
+                lane_solve_with<P>(FacLds<P>{sgrp + t}, d, x);
             } else {
                 lane_solve<P>(F, d, x);
             }

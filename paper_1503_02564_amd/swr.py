@@ -69,7 +69,7 @@ class SwrInfo(ctypes.Structure):
 class SwrSchedule(ctypes.Structure):
     _fields_ = [("pipeline", ctypes.c_int), ("help_max", ctypes.c_int), ("restart", ctypes.c_int),
                 ("pair_from", ctypes.c_int), ("graph", ctypes.c_int), ("check", ctypes.c_int),
-                ("ms", ctypes.c_double),
+                ("group", ctypes.c_int), ("ms", ctypes.c_double),
                 ("candidates", ctypes.c_int)]
 
     def as_dict(self):
@@ -316,11 +316,11 @@ def swr_get_schedule(ctx):
 
 
 def swr_set_schedule(ctx, pipeline=None, help_max=None, restart=None, pair_from=None, graph=None,
-                     check=None):
+                     check=None, group=None):
     """Change some parameters of the context's schedule (the rest stay)."""
     cur = swr_get_schedule(ctx)
     for k, v in (("pipeline", pipeline), ("help_max", help_max), ("restart", restart),
-                 ("pair_from", pair_from), ("graph", graph), ("check", check)):
+                 ("pair_from", pair_from), ("graph", graph), ("check", check), ("group", group)):
         if v is not None:
             setattr(cur, k, int(v))
     _check(_L.swr_set_schedule(ctx, ctypes.byref(cur)), "swr_set_schedule")

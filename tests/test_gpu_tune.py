@@ -117,6 +117,80 @@ def test_two_task_waves_equal_one_task_waves(dev, label, J, nt, trans, sigma, B,
         assert rel(out[True][0][b], O.mono(wl, wl.u0[b])) < 1e-10
 
 
+GROUP_CASES = [
+    # (label, J, nt, trans, sigma, B, pipeline, v_per_problem): a record's
+    # tasks (2 impulse + B d tasks in the build list, B in the final list)
+    # cut into ragged groups; widths 1 to 8
+    ("s02-staged", [60, 90, 75, 128, 200, 47, 250, 480], 300, W.S02, 0j, 3, 0, False),
+    ("s02-pipelined", [60, 90, 75, 128, 200, 47, 250], 300, W.S02, 0j, 5, 64, False),
+    ("robin-staged", [50, 70, 300, 33, 500], 200, W.ROBIN, 1 - 1j, 3, 0, False),
+    ("s02-v-per-problem", [60, 90, 200, 47], 200, W.S02, 0j, 3, 0, True),
+]
+
+
+@pytest.mark.parametrize("label,J,nt,trans,sigma,B,pipeline,vpp", GROUP_CASES)
+def test_shared_factor_groups_equal_one_task_waves(dev, label, J, nt, trans, sigma, B, pipeline, vpp):
+    """Sweeps that run the tasks of one factor record as the waves of one
+    workgroup reading an LDS copy of the record (forced here for every width
+    and launch size, group sizes 2, 3 and 8) perform each task's arithmetic
+    exactly as one-task workgroups: u(T), g, end-node traces, snapshots and
+    the adjoint's gradients are bitwise equal; u(T) matches the monodomain
+    oracle."""
+    import torch
+    import oracle as O
+    from paper_1503_02564_amd import swr
+    from tests.gpu_util import rel
+    wl = W.small_case(J=J, nt=nt, trans=trans, sigma=sigma, B=B, seed=31, a0=-12.0, b0=12.0)
+    Vs = None
+    if vpp:
+        # one potential per problem: every record has its problem's task only
+        # (and the two impulse tasks of each interface in the build list)
+        Vs = np.stack([(1.0 + 0.25 * b) * np.asarray(wl.V) for b in range(B)])
+        wl = W.Workload("pp", wl.a0, wl.b0, wl.J, wl.dt, wl.nt, W.V_STATIC, Vs, trans, sigma, wl.u0)
+    out = {}
+    for grp in (1, 2, 3, 8):
+        say("shared-factor groups", label, "group", grp)
+        pb = _problem(wl, pipeline=pipeline, snapshot_stride=50, v_per_problem=int(vpp))
+        swr.swr_set_schedule(pb.ctx, help_max=0, group=grp)
+        assert swr.swr_get_schedule(pb.ctx).group == grp
+        u0 = to_dev(wl.u0)
+        uT = torch.zeros_like(u0)
+        g = torch.zeros((B, pb.ns, nt), dtype=torch.complex128, device=dev)
+        tr = torch.zeros((B, wl.N, 2, nt + 1), dtype=torch.complex128, device=dev)
+        sn = torch.zeros((B, nt // 50 + 1, wl.nx), dtype=torch.complex128, device=dev)
+        st, info = swr.swr_solve(pb.ctx, u0, uT, g, tr, sn)
+        assert st == swr.SWR_OK and info.residual < 1e-10
+        dV = torch.zeros((B, wl.nx), dtype=torch.float64, device=dev)
+        du0 = torch.zeros_like(u0)
+        st2, _ = swr.swr_grad(pb.ctx, u0, (2.0 * uT).contiguous(), dV, du0)
+        assert st2 == swr.SWR_OK
+        torch.cuda.synchronize()
+        out[grp] = [to_np(x) for x in (uT, g, tr, sn, dV, du0)]
+        pb.close()
+    names = ("uT", "g", "traces", "snapshots", "dJ/dV", "dJ/du0")
+    for grp in (1, 2, 3, 8):
+        for nm, x in zip(names, out[grp]):
+            assert np.isfinite(x).all(), (nm, grp, np.argwhere(~np.isfinite(x))[:4].tolist())
+    for grp in (2, 3, 8):
+        for nm, x, y in zip(names, out[1], out[grp]):
+            assert np.array_equal(x, y), (nm, grp)
+    for b in range(B):
+        ref = O.mono(wl, wl.u0[b], V=Vs[b]) if vpp else O.mono(wl, wl.u0[b])
+        assert rel(out[8][0][b], ref) < 1e-10
+
+
+def test_group_schedule_is_validated(dev):
+    from paper_1503_02564_amd import swr
+    wl = W.small_case(J=[60, 90], nt=64, B=2, seed=3)
+    pb = _problem(wl)
+    assert swr.swr_get_schedule(pb.ctx).group == 4
+    for bad in (0, 9, -1):
+        with pytest.raises(swr.SwrError):
+            swr.swr_set_schedule(pb.ctx, group=bad)
+    assert swr.swr_get_schedule(pb.ctx).group == 4
+    pb.close()
+
+
 @pytest.mark.parametrize("vkind", [W.V_STATIC, W.V_TIME])
 def test_gmres_readback_period_changes_nothing(dev, vkind):
     """GMRES reads its residual estimates back every `check` inner steps:
