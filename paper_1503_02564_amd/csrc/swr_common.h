@@ -244,6 +244,11 @@ constexpr int kPairFrom = kMaxP + 1;
 constexpr int kGroupMax = 8;
 constexpr int kGroupDefault = 4;
 
+// S0^2: the time window is cut into super-chunks of this many steps for the
+// far history (the part of a block's far sum older than its super-chunk is
+// one batched Toeplitz product on the matrix cores per super-chunk)
+constexpr int kFarSuper = 256;
+
 struct SweepArgs {
     int N, nt, B, nx, ns;        // ns = 2N-2 interface slots
     int ntasks;
@@ -299,6 +304,21 @@ struct SweepArgs {
     cd* lfac;                    // [nf][fac_fields(lq max)][64] factor records (static, |u|^2)
     size_t lfstride;             // complex entries per long factor record
     cd* lwork;                   // [ntasks][3 Q (+ fac_fields(Q) for V(t,x))][64] per-task arrays
+    // S0^2 split at super-chunks: [list tasks][2][kFarSuper] the old part of
+    // the far sums of the launch's super-chunk (null: the far sums run from
+    // q = 0; the launch then need not end at a super-chunk boundary)
+    const cd* far_old;
+};
+
+// far_old_kernel: for the super-chunk starting at step C (> 0), every task
+// t < ntasks of a list, both ends e and outputs j < kFarSuper (step C+1+j <=
+// nt): out[t][e][j] = sum_{q <= C-65} beta_{C+1+j-q} x_q, x the task's
+// boundary history hist[t][e][.] ([ntasks][2][nt+1]).
+struct FarOldArgs {
+    const cd* hist;
+    const double* beta;          // [nt + 65]
+    cd* out;
+    int ntasks, nt, C;
 };
 
 struct FactorArgs {
@@ -365,6 +385,8 @@ hipError_t launch_sweep_pairs(const SweepArgs& a, int trans, hipStream_t st);
 // static potential, Robin or S0^2: a.ntasks workgroups of gsize waves, the
 // task groups a.groups[a.task0 ..] (swr_sweep_group.hip)
 hipError_t launch_sweep_groups(const SweepArgs& a, int trans, int gsize, hipStream_t st);
+// the old part of the S0^2 far sums of one super-chunk (swr_sweep.hip)
+hipError_t launch_far_old(const FarOldArgs& a, hipStream_t st);
 hipError_t launch_finalize_ut(int N, int nx, int B, const int* off, const cd* ends, cd* uT,
                               hipStream_t st);
 // the same for every snapshot: ends [B][S][N][2] -> snaps [B][S][nx]

@@ -153,6 +153,12 @@ struct swr_ctx {
     // build sweeps' own S0^2 history, and per-chunk events
     hipStream_t s2 = nullptr, s3 = nullptr;
     cd* dStateB = nullptr;    // [nBuild][2][P][64]
+    cd* dStateL = nullptr;    // [L0 impulse tasks][2][P][64]
+    // S0^2 split at super-chunks: old far-history parts of the current
+    // super-chunk, [list tasks][2][kFarSuper], one buffer per task list
+    cd* dFarB = nullptr;
+    cd* dFarS = nullptr;
+    cd* dFarL = nullptr;
     cd* dStateF = nullptr;    // [nSub][2][P][64]
     cd* dHistB = nullptr;     // [nBuild][2][nt+1]
     std::vector<hipEvent_t> evSync, evTime;
@@ -350,6 +356,11 @@ static void load_schedule(swr_ctx* c, const char* path);
 
 // transmissions whose history is a convolution over the stored boundary values
 static bool conv_hist(int tr) { return tr != SWR_ROBIN && tr <= SWR_S14; }
+
+// S0^2 sweeps of the register form split their far history at super-chunks
+// (old part precomputed on the matrix cores; far_sum_s02, launch_widths);
+// contexts with long-chunk subdomains sum it in one piece
+static bool far_split(const swr_ctx* c) { return c->tr == SWR_S02 && !c->Qlong; }
 
 // Pade strategy (Sec. 2.2): sqrt(z) ~ sum_{s=0}^m a_s - sum_{s=1}^m a_s d_s/(z + d_s)
 // from the partial fractions of the diagonal [m/m] Pade approximant of
@@ -567,6 +578,19 @@ extern "C" swr_status swr_setup(double a0, double b0, int N, const int* J, doubl
         if (c->Qlong) ALLOC(c->L0.lfac, (size_t)N * c->lfstride);
         ALLOC(c->L0.tasks, imp0.size());
     }
+    // S0^2 sweeps carry their state across super-chunk launches and read the
+    // old far-history parts of their super-chunk (see launch_widths)
+    if (far_split(c)) {
+        const size_t st_rec = (size_t)2 * c->P * kWave;
+        ALLOC(c->dStateB, build.size() * st_rec);
+        ALLOC(c->dStateF, sub.size() * st_rec);
+        ALLOC(c->dFarB, build.size() * 2 * kFarSuper);
+        ALLOC(c->dFarS, sub.size() * 2 * kFarSuper);
+        if (c->L0.tasks) {
+            ALLOC(c->dStateL, imp0.size() * st_rec);
+            ALLOC(c->dFarL, imp0.size() * 2 * kFarSuper);
+        }
+    }
     if (vk != SWR_V_CUBIC) {
         // the library's own copy of the potential (zeros when V is NULL)
         const size_t vn = (vk == SWR_V_TIME) ? (size_t)c->nx * (nt + 1)
@@ -771,6 +795,21 @@ static const std::vector<WidthRun>& runs_of(const swr_ctx* c, const Task* tasks)
     return c->runs_L0;
 }
 
+// the old-far-part buffer and the state buffer of a task list
+static cd* far_old_of(const swr_ctx* c, const Task* tasks) {
+    if (tasks == c->dBuild) return c->dFarB;
+    if (tasks == c->dSub) return c->dFarS;
+    if (tasks == c->L0.tasks) return c->dFarL;
+    return nullptr;
+}
+
+static cd* state_of(const swr_ctx* c, const Task* tasks) {
+    if (tasks == c->dBuild) return c->dStateB;
+    if (tasks == c->dSub) return c->dStateF;
+    if (tasks == c->L0.tasks) return c->dStateL;
+    return nullptr;
+}
+
 static const int2* pairs_of(const swr_ctx* c, const Task* tasks) {
     if (tasks == c->dBuild) return c->dPairsB;
     if (tasks == c->dSub) return c->dPairsS;
@@ -802,8 +841,8 @@ static int group_fit(int P, int g) {
 // factor records (two or more per record on average), workgroups of up to
 // group tasks of one record reading one LDS copy of it: the same arithmetic
 // per task in every form.
-static hipError_t launch_widths(const swr_ctx* c, SweepArgs a, int vk, hipStream_t st, bool plain,
-                                int* launches = nullptr) {
+static hipError_t launch_widths_range(const swr_ctx* c, SweepArgs a, int vk, hipStream_t st, bool plain,
+                                      int* launches) {
     const int2* pairs = pairs_of(c, a.tasks);
     const int tr = ktr(c);
     for (const WidthRun& r : runs_of(c, a.tasks)) {
@@ -841,6 +880,45 @@ static hipError_t launch_widths(const swr_ctx* c, SweepArgs a, int vk, hipStream
         }
         if (e != hipSuccess) return e;
         if (launches) *launches += plain ? r.count : 1;
+    }
+    return hipSuccess;
+}
+
+// S0^2 (register sweeps): the steps a.n_begin+1 .. a.n_end are launched in
+// pieces that end at super-chunk boundaries (multiples of kFarSuper), each
+// super-chunk after the first preceded by the batched product of its old
+// far-history parts (far_old_kernel); the sweeps carry their state across
+// the pieces in the list's state buffer.  Every S0^2 sweep of a context goes
+// through here, so all its forms sum the far history alike.
+static hipError_t launch_widths(const swr_ctx* c, SweepArgs a, int vk, hipStream_t st, bool plain,
+                                int* launches = nullptr) {
+    cd* fo = far_split(c) ? far_old_of(c, a.tasks) : nullptr;
+    if (!fo) {
+        a.far_old = nullptr;
+        return launch_widths_range(c, a, vk, st, plain, launches);
+    }
+    if (!a.state) a.state = state_of(c, a.tasks);
+    if (!a.state) return hipErrorInvalidValue;
+    a.far_old = fo;
+    const int n1 = a.n_end;
+    for (int s0 = a.n_begin; s0 < n1;) {
+        const int s1 = std::min(n1, (s0 / kFarSuper + 1) * kFarSuper);
+        if (s0 > 0 && s0 % kFarSuper == 0) {
+            FarOldArgs f{};
+            f.hist = a.hist;
+            f.beta = a.beta;
+            f.out = fo;
+            f.ntasks = a.ntasks;
+            f.nt = c->nt;
+            f.C = s0;
+            const hipError_t e = launch_far_old(f, st);
+            if (e != hipSuccess) return e;
+        }
+        a.n_begin = s0;
+        a.n_end = s1;
+        const hipError_t e = launch_widths_range(c, a, vk, st, plain, launches);
+        if (e != hipSuccess) return e;
+        s0 = s1;
     }
     return hipSuccess;
 }

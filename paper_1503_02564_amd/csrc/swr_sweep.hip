@@ -193,6 +193,83 @@ hipError_t launch_sweep(const SweepArgs& a, int trans, int vk, hipStream_t st, b
     return hipSuccess;
 }
 
+// ---------------------------------------------------------------------------
+// The old part of the S0^2 far sums of one super-chunk (see far_sum_s02): for
+// every task of a list, a lower-triangular Toeplitz product of the beta
+// sequence with the task's two boundary histories, on the matrix cores
+// (v_mfma_f64_16x16x4_f64; lane l supplies A[l%16][l/16] and B[l/16][l%16],
+// accumulator register k of lane l is D[l/16 + 4k][l%16]).  A workgroup
+// takes four tasks, whose 16 (task, end, part) columns fill the instruction's
+// N dimension; wave w takes the output rows 64w .. 64w+63 (four row tiles of
+// 16, one accumulator each).  Sources come in groups of four, q = 4g ..
+// 4g+3, and every output adds its groups in ascending g, one instruction per
+// group: A[r][k] = beta_{C+1+j-4g-k} (j = 16 RT + r), B[k][.] = x_{4g+k};
+// sources past C - 65, absent tasks and outputs past nt give zero operands.
+// Algorithmic work: 4 (C - 64) flops per output per end per task.
+// ---------------------------------------------------------------------------
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void far_old_kernel(FarOldArgs a) {
+    const int t = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int r = t & 15, kq = t >> 4;
+    const int p = r >> 2, e = (r >> 1) & 1, part = r & 1;
+    const int task = blockIdx.x * 4 + p;
+    const bool has = task < a.ntasks;
+    const int C = a.C, nt = a.nt;
+    const int qmax = C - kWave - 1;                 // old part: q <= C - 65
+    const int ng = (qmax + 4) / 4;                  // source groups 0 .. ng-1
+    const int amax = nt + kWave;                    // last beta index held
+    const double* hs = has ? reinterpret_cast<const double*>(a.hist + ((size_t)task * 2 + e) * (nt + 1)) + part
+                           : nullptr;
+    f64x4 acc[4];
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) acc[rr] = f64x4{0.0, 0.0, 0.0, 0.0};
+    constexpr int U = 4;
+    double an[U][4], bn[U];
+    auto fetch = [&](int gs) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int g = gs + u;
+            const int q = 4 * g + kq;
+            bn[u] = (hs && q <= qmax) ? hs[2 * q] : 0.0;
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                const int ia = C + 1 + 16 * (4 * w + rr) + r - 4 * g - kq;
+                an[u][rr] = (ia >= 0 && ia <= amax) ? a.beta[ia] : 0.0;
+            }
+        }
+    };
+    if (ng > 0) fetch(0);
+    for (int g = 0; g < ng; g += U) {
+        double ac[U][4], bc[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            bc[u] = bn[u];
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) ac[u][rr] = an[u][rr];
+        }
+        if (g + U < ng) fetch(g + U);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr)
+                acc[rr] = __builtin_amdgcn_mfma_f64_16x16x4f64(ac[u][rr], bc[u], acc[rr], 0, 0, 0);
+    }
+    if (!has) return;
+    double* o = reinterpret_cast<double*>(a.out + ((size_t)task * 2 + e) * kFarSuper) + part;
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) o[2 * (16 * (4 * w + rr) + kq + 4 * k)] = acc[rr][k];
+}
+
+hipError_t launch_far_old(const FarOldArgs& a, hipStream_t st) {
+    if (a.ntasks == 0) return hipSuccess;
+    if (a.C <= 0 || a.C % kFarSuper != 0 || !a.hist || !a.beta || !a.out) return hipErrorInvalidValue;
+    far_old_kernel<<<(a.ntasks + 3) / 4, 256, 0, st>>>(a);
+    return hipGetLastError();
+}
+
 hipError_t launch_finalize_ut(int N, int nx, int B, const int* off, const cd* ends, cd* uT,
                               hipStream_t st) {
     const int tot = B * (N + 1);

@@ -33,13 +33,29 @@ __host__ __device__ constexpr int sweep_threads(bool help) { return help ? 2 * k
 // and a wave's LDS operations complete in order, so no workgroup barrier is
 // needed (the helper wave cannot take one: the main wave does not join).
 // Positions past the last term hold zeros, which add exact zeros.
+//
+// Split at super-chunks (fo non-null): the time window is cut into
+// super-chunks of kFarSuper steps, and for a block of the super-chunk that
+// starts at step C > 0 the terms q <= C - 65 (the "old" part, the same for
+// all its blocks) come precomputed from far_old_kernel as one lower-triangular
+// Toeplitz product per super-chunk on the matrix cores, fo[e * kFarSuper +
+// j] for the super-chunk's output j and end e; the chain here starts from
+// that value and adds q = C - 64 .. n0 - 64 (at most 193 terms) in ascending
+// order.  Launches of such sweeps end at super-chunk boundaries.
 __device__ inline void far_sum_s02(const SweepArgs& a, const cd* Ha, const cd* Hb, int n0, int t,
-                                   cd* sha, cd* shb, double* sb, cd& fa, cd& fb) {
+                                   cd* sha, cd* shb, double* sb, cd& fa, cd& fb, const cd* fo) {
     const cd zero = mk(0, 0);
     const int qmax = n0 - kWave;
     const int nj = n0 + 1 + t;
     fa = zero;
     fb = zero;
+    const int C = n0 - n0 % kFarSuper;
+    int q0s = 0;
+    if (fo && C > 0) {
+        fa = fo[(n0 - C) + t];
+        fb = fo[kFarSuper + (n0 - C) + t];
+        q0s = C - kWave;
+    }
     cd pa = zero, pb = zero;
     double p0 = 0.0, p1 = 0.0;
     auto fetch = [&](int q0) {
@@ -53,8 +69,8 @@ __device__ inline void far_sum_s02(const SweepArgs& a, const cd* Ha, const cd* H
         if (bbase + t >= 0) p0 = a.beta[bbase + t];
         if (bbase + kWave + t >= 0) p1 = a.beta[bbase + kWave + t];
     };
-    if (qmax >= 0) fetch(0);
-    for (int q0 = 0; q0 <= qmax; q0 += kWave) {
+    if (qmax >= q0s) fetch(q0s);
+    for (int q0 = q0s; q0 <= qmax; q0 += kWave) {
         const int bbase = n0 - q0 - (kWave - 2);
         sha[t] = pa;
         shb[t] = pb;
@@ -80,11 +96,11 @@ __device__ inline void far_sum_s02(const SweepArgs& a, const cd* Ha, const cd* H
 
 __device__ inline void far_helper(const SweepArgs& a, const cd* Ha, const cd* Hb, int t,
                                   cd (*ffa)[kWave], cd (*ffb)[kWave], cd* sha, cd* shb,
-                                  double* sb) {
+                                  double* sb, const cd* fo) {
     const int nbeg = a.n_begin, nend = a.n_end;
     auto far = [&](int n0, int buf) {
         cd fa, fb;
-        far_sum_s02(a, Ha, Hb, n0, t, sha, shb, sb, fa, fb);
+        far_sum_s02(a, Ha, Hb, n0, t, sha, shb, sb, fa, fb, fo);
         ffa[buf][t] = fa;
         ffb[buf][t] = fb;
     };
@@ -194,8 +210,10 @@ __global__ __launch_bounds__(GRP ? kGroupMax * kWave : sweep_threads(HELP)) void
     }
     cd* Ha = a.hist ? a.hist + (size_t)tix * 2 * (nt + 1) : nullptr;
     cd* Hb = Ha ? Ha + (nt + 1) : nullptr;
+    // S0^2 split at super-chunks: this task's old far-history part
+    const cd* fo = a.far_old ? a.far_old + (size_t)tix * 2 * kFarSuper : nullptr;
     if (HELP && wv == 1) {
-        far_helper(a, Ha, Hb, t, ffa, ffb, sha, shb, sb);
+        far_helper(a, Ha, Hb, t, ffa, ffb, sha, shb, sb, fo);
         return;
     }
     // higher-order and Pade operators: coefficients of the two ends (left, right)
@@ -477,7 +495,7 @@ __global__ __launch_bounds__(GRP ? kGroupMax * kWave : sweep_threads(HELP)) void
                 fb = ffb[kb & 1][t];
             } else {
                 __threadfence_block();
-                far_sum_s02(a, Ha, Hb, n0, t, wsha, wshb, wsb, fa, fb);
+                far_sum_s02(a, Ha, Hb, n0, t, wsha, wshb, wsb, fa, fb, fo);
             }
             acc_a = fa + nxt_a;
             acc_b = fb + nxt_b;

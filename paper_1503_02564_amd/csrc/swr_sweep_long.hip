@@ -285,7 +285,8 @@ __global__ __launch_bounds__(64) void sweep_long_kernel(SweepArgs a) {
         if (TR == TR_S02) {
             cd fa, fb;
             __threadfence_block();
-            far_sum_s02(a, Ha, Hb, n0, t, sha, shb, sb, fa, fb);
+            far_sum_s02(a, Ha, Hb, n0, t, sha, shb, sb, fa, fb,
+                        a.far_old ? a.far_old + (size_t)tix * 2 * kFarSuper : nullptr);
             acc_a = fa + nxt_a;
             acc_b = fb + nxt_b;
             nxt_a = zero;

@@ -217,7 +217,8 @@ __global__ __launch_bounds__(kWave) void sweep_pair_kernel(SweepArgs a) {
             for (int c = 0; c < K; ++c) {
                 cd fa = zero, fb = zero;
                 __threadfence_block();
-                far_sum_s02(a, Ha[c], Hb[c], n0, t, sha, shb, sb, fa, fb);
+                far_sum_s02(a, Ha[c], Hb[c], n0, t, sha, shb, sb, fa, fb,
+                            a.far_old ? a.far_old + (size_t)tix[c] * 2 * kFarSuper : nullptr);
                 acc_a[c] = fa + nxt_a[c];
                 acc_b[c] = fb + nxt_b[c];
                 nxt_a[c] = zero;
