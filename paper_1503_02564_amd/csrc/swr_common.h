@@ -246,7 +246,10 @@ constexpr int kGroupDefault = 4;
 
 // S0^2: the time window is cut into super-chunks of this many steps for the
 // far history (the part of a block's far sum older than its super-chunk is
-// one batched Toeplitz product on the matrix cores per super-chunk)
+// one batched Toeplitz product on the matrix cores per super-chunk; a
+// multiple of 256).  Measured on batched-uneven (32 problems, 2000 steps,
+// pipelined solve): 256 steps 146.1 ms, 512 steps 146.6 ms; the shorter one
+// keeps each lane's chain of recent terms shorter (at most 193 terms)
 constexpr int kFarSuper = 256;
 
 struct SweepArgs {

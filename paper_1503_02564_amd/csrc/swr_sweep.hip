@@ -200,8 +200,9 @@ hipError_t launch_sweep(const SweepArgs& a, int trans, int vk, hipStream_t st, b
 // (v_mfma_f64_16x16x4_f64; lane l supplies A[l%16][l/16] and B[l/16][l%16],
 // accumulator register k of lane l is D[l/16 + 4k][l%16]).  A workgroup
 // takes four tasks, whose 16 (task, end, part) columns fill the instruction's
-// N dimension; wave w takes the output rows 64w .. 64w+63 (four row tiles of
-// 16, one accumulator each).  Sources come in groups of four, q = 4g ..
+// N dimension, and 256 output rows (blockIdx.y of the super-chunk's
+// kFarSuper / 256); its wave w takes 64 of them (four row tiles of 16, one
+// accumulator each).  Sources come in groups of four, q = 4g ..
 // 4g+3, and every output adds its groups in ascending g, one instruction per
 // group: A[r][k] = beta_{C+1+j-4g-k} (j = 16 RT + r), B[k][.] = x_{4g+k};
 // sources past C - 65, absent tasks and outputs past nt give zero operands.
@@ -214,6 +215,7 @@ __global__ __launch_bounds__(256) void far_old_kernel(FarOldArgs a) {
     const int r = t & 15, kq = t >> 4;
     const int p = r >> 2, e = (r >> 1) & 1, part = r & 1;
     const int task = blockIdx.x * 4 + p;
+    const int row0 = blockIdx.y * 256 + 64 * w;     // first output row of this wave
     const bool has = task < a.ntasks;
     const int C = a.C, nt = a.nt;
     const int qmax = C - kWave - 1;                 // old part: q <= C - 65
@@ -234,7 +236,7 @@ __global__ __launch_bounds__(256) void far_old_kernel(FarOldArgs a) {
             bn[u] = (hs && q <= qmax) ? hs[2 * q] : 0.0;
 #pragma unroll
             for (int rr = 0; rr < 4; ++rr) {
-                const int ia = C + 1 + 16 * (4 * w + rr) + r - 4 * g - kq;
+                const int ia = C + 1 + row0 + 16 * rr + r - 4 * g - kq;
                 an[u][rr] = (ia >= 0 && ia <= amax) ? a.beta[ia] : 0.0;
             }
         }
@@ -260,13 +262,14 @@ __global__ __launch_bounds__(256) void far_old_kernel(FarOldArgs a) {
 #pragma unroll
     for (int rr = 0; rr < 4; ++rr)
 #pragma unroll
-        for (int k = 0; k < 4; ++k) o[2 * (16 * (4 * w + rr) + kq + 4 * k)] = acc[rr][k];
+        for (int k = 0; k < 4; ++k) o[2 * (row0 + 16 * rr + kq + 4 * k)] = acc[rr][k];
 }
 
 hipError_t launch_far_old(const FarOldArgs& a, hipStream_t st) {
     if (a.ntasks == 0) return hipSuccess;
     if (a.C <= 0 || a.C % kFarSuper != 0 || !a.hist || !a.beta || !a.out) return hipErrorInvalidValue;
-    far_old_kernel<<<(a.ntasks + 3) / 4, 256, 0, st>>>(a);
+    static_assert(kFarSuper % 256 == 0, "far_old_kernel covers the super-chunk in 256-row blocks");
+    far_old_kernel<<<dim3((a.ntasks + 3) / 4, kFarSuper / 256), 256, 0, st>>>(a);
     return hipGetLastError();
 }
 

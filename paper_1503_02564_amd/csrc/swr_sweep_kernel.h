@@ -40,8 +40,9 @@ __host__ __device__ constexpr int sweep_threads(bool help) { return help ? 2 * k
 // all its blocks) come precomputed from far_old_kernel as one lower-triangular
 // Toeplitz product per super-chunk on the matrix cores, fo[e * kFarSuper +
 // j] for the super-chunk's output j and end e; the chain here starts from
-// that value and adds q = C - 64 .. n0 - 64 (at most 193 terms) in ascending
-// order.  Launches of such sweeps end at super-chunk boundaries.
+// that value and adds q = C - 64 .. n0 - 64 (at most kFarSuper - 63 terms)
+// in ascending order.  Launches of such sweeps end at super-chunk
+// boundaries.
 __device__ inline void far_sum_s02(const SweepArgs& a, const cd* Ha, const cd* Hb, int n0, int t,
                                    cd* sha, cd* shb, double* sb, cd& fa, cd& fb, const cd* fo) {
     const cd zero = mk(0, 0);
