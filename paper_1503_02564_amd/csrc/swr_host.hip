@@ -358,9 +358,16 @@ static void load_schedule(swr_ctx* c, const char* path);
 static bool conv_hist(int tr) { return tr != SWR_ROBIN && tr <= SWR_S14; }
 
 // S0^2 sweeps of the register form split their far history at super-chunks
-// (old part precomputed on the matrix cores; far_sum_s02, launch_widths);
-// contexts with long-chunk subdomains sum it in one piece
-static bool far_split(const swr_ctx* c) { return c->tr == SWR_S02 && !c->Qlong; }
+// (old part precomputed on the matrix cores; far_sum_s02, launch_widths).
+// Static potentials always do (every static form then sums alike); V(t,x)
+// and |u|^2 contexts only when their sweeps fill the GPU with one-wave tasks
+// -- with few tasks the S0^2 helper wave already sums the far history beside
+// the sweep, and the extra launches of the split cost more than they save
+// (|u|^2 on 128 x 256 cells, 4000 steps: 815 ms split, 750 ms not).
+// Contexts with long-chunk subdomains sum it in one piece.
+static bool far_split(const swr_ctx* c) {
+    return c->tr == SWR_S02 && !c->Qlong && (c->vk == SWR_V_STATIC || c->nSub > kHelpMaxTasks);
+}
 
 // Pade strategy (Sec. 2.2): sqrt(z) ~ sum_{s=0}^m a_s - sum_{s=1}^m a_s d_s/(z + d_s)
 // from the partial fractions of the diagonal [m/m] Pade approximant of

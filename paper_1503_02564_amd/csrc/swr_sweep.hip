@@ -200,9 +200,11 @@ hipError_t launch_sweep(const SweepArgs& a, int trans, int vk, hipStream_t st, b
 // (v_mfma_f64_16x16x4_f64; lane l supplies A[l%16][l/16] and B[l/16][l%16],
 // accumulator register k of lane l is D[l/16 + 4k][l%16]).  A workgroup
 // takes four tasks, whose 16 (task, end, part) columns fill the instruction's
-// N dimension, and 256 output rows (blockIdx.y of the super-chunk's
-// kFarSuper / 256); its wave w takes 64 of them (four row tiles of 16, one
-// accumulator each).  Sources come in groups of four, q = 4g ..
+// N dimension, and 64 RT output rows (blockIdx.y of the super-chunk's
+// kFarSuper / (64 RT)); its wave w takes RT row tiles of 16 rows (one
+// accumulator each, one B operand for all of them).  RT = 4 for long task
+// lists, RT = 1 for short ones, so that few tasks still spread over many
+// waves; each output adds the same terms in the same order either way.  Sources come in groups of four, q = 4g ..
 // 4g+3, and every output adds its groups in ascending g, one instruction per
 // group: A[r][k] = beta_{C+1+j-4g-k} (j = 16 RT + r), B[k][.] = x_{4g+k};
 // sources past C - 65, absent tasks and outputs past nt give zero operands.
@@ -210,12 +212,13 @@ hipError_t launch_sweep(const SweepArgs& a, int trans, int vk, hipStream_t st, b
 // ---------------------------------------------------------------------------
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
+template <int RT>
 __global__ __launch_bounds__(256) void far_old_kernel(FarOldArgs a) {
     const int t = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const int r = t & 15, kq = t >> 4;
     const int p = r >> 2, e = (r >> 1) & 1, part = r & 1;
     const int task = blockIdx.x * 4 + p;
-    const int row0 = blockIdx.y * 256 + 64 * w;     // first output row of this wave
+    const int row0 = (blockIdx.y * 4 + w) * 16 * RT;   // first output row of this wave
     const bool has = task < a.ntasks;
     const int C = a.C, nt = a.nt;
     const int qmax = C - kWave - 1;                 // old part: q <= C - 65
@@ -223,11 +226,11 @@ __global__ __launch_bounds__(256) void far_old_kernel(FarOldArgs a) {
     const int amax = nt + kWave;                    // last beta index held
     const double* hs = has ? reinterpret_cast<const double*>(a.hist + ((size_t)task * 2 + e) * (nt + 1)) + part
                            : nullptr;
-    f64x4 acc[4];
+    f64x4 acc[RT];
 #pragma unroll
-    for (int rr = 0; rr < 4; ++rr) acc[rr] = f64x4{0.0, 0.0, 0.0, 0.0};
-    constexpr int U = 4;
-    double an[U][4], bn[U];
+    for (int rr = 0; rr < RT; ++rr) acc[rr] = f64x4{0.0, 0.0, 0.0, 0.0};
+    constexpr int U = RT == 1 ? 8 : 4;
+    double an[U][RT], bn[U];
     auto fetch = [&](int gs) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -235,7 +238,7 @@ __global__ __launch_bounds__(256) void far_old_kernel(FarOldArgs a) {
             const int q = 4 * g + kq;
             bn[u] = (hs && q <= qmax) ? hs[2 * q] : 0.0;
 #pragma unroll
-            for (int rr = 0; rr < 4; ++rr) {
+            for (int rr = 0; rr < RT; ++rr) {
                 const int ia = C + 1 + row0 + 16 * rr + r - 4 * g - kq;
                 an[u][rr] = (ia >= 0 && ia <= amax) ? a.beta[ia] : 0.0;
             }
@@ -243,24 +246,24 @@ __global__ __launch_bounds__(256) void far_old_kernel(FarOldArgs a) {
     };
     if (ng > 0) fetch(0);
     for (int g = 0; g < ng; g += U) {
-        double ac[U][4], bc[U];
+        double ac[U][RT], bc[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             bc[u] = bn[u];
 #pragma unroll
-            for (int rr = 0; rr < 4; ++rr) ac[u][rr] = an[u][rr];
+            for (int rr = 0; rr < RT; ++rr) ac[u][rr] = an[u][rr];
         }
         if (g + U < ng) fetch(g + U);
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int rr = 0; rr < 4; ++rr)
+            for (int rr = 0; rr < RT; ++rr)
                 acc[rr] = __builtin_amdgcn_mfma_f64_16x16x4f64(ac[u][rr], bc[u], acc[rr], 0, 0, 0);
     }
     if (!has) return;
     double* o = reinterpret_cast<double*>(a.out + ((size_t)task * 2 + e) * kFarSuper) + part;
 #pragma unroll
-    for (int rr = 0; rr < 4; ++rr)
+    for (int rr = 0; rr < RT; ++rr)
 #pragma unroll
         for (int k = 0; k < 4; ++k) o[2 * (row0 + 16 * rr + kq + 4 * k)] = acc[rr][k];
 }
@@ -269,7 +272,11 @@ hipError_t launch_far_old(const FarOldArgs& a, hipStream_t st) {
     if (a.ntasks == 0) return hipSuccess;
     if (a.C <= 0 || a.C % kFarSuper != 0 || !a.hist || !a.beta || !a.out) return hipErrorInvalidValue;
     static_assert(kFarSuper % 256 == 0, "far_old_kernel covers the super-chunk in 256-row blocks");
-    far_old_kernel<<<dim3((a.ntasks + 3) / 4, kFarSuper / 256), 256, 0, st>>>(a);
+    const unsigned gx = (unsigned)(a.ntasks + 3) / 4;
+    if (a.ntasks >= 4096)
+        far_old_kernel<4><<<dim3(gx, kFarSuper / 256), 256, 0, st>>>(a);
+    else
+        far_old_kernel<1><<<dim3(gx, kFarSuper / 64), 256, 0, st>>>(a);
     return hipGetLastError();
 }
 
