@@ -55,6 +55,39 @@ def test_one_sweep_matches_oracle(dev, label, J, nt, trans, sigma, with_data):
     pb.close()
 
 
+@pytest.mark.parametrize("form", ["helper-wave", "groups"])
+def test_sweeps_across_far_history_super_chunks(dev, form):
+    """S0^2 over 700 steps (three 256-step super-chunks of the far history,
+    the older part of each from the batched matrix-core product between the
+    sweep pieces): one sweep with random fluxes, the impulse columns and d,
+    with every launch in the helper-wave form (the default for few tasks) or
+    forced into shared-factor groups, against the oracle at the one-sweep
+    bar."""
+    import torch
+    from paper_1503_02564_amd import swr
+    B, nt = 3, 700
+    wl = _case([60, 100, 200, 130], nt, W.S02, 0j, B=B, seed=8)
+    say("far-history super-chunks", form)
+    pb = make_problem(wl)
+    if form == "groups":
+        swr.swr_set_schedule(pb.ctx, help_max=0, group=4)
+    rng = np.random.default_rng(21)
+    g = rng.standard_normal((B, pb.ns, nt)) + 1j * rng.standard_normal((B, pb.ns, nt))
+    g_out = torch.zeros((B, pb.ns, nt), dtype=torch.complex128, device=dev)
+    uT = torch.zeros((B, wl.nx), dtype=torch.complex128, device=dev)
+    swr.swr_apply_R(pb.ctx, to_dev(wl.u0), to_dev(g), g_out, uT)
+    cols = torch.zeros((1, wl.N, 4, nt), dtype=torch.complex128, device=dev)
+    d = torch.zeros((B, pb.ns, nt), dtype=torch.complex128, device=dev)
+    swr.swr_build_interface(pb.ctx, to_dev(wl.u0), cols, d)
+    torch.cuda.synchronize()
+    for b in range(B):
+        assert rel(to_np(g_out)[b], O.apply_R(wl, wl.u0[b], g[b])) < 1e-12
+        assert rel(to_np(uT)[b], O.local_solution(wl, wl.u0[b], g[b])[0]) < 1e-12
+        assert rel(to_np(d)[b], O.interface_d(wl, wl.u0[b])) < 1e-12
+    assert rel(to_np(cols)[0], O.impulse_columns(wl)) < 1e-12
+    pb.close()
+
+
 @pytest.mark.parametrize("label,J,nt,trans,sigma", SWEEP_CASES[:3])
 def test_impulse_columns_and_d_match_oracle(dev, label, J, nt, trans, sigma):
     import torch
