@@ -268,13 +268,87 @@ __global__ __launch_bounds__(256) void far_old_kernel(FarOldArgs a) {
         for (int k = 0; k < 4; ++k) o[2 * (row0 + 16 * rr + kq + 4 * k)] = acc[rr][k];
 }
 
+// Long task lists: the same product with the operands staged in LDS.  The
+// workgroup loads each chunk of 64 sources of its four tasks' histories (16
+// columns) and the 319-entry beta window the chunk meets for its 256 rows with
+// coalesced loads, the next chunk's loads in flight while the current one is
+// multiplied (double buffer, two barriers per chunk).  Each output adds the
+// same groups in the same ascending order as far_old_kernel (the chunks'
+// padding groups past C - 65 add exact zeros).
+__global__ __launch_bounds__(256) void far_old_staged_kernel(FarOldArgs a) {
+    __shared__ double sB[2][kWave][16];           // [buffer][source in chunk][column]
+    __shared__ double sA[2][kWave + 256];         // [buffer][beta window]
+    const int tid = threadIdx.x, t = tid & (kWave - 1), w = tid / kWave;
+    const int r = t & 15, kq = t >> 4;
+    const int p = r >> 2, e = (r >> 1) & 1, part = r & 1;
+    const int task0 = blockIdx.x * 4;
+    const int row_base = blockIdx.y * 256;
+    const int rw = 64 * w;                          // first row of this wave within the workgroup's
+    const int C = a.C, nt = a.nt;
+    const int qmax = C - kWave - 1;
+    const int amax = nt + kWave;
+    const int nch = (qmax + kWave) / kWave;         // chunks of 64 sources covering 0 .. qmax
+    // staging: thread tid loads sources i2 and i2 + 32 of history (task, end)
+    // pe = tid / 32, and two beta entries
+    const int pe = tid >> 5, i2 = tid & 31;
+    const int stask = task0 + (pe >> 1);
+    const cd* sx = stask < a.ntasks ? a.hist + ((size_t)stask * 2 + (pe & 1)) * (nt + 1) : nullptr;
+    cd xv0, xv1;
+    double bv0, bv1;
+    auto fetch = [&](int c) {
+        const int q0 = c * kWave;
+        xv0 = (sx && q0 + i2 <= qmax) ? sx[q0 + i2] : mk(0, 0);
+        xv1 = (sx && q0 + 32 + i2 <= qmax) ? sx[q0 + 32 + i2] : mk(0, 0);
+        const int base = C + 1 + row_base - q0 - (kWave - 1);   // beta index of sA[0]
+        const int i0 = base + tid, i1 = base + 256 + tid;
+        bv0 = (i0 >= 0 && i0 <= amax) ? a.beta[i0] : 0.0;
+        bv1 = (tid < kWave - 1 && i1 >= 0 && i1 <= amax) ? a.beta[i1] : 0.0;
+    };
+    auto stage = [&](int buf) {
+        sB[buf][i2][2 * pe] = xv0.x;
+        sB[buf][i2][2 * pe + 1] = xv0.y;
+        sB[buf][32 + i2][2 * pe] = xv1.x;
+        sB[buf][32 + i2][2 * pe + 1] = xv1.y;
+        sA[buf][tid] = bv0;
+        if (tid < kWave - 1) sA[buf][256 + tid] = bv1;
+    };
+    f64x4 acc[4];
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) acc[rr] = f64x4{0.0, 0.0, 0.0, 0.0};
+    fetch(0);
+    stage(0);
+    __syncthreads();
+    for (int c = 0; c < nch; ++c) {
+        const int buf = c & 1;
+        if (c + 1 < nch) fetch(c + 1);
+#pragma unroll 4
+        for (int gl = 0; gl < 16; ++gl) {
+            const double bvv = sB[buf][4 * gl + kq][r];
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                const double avv = sA[buf][rw + 16 * rr + r - 4 * gl - kq + (kWave - 1)];
+                acc[rr] = __builtin_amdgcn_mfma_f64_16x16x4f64(avv, bvv, acc[rr], 0, 0, 0);
+            }
+        }
+        if (c + 1 < nch) stage(buf ^ 1);
+        __syncthreads();
+    }
+    const int task = task0 + p;
+    if (task >= a.ntasks) return;
+    double* o = reinterpret_cast<double*>(a.out + ((size_t)task * 2 + e) * kFarSuper) + part;
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) o[2 * (row_base + rw + 16 * rr + kq + 4 * k)] = acc[rr][k];
+}
+
 hipError_t launch_far_old(const FarOldArgs& a, hipStream_t st) {
     if (a.ntasks == 0) return hipSuccess;
     if (a.C <= 0 || a.C % kFarSuper != 0 || !a.hist || !a.beta || !a.out) return hipErrorInvalidValue;
     static_assert(kFarSuper % 256 == 0, "far_old_kernel covers the super-chunk in 256-row blocks");
     const unsigned gx = (unsigned)(a.ntasks + 3) / 4;
     if (a.ntasks >= 4096)
-        far_old_kernel<4><<<dim3(gx, kFarSuper / 256), 256, 0, st>>>(a);
+        far_old_staged_kernel<<<dim3(gx, kFarSuper / 256), 256, 0, st>>>(a);
     else
         far_old_kernel<1><<<dim3(gx, kFarSuper / 64), 256, 0, st>>>(a);
     return hipGetLastError();
