@@ -202,12 +202,132 @@ __global__ __launch_bounds__(256) void ltt_mfma_kernel(LttArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Batched form of the staged product (at most 256 outputs and 256 sources per
+// segment, one potential for the whole batch): the problems of the batch,
+// which share every coefficient, fill the instruction's N dimension instead
+// of the output blocks.  A workgroup takes one slot, one segment and eight
+// problems; the columns are (problem, real / imaginary part of x), and two
+// accumulators per 16-output block collect Re T [Re x | Im x] and
+// Im T [Re x | Im x], combined at the end (Re y = Re T Re x - Im T Im x, Im y
+// = Re T Im x + Im T Re x) between neighbouring lanes.  Every (output block,
+// source block) pair does useful work, where the one-problem form's columns
+// (output blocks) meet a lag block's sources only partly (about half of its
+// products are zero operands on a 256 x 256 tile).  The workgroup stages the
+// sources of its eight problems (2 sides x 256 x 16 doubles) and the
+// coefficient window (2 x 511) in LDS (80 KiB); wave w takes the output blocks
+// 4w .. 4w+3.  Sum order: source blocks ascending, k-slices ascending, the
+// two sides, per output; it differs from the one-problem form's, so a batch
+// of eight or more problems and the same problem alone agree to rounding.
+// ---------------------------------------------------------------------------
+constexpr int kLttBatch = 8;      // problems per workgroup of the batched form
+
+__device__ inline double swap_pair(double v) {   // the value of lane l ^ 1
+    int2 t = *reinterpret_cast<int2*>(&v);
+    t.x = __builtin_amdgcn_mov_dpp(t.x, 0xB1, 0xf, 0xf, false);   // quad_perm [1,0,3,2]
+    t.y = __builtin_amdgcn_mov_dpp(t.y, 0xB1, 0xf, 0xf, false);
+    return *reinterpret_cast<double*>(&t);
+}
+
+__global__ __launch_bounds__(256) void ltt_batch_kernel(LttArgs a) {
+    extern __shared__ double lds[];
+    double* sx = lds;                                            // [2][256][16]
+    cd* sc = reinterpret_cast<cd*>(lds + 2 * kLttStage * 16);    // [2][2 * kLttStage]
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+    const int r = lane & 15, kq = lane >> 4;
+    const int o = blockIdx.x, b0 = blockIdx.y * kLttBatch, seg = blockIdx.z;
+    const int nlen = a.n_hi - a.n_lo;
+    const int s_lo = a.s_seg > 0 ? a.s_lo + seg * a.s_seg : a.s_lo;
+    const int s_hi = a.s_seg > 0 ? min(a.s_hi, s_lo + a.s_seg) : a.s_hi;
+    const int slen = s_hi - s_lo;
+    int k, pl, pr, sl, sr;
+    slot_sources(o, a.N, k, pl, pr, sl, sr);
+    const cd* cl = a.cols + ((size_t)k * 4 + pl) * a.nt;
+    const cd* cr = a.cols + ((size_t)k * 4 + pr) * a.nt;
+    // sources: thread tid stages source s = tid of every problem and side
+    for (int side = 0; side < 2; ++side) {
+        const int srow = side ? sr : sl;
+#pragma unroll
+        for (int bb = 0; bb < kLttBatch; ++bb) {
+            const int b = b0 + bb;
+            cd x = mk(0, 0);
+            if (srow >= 0 && b < a.B && tid < slen) x = a.x[((size_t)b * a.ns + srow) * a.nt + s_lo + tid];
+            sx[(side * kLttStage + tid) * 16 + 2 * bb] = x.x;
+            sx[(side * kLttStage + tid) * 16 + 2 * bb + 1] = x.y;
+        }
+    }
+    // coefficients: lags lag0 + e, e < nlen + slen - 1
+    const int lag0 = a.n_lo - s_hi + 1, nlag = nlen + slen - 1;
+    for (int e = tid; e < 2 * kLttStage; e += blockDim.x) {
+        const int lag = lag0 + e;
+        const bool ok = e < nlag && lag >= 0 && lag < a.nt;
+        sc[e] = (ok && sl >= 0) ? cl[lag] : mk(0, 0);
+        sc[2 * kLttStage + e] = (ok && sr >= 0) ? cr[lag] : mk(0, 0);
+    }
+    __syncthreads();
+    d4 d1[4], d2[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        d1[i] = d4{0.0, 0.0, 0.0, 0.0};
+        d2[i] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+    const int Jn = (slen + 15) / 16;
+    for (int J = 0; J < Jn; ++J) {
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const int kk = 4 * ks + kq;              // source 16 J + kk: B[kq][col r]
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                if (side == 0 ? sl < 0 : sr < 0) continue;
+                const double bv = sx[(side * kLttStage + 16 * J + kk) * 16 + r];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int I = 4 * w + i;
+                    // A[row r][kq]: lag of output 16 I + r and source 16 J + kk
+                    const int e = 16 * (I - J) + r - kk + slen - 1;
+                    cd av = mk(0, 0);
+                    if (e >= 0 && e < 2 * kLttStage) av = sc[side * 2 * kLttStage + e];
+                    d1[i] = mfma16(av.x, bv, d1[i]);
+                    d2[i] = mfma16(av.y, bv, d2[i]);
+                }
+            }
+        }
+    }
+    // lane with column r = 2 bb + part: part 0 gives Re y = Re T Re x - Im T Im x
+    // (d1 here, d2 of the odd neighbour), part 1 Im y = Re T Im x + Im T Re x
+    const int bb = r >> 1, part = r & 1;
+    const int b = b0 + bb;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double other = swap_pair(d2[i][q]);
+            const double v = part ? d1[i][q] + other : d1[i][q] - other;
+            const int nrel = 16 * (4 * w + i) + kq + 4 * q;
+            if (b < a.B && nrel < nlen) {
+                const size_t yb = ((size_t)b * a.ns + o) * a.y_ld + (size_t)seg * a.y_seg_stride;
+                double* y = reinterpret_cast<double*>(a.y + yb + nrel) + part;
+                double val = a.sign * v;
+                if (a.s_seg <= 0 && a.base) val += reinterpret_cast<const double*>(a.base + yb + nrel)[part];
+                *y = val;
+            }
+        }
+    }
+}
+
 hipError_t launch_ltt(const LttArgs& a, hipStream_t st) {
     if (a.ns == 0 || a.n_hi <= a.n_lo) return hipSuccess;
     if (a.s_lo < 0 || a.s_hi > a.nt || a.n_lo < 0 || a.n_hi > a.nt) return hipErrorInvalidValue;
     const int tiles = (a.n_hi - a.n_lo + 255) / 256;
     const int nseg = a.s_seg > 0 ? (a.s_hi - a.s_lo + a.s_seg - 1) / a.s_seg : 1;
     if ((size_t)a.B * nseg > 65535) return hipErrorInvalidValue;
+    const int slen_max = a.s_seg > 0 ? std::min(a.s_seg, a.s_hi - a.s_lo) : a.s_hi - a.s_lo;
+    if (a.B >= kLttBatch && !a.per_problem && a.n_hi - a.n_lo <= kLttStage && slen_max <= kLttStage) {
+        const size_t lds = sizeof(double) * 2 * kLttStage * 16 + sizeof(cd) * 2 * 2 * kLttStage;
+        dim3 grid(a.ns, (a.B + kLttBatch - 1) / kLttBatch, nseg);
+        ltt_batch_kernel<<<grid, 256, lds, st>>>(a);
+        return hipGetLastError();
+    }
     dim3 grid((tiles + 3) / 4, a.ns, a.B * nseg);
     ltt_mfma_kernel<<<grid, 256, 0, st>>>(a);
     return hipGetLastError();

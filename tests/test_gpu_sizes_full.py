@@ -178,7 +178,8 @@ def test_full_size_batched_uneven(dev):
     one batch, 2000 steps, in the benchmark's launch configuration:
     certified residual, mass of every member conserved, full-length u(T) of
     members 0 and 31 against the oracle, and those members solved alone
-    (another launch shape) equal to their batch result."""
+    (another launch shape: one-problem interface products, one-wave
+    sweeps) equal to their batch result to rounding."""
     from paper_1503_02564_amd import swr
     wl = W.batched_uneven()
     say("full-size", "batched_uneven batch of", wl.B)
