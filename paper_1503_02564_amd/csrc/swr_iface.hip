@@ -215,12 +215,16 @@ __global__ __launch_bounds__(256) void ltt_mfma_kernel(LttArgs a) {
 // (output blocks) meet a lag block's sources only partly (about half of its
 // products are zero operands on a 256 x 256 tile).  The workgroup stages the
 // sources of its eight problems (2 sides x 256 x 16 doubles) and the
-// coefficient window (2 x 511) in LDS (80 KiB); wave w takes the output blocks
-// 4w .. 4w+3.  Sum order: source blocks ascending, k-slices ascending, the
+// coefficient window (2 x 512) in LDS (80 KiB); wave w takes the output blocks
+// 4w .. 4w+3.  The sources sit at the end of their 16-aligned block (zeros
+// first), so the lag index of every (output, source) pair of the tiles lies in
+// [0, 511) and each A operand is one LDS read at a constant offset from a
+// per-lane base, with no range test in the product loop.  Sum order: source blocks ascending, k-slices ascending, the
 // two sides, per output; it differs from the one-problem form's, so a batch
 // of eight or more problems and the same problem alone agree to rounding.
 // ---------------------------------------------------------------------------
 constexpr int kLttBatch = 8;      // problems per workgroup of the batched form
+constexpr int kLttScLen = 2 * kLttStage;   // coefficient window per side
 
 __device__ inline double swap_pair(double v) {   // the value of lane l ^ 1
     int2 t = *reinterpret_cast<int2*>(&v);
@@ -232,7 +236,7 @@ __device__ inline double swap_pair(double v) {   // the value of lane l ^ 1
 __global__ __launch_bounds__(256) void ltt_batch_kernel(LttArgs a) {
     extern __shared__ double lds[];
     double* sx = lds;                                            // [2][256][16]
-    cd* sc = reinterpret_cast<cd*>(lds + 2 * kLttStage * 16);    // [2][2 * kLttStage]
+    cd* sc = reinterpret_cast<cd*>(lds + 2 * kLttStage * 16);    // [2][kLttScLen]
     const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
     const int r = lane & 15, kq = lane >> 4;
     const int o = blockIdx.x, b0 = blockIdx.y * kLttBatch, seg = blockIdx.z;
@@ -244,25 +248,27 @@ __global__ __launch_bounds__(256) void ltt_batch_kernel(LttArgs a) {
     slot_sources(o, a.N, k, pl, pr, sl, sr);
     const cd* cl = a.cols + ((size_t)k * 4 + pl) * a.nt;
     const cd* cr = a.cols + ((size_t)k * 4 + pr) * a.nt;
-    // sources: thread tid stages source s = tid of every problem and side
+    // sources: thread tid stages position tid = source tid - pad0 of every
+    // problem and side, positions below pad0 zero
+    const int Jn = (slen + 15) / 16, pad0 = 16 * Jn - slen, src = tid - pad0;
     for (int side = 0; side < 2; ++side) {
         const int srow = side ? sr : sl;
 #pragma unroll
         for (int bb = 0; bb < kLttBatch; ++bb) {
             const int b = b0 + bb;
             cd x = mk(0, 0);
-            if (srow >= 0 && b < a.B && tid < slen) x = a.x[((size_t)b * a.ns + srow) * a.nt + s_lo + tid];
+            if (srow >= 0 && b < a.B && src >= 0 && src < slen) x = a.x[((size_t)b * a.ns + srow) * a.nt + s_lo + src];
             sx[(side * kLttStage + tid) * 16 + 2 * bb] = x.x;
             sx[(side * kLttStage + tid) * 16 + 2 * bb + 1] = x.y;
         }
     }
     // coefficients: lags lag0 + e, e < nlen + slen - 1
     const int lag0 = a.n_lo - s_hi + 1, nlag = nlen + slen - 1;
-    for (int e = tid; e < 2 * kLttStage; e += blockDim.x) {
+    for (int e = tid; e < kLttScLen; e += blockDim.x) {
         const int lag = lag0 + e;
         const bool ok = e < nlag && lag >= 0 && lag < a.nt;
         sc[e] = (ok && sl >= 0) ? cl[lag] : mk(0, 0);
-        sc[2 * kLttStage + e] = (ok && sr >= 0) ? cr[lag] : mk(0, 0);
+        sc[kLttScLen + e] = (ok && sr >= 0) ? cr[lag] : mk(0, 0);
     }
     __syncthreads();
     d4 d1[4], d2[4];
@@ -271,22 +277,23 @@ __global__ __launch_bounds__(256) void ltt_batch_kernel(LttArgs a) {
         d1[i] = d4{0.0, 0.0, 0.0, 0.0};
         d2[i] = d4{0.0, 0.0, 0.0, 0.0};
     }
-    const int Jn = (slen + 15) / 16;
+    // per-lane bases: B[kq][col r] = position 16 J + 4 ks + kq of column r;
+    // A[row r][kq] = lag index e = 16 (I - J) + r - (4 ks + kq) + 16 Jn - 1,
+    // in [0, 16 Jn + 255) for every output row and position
+    const double* bx = sx + kq * 16 + r;
+    const cd* ac = sc + 64 * w + r - kq + 16 * Jn - 1;
     for (int J = 0; J < Jn; ++J) {
+        const double* bxj = bx + 16 * 16 * J;
+        const cd* acj = ac - 16 * J;
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
-            const int kk = 4 * ks + kq;              // source 16 J + kk: B[kq][col r]
 #pragma unroll
             for (int side = 0; side < 2; ++side) {
                 if (side == 0 ? sl < 0 : sr < 0) continue;
-                const double bv = sx[(side * kLttStage + 16 * J + kk) * 16 + r];
+                const double bv = bxj[(side * kLttStage + 4 * ks) * 16];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    const int I = 4 * w + i;
-                    // A[row r][kq]: lag of output 16 I + r and source 16 J + kk
-                    const int e = 16 * (I - J) + r - kk + slen - 1;
-                    cd av = mk(0, 0);
-                    if (e >= 0 && e < 2 * kLttStage) av = sc[side * 2 * kLttStage + e];
+                    const cd av = acj[side * kLttScLen + 16 * i - 4 * ks];
                     d1[i] = mfma16(av.x, bv, d1[i]);
                     d2[i] = mfma16(av.y, bv, d2[i]);
                 }
@@ -323,7 +330,7 @@ hipError_t launch_ltt(const LttArgs& a, hipStream_t st) {
     if ((size_t)a.B * nseg > 65535) return hipErrorInvalidValue;
     const int slen_max = a.s_seg > 0 ? std::min(a.s_seg, a.s_hi - a.s_lo) : a.s_hi - a.s_lo;
     if (a.B >= kLttBatch && !a.per_problem && a.n_hi - a.n_lo <= kLttStage && slen_max <= kLttStage) {
-        const size_t lds = sizeof(double) * 2 * kLttStage * 16 + sizeof(cd) * 2 * 2 * kLttStage;
+        const size_t lds = sizeof(double) * 2 * kLttStage * 16 + sizeof(cd) * 2 * kLttScLen;
         dim3 grid(a.ns, (a.B + kLttBatch - 1) / kLttBatch, nseg);
         ltt_batch_kernel<<<grid, 256, lds, st>>>(a);
         return hipGetLastError();
