@@ -224,6 +224,7 @@ __global__ __launch_bounds__(256) void ltt_mfma_kernel(LttArgs a) {
 // of eight or more problems and the same problem alone agree to rounding.
 // ---------------------------------------------------------------------------
 constexpr int kLttBatch = 8;      // problems per workgroup of the batched form
+static_assert(2 * kLttBatch == 16, "the 16 columns of a tile are 8 problems x (re, im)");
 constexpr int kLttScLen = 2 * kLttStage;   // coefficient window per side
 
 __device__ inline double swap_pair(double v) {   // the value of lane l ^ 1
@@ -248,18 +249,22 @@ __global__ __launch_bounds__(256) void ltt_batch_kernel(LttArgs a) {
     slot_sources(o, a.N, k, pl, pr, sl, sr);
     const cd* cl = a.cols + ((size_t)k * 4 + pl) * a.nt;
     const cd* cr = a.cols + ((size_t)k * 4 + pr) * a.nt;
-    // sources: thread tid stages position tid = source tid - pad0 of every
-    // problem and side, positions below pad0 zero
-    const int Jn = (slen + 15) / 16, pad0 = 16 * Jn - slen, src = tid - pad0;
-    for (int side = 0; side < 2; ++side) {
-        const int srow = side ? sr : sl;
+    // sources: position p of a side holds source p - pad0 of the eight
+    // problems (positions below pad0 zero) as 8 complex values in a row; item
+    // u = (side, p, bb) goes to thread u mod 256, so a wave writes one
+    // contiguous 1 KiB span of LDS
+    const int Jn = (slen + 15) / 16, pad0 = 16 * Jn - slen;
+    {
+        cd* sxc = reinterpret_cast<cd*>(sx);
+        const int bb = tid & (kLttBatch - 1), b = b0 + bb;
 #pragma unroll
-        for (int bb = 0; bb < kLttBatch; ++bb) {
-            const int b = b0 + bb;
+        for (int it = 0; it < 2 * kLttStage * kLttBatch / 256; ++it) {
+            const int u = it * 256 + tid, side = u / (kLttStage * kLttBatch);
+            const int pos = (u / kLttBatch) % kLttStage, src = pos - pad0;
+            const int srow = side ? sr : sl;
             cd x = mk(0, 0);
             if (srow >= 0 && b < a.B && src >= 0 && src < slen) x = a.x[((size_t)b * a.ns + srow) * a.nt + s_lo + src];
-            sx[(side * kLttStage + tid) * 16 + 2 * bb] = x.x;
-            sx[(side * kLttStage + tid) * 16 + 2 * bb + 1] = x.y;
+            sxc[u] = x;
         }
     }
     // coefficients: lags lag0 + e, e < nlen + slen - 1
@@ -289,7 +294,9 @@ __global__ __launch_bounds__(256) void ltt_batch_kernel(LttArgs a) {
         for (int ks = 0; ks < 4; ++ks) {
 #pragma unroll
             for (int side = 0; side < 2; ++side) {
-                if (side == 0 ? sl < 0 : sr < 0) continue;
+                // a side without a neighbour has zero sources and
+                // coefficients: no branch here, which would move the
+                // accumulators out of the matrix registers around it
                 const double bv = bxj[(side * kLttStage + 4 * ks) * 16];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
