@@ -25,6 +25,11 @@ FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     # no packed FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # matrix-instruction accumulators in ordinary VGPRs: with the AGPR form the
+    # compiler keeps loop-carried accumulators in VGPRs and copies them to and
+    # from AGPRs around every instruction group (two moves per register per
+    # loop trip in the interface and far-history products)
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-Wno-unused-command-line-argument",
     "-I", INC, "-I", CSRC,
 ]
