@@ -46,8 +46,9 @@ sys.path.insert(0, ROOT)
 
 # FP64 peak of the MI355X vector ALUs (published): 78.6 TFLOP/s
 PEAK_FP64_TFLOPS = 78.6
-# the oracle's CPU sample: the first CPU_STEPS steps of member 0
-CPU_STEPS = 500
+# the oracle's CPU sample: whole monodomain solves of batch members 0, 1, ...
+# until at least CPU_MIN_S seconds of CPU work
+CPU_MIN_S = 10.0
 
 
 FAR_SUPER = 256   # super-chunk of the S0^2 far history (kFarSuper in the library)
@@ -112,13 +113,16 @@ SWEEP_SOURCES = ("paper_1503_02564_amd/csrc/swr_sweep_kernel.h", "paper_1503_025
                  "paper_1503_02564_amd/csrc/swr_sweep_static.hip",
                  "paper_1503_02564_amd/csrc/swr_sweep_static_s02.hip",
                  "paper_1503_02564_amd/csrc/swr_sweep_group.hip",
-                 "paper_1503_02564_amd/csrc/swr_sweep.hip")
+                 "paper_1503_02564_amd/csrc/swr_sweep.hip",
+                 "paper_1503_02564_amd/csrc/swr_common.h",
+                 "paper_1503_02564_amd/build.py")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_kernel_batched_uneven_hbm.txt")
 
 
 def sweep_source_hash() -> str:
-    """sha256 over the sources of the static sweep kernel: a traffic figure
-    measured on other sources is not reported."""
+    """sha256 over the sources and build flags of the static sweep kernel and
+    the far-history product between its launches: a traffic figure measured
+    on other code is not reported."""
     import hashlib
     h = hashlib.sha256()
     for rel in SWEEP_SOURCES:
@@ -204,23 +208,24 @@ def cpu_info():
 def cpu_baseline(wl):
     """The oracle as it stands: its monodomain Crank-Nicolson solve (the
     definition every decomposed solve converges to; the paper's T_ref, Sec. 6)
-    of batch member 0 over its first CPU_STEPS steps, single-threaded on one
+    of batch members 0, 1, ... over all steps, one member after the other
+    until at least CPU_MIN_S seconds have passed, single-threaded on one
     pinned host core (the C core is single-threaded)."""
-    import copy
     import oracle as O
     try:
         os.sched_setaffinity(0, {sorted(os.sched_getaffinity(0))[0]})
     except (AttributeError, OSError):
         pass
-    w = copy.copy(wl)
-    w.nt = CPU_STEPS
+    members = 0
     t0 = time.perf_counter()
-    O.mono(w, wl.u0[0])
+    while members < wl.B and (members == 0 or time.perf_counter() - t0 < CPU_MIN_S):
+        O.mono(wl, wl.u0[members])
+        members += 1
     dt = time.perf_counter() - t0
     model, ncpu = cpu_info()
-    return dict(value=wl.nx * CPU_STEPS / dt, unit="pt-steps/s", cores=1, kind="oracle",
-                sample=f"monodomain Crank-Nicolson (the paper's T_ref) of batch member 0, "
-                       f"first {CPU_STEPS} of {wl.nt} steps ({wl.nx} nodes), {dt:.2f} s, "
+    return dict(value=wl.nx * wl.nt * members / dt, unit="pt-steps/s", cores=1, kind="oracle",
+                sample=f"monodomain Crank-Nicolson (the paper's T_ref) of batch members "
+                       f"0..{members - 1}, all {wl.nt} steps each ({wl.nx} nodes), {dt:.2f} s, "
                        f"one pinned core",
                 cpu_model=model, nproc=ncpu)
 
