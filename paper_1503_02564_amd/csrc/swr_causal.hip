@@ -21,7 +21,7 @@
 // super-block to the outputs being solved is formed by one block-Toeplitz
 // product on the matrix cores (launch_ltt).  `causal_far_kernel` adds to d that product and
 // the contribution of the earlier blocks of the current super-block (a short
-// rectangle, one workgroup per output slot);
+// rectangle, one workgroup per subdomain and pair of problems);
 // `causal_near_kernel` then
 // marches through the block on one workgroup per problem: wave 0 runs the
 // per-step PCR solve and adds the lag-1 and lag-2 history, while the other
@@ -143,95 +143,212 @@ struct FarArgs {
                        // super-block to steps s_from .. s_from + kCausalSuper - 1
     int nseg;          // number of finished super-blocks (facc null when 0)
     int s_from;        // this kernel sums steps s_from <= s < n0
+    int B;             // problems
 };
 
-// one workgroup per (slot, problem); thread (i, split): output step n0+i,
-// inputs s in the split's share of [s_from, n0).  out = d + that
-// contribution.  The two source rows over [s_from, n0) and the coefficient
-// window they meet (lags 1 .. n0 + TB - s_from) are first staged in LDS with
-// coalesced loads by the whole workgroup (the range is less than one 256-step
-// super-block), so the sums read no memory; each thread's order of terms is
-// the same as reading them from memory.
+// One workgroup per (subdomain k, kFarPb problems).  Subdomain k feeds the
+// output slots 2k - 2 (if k >= 1) and 2k + 1 (if k <= N - 2); both read the
+// same two source rows, g of slots 2k - 1 and 2k, and with one potential the
+// problems read the same coefficients, so each row is staged in LDS once for
+// all its readers.  Thread (h, bb, split, i): output step n0 + i of slot
+// 2k - 2 (h = 0) or 2k + 1 (h = 1) for problem b0 + bb, inputs s in the
+// split's share of [s_from, n0).  out = d + the finished super-blocks'
+// partials + that contribution.  The source rows over [s_from, n0) and the
+// coefficient window they meet (lags 1 .. n0 + TB - s_from) are staged with
+// coalesced loads (the range is less than one 256-step super-block).  Per
+// output, the source split, the order of terms in each partial sum and the
+// order in which the partials are added depend on TB and the range only.
+constexpr int kFarPb = 2;                     // problems per workgroup
 template <int TB>
-__global__ __launch_bounds__(256) void causal_far_kernel(FarArgs f) {
+__global__ __launch_bounds__(2 * kFarPb * 256) void causal_far_kernel(FarArgs f) {
     constexpr int SPLITS = 256 / TB;
     constexpr int kWin = kCausalSuper + TB;
-    __shared__ cd part[SPLITS][TB];
-    __shared__ cd sg[2][kCausalSuper], sc[2][kWin];
-    const int o = blockIdx.x, b = blockIdx.y;
-    const int i = threadIdx.x % TB, sp = threadIdx.x / TB;
-    int k, pl, pr, sl, sr;
-    slot_src(o, f.N, k, pl, pr, sl, sr);
-    const int v = f.per_problem ? b : 0;
-    const cd* cl = f.cols + ((size_t)(v * f.N + k) * 4 + pl) * f.nt;
-    const cd* cr = f.cols + ((size_t)(v * f.N + k) * 4 + pr) * f.nt;
-    const cd* gl = sl >= 0 ? f.g + ((size_t)b * f.ns + sl) * f.nt : nullptr;
-    const cd* gr = sr >= 0 ? f.g + ((size_t)b * f.ns + sr) * f.nt : nullptr;
-    const int len = f.n0 - f.s_from;                 // < kCausalSuper
+    constexpr int NT = 2 * kFarPb * 256;
+    __shared__ cd part[2][kFarPb][SPLITS][TB];
+    __shared__ cd sg[2][kFarPb][kCausalSuper];
+    __shared__ cd sc[kFarPb][4][kWin];       // [problem or 0][coefficient row p][lag]
+    const int k = blockIdx.x, b0 = blockIdx.y * kFarPb, t = threadIdx.x;
+    const int i = t % TB, sp = (t / TB) % SPLITS, bb = (t / 256) % kFarPb, h = t / (256 * kFarPb);
+    const bool hasl = k >= 1, hasr = k <= f.N - 2;      // source rows 2k - 1, 2k
+    const bool act = h == 0 ? hasl : hasr;              // output slot exists
+    const int o = h == 0 ? 2 * k - 2 : 2 * k + 1;
+    const int b = b0 + bb;
+    const int len = f.n0 - f.s_from;                    // < kCausalSuper
     const int n = f.n0 + i;
+    const bool out_ok = act && b < f.B && i < f.nb;
     // d plus the finished super-blocks' partials, in that order, loaded
     // before the staging so their latency overlaps it
     cd r = mk(0, 0);
-    if (sp == 0 && i < f.nb) {
+    if (out_ok && sp == 0) {
         r = f.d[((size_t)b * f.ns + o) * f.nt + n];
-        const size_t seg_stride = (size_t)gridDim.y * f.ns * kCausalSuper;
+        const size_t seg_stride = (size_t)f.B * f.ns * kCausalSuper;
         const cd* fp = f.facc + ((size_t)b * f.ns + o) * kCausalSuper + (n - f.s_from);
         for (int q = 0; q < f.nseg; ++q) r = r + fp[q * seg_stride];
     }
-    // lags n - s for n in [n0, n0 + TB), s in [s_from, n0): 1 .. len + TB - 1.
-    // 256 threads: one source and at most two coefficient entries each, all
-    // loaded before any is stored
-    static_assert(kCausalSuper == 256 && TB <= 256, "far kernel staging: two rounds of 256");
-    const int e0 = threadIdx.x, e1 = threadIdx.x + 256;
-    cd x0 = mk(0, 0), x1 = mk(0, 0), c0 = mk(0, 0), c1 = mk(0, 0), c2 = mk(0, 0), c3 = mk(0, 0);
-    if (e0 < len) {
-        if (gl) x0 = gl[f.s_from + e0];
-        if (gr) x1 = gr[f.s_from + e0];
+    // sources: thread t stages entry e of row q for problem bq (one each);
+    // coefficients: row p of subdomain k (p = 0, 1: slot 2k - 2 with the left,
+    // right source; p = 2, 3: slot 2k + 1), one copy per problem if each has
+    // its own potential.  All loads are issued before any store.
+    static_assert(kCausalSuper == 256 && TB <= 256, "far kernel staging: one source entry per thread");
+    constexpr int kCoef = kFarPb * 4 * kWin, kCoefTrips = (kCoef + NT - 1) / NT;
+    const int nc = f.per_problem ? kCoef : 4 * kWin;
+    cd x = mk(0, 0), c[kCoefTrips];
+    {
+        const int q = t / (kFarPb * 256), bq = (t / 256) % kFarPb, e = t % 256;
+        if ((q == 0 ? hasl : hasr) && b0 + bq < f.B && e < len)
+            x = f.g[((size_t)(b0 + bq) * f.ns + 2 * k - 1 + q) * f.nt + f.s_from + e];
     }
-    if (e0 < len + TB && e0 < f.nt) {
-        if (gl) c0 = cl[e0];
-        if (gr) c1 = cr[e0];
+#pragma unroll
+    for (int m = 0; m < kCoefTrips; ++m) {
+        const int u = t + m * NT, cb = u / (4 * kWin), p = (u / kWin) % 4, e = u % kWin;
+        const bool row_ok = (p == 0 || p == 2 ? hasl : hasr) && (p < 2 ? hasl : hasr);
+        const int v = f.per_problem ? b0 + cb : 0;
+        c[m] = mk(0, 0);
+        if (u < nc && row_ok && e < len + TB && e < f.nt && (!f.per_problem || v < f.B))
+            c[m] = f.cols[((size_t)(v * f.N + k) * 4 + p) * f.nt + e];
     }
-    if (e1 < len + TB && e1 < f.nt) {
-        if (gl) c2 = cl[e1];
-        if (gr) c3 = cr[e1];
-    }
-    if (e0 < len) {
-        sg[0][e0] = x0;
-        sg[1][e0] = x1;
-    }
-    if (e0 < len + TB) {
-        sc[0][e0] = c0;
-        sc[1][e0] = c1;
-    }
-    if (e1 < len + TB) {
-        sc[0][e1] = c2;
-        sc[1][e1] = c3;
+    (&sg[0][0][0])[t] = x;
+#pragma unroll
+    for (int m = 0; m < kCoefTrips; ++m) {
+        const int u = t + m * NT;
+        if (u < nc) (&sc[0][0][0])[u] = c[m];
     }
     __syncthreads();
     const int per = (len + SPLITS - 1) / SPLITS;
     const int s_lo = f.s_from + sp * per, s_hi = min(f.n0, s_lo + per);
+    const cd* cl = sc[f.per_problem ? bb : 0][2 * h];
+    const cd* cr = sc[f.per_problem ? bb : 0][2 * h + 1];
     double ax = 0, ay = 0;
-    if (i < f.nb) {
+    if (out_ok) {
         for (int s = s_lo; s < s_hi; ++s) {
             const int e = s - f.s_from, lag = n - s;
-            if (gl) {
-                const cd c = sc[0][lag], x = sg[0][e];
-                ax += c.x * x.x - c.y * x.y;
-                ay += c.x * x.y + c.y * x.x;
+            if (hasl) {
+                const cd cc = cl[lag], xx = sg[0][bb][e];
+                ax += cc.x * xx.x - cc.y * xx.y;
+                ay += cc.x * xx.y + cc.y * xx.x;
             }
-            if (gr) {
-                const cd c = sc[1][lag], x = sg[1][e];
-                ax += c.x * x.x - c.y * x.y;
-                ay += c.x * x.y + c.y * x.x;
+            if (hasr) {
+                const cd cc = cr[lag], xx = sg[1][bb][e];
+                ax += cc.x * xx.x - cc.y * xx.y;
+                ay += cc.x * xx.y + cc.y * xx.x;
             }
         }
     }
-    part[sp][i] = mk(ax, ay);
+    part[h][bb][sp][i] = mk(ax, ay);
     __syncthreads();
-    if (sp == 0 && i < f.nb) {
-        for (int q = 0; q < SPLITS; ++q) r = r + part[q][i];
+    if (out_ok && sp == 0) {
+        for (int q = 0; q < SPLITS; ++q) r = r + part[h][bb][q][i];
         f.out[((size_t)b * f.ns + o) * TB + i] = r;
+    }
+}
+
+// Matrix-core form of the same sums for a batch with one potential (at least
+// 8 problems, TB = 8 or 32).  One wave per (subdomain k, 8 problems): the
+// rows of the product are the block's TB outputs of the two slots subdomain
+// k feeds (slot 2k - 2, then slot 2k + 1: 2 TB rows in 16-row blocks), the
+// columns the 8 problems' real and imaginary parts, and K runs over the
+// sources s in [s_from, n0) of the left row (g of slot 2k - 1), then of the
+// right row (slot 2k), four per instruction.  Two accumulators per row block
+// collect Re C [Re x | Im x] and Im C [Re x | Im x]; neighbouring lanes
+// combine them (Re y = Re C Re x - Im C Im x, Im y = Re C Im x + Im C Re x).
+// At N = 500, B = 32 a launch has 2000 waves where the form above has
+// 128000, so it finds room quickly beside the sweeps that run concurrently
+// on the other streams.  Per output: d, the finished super-blocks' partials,
+// then the product (sources ascending in fours, left row before right).
+typedef double fd4 __attribute__((ext_vector_type(4)));
+static __device__ inline fd4 far_mfma(double a, double b, fd4 c) {
+    // lane l supplies A[l%16][l/16] and B[l/16][l%16]; accumulator register
+    // q of lane l is D[l/16 + 4q][l%16]
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+static __device__ inline double far_swap_pair(double v) {   // the value of lane l ^ 1
+    int2 t = *reinterpret_cast<int2*>(&v);
+    t.x = __builtin_amdgcn_mov_dpp(t.x, 0xB1, 0xf, 0xf, false);   // quad_perm [1,0,3,2]
+    t.y = __builtin_amdgcn_mov_dpp(t.y, 0xB1, 0xf, 0xf, false);
+    return *reinterpret_cast<double*>(&t);
+}
+constexpr int kFarMfmaB = 8;    // problems per wave of the matrix-core form
+
+template <int TB>
+__global__ __launch_bounds__(64) void causal_far_mfma_kernel(FarArgs f) {
+    static_assert((2 * TB) % 16 == 0, "whole 16-row blocks");
+    constexpr int RB = 2 * TB / 16;
+    const int k = blockIdx.x, b0 = blockIdx.y * kFarMfmaB;
+    const int lane = threadIdx.x, r = lane & 15, kq = lane >> 4;
+    const bool hasl = k >= 1, hasr = k <= f.N - 2;       // source rows 2k - 1, 2k
+    const cd* crow = f.cols + (size_t)k * 4 * f.nt;       // coefficient rows p = 0..3
+    // B operand column r: problem b0 + r / 2, real (r even) or imaginary part
+    const int bcol = b0 + (r >> 1), part = r & 1;
+    const bool col_ok = bcol < f.B;
+    fd4 d1[RB], d2[RB];
+#pragma unroll
+    for (int I = 0; I < RB; ++I) {
+        d1[I] = fd4{0.0, 0.0, 0.0, 0.0};
+        d2[I] = fd4{0.0, 0.0, 0.0, 0.0};
+    }
+    // operands of U k-steps are loaded one group ahead of the instructions
+    // that use them (k-steps past the range load zeros)
+    constexpr int U = RB == 1 ? 4 : 2;
+    const int nblk = (f.n0 - f.s_from + 3) / 4;
+    for (int side = 0; side < 2; ++side) {
+        if (side == 0 ? !hasl : !hasr) continue;          // uniform over the wave
+        const double* gs = reinterpret_cast<const double*>(
+                               f.g + ((size_t)(col_ok ? bcol : 0) * f.ns + 2 * k - 1 + side) * f.nt) + part;
+        double bv[2][U];
+        cd av[2][U][RB];
+        auto fetch = [&](int buf, int j0) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int s = f.s_from + 4 * (j0 + u) + kq;
+                const bool s_ok = s < f.n0;
+                bv[buf][u] = (col_ok && s_ok) ? gs[2 * (size_t)s] : 0.0;
+#pragma unroll
+                for (int I = 0; I < RB; ++I) {
+                    // A row r of block I: output R = 16 I + r, slot h = R / TB,
+                    // step i = R % TB
+                    const int R = 16 * I + r, h = R / TB, lag = f.n0 + R % TB - s;
+                    const bool a_ok = s_ok && (h == 0 ? hasl : hasr) && lag < f.nt;
+                    av[buf][u][I] = a_ok ? crow[(size_t)(2 * h + side) * f.nt + lag] : mk(0, 0);
+                }
+            }
+        };
+        auto apply = [&](int buf) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+#pragma unroll
+                for (int I = 0; I < RB; ++I) {
+                    d1[I] = far_mfma(av[buf][u][I].x, bv[buf][u], d1[I]);
+                    d2[I] = far_mfma(av[buf][u][I].y, bv[buf][u], d2[I]);
+                }
+            }
+        };
+        fetch(0, 0);
+        for (int j0 = 0; j0 < nblk; j0 += 2 * U) {
+            fetch(1, j0 + U);
+            apply(0);
+            if (j0 + U >= nblk) break;
+            fetch(0, j0 + 2 * U);
+            apply(1);
+        }
+    }
+    const size_t seg_stride = (size_t)f.B * f.ns * kCausalSuper;
+#pragma unroll
+    for (int I = 0; I < RB; ++I) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double other = far_swap_pair(d2[I][q]);
+            const double v = part ? d1[I][q] + other : d1[I][q] - other;
+            const int R = 16 * I + kq + 4 * q, h = R / TB, i = R % TB;
+            if (col_ok && (h == 0 ? hasl : hasr) && i < f.nb) {
+                const int o = h == 0 ? 2 * k - 2 : 2 * k + 1, n = f.n0 + i;
+                const size_t row = (size_t)bcol * f.ns + o;
+                double acc = reinterpret_cast<const double*>(f.d + row * f.nt + n)[part];
+                for (int q2 = 0; q2 < f.nseg; ++q2)
+                    acc += reinterpret_cast<const double*>(f.facc + q2 * seg_stride + row * kCausalSuper +
+                                                           (n - f.s_from))[part];
+                reinterpret_cast<double*>(f.out + row * TB + i)[part] = acc + v;
+            }
+        }
     }
 }
 
@@ -538,9 +655,16 @@ static hipError_t launch_causal_far(int N, int nt, int ns, int B, int per_proble
                                     const cd* facc, int s_from, hipStream_t st) {
     // the staged rows hold less than one super-block of sources
     if (n0 - s_from < 0 || n0 - s_from >= kCausalSuper) return hipErrorInvalidValue;
+    if (ns != 2 * (N - 1)) return hipErrorInvalidValue;
     FarArgs f{N, nt, ns, per_problem, n0, nb, cols, d, g, out, facc,
-              facc ? s_from / kCausalSuper : 0, s_from};
-    causal_far_kernel<TB><<<dim3(ns, B), 256, 0, st>>>(f);
+              facc ? s_from / kCausalSuper : 0, s_from, B};
+    if constexpr (TB == 8 || TB == 32) {
+        if (!per_problem && B >= kFarMfmaB) {
+            causal_far_mfma_kernel<TB><<<dim3(N, (B + kFarMfmaB - 1) / kFarMfmaB), 64, 0, st>>>(f);
+            return hipGetLastError();
+        }
+    }
+    causal_far_kernel<TB><<<dim3(N, (B + kFarPb - 1) / kFarPb), 2 * kFarPb * 256, 0, st>>>(f);
     return hipGetLastError();
 }
 

@@ -320,6 +320,43 @@ def test_batch_and_per_problem_potentials(dev):
     pb.close()
 
 
+@pytest.mark.parametrize("label,J", [
+    ("32-step blocks", [60, 80, 70, 45, 90]),                      # up to 64 interfaces
+    ("8-step blocks", list(np.random.default_rng(5).integers(8, 15, 80))),   # more than 64
+])
+def test_batch_far_history_on_matrix_cores(dev, label, J):
+    """Eleven problems with one potential: the causal solve forms the far
+    part of each time block on the matrix cores for a full group of eight
+    problems and a ragged group of three, over 300 steps (one finished
+    256-step super-block).  u(T) of every member against the monodomain
+    oracle, and against the same member solved alone (where the far part is
+    summed one term per thread) to rounding."""
+    import torch
+    from paper_1503_02564_amd import swr
+    B, nt = 11, 300
+    wl = W.small_case(J=J, nt=nt, trans=W.S02, sigma=0j, B=B, seed=31, a0=-12.0, b0=12.0)
+    say("far part on matrix cores", label, "N", wl.N, "B", B)
+    pb = make_problem(wl, solver=swr.SWR_SOLVER_CAUSAL)
+    uT = torch.zeros((B, wl.nx), dtype=torch.complex128, device=dev)
+    st, info = swr.swr_solve(pb.ctx, to_dev(wl.u0), uT)
+    torch.cuda.synchronize()
+    assert st == swr.SWR_OK and info.residual < 1e-11
+    pb.close()
+    got = to_np(uT)
+    for b in (0, 7, 8, 10):
+        wb = W.Workload(wl.name, wl.a0, wl.b0, wl.J, wl.dt, wl.nt, wl.vkind, wl.V, wl.trans,
+                        wl.sigma, wl.u0[b:b + 1])
+        assert rel(got[b], O.mono(wb, wl.u0[b])) < 1e-10
+        say("far part on matrix cores", label, "member alone", b)
+        p1 = make_problem(wb, solver=swr.SWR_SOLVER_CAUSAL)
+        u1 = torch.zeros((1, wl.nx), dtype=torch.complex128, device=dev)
+        st, info = swr.swr_solve(p1.ctx, to_dev(wl.u0[b:b + 1]), u1)
+        torch.cuda.synchronize()
+        assert st == swr.SWR_OK
+        p1.close()
+        assert rel(got[b], to_np(u1)[0]) < 1e-12
+
+
 @pytest.mark.parametrize("J,nt", [([50], 33), ([300], 70), ([20, 20], 1)])
 def test_edge_cases(dev, J, nt):
     """One subdomain (no interface), one time step."""
