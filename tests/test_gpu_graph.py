@@ -17,6 +17,8 @@ GRAPH_CASES = [
     ("s02-pipelined", [60, 90, 75, 128, 200, 47, 250], 300, W.S02, 0j, 4, 64),
     ("robin-staged", [50, 70, 300, 33], 200, W.ROBIN, 1 - 1j, 3, 0),
     ("s02-staged-wide", [40] * 70, 160, W.S02, 0j, 2, 0),       # 69 interfaces: workgroup PCR
+    # two finished 256-step super-blocks of the causal solve's far history
+    ("s02-pipelined-long", [60, 90, 75, 128, 47], 600, W.S02, 0j, 2, 256),
 ]
 
 
