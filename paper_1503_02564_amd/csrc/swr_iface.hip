@@ -61,8 +61,12 @@ __device__ inline d4 mfma16(double a, double b, d4 c) {
 // for longer ranges by the order of the sum.
 constexpr int kLttStage = 256;
 
+// staged sources: entry e at e + e / 16, so the 16 B-operand lanes of one
+// instruction (sources 16 apart) fall in different LDS banks
+__device__ inline int ltt_xpad(int e) { return e + (e >> 4); }
+
 __global__ __launch_bounds__(256) void ltt_mfma_kernel(LttArgs a) {
-    __shared__ cd st_x[2][kLttStage], st_c[2][2 * kLttStage];
+    __shared__ cd st_x[2][kLttStage + kLttStage / 16], st_c[2][2 * kLttStage];
     __shared__ d4 red[4][2][kWave];               // staged form: the waves' accumulators
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const int tile = blockIdx.x * 4 + w;
@@ -91,8 +95,8 @@ __global__ __launch_bounds__(256) void ltt_mfma_kernel(LttArgs a) {
             cd x0 = mk(0, 0), x1 = mk(0, 0);
             if (xl && e < slen0) x0 = xl[e];
             if (xr && e < slen0) x1 = xr[e];
-            st_x[0][e] = x0;
-            st_x[1][e] = x1;
+            st_x[0][ltt_xpad(e)] = x0;
+            st_x[1][ltt_xpad(e)] = x1;
         }
         for (int e = threadIdx.x; e < 2 * kLttStage; e += blockDim.x) {
             const int lag = lag0 + e;
@@ -154,7 +158,7 @@ __global__ __launch_bounds__(256) void ltt_mfma_kernel(LttArgs a) {
             if (xl) {
                 cd av = mk(0, 0), bv = mk(0, 0);
                 if (lok) av = st_c[0][le];
-                if (sok) bv = st_x[0][si];
+                if (sok) bv = st_x[0][ltt_xpad(si)];
                 ar0 = mfma16(av.x, bv.x, ar0);
                 ar0 = mfma16(-av.y, bv.y, ar0);
                 ai0 = mfma16(av.x, bv.y, ai0);
@@ -163,7 +167,7 @@ __global__ __launch_bounds__(256) void ltt_mfma_kernel(LttArgs a) {
             if (xr) {
                 cd av = mk(0, 0), bv = mk(0, 0);
                 if (lok) av = st_c[1][le];
-                if (sok) bv = st_x[1][si];
+                if (sok) bv = st_x[1][ltt_xpad(si)];
                 ar1 = mfma16(av.x, bv.x, ar1);
                 ar1 = mfma16(-av.y, bv.y, ar1);
                 ai1 = mfma16(av.x, bv.y, ai1);
