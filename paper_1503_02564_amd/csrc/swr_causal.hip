@@ -21,7 +21,9 @@
 // super-block to the outputs being solved is formed by one block-Toeplitz
 // product on the matrix cores (launch_ltt).  `causal_far_kernel` adds to d that product and
 // the contribution of the earlier blocks of the current super-block (a short
-// rectangle, one workgroup per subdomain and pair of problems);
+// rectangle, one workgroup per subdomain and pair of problems; for a batch of
+// eight or more problems with one potential `causal_far_mfma_kernel`, one
+// wave per subdomain and eight problems on the matrix cores);
 // `causal_near_kernel` then
 // marches through the block on one workgroup per problem: wave 0 runs the
 // per-step PCR solve and adds the lag-1 and lag-2 history, while the other
