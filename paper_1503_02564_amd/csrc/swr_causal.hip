@@ -148,7 +148,7 @@ struct FarArgs {
     int B;             // problems
 };
 
-// One workgroup per (subdomain k, kFarPb problems).  Subdomain k feeds the
+// One workgroup per (subdomain k, PB problems).  Subdomain k feeds the
 // output slots 2k - 2 (if k >= 1) and 2k + 1 (if k <= N - 2); both read the
 // same two source rows, g of slots 2k - 1 and 2k, and with one potential the
 // problems read the same coefficients, so each row is staged in LDS once for
@@ -160,17 +160,17 @@ struct FarArgs {
 // coalesced loads (the range is less than one 256-step super-block).  Per
 // output, the source split, the order of terms in each partial sum and the
 // order in which the partials are added depend on TB and the range only.
-constexpr int kFarPb = 2;                     // problems per workgroup
-template <int TB>
-__global__ __launch_bounds__(2 * kFarPb * 256) void causal_far_kernel(FarArgs f) {
+// PB problems per workgroup: 2, or 1 for a single problem (no idle half)
+template <int TB, int PB>
+__global__ __launch_bounds__(2 * PB * 256) void causal_far_kernel(FarArgs f) {
     constexpr int SPLITS = 256 / TB;
     constexpr int kWin = kCausalSuper + TB;
-    constexpr int NT = 2 * kFarPb * 256;
-    __shared__ cd part[2][kFarPb][SPLITS][TB];
-    __shared__ cd sg[2][kFarPb][kCausalSuper];
-    __shared__ cd sc[kFarPb][4][kWin];       // [problem or 0][coefficient row p][lag]
-    const int k = blockIdx.x, b0 = blockIdx.y * kFarPb, t = threadIdx.x;
-    const int i = t % TB, sp = (t / TB) % SPLITS, bb = (t / 256) % kFarPb, h = t / (256 * kFarPb);
+    constexpr int NT = 2 * PB * 256;
+    __shared__ cd part[2][PB][SPLITS][TB];
+    __shared__ cd sg[2][PB][kCausalSuper];
+    __shared__ cd sc[PB][4][kWin];       // [problem or 0][coefficient row p][lag]
+    const int k = blockIdx.x, b0 = blockIdx.y * PB, t = threadIdx.x;
+    const int i = t % TB, sp = (t / TB) % SPLITS, bb = (t / 256) % PB, h = t / (256 * PB);
     const bool hasl = k >= 1, hasr = k <= f.N - 2;      // source rows 2k - 1, 2k
     const bool act = h == 0 ? hasl : hasr;              // output slot exists
     const int o = h == 0 ? 2 * k - 2 : 2 * k + 1;
@@ -192,11 +192,11 @@ __global__ __launch_bounds__(2 * kFarPb * 256) void causal_far_kernel(FarArgs f)
     // right source; p = 2, 3: slot 2k + 1), one copy per problem if each has
     // its own potential.  All loads are issued before any store.
     static_assert(kCausalSuper == 256 && TB <= 256, "far kernel staging: one source entry per thread");
-    constexpr int kCoef = kFarPb * 4 * kWin, kCoefTrips = (kCoef + NT - 1) / NT;
+    constexpr int kCoef = PB * 4 * kWin, kCoefTrips = (kCoef + NT - 1) / NT;
     const int nc = f.per_problem ? kCoef : 4 * kWin;
     cd x = mk(0, 0), c[kCoefTrips];
     {
-        const int q = t / (kFarPb * 256), bq = (t / 256) % kFarPb, e = t % 256;
+        const int q = t / (PB * 256), bq = (t / 256) % PB, e = t % 256;
         if ((q == 0 ? hasl : hasr) && b0 + bq < f.B && e < len)
             x = f.g[((size_t)(b0 + bq) * f.ns + 2 * k - 1 + q) * f.nt + f.s_from + e];
     }
@@ -666,7 +666,8 @@ static hipError_t launch_causal_far(int N, int nt, int ns, int B, int per_proble
             return hipGetLastError();
         }
     }
-    causal_far_kernel<TB><<<dim3(N, (B + kFarPb - 1) / kFarPb), 2 * kFarPb * 256, 0, st>>>(f);
+    if (B == 1) causal_far_kernel<TB, 1><<<dim3(N, 1), 2 * 256, 0, st>>>(f);
+    else causal_far_kernel<TB, 2><<<dim3(N, (B + 1) / 2), 2 * 2 * 256, 0, st>>>(f);
     return hipGetLastError();
 }
 
