@@ -280,6 +280,9 @@ __global__ __launch_bounds__(256) void ltt_batch_kernel(LttArgs a) {
         sc[kLttScLen + e] = (ok && sr >= 0) ? cr[lag] : mk(0, 0);
     }
     __syncthreads();
+    // a wave whose four output blocks all lie past the call's range (a short
+    // last piece of the solve) has nothing to write; no barrier follows
+    if (64 * w >= nlen) return;
     d4 d1[4], d2[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
