@@ -115,14 +115,16 @@ SWEEP_SOURCES = ("paper_1503_02564_amd/csrc/swr_sweep_kernel.h", "paper_1503_025
                  "paper_1503_02564_amd/csrc/swr_sweep_group.hip",
                  "paper_1503_02564_amd/csrc/swr_sweep.hip",
                  "paper_1503_02564_amd/csrc/swr_common.h",
+                 "paper_1503_02564_amd/csrc/swr_host.hip",
                  "paper_1503_02564_amd/build.py")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_kernel_batched_uneven_hbm.txt")
 
 
 def sweep_source_hash() -> str:
     """sha256 over the sources and build flags of the static sweep kernel and
-    the far-history product between its launches: a traffic figure measured
-    on other code is not reported."""
+    the far-history product between its launches, and the host code that
+    cuts the launches: a traffic figure measured on other code is not
+    reported."""
     import hashlib
     h = hashlib.sha256()
     for rel in SWEEP_SOURCES:

@@ -155,9 +155,9 @@ PIPE_CASES = [
 
 def _pipeline_chunks(nt, ch):
     """Time chunks of the pipelined solve: a 64-step first chunk, then
-    multiples of ch, and a short last chunk ending at nt."""
+    multiples of ch up to nt."""
     cut = [0]
-    for x in [64] + list(range(ch, nt, ch)) + [(nt - 1) // 64 * 64]:
+    for x in [64] + list(range(ch, nt, ch)):
         if cut[-1] < x < nt:
             cut.append(x)
     return len(cut)
